@@ -1,0 +1,231 @@
+/*
+ * amggnn.h -- C ABI of the MI355X (gfx950) GNN-smoothed algebraic multigrid solve phase.
+ *
+ * Problem (paper Sec. 2.1, Eq. 1): A u = f with A sparse, symmetric, zero row sums
+ * for all-Neumann problems. The library stores A with a POSITIVE diagonal: a caller
+ * holding the paper's negative semi-definite form passes -A and -f (same solution).
+ *
+ * Conventions for every matrix argument
+ *   CSR, int32 rowptr[n+1] (rowptr[0] == 0), int32 col[nnz] strictly ascending within
+ *   a row, float64 val[nnz]. Square level matrices store their diagonal.
+ *
+ * Memory
+ *   Pointers documented as "device" point to GPU memory owned by the caller (for
+ *   example PyTorch tensors); the context keeps NON-OWNING views of the hierarchy
+ *   arrays handed to amgg_load_level / amgg_load_prolong, which must outlive it.
+ *   Everything the solver derives (R = P^T, FP32 copies, smoother values, dense
+ *   coarse inverse, level vectors, reduction scratch) lives in ONE caller-allocated
+ *   device workspace of amgg_workspace_bytes() bytes. The library never allocates
+ *   device memory; host-side results (amgg_rs_*) are allocated and freed by it.
+ *
+ * Streams
+ *   Every device call takes `void* stream` (a hipStream_t; NULL = default stream) and
+ *   is ordered on it. Calls returning host results synchronise that stream.
+ *
+ * Errors
+ *   0 = success; negative = error (nothing is left half-done on the host side; the
+ *   message is in amgg_last_error(), per thread); positive = solver outcome of
+ *   amgg_solve (not an error). No C++ exception crosses this interface. A context
+ *   is not thread-safe; distinct contexts are independent.
+ */
+#ifndef AMGGNN_H
+#define AMGGNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AMGG_OK 0
+#define AMGG_EINVAL (-1)     /* invalid argument, shape or pattern */
+#define AMGG_EWORKSPACE (-2) /* workspace missing or too small */
+#define AMGG_EHIP (-3)       /* HIP runtime error */
+#define AMGG_ESTATE (-4)     /* call out of order (e.g. vcycle before smoothers are set) */
+#define AMGG_ENONFINITE (-5) /* non-finite input or coefficient */
+
+#define AMGG_MAXIT 1     /* solve: iteration limit reached */
+#define AMGG_DIVERGED 2  /* solve: ||r|| > div_factor ||b|| or non-finite */
+#define AMGG_STAGNATED 3 /* solve: reduction over stag_window iterations worse than stag_ratio */
+#define AMGG_BREAKDOWN 4 /* solve: flexible CG lost positive definiteness (z^T r <= 0 or p^T A p <= 0) */
+
+#define AMGG_MAX_LEVELS 16
+#define AMGG_MAX_DEGREE 4
+#define AMGG_MAX_COARSE_DENSE 4096 /* largest coarsest level solved by the dense inverse */
+
+/* ------------------------------------------------------------------------------------
+ * Host setup: classical Ruge-Stueben hierarchy {A_l, P_l} (paper Sec. 2.2 and Sec. 4:
+ * classical RS coarsening, strength threshold theta = 0.25; App. B.1, Tab. 7: at most
+ * 10 levels; Alg. 1, step 2). The paper names the method only; this implementation
+ * fixes: negative-coupling strength, RS first pass with ties to the smallest index,
+ * direct interpolation with positive couplings lumped on the diagonal, Galerkin
+ * A_c = P^T (A P) by row-wise accumulation in ascending column order with exact zeros
+ * dropped off the diagonal. Coarsening stops at max_levels, at n <= max_coarse, when
+ * no C point exists or when 10 n_c > 9 n.
+ * ------------------------------------------------------------------------------------ */
+typedef struct amgg_rs amgg_rs;
+
+/* Build the hierarchy of the host CSR matrix (n rows). theta in (0,1); max_levels in
+ * [1, AMGG_MAX_LEVELS]; max_coarse >= 1. On success *out owns host memory released by
+ * amgg_rs_free. Also detects the all-Neumann case (|row sum| <= 1e-12 a_ii everywhere).
+ * Errors: AMGG_EINVAL for a bad pattern (unsorted columns, missing or non-positive
+ * diagonal, out-of-range column). */
+int amgg_rs_setup(const int32_t* rowptr, const int32_t* col, const double* val, int32_t n,
+                  double theta, int max_levels, int32_t max_coarse, amgg_rs** out);
+/* Number of levels and the singular (constant null space) flag. */
+int amgg_rs_info(const amgg_rs* h, int* nlevels, int* singular);
+/* Sizes of level lvl: n rows, nnz of A_l, and P_l's column count and nnz (0 on the coarsest). */
+int amgg_rs_level_size(const amgg_rs* h, int lvl, int32_t* n, int32_t* nnz, int32_t* p_ncols, int32_t* p_nnz);
+/* Copy level lvl into caller-allocated host arrays sized by amgg_rs_level_size; the P
+ * arguments are ignored (may be NULL) on the coarsest level. cf (may be NULL) receives
+ * 1 for C points and 0 for F points (all 0 on the coarsest level). */
+int amgg_rs_copy_level(const amgg_rs* h, int lvl, int32_t* rowptr, int32_t* col, double* val,
+                       int32_t* p_rowptr, int32_t* p_col, double* p_val, int8_t* cf);
+void amgg_rs_free(amgg_rs* h);
+
+/* ------------------------------------------------------------------------------------
+ * Device context: hierarchy load (Alg. 1, step 2) and derived data.
+ * ------------------------------------------------------------------------------------ */
+typedef struct amgg_ctx amgg_ctx;
+
+/* Context on HIP device `device` for a hierarchy of `nlevels` levels (1..AMGG_MAX_LEVELS). */
+int amgg_create(amgg_ctx** out, int device, int nlevels);
+int amgg_destroy(amgg_ctx* ctx);
+/* Message of the last failing call on this thread ("" if none). */
+const char* amgg_last_error(void);
+
+/* Level matrix A_l (device CSR, n x n, diagonal stored and positive). */
+int amgg_load_level(amgg_ctx* ctx, int lvl, int32_t n, int32_t nnz, const int32_t* rowptr,
+                    const int32_t* col, const double* val);
+/* Prolongation P_l (device CSR, n_f x n_c) between level lvl and lvl+1; lvl < nlevels-1. */
+int amgg_load_prolong(amgg_ctx* ctx, int lvl, int32_t n_f, int32_t n_c, int32_t nnz,
+                      const int32_t* rowptr, const int32_t* col, const double* val);
+/* Workspace size for the loaded hierarchy (all levels and prolongations must be loaded). */
+int amgg_workspace_bytes(const amgg_ctx* ctx, size_t* bytes);
+/* Bind the workspace (device, 256-byte aligned, >= amgg_workspace_bytes) and derive on the
+ * GPU: R_l = P_l^T as CSR (exact transpose, sorted columns), correctly rounded FP32 copies
+ * of A_l, P_l, R_l, the diagonal and s_l = max |offdiag(A_l)| (Sec. 3.1, Eq. 5), and the
+ * dense FP64 inverse of the coarsest matrix by LU with partial pivoting (Sec. 2.2: direct
+ * solve on the coarsest level). singular != 0 factors A_L + alpha 1 1^T with
+ * alpha = mean(diag A_L)/n_L so that the coarse correction of a consistent right-hand
+ * side has zero mean. Synchronises the stream. Errors: AMGG_EINVAL if the coarsest level
+ * exceeds AMGG_MAX_COARSE_DENSE or a pivot is zero; AMGG_EWORKSPACE. */
+int amgg_finalize(amgg_ctx* ctx, int singular, void* workspace, size_t ws_bytes, void* stream);
+
+/* Device views into the workspace for inspection (any argument may be NULL). */
+typedef struct {
+    int32_t n, nnz, n_coarse, p_nnz;
+    const int32_t* r_rowptr; /* R = P^T: n_coarse + 1 */
+    const int32_t* r_col;    /* p_nnz */
+    const double* r_val;     /* p_nnz */
+    const float* a_val32;    /* nnz */
+    const float* p_val32;    /* p_nnz */
+    const float* r_val32;    /* p_nnz */
+    const double* q_val;     /* nnz, smoother values on A's pattern */
+    const float* q_val32;    /* nnz */
+    const double* diag;      /* n */
+    const double* scale;     /* 1 value: s_l */
+    const double* coarse_inv;/* n*n row-major on the coarsest level, else NULL */
+} amgg_level_view;
+int amgg_level_view_get(const amgg_ctx* ctx, int lvl, amgg_level_view* out);
+
+/* ------------------------------------------------------------------------------------
+ * Smoother: sparse pseudo-inverse Q^{-1} on A_l's pattern (Sec. 3.1, Eq. 5; Alg. 1 step 8)
+ *   q_ii = f_d(a_ii/s)/a_ii,  q_ij = f_o(a_ij/s)/(a_ii + a_jj),  s = max |offdiag(A_l)|
+ *   f_d(x) = d0 + x(d1 + x(d2 + ...)),  f_o(x) = x(o1 + x(o2 + ...))   (Horner, FP64,
+ *   every operation rounded separately, IEEE division).
+ * coeffs = (d0..d_deg, o1..o_deg): 2*degree+1 values, degree in [1, AMGG_MAX_DEGREE].
+ * ------------------------------------------------------------------------------------ */
+/* Host coefficients. When every o_k is zero the smoother is diagonal and the cycle uses
+ * the one-pass diagonal (Jacobi-type) step. */
+int amgg_set_smoother_coeffs(amgg_ctx* ctx, int lvl, int degree, const double* coeffs, void* stream);
+/* Device coefficients (FP32, 2*degree+1 values, e.g. straight from the GCIN output):
+ * always assembled as a general sparse smoother; no host synchronisation. */
+int amgg_set_smoother_coeffs_device(amgg_ctx* ctx, int lvl, int degree, const float* coeffs_dev, void* stream);
+/* omega-Jacobi, the paper's baseline (Sec. 2.3, Eq. 4; Sec. 4: omega = 2/3) = coeffs (omega, 0, ..). */
+int amgg_set_smoother_jacobi(amgg_ctx* ctx, int lvl, double omega, void* stream);
+
+/* ------------------------------------------------------------------------------------
+ * Solve phase (Sec. 2.2; Alg. 1, steps 9-10)
+ * ------------------------------------------------------------------------------------ */
+/* One V(nu1, nu2) cycle u <- V(u, f) on the fine level. f and u are device FP64 vectors of
+ * n_0 entries; u is read and overwritten. precision 64 runs the whole cycle in FP64;
+ * precision 32 casts f and u to FP32, runs the cycle in FP32 (coarse solve in FP64) and
+ * casts back. Pre-smooth nu1 steps u <- u + Q^{-1}(f - A u), restrict r with R = P^T,
+ * recurse from a zero guess, prolongate and correct, post-smooth nu2 steps; the coarsest
+ * level is solved directly. nu1, nu2 in [0, 8]. */
+int amgg_vcycle(amgg_ctx* ctx, int nu1, int nu2, int precision, const double* f, double* u, void* stream);
+
+/* One level operator on its own (the building blocks of the cycle), e.g. to time a kernel
+ * or check an operator. Vectors are device arrays of the given precision (float* for 32,
+ * double* for 64) sized by the level: x, y, f of n_lvl entries except where noted.
+ *   AMGG_OP_SPMV      y = A_l x
+ *   AMGG_OP_RESIDUAL  y = f - A_l x
+ *   AMGG_OP_SMOOTH    y = y + Q_l^{-1} x        (smoother values on A_l's pattern)
+ *   AMGG_OP_JACOBI    y = x + diag(Q_l^{-1}) (f - A_l x)   (the one-pass diagonal step)
+ *   AMGG_OP_RESTRICT  y = R_l x, y of n_{l+1} entries          (lvl < nlevels-1)
+ *   AMGG_OP_PROLONG   y = y + P_l x, x of n_{l+1} entries      (lvl < nlevels-1)
+ *   AMGG_OP_COARSE    y = A_L^{-1} x by the dense inverse       (lvl == nlevels-1)
+ * SMOOTH and JACOBI need the level's smoother to be set. */
+#define AMGG_OP_SPMV 0
+#define AMGG_OP_RESIDUAL 1
+#define AMGG_OP_SMOOTH 2
+#define AMGG_OP_JACOBI 3
+#define AMGG_OP_RESTRICT 4
+#define AMGG_OP_PROLONG 5
+#define AMGG_OP_COARSE 6
+int amgg_level_apply(amgg_ctx* ctx, int lvl, int op, int precision, const void* x, void* y, const void* f,
+                     void* stream);
+
+#define AMGG_OUTER_STATIONARY 0 /* u <- V(u, f) repeated (FP64 cycles only) */
+#define AMGG_OUTER_IR 1         /* x <- x + V(0, b - A x): iterative refinement, FP64 residual */
+#define AMGG_OUTER_FCG 2        /* flexible preconditioned CG, FP64, z = V(0, r) */
+
+typedef struct {
+    int outer;            /* AMGG_OUTER_* */
+    int inner_precision;  /* 64 or 32 (32 not allowed with STATIONARY) */
+    int nu1, nu2;         /* smoothing steps */
+    int maxit;            /* iteration limit (Sec. 4 uses 500) */
+    double tol;           /* stop when ||b - A x|| <= tol ||b|| */
+    int fallback;         /* nonzero: on divergence, stagnation or breakdown switch every
+                             level to omega-Jacobi (omega = 2/3) and continue from x */
+    double div_factor;    /* diverged if ||r|| > div_factor ||b||; <= 0 means 1e3 */
+    double stag_ratio;    /* stagnated if ||r_k|| > stag_ratio ||r_{k-w}||; <= 0 means 0.99 */
+    int stag_window;      /* w; <= 0 means 10 */
+} amgg_solve_opts;
+
+typedef struct {
+    int iterations; /* outer iterations */
+    int vcycles;    /* V-cycles applied */
+    double relres;  /* final ||b - A x|| / ||b|| as tracked by the method */
+    int status;     /* 0 converged, else AMGG_MAXIT / DIVERGED / STAGNATED / BREAKDOWN */
+    int fell_back;  /* 1 if the Jacobi fallback was taken */
+} amgg_solve_info;
+
+/* Solve A x = b from x = 0 (Sec. 4: V-cycles until the relative residual reaches tol).
+ * b, x: device FP64 n_0-vectors (x is overwritten). For a singular hierarchy b is
+ * projected to zero mean first. history (host, may be NULL) receives up to history_cap
+ * relative residuals, entry 0 being 1. Returns 0 on convergence, a positive outcome code
+ * otherwise, negative on error. Synchronises the stream once per iteration. */
+int amgg_solve(amgg_ctx* ctx, const amgg_solve_opts* opts, const double* b, double* x,
+               amgg_solve_info* info, double* history, int history_cap, void* stream);
+
+/* ------------------------------------------------------------------------------------
+ * Learning: residual-reduction loss (Sec. 3.3, Eq. 11) of nvc V-cycles from u0 and its
+ * gradient with respect to every level's smoother coefficients, by a hand-written adjoint
+ * of the cycle that recomputes each level's smoothing iterates from the level's stored
+ * entry vector (no per-step storage).
+ * ------------------------------------------------------------------------------------ */
+/* Coefficients must have been set (all levels, same degree) with amgg_set_smoother_coeffs
+ * or amgg_set_smoother_coeffs_device. f, u0: device FP64 (u0 may be NULL for 0).
+ * precision 64 or 32. loss_dev: device FP64 scalar; dcoeffs_dev: device FP64
+ * [nlevels][2*degree+1] (coarsest row zero). No host synchronisation. */
+int amgg_vcycle_loss_adjoint(amgg_ctx* ctx, int nu1, int nu2, int precision, int nvc,
+                             const double* f, const double* u0, double* loss_dev,
+                             double* dcoeffs_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMGGNN_H */

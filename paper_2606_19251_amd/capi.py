@@ -1,0 +1,223 @@
+"""ctypes binding of libamggnn.so: the C entry points under their C names.
+
+Argument marshalling only. Pointers are passed as Python ints (for device memory,
+``tensor.data_ptr()``); sizes as ints; host arrays as numpy arrays. Every call raises
+``AmggError`` on a negative status. Loading fails loudly when the library is missing:
+there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libamggnn.so")
+
+AMGG_OK = 0
+AMGG_EINVAL = -1
+AMGG_EWORKSPACE = -2
+AMGG_EHIP = -3
+AMGG_ESTATE = -4
+AMGG_ENONFINITE = -5
+AMGG_MAXIT, AMGG_DIVERGED, AMGG_STAGNATED, AMGG_BREAKDOWN = 1, 2, 3, 4
+AMGG_OUTER_STATIONARY, AMGG_OUTER_IR, AMGG_OUTER_FCG = 0, 1, 2
+(AMGG_OP_SPMV, AMGG_OP_RESIDUAL, AMGG_OP_SMOOTH, AMGG_OP_JACOBI, AMGG_OP_RESTRICT, AMGG_OP_PROLONG,
+ AMGG_OP_COARSE) = range(7)
+AMGG_MAX_LEVELS = 16
+AMGG_MAX_COARSE_DENSE = 4096
+
+
+class AmggError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class amgg_level_view(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("n_coarse", C.c_int32), ("p_nnz", C.c_int32),
+                ("r_rowptr", C.c_void_p), ("r_col", C.c_void_p), ("r_val", C.c_void_p),
+                ("a_val32", C.c_void_p), ("p_val32", C.c_void_p), ("r_val32", C.c_void_p),
+                ("q_val", C.c_void_p), ("q_val32", C.c_void_p), ("diag", C.c_void_p),
+                ("scale", C.c_void_p), ("coarse_inv", C.c_void_p)]
+
+
+class amgg_solve_opts(C.Structure):
+    _fields_ = [("outer", C.c_int), ("inner_precision", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
+                ("maxit", C.c_int), ("tol", C.c_double), ("fallback", C.c_int), ("div_factor", C.c_double),
+                ("stag_ratio", C.c_double), ("stag_window", C.c_int)]
+
+
+class amgg_solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("vcycles", C.c_int), ("relres", C.c_double), ("status", C.c_int),
+                ("fell_back", C.c_int)]
+
+
+_VP = C.c_void_p
+_I32 = C.c_int32
+_I = C.c_int
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "amgg_rs_setup": (_I, [_VP, _VP, _VP, _I32, C.c_double, _I, _I32, C.POINTER(_VP)]),
+    "amgg_rs_info": (_I, [_VP, C.POINTER(_I), C.POINTER(_I)]),
+    "amgg_rs_level_size": (_I, [_VP, _I, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32)]),
+    "amgg_rs_copy_level": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "amgg_rs_free": (None, [_VP]),
+    "amgg_create": (_I, [C.POINTER(_VP), _I, _I]),
+    "amgg_destroy": (_I, [_VP]),
+    "amgg_last_error": (C.c_char_p, []),
+    "amgg_load_level": (_I, [_VP, _I, _I32, _I32, _VP, _VP, _VP]),
+    "amgg_load_prolong": (_I, [_VP, _I, _I32, _I32, _I32, _VP, _VP, _VP]),
+    "amgg_workspace_bytes": (_I, [_VP, C.POINTER(C.c_size_t)]),
+    "amgg_finalize": (_I, [_VP, _I, _VP, C.c_size_t, _VP]),
+    "amgg_level_view_get": (_I, [_VP, _I, C.POINTER(amgg_level_view)]),
+    "amgg_set_smoother_coeffs": (_I, [_VP, _I, _I, _VP, _VP]),
+    "amgg_set_smoother_coeffs_device": (_I, [_VP, _I, _I, _VP, _VP]),
+    "amgg_set_smoother_jacobi": (_I, [_VP, _I, C.c_double, _VP]),
+    "amgg_vcycle": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP]),
+    "amgg_level_apply": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _VP]),
+    "amgg_solve": (_I, [_VP, C.POINTER(amgg_solve_opts), _VP, _VP, C.POINTER(amgg_solve_info), _VP, _I, _VP]),
+    "amgg_vcycle_loss_adjoint": (_I, [_VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _VP]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libamggnn.so (once); raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        # The library resolves the HIP runtime by soname; loading torch first (when it is
+        # installed) makes the process use one runtime for torch's memory and our kernels.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not found: build it with `python -m paper_2606_19251_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def amgg_last_error() -> str:
+    return lib().amgg_last_error().decode()
+
+
+def _check(rc: int, name: str) -> int:
+    if rc < 0:
+        raise AmggError(rc, f"{name}: {amgg_last_error()}")
+    return rc
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+# ---------------------------------------------------------------------------- host setup
+def amgg_rs_setup(rowptr: np.ndarray, col: np.ndarray, val: np.ndarray, n: int, theta: float,
+                  max_levels: int, max_coarse: int) -> int:
+    rowptr = np.ascontiguousarray(rowptr, np.int32)
+    col = np.ascontiguousarray(col, np.int32)
+    val = np.ascontiguousarray(val, np.float64)
+    h = _VP()
+    _check(lib().amgg_rs_setup(_np_ptr(rowptr), _np_ptr(col), _np_ptr(val), n, theta, max_levels, max_coarse,
+                               C.byref(h)), "amgg_rs_setup")
+    return h.value
+
+
+def amgg_rs_info(h: int):
+    nl, sg = _I(), _I()
+    _check(lib().amgg_rs_info(h, C.byref(nl), C.byref(sg)), "amgg_rs_info")
+    return nl.value, sg.value
+
+
+def amgg_rs_level_size(h: int, lvl: int):
+    a, b, c, d = _I32(), _I32(), _I32(), _I32()
+    _check(lib().amgg_rs_level_size(h, lvl, C.byref(a), C.byref(b), C.byref(c), C.byref(d)), "amgg_rs_level_size")
+    return a.value, b.value, c.value, d.value
+
+
+def amgg_rs_copy_level(h: int, lvl: int, rowptr, col, val, p_rowptr=None, p_col=None, p_val=None, cf=None):
+    _check(lib().amgg_rs_copy_level(h, lvl, _np_ptr(rowptr), _np_ptr(col), _np_ptr(val), _np_ptr(p_rowptr),
+                                    _np_ptr(p_col), _np_ptr(p_val), _np_ptr(cf)), "amgg_rs_copy_level")
+
+
+def amgg_rs_free(h: int):
+    lib().amgg_rs_free(h)
+
+
+# ---------------------------------------------------------------------------- device context
+def amgg_create(device: int, nlevels: int) -> int:
+    c = _VP()
+    _check(lib().amgg_create(C.byref(c), device, nlevels), "amgg_create")
+    return c.value
+
+
+def amgg_destroy(ctx: int):
+    lib().amgg_destroy(ctx)
+
+
+def amgg_load_level(ctx, lvl, n, nnz, rowptr, col, val):
+    return _check(lib().amgg_load_level(ctx, lvl, n, nnz, rowptr, col, val), "amgg_load_level")
+
+
+def amgg_load_prolong(ctx, lvl, n_f, n_c, nnz, rowptr, col, val):
+    return _check(lib().amgg_load_prolong(ctx, lvl, n_f, n_c, nnz, rowptr, col, val), "amgg_load_prolong")
+
+
+def amgg_workspace_bytes(ctx) -> int:
+    b = C.c_size_t()
+    _check(lib().amgg_workspace_bytes(ctx, C.byref(b)), "amgg_workspace_bytes")
+    return b.value
+
+
+def amgg_finalize(ctx, singular, workspace, ws_bytes, stream):
+    return _check(lib().amgg_finalize(ctx, int(singular), workspace, ws_bytes, stream), "amgg_finalize")
+
+
+def amgg_level_view_get(ctx, lvl) -> amgg_level_view:
+    v = amgg_level_view()
+    _check(lib().amgg_level_view_get(ctx, lvl, C.byref(v)), "amgg_level_view_get")
+    return v
+
+
+def amgg_set_smoother_coeffs(ctx, lvl, degree, coeffs, stream):
+    c = np.ascontiguousarray(coeffs, np.float64)
+    return _check(lib().amgg_set_smoother_coeffs(ctx, lvl, degree, _np_ptr(c), stream), "amgg_set_smoother_coeffs")
+
+
+def amgg_set_smoother_coeffs_device(ctx, lvl, degree, coeffs_dev, stream):
+    return _check(lib().amgg_set_smoother_coeffs_device(ctx, lvl, degree, coeffs_dev, stream),
+                  "amgg_set_smoother_coeffs_device")
+
+
+def amgg_set_smoother_jacobi(ctx, lvl, omega, stream):
+    return _check(lib().amgg_set_smoother_jacobi(ctx, lvl, omega, stream), "amgg_set_smoother_jacobi")
+
+
+def amgg_vcycle(ctx, nu1, nu2, precision, f, u, stream):
+    return _check(lib().amgg_vcycle(ctx, nu1, nu2, precision, f, u, stream), "amgg_vcycle")
+
+
+def amgg_level_apply(ctx, lvl, op, precision, x, y, f, stream):
+    return _check(lib().amgg_level_apply(ctx, lvl, op, precision, x, y, f, stream), "amgg_level_apply")
+
+
+def amgg_solve(ctx, opts: amgg_solve_opts, b, x, history_cap: int, stream):
+    info = amgg_solve_info()
+    hist = np.zeros(max(history_cap, 1), np.float64)
+    rc = _check(lib().amgg_solve(ctx, C.byref(opts), b, x, C.byref(info), _np_ptr(hist), history_cap, stream),
+                "amgg_solve")
+    return rc, info, hist
+
+
+def amgg_vcycle_loss_adjoint(ctx, nu1, nu2, precision, nvc, f, u0, loss_dev, dcoeffs_dev, stream):
+    return _check(lib().amgg_vcycle_loss_adjoint(ctx, nu1, nu2, precision, nvc, f, u0, loss_dev, dcoeffs_dev,
+                                                 stream), "amgg_vcycle_loss_adjoint")

@@ -1,0 +1,321 @@
+// Residual-reduction loss of V-cycles and its gradient with respect to every level's
+// smoother coefficients (paper Sec. 3.3, Eq. 11; Alg. 1, steps 9-13). The paper obtains the
+// gradient by automatic differentiation; here the reverse sweep is written by hand:
+//
+//   smoothing step  u' = u + Q (f - A u):   ubar = ubar' - A (Q ubar'),  fbar += Q ubar',
+//                                          Qbar_ij = ubar'_i r_j  (reduced at once into cbar)
+//   restriction     f_c = R (f - A u):      rbar = P fbar_c,  ubar -= A rbar,  fbar += rbar
+//   prolongation    u'' = u + P e_c:        ebar_c = R ubar''
+//   coarsest        e = A_L^{-1} f:          fbar = A_L^{-1} ebar
+//
+// using A = A^T, Q = Q^T, R = P^T (symmetric up to rounding). dq_ii/dd_m = x_ii^m / a_ii and
+// dq_ij/do_m = x_ij^m / (a_ii + a_jj) with x = a/s. Smoothing iterates are not stored: each
+// level keeps its entry iterate and the iterate after its coarse-grid correction, and the
+// backward sweep recomputes the k-th smoothing iterate from these.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+
+#include "amggnn.h"
+#include "ctx.hpp"
+#include "errors.hpp"
+#include "kernels.hpp"
+
+using namespace amgg;
+
+namespace {
+
+constexpr int kMaxC = 2 * AMGG_MAX_DEGREE + 1;
+
+inline dim3 grid_for(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    return dim3(static_cast<unsigned>(g));
+}
+
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double red[kBlock / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int k = 1; k < kBlock / 64; ++k) s += red[k];
+    __syncthreads();
+    return s;
+}
+
+// t = Q ubar (row-wise) and per-block partial sums of the coefficient gradient:
+//   g[m]       += ubar_i r_i x_ii^m / a_ii                  m = 0..deg      (diagonal part)
+//   g[deg+m]   += ubar_i r_j x_ij^m / (a_ii + a_jj)   j != i, m = 1..deg      (off-diagonal part)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void adj_smooth_kernel(int32_t n, const int32_t* __restrict__ ptr,
+                                                           const int32_t* __restrict__ col,
+                                                           const double* __restrict__ val,
+                                                           const double* __restrict__ diag,
+                                                           const double* __restrict__ scale,
+                                                           const T* __restrict__ q, const T* __restrict__ ubar,
+                                                           const T* __restrict__ r, T* __restrict__ t, int deg,
+                                                           double* __restrict__ partial) {
+    double g[kMaxC];
+    for (int m = 0; m < kMaxC; ++m) g[m] = 0.0;
+    const double s = scale[0];
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += kReduceBlocks * kBlock) {
+        const double ui = static_cast<double>(ubar[i]);
+        const double aii = diag[i];
+        T acc = T(0);
+        for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p) {
+            const int32_t j = col[p];
+            acc += q[p] * ubar[j];
+            const double a = val[p];
+            const double x = a / s;
+            if (j == i) {
+                double w = ui * static_cast<double>(r[i]) / aii;
+                for (int m = 0; m <= deg; ++m) {
+                    g[m] += w;
+                    w *= x;
+                }
+            } else {
+                double w = ui * static_cast<double>(r[j]) / (aii + diag[j]) * x;
+                for (int m = 1; m <= deg; ++m) {
+                    g[deg + m] += w;
+                    w *= x;
+                }
+            }
+        }
+        t[i] = acc;
+    }
+    for (int m = 0; m <= 2 * deg; ++m) {
+        const double v = block_sum(g[m]);
+        if (threadIdx.x == 0) partial[m * kReduceBlocks + blockIdx.x] = v;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void adj_coeff_reduce_kernel(const double* __restrict__ partial, int ncoef,
+                                                                 double* __restrict__ cbar) {
+    __shared__ double red[kBlock];
+    for (int m = 0; m < ncoef; ++m) {
+        double v = 0.0;
+        for (int k = threadIdx.x; k < kReduceBlocks; k += kBlock) v += partial[m * kReduceBlocks + k];
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) cbar[m] += red[0];
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void axpy_kernel(int32_t n, const T* __restrict__ x, T* __restrict__ y) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] += x[i];
+}
+
+template <typename T>
+__global__ void scale_dev_kernel(int32_t n, T* __restrict__ y, const double* __restrict__ s) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] = static_cast<T>(static_cast<double>(y[i]) * s[0]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void dot_partial_kernel(int32_t n, const T* __restrict__ a,
+                                                            const T* __restrict__ b, double* __restrict__ partial) {
+    double v = 0.0;
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += kReduceBlocks * kBlock)
+        v += static_cast<double>(a[i]) * static_cast<double>(b[i]);
+    v = block_sum(v);
+    if (threadIdx.x == 0) partial[blockIdx.x] = v;
+}
+
+// s[0] = ||r_0||^2, s[1] = ||r_N||^2  ->  loss = log10(||r_N|| / ||r_0||),  s[2] = -1 / (ln 10 ||r_N||^2)
+__global__ void loss_kernel(double* __restrict__ s, double* __restrict__ loss) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        loss[0] = 0.5 * log10(s[1] / s[0]);
+        s[2] = -1.0 / (log(10.0) * s[1]);
+    }
+}
+
+struct Adj {
+    amgg_ctx* c;
+    hipStream_t st;
+    int nu1, nu2, deg;
+    double* cbar;
+    hipError_t e = hipSuccess;
+    void ok(hipError_t r) {
+        if (r != hipSuccess && e == hipSuccess) e = r;
+    }
+
+    template <typename T>
+    void axpy(int32_t n, const T* x, T* y) {
+        if (n > 0) axpy_kernel<T><<<grid_for(n), kBlock, 0, st>>>(n, x, y);
+        ok(hipGetLastError());
+    }
+
+    template <typename T>
+    double* dot(int32_t n, const T* a, const T* b, double* out) {
+        dot_partial_kernel<T><<<kReduceBlocks, kBlock, 0, st>>>(n, a, b, c->adj_partial);
+        ok(hipGetLastError());
+        ok(finish_sum(c->adj_partial, out, st));
+        return out;
+    }
+
+    // Iterate before smoothing step k (1-based) of a sequence starting at `entry` (nullptr = 0);
+    // returns nullptr when that iterate is the zero vector.
+    template <typename T>
+    const T* recompute(Level& L, const T* f, const T* entry, int k) {
+        if (k == 1) return entry;
+        T* cur = L.adj<T>(kAdjW);
+        T* oth = L.adj<T>(kAdjT);
+        if (entry) ok(vec_copy<T>(L.n, entry, cur, st));
+        for (int j = 1; j < k; ++j) ok(smooth_step<T>(L, f, cur, oth, L.r<T>(), entry == nullptr && j == 1, st));
+        return cur;
+    }
+
+    // Reverse one smoothing step u' = u + Q (f - A u) whose input iterate is w (nullptr = 0).
+    template <typename T>
+    void step_back(int l, const T* f, const T* w) {
+        Level& L = c->lv[l];
+        const T* r = f;
+        if (w) {
+            ok(csr_apply<T>(L.A(), L.aval<T>(), w, L.adj<T>(kAdjR), f, nullptr, nullptr, Epi::Resid, st));
+            r = L.adj<T>(kAdjR);
+        }
+        T* ub = L.adj<T>(kAdjUbar);
+        T* tq = L.t<T>();
+        adj_smooth_kernel<T><<<kReduceBlocks, kBlock, 0, st>>>(L.n, L.ptr, L.col, L.val, L.diag, L.scale,
+                                                                L.qval<T>(), ub, r, tq, deg, c->adj_partial);
+        ok(hipGetLastError());
+        adj_coeff_reduce_kernel<<<1, kBlock, 0, st>>>(c->adj_partial, 2 * deg + 1, cbar + l * (2 * deg + 1));
+        ok(hipGetLastError());
+        axpy<T>(L.n, tq, L.adj<T>(kAdjFbar));
+        ok(csr_apply<T>(L.A(), L.aval<T>(), tq, ub, nullptr, nullptr, nullptr, Epi::Sub, st));
+    }
+
+    // Given ubar of level l's output (in adj(kAdjUbar)), leave ubar of its input there and the
+    // adjoint of its right-hand side in adj(kAdjFbar).
+    template <typename T>
+    void level_back(int l, const T* f, const T* entry) {
+        Level& L = c->lv[l];
+        T* ub = L.adj<T>(kAdjUbar);
+        T* fb = L.adj<T>(kAdjFbar);
+        if (l == c->nlevels - 1) {
+            ok(dense_gemv<T>(L.n, L.inv, ub, fb, st));
+            return;
+        }
+        ok(vec_zero_bytes(fb, sizeof(T) * L.n, st));
+        for (int k = nu2; k >= 1; --k) step_back<T>(l, f, recompute<T>(L, f, L.adj<T>(kAdjUmid), k));
+        Level& C = c->lv[l + 1];
+        ok(csr_apply<T>(L.R(), L.rv<T>(), ub, C.adj<T>(kAdjUbar), nullptr, nullptr, nullptr, Epi::Store, st));
+        level_back<T>(l + 1, C.f<T>(), nullptr);
+        ok(csr_apply<T>(L.P(), L.pv<T>(), C.adj<T>(kAdjFbar), L.adj<T>(kAdjR), nullptr, nullptr, nullptr, Epi::Store,
+                        st));
+        ok(csr_apply<T>(L.A(), L.aval<T>(), L.adj<T>(kAdjR), ub, nullptr, nullptr, nullptr, Epi::Sub, st));
+        axpy<T>(L.n, L.adj<T>(kAdjR), fb);
+        for (int k = nu1; k >= 1; --k) step_back<T>(l, f, recompute<T>(L, f, entry, k));
+    }
+
+    // u_m from u_0 by m cycles; the level vectors of the m-th cycle are kept for the sweep.
+    // On return adj(kAdjUin) of level 0 holds u_{m-1}.
+    template <typename T>
+    T* forward_to(int m, const T* f0, const T* u0) {
+        Level& L0 = c->lv[0];
+        T* uin = L0.adj<T>(kAdjUin);
+        if (u0)
+            ok(vec_copy<T>(L0.n, u0, uin, st));
+        else
+            ok(vec_zero_bytes(uin, sizeof(T) * L0.n, st));
+        T* res = nullptr;
+        for (int i = 1; i <= m; ++i) {
+            if (i > 1) ok(vec_copy<T>(L0.n, res, uin, st));
+            ok(vec_copy<T>(L0.n, uin, L0.u<T>(), st));
+            ok(vcycle_level<T>(c, 0, f0, L0.u<T>(), L0.t<T>(), false, nu1, nu2, st, &res, i == m));
+        }
+        return res;
+    }
+
+    template <typename T>
+    void run(int nvc, const T* f0, const T* u0, double* loss) {
+        Level& L0 = c->lv[0];
+        const int32_t n = L0.n;
+        double* s = c->adj_scal;
+        // ||r_0||^2
+        T* r0 = L0.adj<T>(kAdjR);
+        if (u0) {
+            ok(csr_apply<T>(L0.A(), L0.aval<T>(), u0, r0, f0, nullptr, nullptr, Epi::Resid, st));
+            dot<T>(n, r0, r0, s + 0);
+        } else {
+            dot<T>(n, f0, f0, s + 0);
+        }
+        // forward, r_N, loss and the seed ubar_N = -(1/ln10) A r_N / ||r_N||^2
+        T* uN = forward_to<T>(nvc, f0, u0);
+        T* rN = L0.adj<T>(kAdjR);
+        ok(csr_apply<T>(L0.A(), L0.aval<T>(), uN, rN, f0, nullptr, nullptr, Epi::Resid, st));
+        dot<T>(n, rN, rN, s + 1);
+        loss_kernel<<<1, 1, 0, st>>>(s, loss);
+        ok(hipGetLastError());
+        T* ub = L0.adj<T>(kAdjUbar);
+        ok(csr_apply<T>(L0.A(), L0.aval<T>(), rN, ub, nullptr, nullptr, nullptr, Epi::Store, st));
+        scale_dev_kernel<T><<<grid_for(n), kBlock, 0, st>>>(n, ub, s + 2);
+        ok(hipGetLastError());
+        for (int m = nvc; m >= 1; --m) {
+            if (m < nvc) {
+                // recompute cycle m (its level vectors were overwritten); ubar is kept in place
+                T* keep = L0.t<T>();
+                ok(vec_copy<T>(n, ub, L0.adj<T>(kAdjFbar), st));
+                forward_to<T>(m, f0, u0);
+                ok(vec_copy<T>(n, L0.adj<T>(kAdjFbar), ub, st));
+                (void)keep;
+            }
+            level_back<T>(0, f0, L0.adj<T>(kAdjUin));
+        }
+    }
+};
+
+}  // namespace
+
+extern "C" int amgg_vcycle_loss_adjoint(amgg_ctx* c, int nu1, int nu2, int precision, int nvc, const double* f,
+                                        const double* u0, double* loss_dev, double* dcoeffs_dev, void* stream) {
+    return guarded([&]() -> int {
+        int rc = check_ready(c, "amgg_vcycle_loss_adjoint");
+        if (rc) return rc;
+        if (!f || !loss_dev || !dcoeffs_dev) return fail(AMGG_EINVAL, "amgg_vcycle_loss_adjoint: null argument");
+        if (nu1 < 0 || nu1 > 8 || nu2 < 0 || nu2 > 8 || nvc < 1 || nvc > 16)
+            return fail(AMGG_EINVAL, "amgg_vcycle_loss_adjoint: nu or nvc out of range");
+        if (precision != 32 && precision != 64)
+            return fail(AMGG_EINVAL, "amgg_vcycle_loss_adjoint: precision must be 32 or 64");
+        const int deg = c->lv[0].degree;
+        for (int l = 0; l + 1 < c->nlevels; ++l)
+            if (c->lv[l].degree != deg)
+                return fail(AMGG_EINVAL, "amgg_vcycle_loss_adjoint: every level needs the same polynomial degree");
+        if (c->nlevels > 1 && deg < 1) return fail(AMGG_ESTATE, "amgg_vcycle_loss_adjoint: smoothers not set");
+        const int d = c->nlevels > 1 ? deg : 1;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        Adj A{c, st, nu1, nu2, d, dcoeffs_dev};
+        A.ok(hipSetDevice(c->device));
+        A.ok(vec_zero_bytes(dcoeffs_dev, sizeof(double) * c->nlevels * (2 * d + 1), st));
+        Level& L0 = c->lv[0];
+        if (precision == 64) {
+            A.run<double>(nvc, f, u0, loss_dev);
+        } else {
+            A.ok(cast_f64_f32(L0.n, f, c->adj_f32, st));
+            float* u32 = nullptr;
+            if (u0) {
+                u32 = L0.adj<float>(kAdjW);  // the FP32 copy of u0 is read once, before recomputation reuses it
+                A.ok(cast_f64_f32(L0.n, u0, L0.r<float>(), st));
+                u32 = L0.r<float>();
+            }
+            if (u0) {
+                // keep u0 in a buffer the sweep never writes: the level's forward f buffer
+                A.ok(vec_copy<float>(L0.n, u32, L0.f<float>(), st));
+                u32 = L0.f<float>();
+            }
+            A.run<float>(nvc, c->adj_f32, u32, loss_dev);
+        }
+        if (A.e != hipSuccess) return hip_fail(A.e, "amgg_vcycle_loss_adjoint");
+        return AMGG_OK;
+    });
+}

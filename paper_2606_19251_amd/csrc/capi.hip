@@ -1,0 +1,473 @@
+// C interface of the solver: context and workspace management, hierarchy load, smoother
+// assembly, the V-cycle (paper Sec. 2.2; Alg. 1, step 9) and the outer FP64 loops.
+// Host code here only sequences kernels on the caller's stream; every arithmetic step of
+// the solve runs in the kernels of k_*.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "amggnn.h"
+#include "ctx.hpp"
+#include "errors.hpp"
+#include "kernels.hpp"
+
+using namespace amgg;
+
+namespace amgg {
+
+int hip_fail(hipError_t e, const char* where) {
+    return fail(AMGG_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+struct Bump {
+    uintptr_t base;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~static_cast<size_t>(255);
+        T* p = reinterpret_cast<T*>(base + off);
+        off += std::max<size_t>(count, 1) * sizeof(T);
+        return p;
+    }
+};
+
+}  // namespace
+
+// Carve the workspace; with base == 0 only the size is computed.
+size_t layout(amgg_ctx* c, uintptr_t base) {
+    Bump b{base};
+    int32_t max_nc = 1;
+    for (int l = 0; l < c->nlevels; ++l) {
+        Level& L = c->lv[l];
+        const size_t n = L.n, z = L.nnz;
+        L.val32 = b.take<float>(z);
+        L.q64 = b.take<double>(z);
+        L.q32 = b.take<float>(z);
+        L.diag = b.take<double>(n);
+        L.qd64 = b.take<double>(n);
+        L.qd32 = b.take<float>(n);
+        L.scale = b.take<double>(1);
+        L.u64 = b.take<double>(n);
+        L.f64 = b.take<double>(n);
+        L.r64 = b.take<double>(n);
+        L.t64 = b.take<double>(n);
+        L.u32 = b.take<float>(n);
+        L.f32 = b.take<float>(n);
+        L.r32 = b.take<float>(n);
+        L.t32 = b.take<float>(n);
+        if (l + 1 < c->nlevels) {
+            const size_t pz = L.pnnz;
+            L.pval32 = b.take<float>(pz);
+            L.rptr = b.take<int32_t>(L.nc + 1);
+            L.rcol = b.take<int32_t>(pz);
+            L.rval = b.take<double>(pz);
+            L.rval32 = b.take<float>(pz);
+            max_nc = std::max(max_nc, L.nc);
+            L.dense = L.inv = nullptr;
+            L.piv = nullptr;
+        } else {
+            L.dense = b.take<double>(n * n);
+            L.inv = b.take<double>(n * n);
+            L.piv = b.take<int32_t>(n);
+        }
+        for (int k = 0; k < kAdjVecs; ++k) {
+            L.adj64[k] = b.take<double>(n);
+            L.adj32[k] = b.take<float>(n);
+        }
+    }
+    const size_t n0 = c->lv[0].n;
+    c->scal = b.take<double>(kSlots);
+    c->partial = b.take<double>(kReduceBlocks);
+    c->partial2 = b.take<double>(2 * kReduceBlocks);
+    c->flags = b.take<int32_t>(8);
+    c->cursor = b.take<int32_t>(max_nc + 1);
+    c->ra = b.take<double>(n0);
+    c->rb = b.take<double>(n0);
+    c->z = b.take<double>(n0);
+    c->p = b.take<double>(n0);
+    c->q = b.take<double>(n0);
+    c->bproj = b.take<double>(n0);
+    c->adj_partial = b.take<double>(static_cast<size_t>(2 * AMGG_MAX_DEGREE + 1) * kReduceBlocks);
+    c->adj_scal = b.take<double>(64);
+    c->adj_f32 = b.take<float>(n0);
+    return (b.off + 255) & ~static_cast<size_t>(255);
+}
+
+// ------------------------------------------------------------------------------------
+// V-cycle
+// ------------------------------------------------------------------------------------
+template <typename T>
+hipError_t smooth_step(Level& L, const T* f, T*& cur, T*& oth, T* r, bool from_zero, hipStream_t st) {
+    const CsrView A = L.A();
+    hipError_t e;
+    if (L.smoother == kSmootherDiagonal) {
+        if (from_zero) return vec_mul<T>(L.n, L.qd<T>(), f, cur, st);
+        e = csr_apply<T>(A, L.aval<T>(), cur, oth, f, L.qd<T>(), cur, Epi::Jacobi, st);
+        std::swap(cur, oth);
+        return e;
+    }
+    if (from_zero) return csr_apply<T>(A, L.qval<T>(), f, cur, nullptr, nullptr, nullptr, Epi::Store, st);
+    if ((e = csr_apply<T>(A, L.aval<T>(), cur, r, f, nullptr, nullptr, Epi::Resid, st)) != hipSuccess) return e;
+    return csr_apply<T>(A, L.qval<T>(), r, cur, nullptr, nullptr, nullptr, Epi::Add, st);
+}
+template hipError_t smooth_step<float>(Level&, const float*, float*&, float*&, float*, bool, hipStream_t);
+template hipError_t smooth_step<double>(Level&, const double*, double*&, double*&, double*, bool, hipStream_t);
+
+template <typename T>
+hipError_t vcycle_level(amgg_ctx* c, int l, const T* f, T* u, T* t, bool zero, int nu1, int nu2, hipStream_t st,
+                        T** result, bool store) {
+    Level& L = c->lv[l];
+    hipError_t e;
+    if (l == c->nlevels - 1) {
+        *result = u;
+        return dense_gemv<T>(L.n, L.inv, f, u, st);
+    }
+    T* cur = u;
+    T* oth = t;
+    T* r = L.r<T>();
+    for (int k = 0; k < nu1; ++k)
+        if ((e = smooth_step<T>(L, f, cur, oth, r, zero && k == 0, st)) != hipSuccess) return e;
+    const bool still_zero = zero && nu1 == 0;
+    const T* res = f;
+    if (!still_zero) {
+        if ((e = csr_apply<T>(L.A(), L.aval<T>(), cur, r, f, nullptr, nullptr, Epi::Resid, st)) != hipSuccess)
+            return e;
+        res = r;
+    }
+    Level& C = c->lv[l + 1];
+    if ((e = csr_apply<T>(L.R(), L.rv<T>(), res, C.f<T>(), nullptr, nullptr, nullptr, Epi::Store, st)) != hipSuccess)
+        return e;
+    T* ec = nullptr;
+    if ((e = vcycle_level<T>(c, l + 1, C.f<T>(), C.u<T>(), C.t<T>(), true, nu1, nu2, st, &ec, store)) != hipSuccess)
+        return e;
+    if ((e = csr_apply<T>(L.P(), L.pv<T>(), ec, cur, nullptr, nullptr, nullptr, still_zero ? Epi::Store : Epi::Add,
+                          st)) != hipSuccess)
+        return e;
+    // the adjoint recomputes post-smoothing from this iterate
+    if (store && (e = vec_copy<T>(L.n, cur, L.adj<T>(kAdjUmid), st)) != hipSuccess) return e;
+    for (int k = 0; k < nu2; ++k)
+        if ((e = smooth_step<T>(L, f, cur, oth, r, false, st)) != hipSuccess) return e;
+    *result = cur;
+    return hipSuccess;
+}
+
+template hipError_t vcycle_level<float>(amgg_ctx*, int, const float*, float*, float*, bool, int, int, hipStream_t,
+                                        float**, bool);
+template hipError_t vcycle_level<double>(amgg_ctx*, int, const double*, double*, double*, bool, int, int,
+                                         hipStream_t, double**, bool);
+
+int check_ready(const amgg_ctx* c, const char* where) {
+    if (!c) return fail(AMGG_EINVAL, std::string(where) + ": null context");
+    if (!c->finalized) return fail(AMGG_ESTATE, std::string(where) + ": hierarchy not finalized");
+    for (int l = 0; l + 1 < c->nlevels; ++l)
+        if (c->lv[l].smoother == kSmootherNone)
+            return fail(AMGG_ESTATE, std::string(where) + ": smoother of level " + std::to_string(l) + " not set");
+    return AMGG_OK;
+}
+
+}  // namespace amgg
+
+// ------------------------------------------------------------------------------------
+// Context and hierarchy
+// ------------------------------------------------------------------------------------
+extern "C" int amgg_create(amgg_ctx** out, int device, int nlevels) {
+    return guarded([&]() -> int {
+        if (!out) return fail(AMGG_EINVAL, "amgg_create: null output");
+        if (nlevels < 1 || nlevels > AMGG_MAX_LEVELS) return fail(AMGG_EINVAL, "amgg_create: nlevels out of range");
+        int count = 0;
+        hipError_t e = hipGetDeviceCount(&count);
+        if (e != hipSuccess) return hip_fail(e, "amgg_create");
+        if (device < 0 || device >= count) return fail(AMGG_EINVAL, "amgg_create: no such device");
+        auto* c = new amgg_ctx();
+        c->device = device;
+        c->nlevels = nlevels;
+        if ((e = hipSetDevice(device)) != hipSuccess || (e = hipHostMalloc(&c->host_scal, sizeof(double) * kSlots)) != hipSuccess) {
+            delete c;
+            return hip_fail(e, "amgg_create");
+        }
+        *out = c;
+        return AMGG_OK;
+    });
+}
+
+extern "C" int amgg_destroy(amgg_ctx* c) {
+    if (!c) return AMGG_OK;
+    if (c->host_scal) (void)hipHostFree(c->host_scal);
+    delete c;
+    return AMGG_OK;
+}
+
+extern "C" int amgg_load_level(amgg_ctx* c, int lvl, int32_t n, int32_t nnz, const int32_t* rowptr,
+                               const int32_t* col, const double* val) {
+    if (!c || lvl < 0 || lvl >= c->nlevels) return fail(AMGG_EINVAL, "amgg_load_level: bad context or level");
+    if (n <= 0 || nnz < n || !rowptr || !col || !val) return fail(AMGG_EINVAL, "amgg_load_level: bad sizes or null array");
+    Level& L = c->lv[lvl];
+    L.n = n;
+    L.nnz = nnz;
+    L.ptr = rowptr;
+    L.col = col;
+    L.val = val;
+    L.loaded = true;
+    c->finalized = false;
+    return AMGG_OK;
+}
+
+extern "C" int amgg_load_prolong(amgg_ctx* c, int lvl, int32_t n_f, int32_t n_c, int32_t nnz,
+                                 const int32_t* rowptr, const int32_t* col, const double* val) {
+    if (!c || lvl < 0 || lvl + 1 >= c->nlevels) return fail(AMGG_EINVAL, "amgg_load_prolong: bad context or level");
+    if (n_f <= 0 || n_c <= 0 || nnz < 0 || !rowptr || (nnz > 0 && (!col || !val)))
+        return fail(AMGG_EINVAL, "amgg_load_prolong: bad sizes or null array");
+    Level& L = c->lv[lvl];
+    L.pn_f = n_f;
+    L.nc = n_c;
+    L.pnnz = nnz;
+    L.pptr = rowptr;
+    L.pcol = col;
+    L.pval = val;
+    L.p_loaded = true;
+    c->finalized = false;
+    return AMGG_OK;
+}
+
+static int check_loaded(const amgg_ctx* c, const char* where) {
+    for (int l = 0; l < c->nlevels; ++l) {
+        const Level& L = c->lv[l];
+        if (!L.loaded) return fail(AMGG_ESTATE, std::string(where) + ": level " + std::to_string(l) + " not loaded");
+        if (l + 1 < c->nlevels) {
+            if (!L.p_loaded)
+                return fail(AMGG_ESTATE, std::string(where) + ": prolongation " + std::to_string(l) + " not loaded");
+            if (L.pn_f != L.n || L.nc != c->lv[l + 1].n)
+                return fail(AMGG_EINVAL, std::string(where) + ": prolongation " + std::to_string(l) +
+                                             " does not match the level sizes");
+        }
+    }
+    const int32_t nL = c->lv[c->nlevels - 1].n;
+    if (nL > AMGG_MAX_COARSE_DENSE)
+        return fail(AMGG_EINVAL, std::string(where) + ": coarsest level has " + std::to_string(nL) +
+                                     " rows, more than the dense limit " + std::to_string(AMGG_MAX_COARSE_DENSE));
+    return AMGG_OK;
+}
+
+extern "C" int amgg_workspace_bytes(const amgg_ctx* c, size_t* bytes) {
+    return guarded([&]() -> int {
+        if (!c || !bytes) return fail(AMGG_EINVAL, "amgg_workspace_bytes: null argument");
+        int rc = check_loaded(c, "amgg_workspace_bytes");
+        if (rc) return rc;
+        amgg_ctx tmp = *c;
+        *bytes = layout(&tmp, 0);
+        return AMGG_OK;
+    });
+}
+
+extern "C" int amgg_finalize(amgg_ctx* c, int singular, void* workspace, size_t ws_bytes, void* stream) {
+    return guarded([&]() -> int {
+        if (!c) return fail(AMGG_EINVAL, "amgg_finalize: null context");
+        int rc = check_loaded(c, "amgg_finalize");
+        if (rc) return rc;
+        if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u))
+            return fail(AMGG_EWORKSPACE, "amgg_finalize: workspace null or not 256-byte aligned");
+        amgg_ctx tmp = *c;
+        const size_t need = layout(&tmp, 0);
+        if (ws_bytes < need)
+            return fail(AMGG_EWORKSPACE, "amgg_finalize: workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
+                                             std::to_string(need));
+        hipError_t e = hipSetDevice(c->device);
+        if (e != hipSuccess) return hip_fail(e, "amgg_finalize");
+        layout(c, reinterpret_cast<uintptr_t>(workspace));
+        c->ws = workspace;
+        c->ws_bytes = ws_bytes;
+        c->singular = singular ? 1 : 0;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        auto ok = [&](hipError_t r) { if (r != hipSuccess && e == hipSuccess) e = r; };
+        ok(vec_zero_bytes(c->flags, sizeof(int32_t) * 8, st));
+        ok(vec_zero_bytes(c->scal, sizeof(double) * kSlots, st));
+        for (int l = 0; l < c->nlevels; ++l) {
+            Level& L = c->lv[l];
+            L.smoother = kSmootherNone;
+            ok(extract_diag(L.n, L.ptr, L.col, L.val, L.diag, c->flags + 0, st));
+            ok(offdiag_absmax(L.n, L.ptr, L.col, L.val, c->partial, L.scale, st));
+            ok(cast_f64_f32(L.nnz, L.val, L.val32, st));
+            if (l + 1 < c->nlevels) {
+                ok(cast_f64_f32(L.pnnz, L.pval, L.pval32, st));
+                ok(transpose_csr(L.n, L.nc, L.pnnz, L.pptr, L.pcol, L.pval, L.rptr, L.rcol, L.rval, c->cursor, st));
+                ok(cast_f64_f32(L.pnnz, L.rval, L.rval32, st));
+            }
+        }
+        Level& Lc = c->lv[c->nlevels - 1];
+        ok(dense_from_csr(Lc.n, Lc.ptr, Lc.col, Lc.val, Lc.dense, c->singular, st));
+        ok(dense_lu_inverse(Lc.n, Lc.dense, Lc.piv, Lc.inv, c->flags + 1, st));
+        if (e != hipSuccess) return hip_fail(e, "amgg_finalize (launch)");
+        int32_t flags[2] = {0, 0};
+        if ((e = hipMemcpyAsync(flags, c->flags, sizeof(flags), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess)
+            return hip_fail(e, "amgg_finalize (sync)");
+        if (flags[0]) return fail(AMGG_EINVAL, "amgg_finalize: a level matrix has a missing or non-positive diagonal");
+        if (flags[1]) return fail(AMGG_EINVAL, "amgg_finalize: coarsest matrix is singular (zero pivot)");
+        c->finalized = true;
+        return AMGG_OK;
+    });
+}
+
+extern "C" int amgg_level_view_get(const amgg_ctx* c, int lvl, amgg_level_view* v) {
+    if (!c || !v || lvl < 0 || lvl >= c->nlevels) return fail(AMGG_EINVAL, "amgg_level_view_get: bad argument");
+    if (!c->finalized) return fail(AMGG_ESTATE, "amgg_level_view_get: hierarchy not finalized");
+    const Level& L = c->lv[lvl];
+    const bool coarse = lvl == c->nlevels - 1;
+    std::memset(v, 0, sizeof(*v));
+    v->n = L.n;
+    v->nnz = L.nnz;
+    v->n_coarse = coarse ? 0 : L.nc;
+    v->p_nnz = coarse ? 0 : L.pnnz;
+    v->r_rowptr = coarse ? nullptr : L.rptr;
+    v->r_col = coarse ? nullptr : L.rcol;
+    v->r_val = coarse ? nullptr : L.rval;
+    v->a_val32 = L.val32;
+    v->p_val32 = coarse ? nullptr : L.pval32;
+    v->r_val32 = coarse ? nullptr : L.rval32;
+    v->q_val = L.q64;
+    v->q_val32 = L.q32;
+    v->diag = L.diag;
+    v->scale = L.scale;
+    v->coarse_inv = coarse ? L.inv : nullptr;
+    return AMGG_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Smoother
+// ------------------------------------------------------------------------------------
+static int set_coeffs_impl(amgg_ctx* c, int lvl, int degree, const double* coeffs, const float* dev, void* stream) {
+    if (!c || lvl < 0 || lvl >= c->nlevels) return fail(AMGG_EINVAL, "amgg_set_smoother: bad context or level");
+    if (!c->finalized) return fail(AMGG_ESTATE, "amgg_set_smoother: hierarchy not finalized");
+    if (degree < 1 || degree > AMGG_MAX_DEGREE) return fail(AMGG_EINVAL, "amgg_set_smoother: degree out of range");
+    if (!coeffs && !dev) return fail(AMGG_EINVAL, "amgg_set_smoother: null coefficients");
+    PolyCoeffs pc{};
+    pc.degree = degree;
+    bool diagonal = false;
+    if (coeffs) {
+        diagonal = true;
+        for (int k = 0; k < 2 * degree + 1; ++k) {
+            if (!std::isfinite(coeffs[k])) return fail(AMGG_ENONFINITE, "amgg_set_smoother: non-finite coefficient");
+            pc.c[k] = coeffs[k];
+            if (k > degree && coeffs[k] != 0.0) diagonal = false;
+        }
+    }
+    Level& L = c->lv[lvl];
+    hipError_t e = hipSetDevice(c->device);
+    if (e == hipSuccess)
+        e = assemble_smoother(L.n, L.ptr, L.col, L.val, L.diag, L.scale, pc, coeffs ? nullptr : dev, L.q64, L.q32,
+                              L.qd64, L.qd32, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "amgg_set_smoother");
+    L.smoother = diagonal ? kSmootherDiagonal : kSmootherSparse;
+    L.degree = degree;
+    return AMGG_OK;
+}
+
+extern "C" int amgg_set_smoother_coeffs(amgg_ctx* c, int lvl, int degree, const double* coeffs, void* stream) {
+    return guarded([&] { return set_coeffs_impl(c, lvl, degree, coeffs, nullptr, stream); });
+}
+
+extern "C" int amgg_set_smoother_coeffs_device(amgg_ctx* c, int lvl, int degree, const float* coeffs_dev,
+                                               void* stream) {
+    return guarded([&] { return set_coeffs_impl(c, lvl, degree, nullptr, coeffs_dev, stream); });
+}
+
+extern "C" int amgg_set_smoother_jacobi(amgg_ctx* c, int lvl, double omega, void* stream) {
+    double cf[3] = {omega, 0.0, 0.0};
+    return guarded([&] { return set_coeffs_impl(c, lvl, 1, cf, nullptr, stream); });
+}
+
+// ------------------------------------------------------------------------------------
+// V-cycle entry point
+// ------------------------------------------------------------------------------------
+extern "C" int amgg_vcycle(amgg_ctx* c, int nu1, int nu2, int precision, const double* f, double* u, void* stream) {
+    return guarded([&]() -> int {
+        int rc = check_ready(c, "amgg_vcycle");
+        if (rc) return rc;
+        if (!f || !u) return fail(AMGG_EINVAL, "amgg_vcycle: null vector");
+        if (nu1 < 0 || nu1 > 8 || nu2 < 0 || nu2 > 8) return fail(AMGG_EINVAL, "amgg_vcycle: nu out of range");
+        if (precision != 64 && precision != 32) return fail(AMGG_EINVAL, "amgg_vcycle: precision must be 64 or 32");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        hipError_t e = hipSetDevice(c->device);
+        Level& L0 = c->lv[0];
+        if (e == hipSuccess && precision == 64) {
+            double* res = nullptr;
+            e = vec_copy<double>(L0.n, u, L0.u64, st);
+            if (e == hipSuccess) e = vcycle_level<double>(c, 0, f, L0.u64, L0.t64, false, nu1, nu2, st, &res);
+            if (e == hipSuccess) e = vec_copy<double>(L0.n, res, u, st);
+        } else if (e == hipSuccess) {
+            float* res = nullptr;
+            e = cast_f64_f32(L0.n, f, L0.f32, st);
+            if (e == hipSuccess) e = cast_f64_f32(L0.n, u, L0.u32, st);
+            if (e == hipSuccess) e = vcycle_level<float>(c, 0, L0.f32, L0.u32, L0.t32, false, nu1, nu2, st, &res);
+            if (e == hipSuccess) e = cast_f32_f64(L0.n, res, u, st);
+        }
+        if (e != hipSuccess) return hip_fail(e, "amgg_vcycle");
+        return AMGG_OK;
+    });
+}
+
+// ------------------------------------------------------------------------------------
+// Single level operators
+// ------------------------------------------------------------------------------------
+namespace {
+
+template <typename T>
+hipError_t level_apply_t(amgg_ctx* c, int lvl, int op, const T* x, T* y, const T* f, hipStream_t st) {
+    Level& L = c->lv[lvl];
+    switch (op) {
+        case AMGG_OP_SPMV:
+            return csr_apply<T>(L.A(), L.aval<T>(), x, y, nullptr, nullptr, nullptr, Epi::Store, st);
+        case AMGG_OP_RESIDUAL:
+            return csr_apply<T>(L.A(), L.aval<T>(), x, y, f, nullptr, nullptr, Epi::Resid, st);
+        case AMGG_OP_SMOOTH:
+            return csr_apply<T>(L.A(), L.qval<T>(), x, y, nullptr, nullptr, nullptr, Epi::Add, st);
+        case AMGG_OP_JACOBI:
+            return csr_apply<T>(L.A(), L.aval<T>(), x, y, f, L.qd<T>(), x, Epi::Jacobi, st);
+        case AMGG_OP_RESTRICT:
+            return csr_apply<T>(L.R(), L.rv<T>(), x, y, nullptr, nullptr, nullptr, Epi::Store, st);
+        case AMGG_OP_PROLONG:
+            return csr_apply<T>(L.P(), L.pv<T>(), x, y, nullptr, nullptr, nullptr, Epi::Add, st);
+        case AMGG_OP_COARSE:
+            return dense_gemv<T>(L.n, L.inv, x, y, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+extern "C" int amgg_level_apply(amgg_ctx* c, int lvl, int op, int precision, const void* x, void* y, const void* f,
+                                void* stream) {
+    return guarded([&]() -> int {
+        if (!c || lvl < 0 || lvl >= c->nlevels) return fail(AMGG_EINVAL, "amgg_level_apply: bad context or level");
+        if (!c->finalized) return fail(AMGG_ESTATE, "amgg_level_apply: hierarchy not finalized");
+        if (op < AMGG_OP_SPMV || op > AMGG_OP_COARSE) return fail(AMGG_EINVAL, "amgg_level_apply: unknown op");
+        if (precision != 32 && precision != 64) return fail(AMGG_EINVAL, "amgg_level_apply: precision must be 32 or 64");
+        const bool coarsest = lvl == c->nlevels - 1;
+        if ((op == AMGG_OP_RESTRICT || op == AMGG_OP_PROLONG) && coarsest)
+            return fail(AMGG_EINVAL, "amgg_level_apply: no transfer below the coarsest level");
+        if (op == AMGG_OP_COARSE && !coarsest) return fail(AMGG_EINVAL, "amgg_level_apply: COARSE needs the coarsest level");
+        if ((op == AMGG_OP_SMOOTH || op == AMGG_OP_JACOBI) && c->lv[lvl].smoother == kSmootherNone)
+            return fail(AMGG_ESTATE, "amgg_level_apply: smoother not set");
+        if (!x || !y || ((op == AMGG_OP_RESIDUAL || op == AMGG_OP_JACOBI) && !f))
+            return fail(AMGG_EINVAL, "amgg_level_apply: null vector");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        hipError_t e = hipSetDevice(c->device);
+        if (e == hipSuccess) {
+            if (precision == 64)
+                e = level_apply_t<double>(c, lvl, op, static_cast<const double*>(x), static_cast<double*>(y),
+                                          static_cast<const double*>(f), st);
+            else
+                e = level_apply_t<float>(c, lvl, op, static_cast<const float*>(x), static_cast<float*>(y),
+                                         static_cast<const float*>(f), st);
+        }
+        if (e != hipSuccess) return hip_fail(e, "amgg_level_apply");
+        return AMGG_OK;
+    });
+}

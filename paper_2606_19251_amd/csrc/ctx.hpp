@@ -1,0 +1,116 @@
+// Internal state of a solver context: per-level views of the caller's hierarchy arrays
+// and the arrays carved from the caller's workspace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "amggnn.h"
+#include "kernels.hpp"
+
+namespace amgg {
+
+enum : int { kSmootherNone = 0, kSmootherDiagonal = 1, kSmootherSparse = 2 };
+
+struct Level {
+    bool loaded = false, p_loaded = false;
+    // A_l (caller-owned, device)
+    int32_t n = 0, nnz = 0;
+    const int32_t* ptr = nullptr;
+    const int32_t* col = nullptr;
+    const double* val = nullptr;
+    // P_l (caller-owned, device), n x nc
+    int32_t pn_f = 0, nc = 0, pnnz = 0;
+    const int32_t* pptr = nullptr;
+    const int32_t* pcol = nullptr;
+    const double* pval = nullptr;
+    // workspace
+    float* val32 = nullptr;
+    float* pval32 = nullptr;
+    int32_t* rptr = nullptr;
+    int32_t* rcol = nullptr;
+    double* rval = nullptr;
+    float* rval32 = nullptr;
+    double* diag = nullptr;
+    double* scale = nullptr;
+    double* q64 = nullptr;
+    float* q32 = nullptr;
+    double* qd64 = nullptr;
+    float* qd32 = nullptr;
+    double *u64 = nullptr, *f64 = nullptr, *r64 = nullptr, *t64 = nullptr;
+    float *u32 = nullptr, *f32 = nullptr, *r32 = nullptr, *t32 = nullptr;
+    double* dense = nullptr;
+    double* inv = nullptr;
+    int32_t* piv = nullptr;
+    // adjoint scratch, kAdjVecs vectors of n per precision (see AdjVec)
+    double* adj64[8] = {};
+    float* adj32[8] = {};
+    // smoother state
+    int smoother = kSmootherNone;
+    int degree = 0;
+
+    CsrView A() const { return {n, nnz, ptr, col, lanes_for(n, nnz)}; }
+    CsrView P() const { return {n, pnnz, pptr, pcol, lanes_for(n, pnnz)}; }
+    CsrView R() const { return {nc, pnnz, rptr, rcol, lanes_for(nc, pnnz)}; }
+
+    template <typename T> const T* aval() const { if constexpr (std::is_same_v<T, double>) return val; else return val32; }
+    template <typename T> const T* qval() const { if constexpr (std::is_same_v<T, double>) return q64; else return q32; }
+    template <typename T> const T* qd() const { if constexpr (std::is_same_v<T, double>) return qd64; else return qd32; }
+    template <typename T> const T* pv() const { if constexpr (std::is_same_v<T, double>) return pval; else return pval32; }
+    template <typename T> const T* rv() const { if constexpr (std::is_same_v<T, double>) return rval; else return rval32; }
+    template <typename T> T* u() const { if constexpr (std::is_same_v<T, double>) return u64; else return u32; }
+    template <typename T> T* f() const { if constexpr (std::is_same_v<T, double>) return f64; else return f32; }
+    template <typename T> T* r() const { if constexpr (std::is_same_v<T, double>) return r64; else return r32; }
+    template <typename T> T* t() const { if constexpr (std::is_same_v<T, double>) return t64; else return t32; }
+    template <typename T> T* adj(int k) const { if constexpr (std::is_same_v<T, double>) return adj64[k]; else return adj32[k]; }
+};
+
+// Adjoint work vectors of a level
+enum AdjVec : int {
+    kAdjUin = 0,   // entry iterate of the level (fine level only; coarser levels start from 0)
+    kAdjUmid = 1,  // iterate after the coarse-grid correction (entry of post-smoothing)
+    kAdjUbar = 2,  // adjoint of the level's iterate
+    kAdjFbar = 3,  // adjoint of the level's right-hand side
+    kAdjR = 4,     // recomputed residual / restricted adjoint
+    kAdjW = 5,     // recomputed smoothing iterate
+    kAdjT = 6,     // second buffer of the recomputation (diagonal step ping-pong) / Q ubar
+    kAdjVecs = 7
+};
+
+}  // namespace amgg
+
+struct amgg_ctx {
+    int device = 0;
+    int nlevels = 0;
+    amgg::Level lv[AMGG_MAX_LEVELS];
+    bool finalized = false;
+    int singular = 0;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    double* host_scal = nullptr;  // pinned host copy of the device scalars
+    // workspace
+    double* scal = nullptr;
+    double* partial = nullptr;
+    double* partial2 = nullptr;
+    int32_t* flags = nullptr;
+    int32_t* cursor = nullptr;
+    double *ra = nullptr, *rb = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *bproj = nullptr;
+    double* adj_partial = nullptr;
+    double* adj_scal = nullptr;
+    float* adj_f32 = nullptr;
+};
+
+namespace amgg {
+
+size_t layout(amgg_ctx* c, uintptr_t base);
+int hip_fail(hipError_t e, const char* where);
+int check_ready(const amgg_ctx* c, const char* where);
+template <typename T>
+hipError_t vcycle_level(amgg_ctx* c, int l, const T* f, T* u, T* t, bool zero, int nu1, int nu2, hipStream_t st,
+                        T** result, bool store = false);
+template <typename T>
+hipError_t smooth_step(Level& L, const T* f, T*& cur, T*& oth, T* r, bool from_zero, hipStream_t st);
+
+}  // namespace amgg

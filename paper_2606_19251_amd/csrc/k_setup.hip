@@ -1,0 +1,327 @@
+// Setup-side kernels: diagonal and off-diagonal scale of each level, the exact transpose
+// R = P^T, and the dense coarsest-level factorisation, inverse and per-cycle product.
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace amgg {
+
+namespace {
+
+inline dim3 grid_for(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    return dim3(static_cast<unsigned>(g));
+}
+
+__global__ void extract_diag_kernel(int32_t n, const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                    const double* __restrict__ val, double* __restrict__ diag,
+                                    int32_t* __restrict__ bad) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double d = 0.0;
+    bool found = false;
+    for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p)
+        if (col[p] == i) {
+            d = val[p];
+            found = true;
+        }
+    diag[i] = d;
+    if (!found || !(d > 0.0)) atomicOr(bad, 1);
+}
+
+__global__ __launch_bounds__(kBlock) void absmax_partial_kernel(int32_t n, const int32_t* __restrict__ ptr,
+                                                               const int32_t* __restrict__ col,
+                                                               const double* __restrict__ val,
+                                                               double* __restrict__ partial) {
+    __shared__ double red[kBlock];
+    double m = -1.0;  // -1 marks "no off-diagonal seen"
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += kReduceBlocks * kBlock)
+        for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p)
+            if (col[p] != i) m = fmax(m, fabs(val[p]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void absmax_final_kernel(const double* __restrict__ partial,
+                                                             double* __restrict__ scale) {
+    __shared__ double red[kBlock];
+    double m = -1.0;
+    for (int k = threadIdx.x; k < kReduceBlocks; k += kBlock) m = fmax(m, partial[k]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) scale[0] = red[0] < 0.0 ? 1.0 : red[0];
+}
+
+// --- transpose -----------------------------------------------------------------------
+__global__ void count_cols_kernel(int32_t nnz, const int32_t* __restrict__ col, int32_t* __restrict__ cnt) {
+    const int32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p < nnz) atomicAdd(&cnt[col[p] + 1], 1);
+}
+
+// In-place inclusive scan of a[1..m] by one workgroup of 1024 threads (setup only).
+__global__ __launch_bounds__(1024) void scan_kernel(int32_t m, int32_t* __restrict__ a) {
+    __shared__ int32_t part[1024];
+    const int32_t chunk = (m + 1023) / 1024;
+    const int32_t lo = 1 + threadIdx.x * chunk;
+    const int32_t hi = min(lo + chunk, m + 1);
+    int32_t s = 0;
+    for (int32_t k = lo; k < hi; ++k) s += a[k];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int k = 0; k < 1024; ++k) {
+            const int32_t v = part[k];
+            part[k] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int32_t run = part[threadIdx.x];
+    for (int32_t k = lo; k < hi; ++k) {
+        run += a[k];
+        a[k] = run;
+    }
+}
+
+__global__ void scatter_transpose_kernel(int32_t nf, const int32_t* __restrict__ p_ptr,
+                                         const int32_t* __restrict__ p_col, const double* __restrict__ p_val,
+                                         int32_t* __restrict__ cursor, int32_t* __restrict__ r_col,
+                                         double* __restrict__ r_val) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nf) return;
+    for (int32_t p = p_ptr[i]; p < p_ptr[i + 1]; ++p) {
+        const int32_t dst = atomicAdd(&cursor[p_col[p]], 1);
+        r_col[dst] = i;
+        r_val[dst] = p_val[p];
+    }
+}
+
+// The scatter order within a row depends on atomics; sorting by column restores the one
+// exact transpose.
+__global__ void sort_rows_kernel(int32_t nc, const int32_t* __restrict__ r_ptr, int32_t* __restrict__ r_col,
+                                 double* __restrict__ r_val) {
+    const int32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= nc) return;
+    const int32_t lo = r_ptr[c], hi = r_ptr[c + 1];
+    for (int32_t a = lo + 1; a < hi; ++a) {
+        const int32_t key = r_col[a];
+        const double v = r_val[a];
+        int32_t b = a - 1;
+        while (b >= lo && r_col[b] > key) {
+            r_col[b + 1] = r_col[b];
+            r_val[b + 1] = r_val[b];
+            --b;
+        }
+        r_col[b + 1] = key;
+        r_val[b + 1] = v;
+    }
+}
+
+// --- dense coarsest level --------------------------------------------------------------
+__global__ void dense_zero_kernel(int64_t total, double* __restrict__ M) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (k < total) M[k] = 0.0;
+}
+
+__global__ void dense_scatter_kernel(int32_t n, const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                     const double* __restrict__ val, double* __restrict__ M) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p) M[static_cast<int64_t>(i) * n + col[p]] = val[p];
+}
+
+// A_L + alpha 1 1^T with alpha = mean(diag)/n (constant null space of all-Neumann problems).
+__global__ __launch_bounds__(1024) void dense_rank_one_kernel(int32_t n, double* __restrict__ M) {
+    __shared__ double red[1024];
+    double s = 0.0;
+    for (int32_t i = threadIdx.x; i < n; i += 1024) s += M[static_cast<int64_t>(i) * n + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double alpha = red[0] / n / n;
+    const int64_t total = static_cast<int64_t>(n) * n;
+    for (int64_t k = threadIdx.x; k < total; k += 1024) M[k] += alpha;
+}
+
+// LU with partial pivoting (largest |pivot|, smallest row index on ties) by one workgroup.
+__global__ __launch_bounds__(1024) void dense_lu_kernel(int32_t n, double* __restrict__ M, int32_t* __restrict__ piv,
+                                                        int32_t* __restrict__ bad) {
+    __shared__ double sval[1024];
+    __shared__ int32_t sidx[1024];
+    const int tid = threadIdx.x;
+    for (int32_t k = tid; k < n; k += 1024) piv[k] = k;
+    __syncthreads();
+    for (int32_t k = 0; k < n; ++k) {
+        double best = -1.0;
+        int32_t bi = n;
+        for (int32_t i = k + tid; i < n; i += 1024) {
+            const double v = fabs(M[static_cast<int64_t>(i) * n + k]);
+            if (v > best) {
+                best = v;
+                bi = i;
+            }
+        }
+        sval[tid] = best;
+        sidx[tid] = bi;
+        __syncthreads();
+        for (int w = 512; w > 0; w >>= 1) {
+            if (tid < w) {
+                const double ov = sval[tid + w];
+                const int32_t oi = sidx[tid + w];
+                if (ov > sval[tid] || (ov == sval[tid] && oi < sidx[tid])) {
+                    sval[tid] = ov;
+                    sidx[tid] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        const int32_t p = sidx[0];
+        const double pv = sval[0];
+        __syncthreads();
+        if (!(pv > 0.0)) {
+            if (tid == 0) bad[0] = 1;
+            return;
+        }
+        if (p != k)
+            for (int32_t j = tid; j < n; j += 1024) {
+                const double t = M[static_cast<int64_t>(k) * n + j];
+                M[static_cast<int64_t>(k) * n + j] = M[static_cast<int64_t>(p) * n + j];
+                M[static_cast<int64_t>(p) * n + j] = t;
+            }
+        if (tid == 0) piv[k] = p;
+        __syncthreads();
+        const double pivot = M[static_cast<int64_t>(k) * n + k];
+        for (int32_t i = k + 1 + tid; i < n; i += 1024) M[static_cast<int64_t>(i) * n + k] /= pivot;
+        __syncthreads();
+        const int32_t m = n - k - 1;
+        const int64_t cnt = static_cast<int64_t>(m) * m;
+        for (int64_t e = tid; e < cnt; e += 1024) {
+            const int32_t i = k + 1 + static_cast<int32_t>(e / m);
+            const int32_t j = k + 1 + static_cast<int32_t>(e % m);
+            M[static_cast<int64_t>(i) * n + j] -= M[static_cast<int64_t>(i) * n + k] * M[static_cast<int64_t>(k) * n + j];
+        }
+        __syncthreads();
+    }
+}
+
+// Column j of the inverse: solve L U x = Perm e_j, one workgroup per column, x in LDS.
+__global__ __launch_bounds__(kBlock) void dense_inverse_cols_kernel(int32_t n, const double* __restrict__ LU,
+                                                                   const int32_t* __restrict__ piv,
+                                                                   const int32_t* __restrict__ bad,
+                                                                   double* __restrict__ inv) {
+    extern __shared__ double b[];
+    if (bad[0]) return;  // factorisation failed: leave the inverse untouched
+    const int32_t j = blockIdx.x;
+    const int tid = threadIdx.x;
+    for (int32_t i = tid; i < n; i += kBlock) b[i] = (i == j) ? 1.0 : 0.0;
+    __syncthreads();
+    if (tid == 0)
+        for (int32_t k = 0; k < n; ++k) {
+            const int32_t p = piv[k];
+            if (p != k && p >= 0 && p < n) {
+                const double t = b[k];
+                b[k] = b[p];
+                b[p] = t;
+            }
+        }
+    __syncthreads();
+    for (int32_t k = 0; k < n; ++k) {
+        const double bk = b[k];
+        for (int32_t i = k + 1 + tid; i < n; i += kBlock) b[i] -= LU[static_cast<int64_t>(i) * n + k] * bk;
+        __syncthreads();
+    }
+    for (int32_t k = n - 1; k >= 0; --k) {
+        if (tid == 0) b[k] /= LU[static_cast<int64_t>(k) * n + k];
+        __syncthreads();
+        const double bk = b[k];
+        for (int32_t i = tid; i < k; i += kBlock) b[i] -= LU[static_cast<int64_t>(i) * n + k] * bk;
+        __syncthreads();
+    }
+    for (int32_t i = tid; i < n; i += kBlock) inv[static_cast<int64_t>(i) * n + j] = b[i];
+}
+
+// y = inv x in FP64, one wavefront per row (coalesced row reads of the inverse).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void dense_gemv_kernel(int32_t n, const double* __restrict__ inv,
+                                                           const T* __restrict__ x, T* __restrict__ y) {
+    const int32_t row = blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    double s = 0.0;
+    if (row < n) {
+        const double* a = inv + static_cast<int64_t>(row) * n;
+        for (int32_t j = lane; j < n; j += 64) s += a[j] * static_cast<double>(x[j]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (row < n && lane == 0) y[row] = static_cast<T>(s);
+}
+
+}  // namespace
+
+hipError_t extract_diag(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, double* diag,
+                        int32_t* bad, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    extract_diag_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, ptr, col, val, diag, bad);
+    return hipGetLastError();
+}
+
+hipError_t offdiag_absmax(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, double* partial,
+                          double* scale, hipStream_t stream) {
+    absmax_partial_kernel<<<kReduceBlocks, kBlock, 0, stream>>>(n, ptr, col, val, partial);
+    absmax_final_kernel<<<1, kBlock, 0, stream>>>(partial, scale);
+    return hipGetLastError();
+}
+
+hipError_t transpose_csr(int32_t nf, int32_t nc, int32_t nnz, const int32_t* p_ptr, const int32_t* p_col,
+                         const double* p_val, int32_t* r_ptr, int32_t* r_col, double* r_val, int32_t* cursor,
+                         hipStream_t stream) {
+    hipError_t e = vec_zero_bytes(r_ptr, sizeof(int32_t) * (nc + 1), stream);
+    if (e != hipSuccess) return e;
+    if (nnz > 0) count_cols_kernel<<<grid_for(nnz), kBlock, 0, stream>>>(nnz, p_col, r_ptr);
+    scan_kernel<<<1, 1024, 0, stream>>>(nc, r_ptr);
+    if ((e = vec_copy<int32_t>(nc, r_ptr, cursor, stream)) != hipSuccess) return e;
+    scatter_transpose_kernel<<<grid_for(nf), kBlock, 0, stream>>>(nf, p_ptr, p_col, p_val, cursor, r_col, r_val);
+    sort_rows_kernel<<<grid_for(nc), kBlock, 0, stream>>>(nc, r_ptr, r_col, r_val);
+    return hipGetLastError();
+}
+
+hipError_t dense_from_csr(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, double* M,
+                          int singular, hipStream_t stream) {
+    const int64_t total = static_cast<int64_t>(n) * n;
+    dense_zero_kernel<<<grid_for(total), kBlock, 0, stream>>>(total, M);
+    dense_scatter_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, ptr, col, val, M);
+    if (singular) dense_rank_one_kernel<<<1, 1024, 0, stream>>>(n, M);
+    return hipGetLastError();
+}
+
+hipError_t dense_lu_inverse(int32_t n, double* M, int32_t* piv, double* inv, int32_t* bad, hipStream_t stream) {
+    dense_lu_kernel<<<1, 1024, 0, stream>>>(n, M, piv, bad);
+    dense_inverse_cols_kernel<<<n, kBlock, sizeof(double) * n, stream>>>(n, M, piv, bad, inv);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dense_gemv(int32_t n, const double* inv, const T* x, T* y, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const dim3 grid(static_cast<unsigned>((n + kBlock / 64 - 1) / (kBlock / 64)));
+    dense_gemv_kernel<T><<<grid, kBlock, 0, stream>>>(n, inv, x, y);
+    return hipGetLastError();
+}
+template hipError_t dense_gemv<float>(int32_t, const double*, const float*, float*, hipStream_t);
+template hipError_t dense_gemv<double>(int32_t, const double*, const double*, double*, hipStream_t);
+
+}  // namespace amgg

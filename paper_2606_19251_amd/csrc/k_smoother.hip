@@ -1,0 +1,77 @@
+// Sparse pseudo-inverse smoother assembly (paper Sec. 3.1, Eq. 5):
+//   q_ii = f_d(a_ii/s) / a_ii,   q_ij = f_o(a_ij/s) / (a_ii + a_jj),   s = max |offdiag(A)|,
+//   f_d(x) = d0 + x(d1 + x(d2 + ...)),   f_o(x) = x(o1 + x(o2 + ...)).
+// Evaluated in FP64 with Horner's rule, each operation rounded on its own (this file is
+// built with -ffp-contract=off and the pragma below) and IEEE division, so the values
+// are reproducible bit for bit by any implementation that follows the same order.
+// One thread per row: the entries of a row are contiguous, and the diagonal of the
+// neighbour j is a gather from the level's diagonal array.
+#include "kernels.hpp"
+
+namespace amgg {
+
+namespace {
+
+__device__ __forceinline__ double horner_diag(double x, const double* c, int deg) {
+#pragma clang fp contract(off)
+    double t = c[deg];
+    for (int k = deg - 1; k >= 0; --k) t = c[k] + x * t;
+    return t;
+}
+
+__device__ __forceinline__ double horner_off(double x, const double* o, int deg) {
+#pragma clang fp contract(off)
+    // o[0] = o1 ... o[deg-1] = o_deg
+    double t = o[deg - 1];
+    for (int k = deg - 2; k >= 0; --k) t = o[k] + x * t;
+    return x * t;
+}
+
+__global__ __launch_bounds__(kBlock) void assemble_kernel(int32_t n, const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ col,
+                                                         const double* __restrict__ val,
+                                                         const double* __restrict__ diag,
+                                                         const double* __restrict__ scale, PolyCoeffs pc,
+                                                         const float* __restrict__ coeffs_dev,
+                                                         double* __restrict__ q64, float* __restrict__ q32,
+                                                         double* __restrict__ qd64, float* __restrict__ qd32) {
+#pragma clang fp contract(off)
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int deg = pc.degree;
+    double c[2 * 4 + 1];
+    for (int k = 0; k < 2 * deg + 1; ++k) c[k] = coeffs_dev ? static_cast<double>(coeffs_dev[k]) : pc.c[k];
+    const double s = scale[0];
+    const double aii = diag[i];
+    for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p) {
+        const int32_t j = col[p];
+        const double a = val[p];
+        const double x = a / s;
+        double q;
+        if (j == i) {
+            q = horner_diag(x, c, deg) / a;
+            qd64[i] = q;
+            qd32[i] = static_cast<float>(q);
+        } else {
+            q = horner_off(x, c + deg + 1, deg) / (aii + diag[j]);
+        }
+        q64[p] = q;
+        q32[p] = static_cast<float>(q);
+    }
+}
+
+}  // namespace
+
+hipError_t assemble_smoother(int32_t n, const int32_t* ptr, const int32_t* col, const double* val,
+                             const double* diag, const double* scale, const PolyCoeffs& pc,
+                             const float* coeffs_dev, double* q64, float* q32, double* qd64, float* qd32,
+                             hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    if (pc.degree < 1 || pc.degree > 4) return hipErrorInvalidValue;
+    const dim3 grid(static_cast<unsigned>((n + kBlock - 1) / kBlock));
+    assemble_kernel<<<grid, kBlock, 0, stream>>>(n, ptr, col, val, diag, scale, pc, coeffs_dev, q64, q32, qd64,
+                                                  qd32);
+    return hipGetLastError();
+}
+
+}  // namespace amgg

@@ -1,0 +1,327 @@
+// Streaming vector kernels, deterministic reductions and the scalar steps of the outer
+// FP64 loops. Reductions always use kReduceBlocks workgroups with a grid-stride loop and
+// a fixed combination tree, so every sum is bitwise reproducible from run to run.
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace amgg {
+
+namespace {
+
+inline dim3 grid_for(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    return dim3(static_cast<unsigned>(g));
+}
+
+__device__ __forceinline__ void block_partial(double v, double* partial) {
+    __shared__ double red[kBlock / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = red[0];
+        for (int k = 1; k < kBlock / 64; ++k) s += red[k];
+        partial[blockIdx.x] = s;
+    }
+}
+
+// Sum of kReduceBlocks partials by one workgroup, in a fixed order.
+__device__ __forceinline__ double sum_partials(const double* partial) {
+    __shared__ double red[kBlock];
+    double v = 0.0;
+    for (int k = threadIdx.x; k < kReduceBlocks; k += kBlock) v += partial[k];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+template <typename T>
+__global__ void mul_kernel(int32_t n, const T* __restrict__ a, const T* __restrict__ b, T* __restrict__ y) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] = a[i] * b[i];
+}
+
+template <typename T>
+__global__ void copy_kernel(int32_t n, const T* __restrict__ a, T* __restrict__ y) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] = a[i];
+}
+
+__global__ void zero_kernel(uint32_t* __restrict__ p, int64_t words) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < words) p[i] = 0u;
+}
+
+__global__ void cast_scaled_kernel(int32_t n, const double* __restrict__ x, const double* __restrict__ scale,
+                                   float* __restrict__ y) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] = static_cast<float>(x[i] * scale[0]);
+}
+
+__global__ void cast_d2f_kernel(int32_t n, const double* __restrict__ x, float* __restrict__ y) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] = static_cast<float>(x[i]);
+}
+
+__global__ void cast_f2d_kernel(int32_t n, const float* __restrict__ x, double* __restrict__ y) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] = static_cast<double>(x[i]);
+}
+
+__global__ void sub_mean_kernel(int32_t n, const double* __restrict__ x, const double* __restrict__ sum,
+                                double* __restrict__ y) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] = x[i] - sum[0] / static_cast<double>(n);
+}
+
+__global__ __launch_bounds__(kBlock) void partial_dot_kernel(int32_t n, const double* __restrict__ a,
+                                                            const double* __restrict__ b,
+                                                            double* __restrict__ partial) {
+    double v = 0.0;
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += kReduceBlocks * kBlock) v += a[i] * b[i];
+    block_partial(v, partial);
+}
+
+__global__ __launch_bounds__(kBlock) void partial_sum_kernel(int32_t n, const double* __restrict__ a,
+                                                            double* __restrict__ partial) {
+    double v = 0.0;
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += kReduceBlocks * kBlock) v += a[i];
+    block_partial(v, partial);
+}
+
+__global__ __launch_bounds__(kBlock) void finish_sum_kernel(const double* __restrict__ partial,
+                                                           double* __restrict__ out) {
+    const double s = sum_partials(partial);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void fcg_finish_pq_kernel(const double* __restrict__ partial,
+                                                              double* __restrict__ s) {
+    const double pq = sum_partials(partial);
+    if (threadIdx.x == 0) {
+        s[kPQ] = pq;
+        if (!(pq > 0.0)) s[kFlag] = 1.0;
+        s[kAlpha] = s[kGamma] / pq;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void fcg_update_xr_kernel(int32_t n, double* __restrict__ x,
+                                                              const double* __restrict__ p,
+                                                              const double* __restrict__ r,
+                                                              const double* __restrict__ q,
+                                                              double* __restrict__ rnew,
+                                                              const double* __restrict__ s,
+                                                              double* __restrict__ partial) {
+    const double a = s[kAlpha];
+    double v = 0.0;
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += kReduceBlocks * kBlock) {
+        x[i] += a * p[i];
+        const double ri = r[i] - a * q[i];
+        rnew[i] = ri;
+        v += ri * ri;
+    }
+    block_partial(v, partial);
+}
+
+__global__ __launch_bounds__(kBlock) void fcg_finish_rr_kernel(const double* __restrict__ partial,
+                                                              double* __restrict__ s) {
+    const double rr = sum_partials(partial);
+    if (threadIdx.x == 0) {
+        s[kRR] = rr;
+        const double nrm = sqrt(rr);
+        s[kNorm] = nrm;
+        s[kInvNorm] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void fcg_castback_dots_kernel(int32_t n, const float* __restrict__ u32,
+                                                                  const double* __restrict__ s,
+                                                                  const double* __restrict__ rnew,
+                                                                  const double* __restrict__ rold,
+                                                                  double* __restrict__ z,
+                                                                  double* __restrict__ partial2) {
+    const double nrm = s[kNorm];
+    double a = 0.0, b = 0.0;
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += kReduceBlocks * kBlock) {
+        const double zi = static_cast<double>(u32[i]) * nrm;
+        z[i] = zi;
+        a += zi * rnew[i];
+        if (rold) b += zi * rold[i];
+    }
+    block_partial(a, partial2);
+    __syncthreads();
+    block_partial(b, partial2 + kReduceBlocks);
+}
+
+__global__ __launch_bounds__(kBlock) void fcg_dots64_kernel(int32_t n, const double* __restrict__ z,
+                                                           const double* __restrict__ rnew,
+                                                           const double* __restrict__ rold,
+                                                           double* __restrict__ partial2) {
+    double a = 0.0, b = 0.0;
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += kReduceBlocks * kBlock) {
+        a += z[i] * rnew[i];
+        if (rold) b += z[i] * rold[i];
+    }
+    block_partial(a, partial2);
+    __syncthreads();
+    block_partial(b, partial2 + kReduceBlocks);
+}
+
+__global__ __launch_bounds__(kBlock) void fcg_finish_beta_kernel(const double* __restrict__ partial2,
+                                                                double* __restrict__ s, int first) {
+    const double zr = sum_partials(partial2);
+    __syncthreads();
+    const double zro = sum_partials(partial2 + kReduceBlocks);
+    if (threadIdx.x == 0) {
+        s[kZR] = zr;
+        s[kZRold] = zro;
+        if (!(zr > 0.0)) s[kFlag] = 1.0;
+        s[kBeta] = first ? 0.0 : (zr - zro) / s[kGamma];
+        s[kGamma] = zr;
+    }
+}
+
+__global__ void fcg_update_p_kernel(int32_t n, const double* __restrict__ z, double* __restrict__ p,
+                                    const double* __restrict__ s, int first) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = first ? z[i] : z[i] + s[kBeta] * p[i];
+}
+
+__global__ void ir_update_f32_kernel(int32_t n, double* __restrict__ x, const float* __restrict__ u32,
+                                     const double* __restrict__ s) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) x[i] += static_cast<double>(u32[i]) * s[kNorm];
+}
+
+__global__ void ir_update_f64_kernel(int32_t n, double* __restrict__ x, const double* __restrict__ e) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) x[i] += e[i];
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t vec_mul(int32_t n, const T* a, const T* b, T* y, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    mul_kernel<T><<<grid_for(n), kBlock, 0, stream>>>(n, a, b, y);
+    return hipGetLastError();
+}
+template hipError_t vec_mul<float>(int32_t, const float*, const float*, float*, hipStream_t);
+template hipError_t vec_mul<double>(int32_t, const double*, const double*, double*, hipStream_t);
+
+template <typename T>
+hipError_t vec_copy(int32_t n, const T* a, T* y, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    copy_kernel<T><<<grid_for(n), kBlock, 0, stream>>>(n, a, y);
+    return hipGetLastError();
+}
+template hipError_t vec_copy<float>(int32_t, const float*, float*, hipStream_t);
+template hipError_t vec_copy<double>(int32_t, const double*, double*, hipStream_t);
+template hipError_t vec_copy<int32_t>(int32_t, const int32_t*, int32_t*, hipStream_t);
+
+hipError_t vec_zero_bytes(void* p, size_t bytes, hipStream_t stream) {
+    // a fill kernel rather than a memset node keeps the cycle capturable in a graph
+    const int64_t words = static_cast<int64_t>((bytes + 3) / 4);
+    if (words <= 0) return hipSuccess;
+    zero_kernel<<<grid_for(words), kBlock, 0, stream>>>(static_cast<uint32_t*>(p), words);
+    return hipGetLastError();
+}
+
+hipError_t cast_scaled_f64_f32(int32_t n, const double* x, const double* scale, float* y, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    cast_scaled_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, x, scale, y);
+    return hipGetLastError();
+}
+
+hipError_t cast_f64_f32(int32_t n, const double* x, float* y, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    cast_d2f_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, x, y);
+    return hipGetLastError();
+}
+
+hipError_t cast_f32_f64(int32_t n, const float* x, double* y, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    cast_f2d_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, x, y);
+    return hipGetLastError();
+}
+
+hipError_t sub_mean(int32_t n, const double* x, const double* sum, double* y, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    sub_mean_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, x, sum, y);
+    return hipGetLastError();
+}
+
+hipError_t partial_dot(int32_t n, const double* a, const double* b, double* partial, hipStream_t stream) {
+    partial_dot_kernel<<<kReduceBlocks, kBlock, 0, stream>>>(n, a, b, partial);
+    return hipGetLastError();
+}
+
+hipError_t partial_sum(int32_t n, const double* a, double* partial, hipStream_t stream) {
+    partial_sum_kernel<<<kReduceBlocks, kBlock, 0, stream>>>(n, a, partial);
+    return hipGetLastError();
+}
+
+hipError_t finish_sum(const double* partial, double* out, hipStream_t stream) {
+    finish_sum_kernel<<<1, kBlock, 0, stream>>>(partial, out);
+    return hipGetLastError();
+}
+
+hipError_t fcg_finish_pq(const double* partial, double* s, hipStream_t stream) {
+    fcg_finish_pq_kernel<<<1, kBlock, 0, stream>>>(partial, s);
+    return hipGetLastError();
+}
+
+hipError_t fcg_update_xr(int32_t n, double* x, const double* p, const double* r, const double* q, double* rnew,
+                         const double* s, double* partial, hipStream_t stream) {
+    fcg_update_xr_kernel<<<kReduceBlocks, kBlock, 0, stream>>>(n, x, p, r, q, rnew, s, partial);
+    return hipGetLastError();
+}
+
+hipError_t fcg_finish_rr(const double* partial, double* s, hipStream_t stream) {
+    fcg_finish_rr_kernel<<<1, kBlock, 0, stream>>>(partial, s);
+    return hipGetLastError();
+}
+
+hipError_t fcg_castback_dots(int32_t n, const float* u32, const double* s, const double* rnew, const double* rold,
+                             double* z, double* partial2, hipStream_t stream) {
+    fcg_castback_dots_kernel<<<kReduceBlocks, kBlock, 0, stream>>>(n, u32, s, rnew, rold, z, partial2);
+    return hipGetLastError();
+}
+
+hipError_t fcg_dots64(int32_t n, const double* z, const double* rnew, const double* rold, double* partial2,
+                      hipStream_t stream) {
+    fcg_dots64_kernel<<<kReduceBlocks, kBlock, 0, stream>>>(n, z, rnew, rold, partial2);
+    return hipGetLastError();
+}
+
+hipError_t fcg_finish_beta(const double* partial2, double* s, int first, hipStream_t stream) {
+    fcg_finish_beta_kernel<<<1, kBlock, 0, stream>>>(partial2, s, first);
+    return hipGetLastError();
+}
+
+hipError_t fcg_update_p(int32_t n, const double* z, double* p, const double* s, int first, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    fcg_update_p_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, z, p, s, first);
+    return hipGetLastError();
+}
+
+hipError_t ir_update_f32(int32_t n, double* x, const float* u32, const double* s, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    ir_update_f32_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, x, u32, s);
+    return hipGetLastError();
+}
+
+hipError_t ir_update_f64(int32_t n, double* x, const double* e, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    ir_update_f64_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, x, e);
+    return hipGetLastError();
+}
+
+}  // namespace amgg

@@ -1,0 +1,129 @@
+// Launchers of the gfx950 kernels used by the solver. Every launcher enqueues work on
+// `stream` and returns hipSuccess or the launch error; none synchronises.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace amgg {
+
+constexpr int kBlock = 256;         // threads per workgroup (4 wavefronts of 64)
+constexpr int kReduceBlocks = 1024; // fixed partial count: reductions are deterministic
+
+// ---------------------------------------------------------------------------------------
+// Row-wise CSR products y = epilogue(sum_j a_ij x_j); `lanes` threads cooperate on a row.
+// ---------------------------------------------------------------------------------------
+enum class Epi : int {
+    Store = 0,   // y_i = s
+    Resid = 1,   // y_i = f_i - s
+    Add = 2,     // y_i += s
+    Jacobi = 3,  // y_i = u_i + qd_i (f_i - s)      (one-pass diagonal smoothing step)
+    Sub = 4,     // y_i -= s
+};
+
+struct CsrView {
+    int32_t nrows;
+    int32_t nnz;
+    const int32_t* ptr;
+    const int32_t* col;
+    int lanes;  // 1, 2, 4, ..., 64
+};
+
+int lanes_for(int32_t nrows, int32_t nnz);
+
+template <typename T>
+hipError_t csr_apply(const CsrView& m, const T* val, const T* x, T* y, const T* f, const T* qd, const T* u,
+                     Epi epi, hipStream_t stream);
+
+// q = A p and per-block partial sums of p_i q_i (FP64 outer loop).
+hipError_t csr_spmv_dot(const CsrView& m, const double* val, const double* p, double* q, double* partial,
+                        hipStream_t stream);
+// r = b - A x and per-block partial sums of r_i^2.
+hipError_t csr_resid_norm(const CsrView& m, const double* val, const double* x, const double* b, double* r,
+                          double* partial, hipStream_t stream);
+
+// ---------------------------------------------------------------------------------------
+// Vector kernels
+// ---------------------------------------------------------------------------------------
+template <typename T>
+hipError_t vec_mul(int32_t n, const T* a, const T* b, T* y, hipStream_t stream);  // y = a * b
+template <typename T>
+hipError_t vec_copy(int32_t n, const T* a, T* y, hipStream_t stream);
+hipError_t vec_zero_bytes(void* p, size_t bytes, hipStream_t stream);
+// y32 = (float)(x * scale[0]) ; scale on device
+hipError_t cast_scaled_f64_f32(int32_t n, const double* x, const double* scale, float* y, hipStream_t stream);
+hipError_t cast_f64_f32(int32_t n, const double* x, float* y, hipStream_t stream);
+hipError_t cast_f32_f64(int32_t n, const float* x, double* y, hipStream_t stream);
+// y = x - mean, mean = sum/n from a device scalar sum
+hipError_t sub_mean(int32_t n, const double* x, const double* sum, double* y, hipStream_t stream);
+
+// Deterministic two-stage reductions into partial[kReduceBlocks]
+hipError_t partial_dot(int32_t n, const double* a, const double* b, double* partial, hipStream_t stream);
+hipError_t partial_sum(int32_t n, const double* a, double* partial, hipStream_t stream);
+// final: scalars[out] = sum(partial[0..kReduceBlocks))
+hipError_t finish_sum(const double* partial, double* out, hipStream_t stream);
+
+// FCG pieces; s = device scalars (see fcg_slot)
+enum FcgSlot : int {
+    kGamma = 0,   // z^T r
+    kAlpha = 1,
+    kBeta = 2,
+    kRR = 3,      // ||r||^2
+    kPQ = 4,      // p^T A p
+    kNorm = 5,    // ||r||
+    kInvNorm = 6, // 1/||r||
+    kZR = 7,
+    kZRold = 8,
+    kBB = 9,      // ||b||^2
+    kSum = 10,    // scratch sum (mean projection)
+    kFlag = 11,   // breakdown flag (1.0 = breakdown)
+    kSlots = 16
+};
+hipError_t fcg_finish_pq(const double* partial, double* s, hipStream_t stream);       // pq, alpha = gamma/pq
+hipError_t fcg_update_xr(int32_t n, double* x, const double* p, const double* r, const double* q, double* rnew,
+                         const double* s, double* partial, hipStream_t stream);      // x += a p ; rnew = r - a q
+hipError_t fcg_finish_rr(const double* partial, double* s, hipStream_t stream);       // rr, norm, invnorm
+// z = (double)u32 * norm and partials of z.rnew, z.rold (2 * kReduceBlocks)
+hipError_t fcg_castback_dots(int32_t n, const float* u32, const double* s, const double* rnew, const double* rold,
+                             double* z, double* partial2, hipStream_t stream);
+hipError_t fcg_dots64(int32_t n, const double* z, const double* rnew, const double* rold, double* partial2,
+                      hipStream_t stream);
+hipError_t fcg_finish_beta(const double* partial2, double* s, int first, hipStream_t stream);
+hipError_t fcg_update_p(int32_t n, const double* z, double* p, const double* s, int first, hipStream_t stream);
+// IR: x += (double)u32 * norm  (or x += e64)
+hipError_t ir_update_f32(int32_t n, double* x, const float* u32, const double* s, hipStream_t stream);
+hipError_t ir_update_f64(int32_t n, double* x, const double* e, hipStream_t stream);
+
+// ---------------------------------------------------------------------------------------
+// Setup kernels
+// ---------------------------------------------------------------------------------------
+// diag[i] = a_ii; bad[0] set to 1 when a row has no positive stored diagonal
+hipError_t extract_diag(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, double* diag,
+                        int32_t* bad, hipStream_t stream);
+// scale[0] = max |a_ij| over off-diagonal entries, or 1 when there are none
+hipError_t offdiag_absmax(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, double* partial,
+                          double* scale, hipStream_t stream);
+// R = P^T: counts (r_ptr must be zeroed, size n_c + 1), scan, scatter, per-row sort
+hipError_t transpose_csr(int32_t nf, int32_t nc, int32_t nnz, const int32_t* p_ptr, const int32_t* p_col,
+                         const double* p_val, int32_t* r_ptr, int32_t* r_col, double* r_val, int32_t* cursor,
+                         hipStream_t stream);
+
+struct PolyCoeffs {
+    double c[2 * 4 + 1];
+    int degree;
+};
+// Eq. (5) smoother values on A's pattern; also the diagonal of Q^{-1} in both precisions.
+hipError_t assemble_smoother(int32_t n, const int32_t* ptr, const int32_t* col, const double* val,
+                             const double* diag, const double* scale, const PolyCoeffs& pc,
+                             const float* coeffs_dev, double* q64, float* q32, double* qd64, float* qd32,
+                             hipStream_t stream);
+
+// Dense coarse solve
+hipError_t dense_from_csr(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, double* M,
+                          int singular, hipStream_t stream);
+hipError_t dense_lu_inverse(int32_t n, double* M, int32_t* piv, double* inv, int32_t* bad, hipStream_t stream);
+template <typename T>
+hipError_t dense_gemv(int32_t n, const double* inv, const T* x, T* y, hipStream_t stream);
+
+}  // namespace amgg

@@ -1,0 +1,181 @@
+"""Plumbing around the C ABI: host hierarchy arrays, device memory held in torch tensors.
+
+PyTorch is used here for device memory and streams only; every arithmetic step of the
+setup and of the solve runs in libamggnn (host C++ setup, HIP kernels).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import capi
+
+
+@dataclass
+class HostLevel:
+    n: int
+    rowptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+    p_ncols: int = 0
+    p_rowptr: np.ndarray | None = None
+    p_col: np.ndarray | None = None
+    p_val: np.ndarray | None = None
+    cf: np.ndarray | None = None
+
+    @property
+    def nnz(self):
+        return int(self.col.size)
+
+
+@dataclass
+class HostHierarchy:
+    """Ruge-Stueben hierarchy computed by ``amgg_rs_setup`` and copied to numpy arrays."""
+
+    levels: list = field(default_factory=list)
+    singular: bool = False
+
+    @classmethod
+    def build(cls, rowptr, col, val, theta=0.25, max_levels=10, max_coarse=500):
+        rowptr = np.ascontiguousarray(rowptr, np.int32)
+        n = rowptr.size - 1
+        h = capi.amgg_rs_setup(rowptr, col, val, n, theta, max_levels, max_coarse)
+        try:
+            nl, sing = capi.amgg_rs_info(h)
+            out = cls([], bool(sing))
+            for l in range(nl):
+                n_l, nnz, pnc, pnnz = capi.amgg_rs_level_size(h, l)
+                L = HostLevel(n_l, np.empty(n_l + 1, np.int32), np.empty(nnz, np.int32), np.empty(nnz, np.float64))
+                L.cf = np.empty(n_l, np.int8)
+                if l + 1 < nl:
+                    L.p_ncols = pnc
+                    L.p_rowptr = np.empty(n_l + 1, np.int32)
+                    L.p_col = np.empty(pnnz, np.int32)
+                    L.p_val = np.empty(pnnz, np.float64)
+                capi.amgg_rs_copy_level(h, l, L.rowptr, L.col, L.val, L.p_rowptr, L.p_col, L.p_val, L.cf)
+                out.levels.append(L)
+            return out
+        finally:
+            capi.amgg_rs_free(h)
+
+    @property
+    def nlevels(self):
+        return len(self.levels)
+
+
+def _stream_ptr(torch, device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class DeviceSolver:
+    """A finalized solver context on one GPU; owns the device copies and the workspace."""
+
+    def __init__(self, hier: HostHierarchy, device: int = 0):
+        import torch
+
+        self.torch = torch
+        self.hier = hier
+        self.device = torch.device("cuda", device)
+        self.nlevels = hier.nlevels
+        self.n = hier.levels[0].n
+        self._keep = []
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(self.device)
+        self.ctx = capi.amgg_create(device, self.nlevels)
+        try:
+            self.A = []
+            for l, L in enumerate(hier.levels):
+                rp, cl, vl = t(L.rowptr), t(L.col), t(L.val)
+                self.A.append((rp, cl, vl))
+                self._keep += [rp, cl, vl]
+                capi.amgg_load_level(self.ctx, l, L.n, L.nnz, rp.data_ptr(), cl.data_ptr(), vl.data_ptr())
+                if l + 1 < self.nlevels:
+                    pr, pc, pv = t(L.p_rowptr), t(L.p_col), t(L.p_val)
+                    self._keep += [pr, pc, pv]
+                    capi.amgg_load_prolong(self.ctx, l, L.n, L.p_ncols, int(L.p_col.size), pr.data_ptr(),
+                                           pc.data_ptr() if L.p_col.size else 0, pv.data_ptr() if L.p_col.size else 0)
+            self.ws_bytes = capi.amgg_workspace_bytes(self.ctx)
+            raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-raw.data_ptr()) % 256
+            self.ws = raw[off:off + self.ws_bytes]
+            self._raw = raw
+            capi.amgg_finalize(self.ctx, int(hier.singular), self.ws.data_ptr(), self.ws_bytes, self.stream)
+        except Exception:
+            capi.amgg_destroy(self.ctx)
+            self.ctx = None
+            raise
+
+    @property
+    def stream(self):
+        return _stream_ptr(self.torch, self.device)
+
+    def close(self):
+        if self.ctx:
+            capi.amgg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- smoother
+    def set_coeffs(self, coeffs, degree=2, levels=None):
+        coeffs = np.asarray(coeffs, np.float64)
+        if coeffs.ndim == 1:
+            coeffs = np.tile(coeffs, (self.nlevels, 1))
+        for l in (range(self.nlevels) if levels is None else levels):
+            capi.amgg_set_smoother_coeffs(self.ctx, l, degree, coeffs[l], self.stream)
+
+    def set_coeffs_device(self, coeffs_dev, degree):
+        """coeffs_dev: float32 CUDA tensor [nlevels, 2*degree+1]."""
+        assert coeffs_dev.dtype == self.torch.float32 and coeffs_dev.is_contiguous()
+        stride = coeffs_dev.shape[1] * 4
+        for l in range(self.nlevels):
+            capi.amgg_set_smoother_coeffs_device(self.ctx, l, degree, coeffs_dev.data_ptr() + l * stride, self.stream)
+
+    def set_jacobi(self, omega=2.0 / 3.0):
+        for l in range(self.nlevels):
+            capi.amgg_set_smoother_jacobi(self.ctx, l, omega, self.stream)
+
+    # ---------------------------------------------------------------- solve phase
+    def vcycle(self, f, u, nu1=1, nu2=1, precision=64):
+        capi.amgg_vcycle(self.ctx, nu1, nu2, precision, f.data_ptr(), u.data_ptr(), self.stream)
+        return u
+
+    def solve(self, b, x=None, outer=capi.AMGG_OUTER_FCG, precision=32, nu1=1, nu2=1, tol=1e-8, maxit=500,
+              fallback=True, history_cap=0, div_factor=0.0, stag_ratio=0.0, stag_window=0):
+        if x is None:
+            x = self.torch.empty_like(b)
+        o = capi.amgg_solve_opts(outer, precision, nu1, nu2, maxit, tol, int(fallback), div_factor, stag_ratio,
+                                 stag_window)
+        rc, info, hist = capi.amgg_solve(self.ctx, o, b.data_ptr(), x.data_ptr(), history_cap, self.stream)
+        return x, rc, info, hist[: max(0, min(history_cap, info.iterations + 1))]
+
+    # ---------------------------------------------------------------- inspection
+    def _ws_slice(self, ptr, count, dtype):
+        torch = self.torch
+        if not ptr:
+            return None
+        off = ptr - self.ws.data_ptr()
+        itemsize = torch.empty((), dtype=dtype).element_size()
+        return self.ws[off:off + count * itemsize].view(dtype)
+
+    def level_view(self, lvl):
+        torch = self.torch
+        v = capi.amgg_level_view_get(self.ctx, lvl)
+        s = self._ws_slice
+        return {
+            "r_rowptr": s(v.r_rowptr, v.n_coarse + 1, torch.int32) if v.r_rowptr else None,
+            "r_col": s(v.r_col, v.p_nnz, torch.int32),
+            "r_val": s(v.r_val, v.p_nnz, torch.float64),
+            "a_val32": s(v.a_val32, v.nnz, torch.float32),
+            "p_val32": s(v.p_val32, v.p_nnz, torch.float32),
+            "r_val32": s(v.r_val32, v.p_nnz, torch.float32),
+            "q_val": s(v.q_val, v.nnz, torch.float64),
+            "q_val32": s(v.q_val32, v.nnz, torch.float32),
+            "diag": s(v.diag, v.n, torch.float64),
+            "scale": s(v.scale, 1, torch.float64),
+            "coarse_inv": s(v.coarse_inv, v.n * v.n, torch.float64),
+        }

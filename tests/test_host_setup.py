@@ -1,0 +1,119 @@
+"""CPU tests of the product's host side: the library loads and exports its C ABI, the
+C++ Ruge-Stueben setup agrees bit for bit with the oracle, argument errors are reported."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import amg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _capi():
+    from paper_2606_19251_amd import capi
+    return capi
+
+
+def _declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b((?:amgg|gcin|adam)_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    capi = _capi()
+    lib = capi.lib()
+    names = _declared_functions()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in include/ but not exported"
+        assert name in capi.SIGNATURES or name.startswith(("gcin_", "adam_")), f"{name} has no Python binding"
+
+
+def _bits(a):
+    a = np.ascontiguousarray(a)
+    return a.view(np.uint64) if a.dtype == np.float64 else a
+
+
+def _compare(A, **kw):
+    from paper_2606_19251_amd.solver import HostHierarchy
+
+    Ao = amg.to_scipy(A)
+    sing = kw.pop("singular", False)
+    ho = amg.setup(Ao, singular=sing, **kw)
+    hp = HostHierarchy.build(A.rowptr, A.col, A.val, theta=0.25, max_levels=kw.get("max_levels", 10),
+                             max_coarse=kw.get("max_coarse", 500))
+    assert hp.nlevels == ho.nlevels
+    assert hp.singular == sing
+    for l in range(ho.nlevels):
+        Lo, Lp = ho.levels[l], hp.levels[l]
+        assert np.array_equal(Lo.A.indptr, Lp.rowptr)
+        assert np.array_equal(Lo.A.indices, Lp.col)
+        assert np.array_equal(_bits(Lo.A.data), _bits(Lp.val)), f"A_{l} values differ"
+        if l + 1 < ho.nlevels:
+            assert np.array_equal(Lo.state, Lp.cf.astype(np.int64)), f"C/F split of level {l} differs"
+            assert Lo.P.shape[1] == Lp.p_ncols
+            assert np.array_equal(Lo.P.indptr, Lp.p_rowptr)
+            assert np.array_equal(Lo.P.indices, Lp.p_col)
+            assert np.array_equal(_bits(Lo.P.data), _bits(Lp.p_val)), f"P_{l} values differ"
+    return ho, hp
+
+
+def test_rs_bitexact_grid64_three_levels():
+    ho, hp = _compare(W.grid5(64), max_levels=3)
+    assert [L.n for L in hp.levels][:2] == [4096, 2048]
+
+
+def test_rs_bitexact_grid_full_depth():
+    _compare(W.grid5(40), max_levels=10, max_coarse=10)
+
+
+@pytest.mark.parametrize("npts,seed", [(2000, 0), (9000, 3)])
+def test_rs_bitexact_delaunay(npts, seed):
+    _compare(W.delaunay_p1(W.uniform_points(npts, seed)), singular=True, max_coarse=50)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_rs_bitexact_gmm_meshes(seed):
+    _compare(W.delaunay_p1(W.gmm_points(6000, seed)), singular=True, max_coarse=100)
+
+
+def test_rs_setup_rejects_bad_pattern():
+    capi = _capi()
+    A = W.grid5(4)
+    col = A.col.copy()
+    col[[1, 2]] = col[[2, 1]]  # unsorted row
+    with pytest.raises(capi.AmggError) as e:
+        capi.amgg_rs_setup(A.rowptr, col, A.val, A.nrows, 0.25, 10, 5)
+    assert e.value.code == capi.AMGG_EINVAL
+    val = A.val.copy()
+    val[A.col == np.repeat(np.arange(16), np.diff(A.rowptr))] *= -1  # negative diagonal
+    with pytest.raises(capi.AmggError):
+        capi.amgg_rs_setup(A.rowptr, A.col, val, A.nrows, 0.25, 10, 5)
+    with pytest.raises(capi.AmggError):
+        capi.amgg_rs_setup(A.rowptr, A.col, A.val, A.nrows, 1.5, 10, 5)
+
+
+def test_create_rejects_bad_level_count():
+    capi = _capi()
+    with pytest.raises(capi.AmggError) as e:
+        capi.amgg_create(0, 0)
+    assert e.value.code == capi.AMGG_EINVAL
+    with pytest.raises(capi.AmggError):
+        capi.amgg_create(0, capi.AMGG_MAX_LEVELS + 1)
+
+
+def test_one_level_hierarchy_when_small():
+    from paper_2606_19251_amd.solver import HostHierarchy
+
+    A = W.grid5(10)
+    h = HostHierarchy.build(A.rowptr, A.col, A.val, max_coarse=500)
+    assert h.nlevels == 1 and h.levels[0].p_rowptr is None

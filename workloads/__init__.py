@@ -110,38 +110,55 @@ def morton_order(points: np.ndarray) -> np.ndarray:
     return np.argsort(code, kind="stable")
 
 
-_CORNERS = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0], [1.0, 1.0]])
+def boundary_points(m: int) -> np.ndarray:
+    """4m points evenly spaced on the boundary of the unit square (spacing 1/m, corners included)."""
+    t = np.arange(m) / m
+    z, o = np.zeros(m), np.ones(m)
+    return np.concatenate([np.stack([t, z], 1), np.stack([o, t], 1), np.stack([1 - t, o], 1), np.stack([z, 1 - t], 1)])
+
+
+def _with_boundary(npts: int):
+    """Boundary spacing h = 1/m with m = ceil(sqrt(npts)) (the mean spacing of npts points) and
+    the number of interior points; interior points keep a distance of 0.3 h from the boundary so
+    that no sliver triangle forms along it."""
+    m = max(2, int(np.ceil(np.sqrt(npts))))
+    nin = npts - 4 * m
+    if nin < 1:
+        raise ValueError("too few points for the boundary layout")
+    return boundary_points(m), nin, 0.3 / m
 
 
 def uniform_points(npts: int, seed: int) -> np.ndarray:
-    """``npts`` uniform points in the unit square plus its 4 corners, Morton sorted."""
+    """``npts`` points in the unit square: evenly spaced on the boundary, uniform inside; Morton sorted."""
+    bnd, nin, gap = _with_boundary(npts)
     rng = np.random.default_rng(seed)
-    p = np.concatenate([rng.random((npts, 2)), _CORNERS])
+    p = np.concatenate([gap + (1.0 - 2.0 * gap) * rng.random((nin, 2)), bnd])
     return p[morton_order(p)]
 
 
 def gmm_points(npts: int, seed: int) -> np.ndarray:
     """Points clustered by a random Gaussian mixture, plus 20% uniform background.
 
-    K ~ U{2..6} components, means in [0.1, 0.9]^2, isotropic sigma ~ U[0.02, 0.15];
-    samples outside the unit square are rejected. The 4 corners are added and
-    the result is Morton sorted.
+    K ~ U{2..6} components, means in [0.1, 0.9]^2, isotropic sigma ~ U[0.02, 0.15]; samples
+    closer than the boundary gap to the border are rejected. Evenly spaced boundary points
+    close the domain; the result is Morton sorted.
     """
+    bnd, nin, gap = _with_boundary(npts)
     rng = np.random.default_rng(seed)
     K = int(rng.integers(2, 7))
     means = rng.uniform(0.1, 0.9, size=(K, 2))
     sig = rng.uniform(0.02, 0.15, size=K)
-    nbg = int(round(0.2 * npts))
-    out = [rng.random((nbg, 2))]
-    need = npts - nbg
+    nbg = int(round(0.2 * nin))
+    out = [gap + (1.0 - 2.0 * gap) * rng.random((nbg, 2))]
+    need = nin - nbg
     while need > 0:
         comp = rng.integers(0, K, size=2 * need)
         cand = means[comp] + sig[comp, None] * rng.standard_normal((2 * need, 2))
-        ok = np.all((cand > 0.0) & (cand < 1.0), axis=1)
+        ok = np.all((cand > gap) & (cand < 1.0 - gap), axis=1)
         cand = cand[ok][:need]
         out.append(cand)
         need -= cand.shape[0]
-    p = np.concatenate(out + [_CORNERS])
+    p = np.concatenate(out + [bnd])
     return p[morton_order(p)]
 
 
@@ -165,6 +182,8 @@ def delaunay_p1(points: np.ndarray) -> CSRMatrix:
         v = pc - pa
         dot = u[:, 0] * v[:, 0] + u[:, 1] * v[:, 1]
         cross = np.abs(u[:, 0] * v[:, 1] - u[:, 1] * v[:, 0])
+        if not np.all(cross > 0):
+            raise ValueError("degenerate (zero-area) triangle")
         w = 0.5 * dot / cross  # half the cotangent of the angle at vertex a, for edge (b, c)
         lo = np.minimum(tri[:, b], tri[:, c])
         hi = np.maximum(tri[:, b], tri[:, c])
@@ -193,7 +212,7 @@ def poisson_grid_64(seed: int = 0):
 
 
 def delaunay_p1_problem(npts: int, seed: int = 0):
-    """P1 Laplacian on a Delaunay mesh of ``npts`` uniform random points (+4 corners), zero-mean RHS."""
+    """P1 Laplacian on a Delaunay mesh of ``npts`` points (uniform inside, even on the boundary), zero-mean RHS."""
     A = delaunay_p1(uniform_points(npts, seed))
     return A, rhs_uniform(A.nrows, seed + 1000, zero_mean=True)
 
