@@ -262,14 +262,9 @@ struct Adj {
         scale_dev_kernel<T><<<grid_for(n), kBlock, 0, st>>>(n, ub, s + 2);
         ok(hipGetLastError());
         for (int m = nvc; m >= 1; --m) {
-            if (m < nvc) {
-                // recompute cycle m (its level vectors were overwritten); ubar is kept in place
-                T* keep = L0.t<T>();
-                ok(vec_copy<T>(n, ub, L0.adj<T>(kAdjFbar), st));
-                forward_to<T>(m, f0, u0);
-                ok(vec_copy<T>(n, L0.adj<T>(kAdjFbar), ub, st));
-                (void)keep;
-            }
+            // recompute cycle m (a later cycle overwrote its level vectors); the forward pass
+            // does not touch ubar
+            if (m < nvc) forward_to<T>(m, f0, u0);
             level_back<T>(0, f0, L0.adj<T>(kAdjUin));
         }
     }
@@ -304,14 +299,10 @@ extern "C" int amgg_vcycle_loss_adjoint(amgg_ctx* c, int nu1, int nu2, int preci
             A.ok(cast_f64_f32(L0.n, f, c->adj_f32, st));
             float* u32 = nullptr;
             if (u0) {
-                u32 = L0.adj<float>(kAdjW);  // the FP32 copy of u0 is read once, before recomputation reuses it
-                A.ok(cast_f64_f32(L0.n, u0, L0.r<float>(), st));
-                u32 = L0.r<float>();
-            }
-            if (u0) {
-                // keep u0 in a buffer the sweep never writes: the level's forward f buffer
-                A.ok(vec_copy<float>(L0.n, u32, L0.f<float>(), st));
+                // the fine level's own right-hand-side buffer is not used by the sweep (f comes
+                // from adj_f32), so it holds the FP32 copy of u0
                 u32 = L0.f<float>();
+                A.ok(cast_f64_f32(L0.n, u0, u32, st));
             }
             A.run<float>(nvc, c->adj_f32, u32, loss_dev);
         }

@@ -349,13 +349,15 @@ static int set_coeffs_impl(amgg_ctx* c, int lvl, int degree, const double* coeff
     if (!coeffs && !dev) return fail(AMGG_EINVAL, "amgg_set_smoother: null coefficients");
     PolyCoeffs pc{};
     pc.degree = degree;
-    bool diagonal = false;
+    bool diagonal = false, baseline = false;
     if (coeffs) {
         diagonal = true;
+        baseline = coeffs[0] == 2.0 / 3.0;
         for (int k = 0; k < 2 * degree + 1; ++k) {
             if (!std::isfinite(coeffs[k])) return fail(AMGG_ENONFINITE, "amgg_set_smoother: non-finite coefficient");
             pc.c[k] = coeffs[k];
             if (k > degree && coeffs[k] != 0.0) diagonal = false;
+            if (k > 0 && coeffs[k] != 0.0) baseline = false;
         }
     }
     Level& L = c->lv[lvl];
@@ -366,6 +368,7 @@ static int set_coeffs_impl(amgg_ctx* c, int lvl, int degree, const double* coeff
     if (e != hipSuccess) return hip_fail(e, "amgg_set_smoother");
     L.smoother = diagonal ? kSmootherDiagonal : kSmootherSparse;
     L.degree = degree;
+    L.baseline = baseline;
     return AMGG_OK;
 }
 

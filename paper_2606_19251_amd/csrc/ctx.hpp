@@ -50,6 +50,7 @@ struct Level {
     // smoother state
     int smoother = kSmootherNone;
     int degree = 0;
+    bool baseline = false;  // exactly the omega = 2/3 Jacobi smoother (the fallback target)
 
     CsrView A() const { return {n, nnz, ptr, col, lanes_for(n, nnz)}; }
     CsrView P() const { return {n, pnnz, pptr, pcol, lanes_for(n, pnnz)}; }

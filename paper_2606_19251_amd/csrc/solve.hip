@@ -185,7 +185,7 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
             if (outcome == 0 && k >= o->maxit) return finish(AMGG_MAXIT, rel, k);
             if (outcome != 0) {
                 bool learned = false;
-                for (int l = 0; l + 1 < c->nlevels; ++l) learned |= c->lv[l].smoother != kSmootherDiagonal;
+                for (int l = 0; l + 1 < c->nlevels; ++l) learned |= !c->lv[l].baseline;
                 if (!o->fallback || inf.fell_back || !learned || k >= o->maxit) return finish(outcome, rel, k);
                 // Jacobi fallback: the cycle stays a linear operator, so the iteration may
                 // continue from the current x with the paper's baseline smoother.

@@ -93,8 +93,10 @@ def test_derived_hierarchy_bitexact(kind):
 
 COEFFS = {
     "jacobi": (amg.jacobi_coeffs(), 2),
-    "poly2": (np.array([0.62, 0.031, -0.004, 0.21, 0.017]), 2),
-    "poly3": (np.array([0.6, 0.02, -0.003, 0.0004, 0.2, 0.01, -0.002]), 3),
+    # convergent smoothers on the 5-point grid: Q^{-1} eigenvalues alpha + beta kappa stay in
+    # (0, 2/(4 - kappa)) (alpha = f_d(4)/4, beta = f_o(-1)/8)
+    "poly2": (np.array([0.6, 0.01, -0.001, 0.12, 0.01]), 2),
+    "poly3": (np.array([0.6, 0.01, -0.001, 0.0001, 0.12, 0.01, -0.001]), 3),
 }
 
 
@@ -174,8 +176,9 @@ def test_fp32_cycle_fp64_outer_reaches_tolerance(kind, outer, cname):
     c, deg = COEFFS[cname]
     ds.set_coeffs(c, deg)
     om = capi.AMGG_OUTER_FCG if outer == "fcg" else capi.AMGG_OUTER_IR
-    x, rc, info, hist = ds.solve(_dev(f), outer=om, precision=32, tol=1e-8, history_cap=600)
+    x, rc, info, hist = ds.solve(_dev(f), outer=om, precision=32, tol=1e-8, history_cap=600, fallback=False)
     assert rc == 0, (rc, info.status, info.relres)
+    assert info.fell_back == 0
     xe = x.cpu().numpy()
     An = ho.levels[0].A
     fb = f - f.mean() if ho.singular else f
