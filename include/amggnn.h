@@ -225,6 +225,11 @@ int amgg_vcycle_loss_adjoint(amgg_ctx* ctx, int nu1, int nu2, int precision, int
                              const double* f, const double* u0, double* loss_dev,
                              double* dcoeffs_dev, void* stream);
 
+/* out[i] = (float)(in[i] * scale) for i < n (device arrays): hands the FP64 coefficient
+ * gradients of amgg_vcycle_loss_adjoint, scaled by 1/|batch| (Alg. 1, step 12: batch-mean
+ * loss), to the FP32 predictor backward. */
+int amgg_cast_scale_f64_f32(const double* in, float* out, int64_t n, double scale, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -54,6 +54,13 @@ class amgg_solve_info(C.Structure):
                 ("fell_back", C.c_int)]
 
 
+class gcin_graph(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("rowptr", C.c_void_p), ("col", C.c_void_p),
+                ("val", C.c_void_p)]
+
+
+GCIN_FP32, GCIN_BF16, GCIN_BF16X3 = 0, 1, 2
+
 _VP = C.c_void_p
 _I32 = C.c_int32
 _I = C.c_int
@@ -80,6 +87,17 @@ SIGNATURES = {
     "amgg_level_apply": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _VP]),
     "amgg_solve": (_I, [_VP, C.POINTER(amgg_solve_opts), _VP, _VP, C.POINTER(amgg_solve_info), _VP, _I, _VP]),
     "amgg_vcycle_loss_adjoint": (_I, [_VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _VP]),
+    "amgg_cast_scale_f64_f32": (_I, [_VP, _VP, C.c_int64, C.c_double, _VP]),
+    "gcin_param_count": (C.c_int64, [_I]),
+    "gcin_batch_workspace_bytes": (_I, [_I, _VP, _VP, C.POINTER(C.c_size_t)]),
+    "gcin_batch_create": (_I, [_I, C.POINTER(gcin_graph), _VP, C.c_size_t, _VP, C.POINTER(_VP)]),
+    "gcin_batch_destroy": (_I, [_VP]),
+    "gcin_forward": (_I, [_VP, _I, _I, _VP, _VP, _VP]),
+    "gcin_backward": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP]),
+    "gcin_tile_gemm_check": (_I, [_VP, _VP, _VP, _VP, _VP]),
+    "adam_scratch_bytes": (C.c_size_t, []),
+    "adam_step": (_I, [_VP, _VP, _VP, _VP, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, _I, C.c_float,
+                       _VP, _VP, _VP]),
 }
 
 _lib = None
@@ -221,3 +239,56 @@ def amgg_solve(ctx, opts: amgg_solve_opts, b, x, history_cap: int, stream):
 def amgg_vcycle_loss_adjoint(ctx, nu1, nu2, precision, nvc, f, u0, loss_dev, dcoeffs_dev, stream):
     return _check(lib().amgg_vcycle_loss_adjoint(ctx, nu1, nu2, precision, nvc, f, u0, loss_dev, dcoeffs_dev,
                                                  stream), "amgg_vcycle_loss_adjoint")
+
+
+def amgg_cast_scale_f64_f32(src, dst, n, scale, stream):
+    return _check(lib().amgg_cast_scale_f64_f32(src, dst, n, scale, stream), "amgg_cast_scale_f64_f32")
+
+
+# ---------------------------------------------------------------------------- GCIN predictor
+def gcin_param_count(degree: int) -> int:
+    v = lib().gcin_param_count(degree)
+    if v < 0:
+        raise AmggError(AMGG_EINVAL, "gcin_param_count: degree out of range")
+    return v
+
+
+def gcin_batch_workspace_bytes(n, nnz) -> int:
+    n = np.ascontiguousarray(n, np.int32)
+    nnz = np.ascontiguousarray(nnz, np.int32)
+    b = C.c_size_t()
+    _check(lib().gcin_batch_workspace_bytes(n.size, _np_ptr(n), _np_ptr(nnz), C.byref(b)), "gcin_batch_workspace_bytes")
+    return b.value
+
+
+def gcin_batch_create(graphs, workspace, ws_bytes, stream) -> int:
+    """graphs: list of (n, nnz, rowptr_ptr, col_ptr, val_ptr) device CSR views."""
+    arr = (gcin_graph * len(graphs))(*[gcin_graph(*g) for g in graphs])
+    h = _VP()
+    _check(lib().gcin_batch_create(len(graphs), arr, workspace, ws_bytes, stream, C.byref(h)), "gcin_batch_create")
+    return h.value
+
+
+def gcin_batch_destroy(b):
+    lib().gcin_batch_destroy(b)
+
+
+def gcin_forward(b, degree, precision, params, coeffs_out, stream):
+    return _check(lib().gcin_forward(b, degree, precision, params, coeffs_out, stream), "gcin_forward")
+
+
+def gcin_backward(b, degree, precision, params, dcoeffs, grads, stream):
+    return _check(lib().gcin_backward(b, degree, precision, params, dcoeffs, grads, stream), "gcin_backward")
+
+
+def adam_scratch_bytes() -> int:
+    return lib().adam_scratch_bytes()
+
+
+def adam_step(params, grads, m, v, n, lr, b1, b2, eps, step, clip, gnorm_out, scratch, stream):
+    return _check(lib().adam_step(params, grads, m, v, n, lr, b1, b2, eps, step, clip, gnorm_out, scratch, stream),
+                  "adam_step")
+
+
+def gcin_tile_gemm_check(A, B, D_fp32, D_bf16, stream):
+    return _check(lib().gcin_tile_gemm_check(A, B, D_fp32, D_bf16, stream), "gcin_tile_gemm_check")

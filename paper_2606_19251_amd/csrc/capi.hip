@@ -474,3 +474,10 @@ extern "C" int amgg_level_apply(amgg_ctx* c, int lvl, int op, int precision, con
         return AMGG_OK;
     });
 }
+
+extern "C" int amgg_cast_scale_f64_f32(const double* in, float* out, int64_t n, double scale, void* stream) {
+    if (!in || !out || n < 0) return fail(AMGG_EINVAL, "amgg_cast_scale_f64_f32: bad argument");
+    const hipError_t e = cast_scale_f64_f32(n, in, scale, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "amgg_cast_scale_f64_f32");
+    return AMGG_OK;
+}

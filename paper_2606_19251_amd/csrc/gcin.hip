@@ -1,1 +1,1148 @@
-// GCIN kernels (added with the learned predictor)
+// GCIN smoother-coefficient predictor on gfx950 (paper Sec. 3.2, Eqs. 6-10; App. A.1,
+// Tab. 5): forward, hand-written backward and Adam.
+//
+// Layout. All graphs of a batch (every level of every problem, Alg. 1 steps 3-6) are
+// concatenated; each graph starts on a 64-row tile boundary (pad rows carry no edges and
+// are masked), so a tile belongs to exactly one graph and per-graph statistics are fixed
+// order sums of per-tile partials (no atomics, bitwise reproducible). Activations are
+// FP32 [N x 64] row-major; a tile is processed by one 256-thread workgroup (4 wavefronts x
+// 16 rows, lane = channel), so every row access is one coalesced 256-byte transaction.
+//
+// Each GCIN layer is one pass: the neighbour features are normalised and rectified on
+// load (InstanceNorm + ReLU of the previous layer applied by the consumer), aggregated
+// with the edge weights (A_hat = (A - D) + I), multiplied by Theta_l (64 x 64) and the
+// per-tile sums of y and y^2 are emitted for the next InstanceNorm. In BF16 mode the
+// 64 x 64 products run on v_mfma_f32_16x16x32_bf16 with FP32 accumulation.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "amggnn.h"
+#include "errors.hpp"
+#include "gcin.h"
+
+namespace {
+
+constexpr int HD = 64;     // hidden width
+constexpr int NL = 4;      // GCIN layers
+constexpr int RO = 32;     // readout width per layer
+constexpr int JK = RO * NL;
+constexpr int M1 = 128, M2 = 64;
+constexpr int TILE = 64;
+constexpr int NT = 256;       // threads per workgroup
+constexpr int kWBlocks = 512; // fixed grid of the weight-gradient reductions
+constexpr int kMaxOut = 9;    // 2 d + 1 for d <= 4
+constexpr float kEps = 1e-5f;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------------------------------
+// parameter offsets (order documented in gcin.h)
+// ------------------------------------------------------------------------------------------
+struct Offs {
+    int64_t convW[NL], convb[NL], gam[NL], bet[NL], roW[NL], rob[NL];
+    int64_t lng, lnb, m0W, m0b, m1W, m1b, m2W, m2b, head0, total;
+    int nout;
+};
+
+Offs offsets(int d) {
+    Offs o{};
+    int64_t k = 0;
+    for (int l = 0; l < NL; ++l) {
+        const int in = l == 0 ? 2 : HD;
+        o.convW[l] = k; k += in * HD;
+        o.convb[l] = k; k += HD;
+        o.gam[l] = k; k += HD;
+        o.bet[l] = k; k += HD;
+    }
+    o.head0 = k;
+    for (int l = 0; l < NL; ++l) {
+        o.roW[l] = k; k += 2 * HD * RO;
+        o.rob[l] = k; k += RO;
+    }
+    o.nout = 2 * d + 1;
+    o.lng = k; k += JK;
+    o.lnb = k; k += JK;
+    o.m0W = k; k += JK * M1;
+    o.m0b = k; k += M1;
+    o.m1W = k; k += M1 * M2;
+    o.m1b = k; k += M2;
+    o.m2W = k; k += M2 * o.nout;
+    o.m2b = k; k += o.nout;
+    o.total = k;
+    return o;
+}
+
+__device__ __forceinline__ unsigned short f2bf(float f) {
+    // round to nearest even (inputs are finite)
+    unsigned int u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return static_cast<unsigned short>(u >> 16);
+}
+
+__device__ __forceinline__ float normrelu(float y, float mu, float rs, float ga, float be) {
+    return fmaxf((y - mu) * rs * ga + be, 0.0f);
+}
+
+// Sum over the 4 wavefronts of a workgroup, per channel (lane), into out[c] (thread wave 0).
+__device__ __forceinline__ double wave4_sum(double v, double (*sh)[HD]) {
+    const int wv = threadIdx.x / HD, c = threadIdx.x % HD;
+    sh[wv][c] = v;
+    __syncthreads();
+    const double s = sh[0][c] + sh[1][c] + sh[2][c] + sh[3][c];
+    __syncthreads();
+    return s;
+}
+
+// ------------------------------------------------------------------------------------------
+// batch construction
+// ------------------------------------------------------------------------------------------
+__global__ void fill_graph_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ cl,
+                                  const double* __restrict__ va, int32_t row0, int32_t e0, int32_t* __restrict__ ptr,
+                                  int32_t* __restrict__ col, float* __restrict__ w, float* __restrict__ x0) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t b = rp[i], e = rp[i + 1];
+    ptr[row0 + i] = e0 + b;
+    double aii = 0.0;
+    for (int32_t p = b; p < e; ++p) {
+        const int32_t j = cl[p];
+        if (j == i) {
+            col[e0 + p] = row0 + i;
+            w[e0 + p] = 1.0f;  // self-loop of A_hat
+            aii = va[p];
+        } else {
+            col[e0 + p] = row0 + j;
+            w[e0 + p] = static_cast<float>(va[p]);
+        }
+    }
+    x0[2 * (row0 + i)] = static_cast<float>(aii);
+    x0[2 * (row0 + i) + 1] = static_cast<float>(e - b - 1);
+}
+
+__global__ void set_int_kernel(int32_t* __restrict__ p, int32_t v) { p[0] = v; }
+
+__global__ void pad_rows_kernel(int32_t from, int32_t to, int32_t eptr, int32_t* __restrict__ ptr,
+                                float* __restrict__ x0) {
+    const int32_t i = from + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= to) return;
+    ptr[i] = eptr;
+    x0[2 * i] = 0.0f;
+    x0[2 * i + 1] = 0.0f;
+}
+
+// ------------------------------------------------------------------------------------------
+// forward
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void layer0_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                                    const float* __restrict__ w, const float* __restrict__ x0,
+                                                    const int32_t* __restrict__ tile_graph,
+                                                    const int32_t* __restrict__ gend, const float* __restrict__ W0,
+                                                    const float* __restrict__ b0, float* __restrict__ H0,
+                                                    float* __restrict__ Y, double* __restrict__ tstat) {
+    __shared__ double sh[4][HD];
+    const int tile = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
+    const int32_t end = gend[tile_graph[tile]];
+    const float w0 = W0[c], w1 = W0[HD + c], bb = b0[c];
+    double s1 = 0.0, s2 = 0.0;
+    for (int r = 0; r < 16; ++r) {
+        const int32_t row = tile * TILE + wv * 16 + r;
+        float y = 0.0f;
+        if (row < end) {
+            float h0 = 0.0f, h1 = 0.0f;
+            for (int32_t p = ptr[row]; p < ptr[row + 1]; ++p) {
+                const int32_t j = col[p];
+                h0 += w[p] * x0[2 * j];
+                h1 += w[p] * x0[2 * j + 1];
+            }
+            y = bb + h0 * w0 + h1 * w1;
+            if (c == 0) {
+                H0[2 * row] = h0;
+                H0[2 * row + 1] = h1;
+            }
+            s1 += y;
+            s2 += static_cast<double>(y) * y;
+        }
+        Y[static_cast<int64_t>(row) * HD + c] = y;
+    }
+    s1 = wave4_sum(s1, sh);
+    s2 = wave4_sum(s2, sh);
+    if (wv == 0) {
+        tstat[tile * 2 * HD + c] = s1;
+        tstat[tile * 2 * HD + HD + c] = s2;
+    }
+}
+
+// y (64 values of `rows` in LDS tile A[64][65]) times B (64 x 64) -> D tile [64][65] in LDS.
+// FP32: lane c computes column c. BF16: v_mfma_f32_16x16x32_bf16 on the wavefront's 16 rows;
+// Bt is the bf16 copy of B stored [col][k] (k contiguous) in LDS.
+//
+// SPLIT: A is passed as a_hi + a_lo, two bf16 numbers (16 significant bits), with one MFMA
+// each. The aggregated features of a GCIN layer have a per-graph mean that is large next to
+// their spread across nodes (the raw features a_ii, deg(i) are not centred), and the
+// InstanceNorm that follows subtracts that mean: rounding each node's A row to a single bf16
+// would be amplified by |A| / std(A) in the normalised output. Rounding of the weights is
+// not amplified (it moves the mean and the rows alike), so B stays single bf16.
+__device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned short& lo) {
+    hi = f2bf(x);
+    lo = f2bf(x - __uint_as_float(static_cast<unsigned int>(hi) << 16));
+}
+
+// SPLITB: B is passed as b_hi + b_lo as well and the product a_hi b_lo is added (the
+// a_lo b_lo term is below FP32 resolution): an FP32-accurate product on the BF16 MFMA
+// units, used where the result feeds non-smooth operations (ReLU masks, arg-max pooling)
+// whose gradients must match an FP32/FP64 evaluation.
+template <bool MFMA, bool SPLIT = false, bool SPLITB = false>
+__device__ __forceinline__ void tile_gemm(const float (*A)[HD + 1], const float* __restrict__ Bf,
+                                          const unsigned short (*Bt)[HD + 8], float (*D)[HD + 1],
+                                          const unsigned short (*Btlo)[HD + 8] = nullptr) {
+    const int wv = threadIdx.x / HD, lane = threadIdx.x % HD;
+    if constexpr (!MFMA) {
+        for (int r = 0; r < 16; ++r) {
+            const int lr = wv * 16 + r;
+            float acc = 0.0f;
+#pragma unroll 8
+            for (int k = 0; k < HD; ++k) acc += A[lr][k] * Bf[k * HD + lane];
+            D[lr][lane] = acc;
+        }
+    } else {
+        const int i = lane % 16, kq = (lane / 16) * 8;
+        f32x4 acc[4];
+        for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < HD; ks += 32) {
+            u16x8 av, alv;
+            for (int e = 0; e < 8; ++e) {
+                if constexpr (SPLIT) {
+                    unsigned short h, l;
+                    split_bf16(A[wv * 16 + i][ks + kq + e], h, l);
+                    av[e] = h;
+                    alv[e] = l;
+                } else {
+                    av[e] = f2bf(A[wv * 16 + i][ks + kq + e]);
+                }
+            }
+            const bf16x8 a = __builtin_bit_cast(bf16x8, av);
+            const bf16x8 al = __builtin_bit_cast(bf16x8, alv);
+            for (int nb = 0; nb < 4; ++nb) {
+                u16x8 bv;
+                for (int e = 0; e < 8; ++e) bv[e] = Bt[nb * 16 + i][ks + kq + e];
+                const bf16x8 b = __builtin_bit_cast(bf16x8, bv);
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nb], 0, 0, 0);
+                if constexpr (SPLIT) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b, acc[nb], 0, 0, 0);
+                if constexpr (SPLITB) {
+                    u16x8 blv;
+                    for (int e = 0; e < 8; ++e) blv[e] = Btlo[nb * 16 + i][ks + kq + e];
+                    const bf16x8 bl = __builtin_bit_cast(bf16x8, blv);
+                    acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc[nb], 0, 0, 0);
+                }
+            }
+        }
+        for (int nb = 0; nb < 4; ++nb)
+            for (int e = 0; e < 4; ++e) D[wv * 16 + (lane / 16) * 4 + e][nb * 16 + i] = acc[nb][e];
+    }
+}
+
+// Stage a 64 x 64 FP32 matrix M (row-major [k][c]) for tile_gemm: bf16 copy as Bt[c][k] when
+// `transpose`, else as Bt[k'][c'] = M[k'][c'] (used for products with M^T).
+__device__ __forceinline__ void stage_bf16(const float* __restrict__ M, bool transpose, unsigned short (*Bt)[HD + 8]) {
+    for (int e = threadIdx.x; e < HD * HD; e += NT) {
+        const int k = e / HD, c = e % HD;
+        if (transpose)
+            Bt[c][k] = f2bf(M[e]);
+        else
+            Bt[k][c] = f2bf(M[e]);
+    }
+}
+
+// hi/lo bf16 pair of M^T (Bt[c][k] = hi, Btlo[c][k] = lo of M[k][c]).
+__device__ __forceinline__ void stage_bf16_split_t(const float* __restrict__ M, unsigned short (*Bt)[HD + 8],
+                                                   unsigned short (*Btlo)[HD + 8]) {
+    for (int e = threadIdx.x; e < HD * HD; e += NT) {
+        const int k = e / HD, c = e % HD;
+        unsigned short h, l;
+        split_bf16(M[e], h, l);
+        Bt[c][k] = h;
+        Btlo[c][k] = l;
+    }
+}
+
+template <bool MFMA, bool X3>
+__global__ __launch_bounds__(NT) void layer_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                                   const float* __restrict__ w, const int32_t* __restrict__ tile_graph,
+                                                   const int32_t* __restrict__ gend, const float* __restrict__ Yp,
+                                                   const float* __restrict__ mup, const float* __restrict__ rsp,
+                                                   const float* __restrict__ gam, const float* __restrict__ bet,
+                                                   const float* __restrict__ W, const float* __restrict__ b,
+                                                   float* __restrict__ Hout, float* __restrict__ Y,
+                                                   double* __restrict__ tstat) {
+    __shared__ float Hs[TILE][HD + 1];
+    __shared__ float Ds[TILE][HD + 1];
+    __shared__ unsigned short Bt[HD][HD + 8];
+    __shared__ unsigned short Btlo[X3 ? HD : 1][HD + 8];
+    __shared__ double sh[4][HD];
+    const int tile = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
+    const int g = tile_graph[tile];
+    const int32_t end = gend[g];
+    const float mu = mup[g * HD + c], rs = rsp[g * HD + c], ga = gam[c], be = bet[c];
+    if constexpr (X3)
+        stage_bf16_split_t(W, Bt, Btlo);
+    else if constexpr (MFMA)
+        stage_bf16(W, true, Bt);
+    for (int r = 0; r < 16; ++r) {
+        const int lr = wv * 16 + r;
+        const int32_t row = tile * TILE + lr;
+        float h = 0.0f;
+        if (row < end)
+            for (int32_t p = ptr[row]; p < ptr[row + 1]; ++p)
+                h += w[p] * normrelu(Yp[static_cast<int64_t>(col[p]) * HD + c], mu, rs, ga, be);
+        Hs[lr][c] = h;
+        Hout[static_cast<int64_t>(row) * HD + c] = h;
+    }
+    __syncthreads();
+    tile_gemm<MFMA, true, X3>(Hs, W, Bt, Ds, Btlo);
+    __syncthreads();
+    const float bc = b[c];
+    double s1 = 0.0, s2 = 0.0;
+    for (int r = 0; r < 16; ++r) {
+        const int lr = wv * 16 + r;
+        const int32_t row = tile * TILE + lr;
+        float y = 0.0f;
+        if (row < end) {
+            y = Ds[lr][c] + bc;
+            s1 += y;
+            s2 += static_cast<double>(y) * y;
+        }
+        Y[static_cast<int64_t>(row) * HD + c] = y;
+    }
+    s1 = wave4_sum(s1, sh);
+    s2 = wave4_sum(s2, sh);
+    if (wv == 0) {
+        tstat[tile * 2 * HD + c] = s1;
+        tstat[tile * 2 * HD + HD + c] = s2;
+    }
+}
+
+// Per graph and channel: mean and 1/sqrt(biased variance + eps) from the tile sums.
+__global__ void stats_final_kernel(const double* __restrict__ tstat, const int32_t* __restrict__ gtile,
+                                   const float* __restrict__ gcnt, float* __restrict__ mu, float* __restrict__ rstd) {
+    const int g = blockIdx.x, c = threadIdx.x;
+    double s1 = 0.0, s2 = 0.0;
+    for (int t = gtile[g]; t < gtile[g + 1]; ++t) {
+        s1 += tstat[t * 2 * HD + c];
+        s2 += tstat[t * 2 * HD + HD + c];
+    }
+    const double n = gcnt[g];
+    const double m = s1 / n;
+    double var = s2 / n - m * m;
+    if (var < 0.0) var = 0.0;
+    mu[g * HD + c] = static_cast<float>(m);
+    rstd[g * HD + c] = static_cast<float>(1.0 / sqrt(var + static_cast<double>(kEps)));
+}
+
+// Per tile: sum, max and first arg-max of x = ReLU(IN(y)) per channel.
+__global__ __launch_bounds__(NT) void pool_tile_kernel(const int32_t* __restrict__ tile_graph,
+                                                       const int32_t* __restrict__ gend, const float* __restrict__ Y,
+                                                       const float* __restrict__ mu, const float* __restrict__ rstd,
+                                                       const float* __restrict__ gam, const float* __restrict__ bet,
+                                                       double* __restrict__ tsum, float* __restrict__ tmax,
+                                                       int32_t* __restrict__ targ) {
+    __shared__ double sh[4][HD];
+    __shared__ float smax[4][HD];
+    __shared__ int32_t sarg[4][HD];
+    const int tile = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
+    const int g = tile_graph[tile];
+    const int32_t end = gend[g];
+    const float m = mu[g * HD + c], rs = rstd[g * HD + c], ga = gam[c], be = bet[c];
+    double s = 0.0;
+    float mx = -INFINITY;
+    int32_t am = INT32_MAX;
+    for (int r = 0; r < 16; ++r) {
+        const int32_t row = tile * TILE + wv * 16 + r;
+        if (row < end) {
+            const float x = normrelu(Y[static_cast<int64_t>(row) * HD + c], m, rs, ga, be);
+            s += x;
+            if (x > mx) {
+                mx = x;
+                am = row;
+            }
+        }
+    }
+    smax[wv][c] = mx;
+    sarg[wv][c] = am;
+    s = wave4_sum(s, sh);
+    if (wv == 0) {
+        for (int k = 1; k < 4; ++k)
+            if (smax[k][c] > mx) {
+                mx = smax[k][c];
+                am = sarg[k][c];
+            }
+        tsum[tile * HD + c] = s;
+        tmax[tile * HD + c] = mx;
+        targ[tile * HD + c] = am;
+    }
+}
+
+__global__ void pool_final_kernel(const double* __restrict__ tsum, const float* __restrict__ tmax,
+                                  const int32_t* __restrict__ targ, const int32_t* __restrict__ gtile,
+                                  const float* __restrict__ gcnt, int layer, float* __restrict__ pooled,
+                                  int32_t* __restrict__ argmax) {
+    const int g = blockIdx.x, c = threadIdx.x;
+    double s = 0.0;
+    float mx = -INFINITY;
+    int32_t am = INT32_MAX;
+    for (int t = gtile[g]; t < gtile[g + 1]; ++t) {
+        s += tsum[t * HD + c];
+        if (tmax[t * HD + c] > mx) {
+            mx = tmax[t * HD + c];
+            am = targ[t * HD + c];
+        }
+    }
+    pooled[(g * NL + layer) * 2 * HD + c] = static_cast<float>(s / gcnt[g]);
+    pooled[(g * NL + layer) * 2 * HD + HD + c] = mx;
+    argmax[(g * NL + layer) * HD + c] = am;
+}
+
+__device__ __forceinline__ float block128_sum(float v, float* red) {
+    // 128 threads
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 64; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const float r = red[0];
+    __syncthreads();
+    return r;
+}
+
+struct HeadSave {
+    float* z;    // [G][128] readout concatenation
+    float* ln;   // [G][2]   mean, rstd
+    float* s;    // [G][128] sigmoid output
+    float* a1;   // [G][128]
+    float* a2;   // [G][64]
+};
+
+// Readout, LayerNorm, sigmoid and predictive MLP of one graph per workgroup (128 threads).
+__global__ __launch_bounds__(128) void head_fwd_kernel(const float* __restrict__ P, Offs o,
+                                                       const float* __restrict__ pooled, HeadSave hs,
+                                                       float* __restrict__ out) {
+    __shared__ float p[NL * 2 * HD], z[JK], s[JK], a1[M1], a2[M2], red[128];
+    const int g = blockIdx.x, t = threadIdx.x;
+    for (int k = t; k < NL * 2 * HD; k += 128) p[k] = pooled[g * NL * 2 * HD + k];
+    __syncthreads();
+    {
+        const int l = t / RO, oo = t % RO;
+        float acc = P[o.rob[l] + oo];
+        for (int k = 0; k < 2 * HD; ++k) acc += p[l * 2 * HD + k] * P[o.roW[l] + k * RO + oo];
+        z[t] = acc;
+    }
+    __syncthreads();
+    const float m = block128_sum(z[t], red) / JK;
+    const float dz = z[t] - m;
+    const float v = block128_sum(dz * dz, red) / JK;
+    const float rs = 1.0f / sqrtf(v + kEps);
+    const float zn = dz * rs * P[o.lng + t] + P[o.lnb + t];
+    s[t] = 1.0f / (1.0f + expf(-zn));
+    __syncthreads();
+    {
+        float acc = P[o.m0b + t];
+        for (int k = 0; k < JK; ++k) acc += s[k] * P[o.m0W + k * M1 + t];
+        a1[t] = fmaxf(acc, 0.0f);
+    }
+    __syncthreads();
+    if (t < M2) {
+        float acc = P[o.m1b + t];
+        for (int k = 0; k < M1; ++k) acc += a1[k] * P[o.m1W + k * M2 + t];
+        a2[t] = fmaxf(acc, 0.0f);
+    }
+    __syncthreads();
+    if (t < o.nout) {
+        float acc = P[o.m2b + t];
+        for (int k = 0; k < M2; ++k) acc += a2[k] * P[o.m2W + k * o.nout + t];
+        out[g * o.nout + t] = acc;
+    }
+    hs.z[g * JK + t] = z[t];
+    hs.s[g * JK + t] = s[t];
+    hs.a1[g * M1 + t] = a1[t];
+    if (t < M2) hs.a2[g * M2 + t] = a2[t];
+    if (t == 0) {
+        hs.ln[2 * g] = m;
+        hs.ln[2 * g + 1] = rs;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// backward
+// ------------------------------------------------------------------------------------------
+// Head backward of one graph; writes this graph's head-parameter gradients (relative to
+// o.head0) into gh[g][*] and the pooled-feature gradients into dpooled[g].
+__global__ __launch_bounds__(128) void head_bwd_kernel(const float* __restrict__ P, Offs o,
+                                                       const float* __restrict__ pooled, HeadSave hs,
+                                                       const float* __restrict__ dout, float* __restrict__ gh,
+                                                       int64_t ghstride, float* __restrict__ dpooled) {
+    __shared__ float p[NL * 2 * HD], s[JK], a1[M1], a2[M2], d2[M2], d1[M1], dzv[JK], red[128], dov[kMaxOut];
+    const int g = blockIdx.x, t = threadIdx.x;
+    float* const gbase = gh + g * ghstride;
+    auto G = [&](int64_t off) -> float& { return gbase[off - o.head0]; };  // absolute parameter offsets
+    for (int k = t; k < NL * 2 * HD; k += 128) p[k] = pooled[g * NL * 2 * HD + k];
+    s[t] = hs.s[g * JK + t];
+    a1[t] = hs.a1[g * M1 + t];
+    if (t < M2) a2[t] = hs.a2[g * M2 + t];
+    if (t < o.nout) dov[t] = dout[g * o.nout + t];
+    __syncthreads();
+    // out = a2 W3 + b3
+    if (t < o.nout) G(o.m2b + t) = dov[t];
+    for (int e = t; e < M2 * o.nout; e += 128) G(o.m2W + e) = a2[e / o.nout] * dov[e % o.nout];
+    if (t < M2) {
+        float acc = 0.0f;
+        for (int q = 0; q < o.nout; ++q) acc += dov[q] * P[o.m2W + t * o.nout + q];
+        d2[t] = a2[t] > 0.0f ? acc : 0.0f;
+    }
+    __syncthreads();
+    // a2 = relu(a1 W2 + b2)
+    if (t < M2) G(o.m1b + t) = d2[t];
+    for (int e = t; e < M1 * M2; e += 128) G(o.m1W + e) = a1[e / M2] * d2[e % M2];
+    {
+        float acc = 0.0f;
+        for (int q = 0; q < M2; ++q) acc += d2[q] * P[o.m1W + t * M2 + q];
+        d1[t] = a1[t] > 0.0f ? acc : 0.0f;
+    }
+    __syncthreads();
+    // a1 = relu(s W1 + b1)
+    G(o.m0b + t) = d1[t];
+    for (int e = t; e < JK * M1; e += 128) G(o.m0W + e) = s[e / M1] * d1[e % M1];
+    float ds = 0.0f;
+    for (int q = 0; q < M1; ++q) ds += d1[q] * P[o.m0W + t * M1 + q];
+    // s = sigmoid(zn), zn = zhat gamma + beta, zhat = (z - m) rstd
+    const float dzn = ds * s[t] * (1.0f - s[t]);
+    const float m = hs.ln[2 * g], rs = hs.ln[2 * g + 1];
+    const float zh = (hs.z[g * JK + t] - m) * rs;
+    G(o.lng + t) = dzn * zh;
+    G(o.lnb + t) = dzn;
+    const float dzh = dzn * P[o.lng + t];
+    const float mean_a = block128_sum(dzh, red) / JK;
+    const float mean_b = block128_sum(dzh * zh, red) / JK;
+    dzv[t] = rs * (dzh - mean_a - zh * mean_b);
+    __syncthreads();
+    // z[l*32+o] = rob_l[o] + sum_k p_l[k] roW_l[k][o]
+    for (int l = 0; l < NL; ++l) {
+        if (t < RO) G(o.rob[l] + t) = dzv[l * RO + t];
+        for (int e = t; e < 2 * HD * RO; e += 128) G(o.roW[l] + e) = p[l * 2 * HD + e / RO] * dzv[l * RO + e % RO];
+        {
+            float acc = 0.0f;
+            for (int q = 0; q < RO; ++q) acc += dzv[l * RO + q] * P[o.roW[l] + t * RO + q];
+            dpooled[(g * NL + l) * 2 * HD + t] = acc;
+        }
+    }
+}
+
+// Layer backward, first half, per tile: dX from pooling (mean and arg-max) and, below the last
+// layer, from the next layer's aggregation (A_hat^T dH = A_hat dH, A symmetric); ReLU and the
+// affine part of InstanceNorm; per-tile sums for the normalisation backward and gamma/beta.
+__global__ __launch_bounds__(NT) void bwd_a_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                                   const float* __restrict__ w, const int32_t* __restrict__ tile_graph,
+                                                   const int32_t* __restrict__ gend, const float* __restrict__ gcnt,
+                                                   const float* __restrict__ Y, const float* __restrict__ mu,
+                                                   const float* __restrict__ rstd, const float* __restrict__ gam,
+                                                   const float* __restrict__ bet, const float* __restrict__ dpooled,
+                                                   const int32_t* __restrict__ argmax, int layer,
+                                                   const float* __restrict__ dHn, float* __restrict__ dxh,
+                                                   double* __restrict__ tb) {
+    __shared__ double sh[4][HD];
+    const int tile = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
+    const int g = tile_graph[tile];
+    const int32_t end = gend[g];
+    const float m = mu[g * HD + c], rs = rstd[g * HD + c], ga = gam[c], be = bet[c];
+    const float dmean = dpooled[(g * NL + layer) * 2 * HD + c] / gcnt[g];
+    const float dmax = dpooled[(g * NL + layer) * 2 * HD + HD + c];
+    const int32_t am = argmax[(g * NL + layer) * HD + c];
+    double sa = 0.0, sb = 0.0, sg = 0.0, sbe = 0.0;
+    for (int r = 0; r < 16; ++r) {
+        const int32_t row = tile * TILE + wv * 16 + r;
+        float d = 0.0f;
+        if (row < end) {
+            float dx = dmean + (row == am ? dmax : 0.0f);
+            if (dHn)
+                for (int32_t p = ptr[row]; p < ptr[row + 1]; ++p) dx += w[p] * dHn[static_cast<int64_t>(col[p]) * HD + c];
+            const float xh = (Y[static_cast<int64_t>(row) * HD + c] - m) * rs;
+            const float xn = xh * ga + be;
+            const float dxn = xn > 0.0f ? dx : 0.0f;
+            d = dxn * ga;
+            sa += d;
+            sb += static_cast<double>(d) * xh;
+            sg += static_cast<double>(dxn) * xh;
+            sbe += dxn;
+        }
+        dxh[static_cast<int64_t>(row) * HD + c] = d;
+    }
+    sa = wave4_sum(sa, sh);
+    sb = wave4_sum(sb, sh);
+    sg = wave4_sum(sg, sh);
+    sbe = wave4_sum(sbe, sh);
+    if (wv == 0) {
+        tb[tile * 4 * HD + c] = sa;
+        tb[tile * 4 * HD + HD + c] = sb;
+        tb[tile * 4 * HD + 2 * HD + c] = sg;
+        tb[tile * 4 * HD + 3 * HD + c] = sbe;
+    }
+}
+
+// Per graph: means of dxhat and dxhat*xhat; gamma/beta gradients of the graph.
+__global__ void bwd_final_kernel(const double* __restrict__ tb, const int32_t* __restrict__ gtile,
+                                 const float* __restrict__ gcnt, float* __restrict__ gmean, double* __restrict__ ggb) {
+    const int g = blockIdx.x, c = threadIdx.x;
+    double sa = 0.0, sb = 0.0, sg = 0.0, sbe = 0.0;
+    for (int t = gtile[g]; t < gtile[g + 1]; ++t) {
+        sa += tb[t * 4 * HD + c];
+        sb += tb[t * 4 * HD + HD + c];
+        sg += tb[t * 4 * HD + 2 * HD + c];
+        sbe += tb[t * 4 * HD + 3 * HD + c];
+    }
+    gmean[g * 2 * HD + c] = static_cast<float>(sa / gcnt[g]);
+    gmean[g * 2 * HD + HD + c] = static_cast<float>(sb / gcnt[g]);
+    ggb[g * 2 * HD + c] = sg;
+    ggb[g * 2 * HD + HD + c] = sbe;
+}
+
+// Layer backward, second half. dY = rstd (dxhat - mean(dxhat) - xhat mean(dxhat xhat));
+// dH = dY W^T (stored for the layer below unless first); partial dW = H^T dY and db = sum dY
+// accumulated over the tiles a workgroup visits (fixed grid of kWBlocks, fixed order).
+template <bool MFMA>
+__global__ __launch_bounds__(NT) void bwd_b_kernel(int ntiles, const int32_t* __restrict__ tile_graph,
+                                                   const int32_t* __restrict__ gend, const float* __restrict__ Y,
+                                                   const float* __restrict__ mu, const float* __restrict__ rstd,
+                                                   const float* __restrict__ gmean, const float* __restrict__ dxh,
+                                                   const float* __restrict__ H, int in_dim,
+                                                   const float* __restrict__ W, float* __restrict__ dH,
+                                                   float* __restrict__ wpart, double* __restrict__ bpart) {
+    __shared__ float dYs[TILE][HD + 1];
+    __shared__ float Hs[TILE][HD + 1];
+    __shared__ float Ds[TILE][HD + 1];
+    __shared__ unsigned short Bt[HD][HD + 8];
+    __shared__ double sh[4][HD];
+    const int wv = threadIdx.x / HD, c = threadIdx.x % HD;
+    if constexpr (MFMA) {
+        if (dH) stage_bf16(W, false, Bt);  // dH = dY W^T: B[c'][k] = W[k][c'] read as rows of W
+    }
+    // dW accumulator: thread owns W entries e = threadIdx.x + q*NT (in_dim*64 entries)
+    float accw[16];
+    for (int q = 0; q < 16; ++q) accw[q] = 0.0f;
+    double accb = 0.0;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int g = tile_graph[tile];
+        const int32_t end = gend[g];
+        const float m = mu[g * HD + c], rs = rstd[g * HD + c];
+        const float ma = gmean[g * 2 * HD + c], mb = gmean[g * 2 * HD + HD + c];
+        for (int r = 0; r < 16; ++r) {
+            const int lr = wv * 16 + r;
+            const int32_t row = tile * TILE + lr;
+            float dy = 0.0f, h = 0.0f;
+            if (row < end) {
+                const int64_t k = static_cast<int64_t>(row) * HD + c;
+                const float xh = (Y[k] - m) * rs;
+                dy = rs * (dxh[k] - ma - xh * mb);
+                if (c < in_dim) h = H[static_cast<int64_t>(row) * in_dim + c];
+            }
+            dYs[lr][c] = dy;
+            Hs[lr][c] = h;
+            accb += dy;
+        }
+        __syncthreads();
+        if (dH) {
+            if constexpr (!MFMA) {
+                for (int r = 0; r < 16; ++r) {
+                    const int lr = wv * 16 + r;
+                    float acc = 0.0f;
+#pragma unroll 8
+                    for (int q = 0; q < HD; ++q) acc += dYs[lr][q] * W[c * HD + q];
+                    Ds[lr][c] = acc;
+                }
+            } else {
+                tile_gemm<true>(dYs, W, Bt, Ds);
+            }
+            __syncthreads();
+            for (int r = 0; r < 16; ++r) {
+                const int lr = wv * 16 + r;
+                const int32_t row = tile * TILE + lr;
+                dH[static_cast<int64_t>(row) * HD + c] = row < end ? Ds[lr][c] : 0.0f;
+            }
+        }
+        // dW[k][c'] += sum_rows H[row][k] dY[row][c']
+        if constexpr (!MFMA) {
+            for (int q = 0; q < 16; ++q) {
+                const int e = threadIdx.x + q * NT;
+                if (e < in_dim * HD) {
+                    const int k = e / HD, cc = e % HD;
+                    float acc = 0.0f;
+                    for (int r = 0; r < TILE; ++r) acc += Hs[r][k] * dYs[r][cc];
+                    accw[q] += acc;
+                }
+            }
+        } else {
+            if (in_dim == HD) {
+                // 64 x 64 = (H^T)(64 x 64 rows) (dY): wavefront wv owns output rows k in [16 wv, 16 wv + 16)
+                const int lane = c, i = lane % 16, kq = (lane / 16) * 8;
+                f32x4 acc[4];
+                for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int ks = 0; ks < TILE; ks += 32) {
+                    // H^T is the uncentred operand here as in the forward product: split it
+                    u16x8 av, alv;
+                    for (int e = 0; e < 8; ++e) {
+                        unsigned short h, l;
+                        split_bf16(Hs[ks + kq + e][wv * 16 + i], h, l);
+                        av[e] = h;
+                        alv[e] = l;
+                    }
+                    const bf16x8 a = __builtin_bit_cast(bf16x8, av);
+                    const bf16x8 al = __builtin_bit_cast(bf16x8, alv);
+                    for (int nb = 0; nb < 4; ++nb) {
+                        u16x8 bv;
+                        for (int e = 0; e < 8; ++e) bv[e] = f2bf(dYs[ks + kq + e][nb * 16 + i]);
+                        const bf16x8 b = __builtin_bit_cast(bf16x8, bv);
+                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nb], 0, 0, 0);
+                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b, acc[nb], 0, 0, 0);
+                    }
+                }
+                // lane holds rows k = 16 wv + 4 (lane/16) + e, column 16 nb + i; map to accw slots
+                for (int nb = 0; nb < 4; ++nb)
+                    for (int e = 0; e < 4; ++e) accw[nb * 4 + e] += acc[nb][e];
+            } else {
+                for (int q = 0; q < 16; ++q) {
+                    const int e = threadIdx.x + q * NT;
+                    if (e < in_dim * HD) {
+                        const int k = e / HD, cc = e % HD;
+                        float acc = 0.0f;
+                        for (int r = 0; r < TILE; ++r) acc += Hs[r][k] * dYs[r][cc];
+                        accw[q] += acc;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // write this workgroup's partials in plain [k][c] order
+    if (MFMA && in_dim == HD) {
+        const int lane = c, i = lane % 16;
+        for (int nb = 0; nb < 4; ++nb)
+            for (int e = 0; e < 4; ++e) {
+                const int k = wv * 16 + (lane / 16) * 4 + e, cc = nb * 16 + i;
+                wpart[static_cast<int64_t>(blockIdx.x) * HD * HD + k * HD + cc] = accw[nb * 4 + e];
+            }
+    } else {
+        for (int q = 0; q < 16; ++q) {
+            const int e = threadIdx.x + q * NT;
+            if (e < in_dim * HD) wpart[static_cast<int64_t>(blockIdx.x) * HD * HD + e] = accw[q];
+        }
+    }
+    accb = wave4_sum(accb, sh);
+    if (wv == 0) bpart[blockIdx.x * HD + c] = accb;
+}
+
+// One workgroup: D1 = A B by the FP32 path and D2 = A B by the BF16 MFMA path of tile_gemm.
+__global__ __launch_bounds__(NT) void tile_gemm_check_kernel(const float* __restrict__ A, const float* __restrict__ B,
+                                                             float* __restrict__ D1, float* __restrict__ D2) {
+    __shared__ float As[TILE][HD + 1];
+    __shared__ float Ds[TILE][HD + 1];
+    __shared__ unsigned short Bt[HD][HD + 8];
+    for (int e = threadIdx.x; e < TILE * HD; e += NT) As[e / HD][e % HD] = A[e];
+    stage_bf16(B, true, Bt);
+    __syncthreads();
+    tile_gemm<false>(As, B, Bt, Ds);
+    __syncthreads();
+    for (int e = threadIdx.x; e < TILE * HD; e += NT) D1[e] = Ds[e / HD][e % HD];
+    __syncthreads();
+    tile_gemm<true, true>(As, B, Bt, Ds);
+    __syncthreads();
+    for (int e = threadIdx.x; e < TILE * HD; e += NT) D2[e] = Ds[e / HD][e % HD];
+}
+
+// grads[off + e] = sum over `parts` partial arrays (stride `stride`) in order.
+__global__ void reduce_parts_f32_kernel(const float* __restrict__ part, int parts, int64_t stride, int64_t count,
+                                        float* __restrict__ out) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double s = 0.0;
+    for (int k = 0; k < parts; ++k) s += part[k * stride + e];
+    out[e] = static_cast<float>(s);
+}
+
+__global__ void reduce_parts_f64_kernel(const double* __restrict__ part, int parts, int64_t stride, int64_t count,
+                                        float* __restrict__ out) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double s = 0.0;
+    for (int k = 0; k < parts; ++k) s += part[k * stride + e];
+    out[e] = static_cast<float>(s);
+}
+
+// ------------------------------------------------------------------------------------------
+// Adam
+// ------------------------------------------------------------------------------------------
+constexpr int kAdamBlocks = 256;
+
+__global__ __launch_bounds__(NT) void sumsq_kernel(const float* __restrict__ g, int64_t n, double* __restrict__ part) {
+    __shared__ double red[NT];
+    double s = 0.0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += static_cast<int64_t>(gridDim.x) * NT)
+        s += static_cast<double>(g[i]) * g[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void clipcoef_kernel(const double* __restrict__ part, float clip, double* __restrict__ scal,
+                                float* __restrict__ gnorm_out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int k = 0; k < kAdamBlocks; ++k) s += part[k];
+    const double nrm = sqrt(s);
+    double coef = 1.0;
+    if (clip > 0.0f) {
+        coef = static_cast<double>(clip) / (nrm + 1e-6);
+        if (coef > 1.0) coef = 1.0;
+    }
+    scal[0] = coef;
+    scal[1] = nrm;
+    if (gnorm_out) gnorm_out[0] = static_cast<float>(nrm);
+}
+
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float bc1,
+                            float bc2, const double* __restrict__ scal) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = static_cast<float>(g[i] * scal[0]);
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+inline dim3 grid_of(int64_t n, int block) { return dim3(static_cast<unsigned>((n + block - 1) / block)); }
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// batch object
+// ------------------------------------------------------------------------------------------
+struct gcin_batch {
+    int G = 0;
+    int64_t N = 0, E = 0;
+    int ntiles = 0;
+    std::vector<int32_t> goff, gend, gtile, gn;
+    // device
+    int32_t *d_gend = nullptr, *d_gtile = nullptr, *d_tile_graph = nullptr;
+    float* d_gcnt = nullptr;
+    int32_t *ptr = nullptr, *col = nullptr;
+    float *w = nullptr, *x0 = nullptr, *H0 = nullptr;
+    float* Y[NL] = {};
+    float* H[NL] = {};
+    double* tstat = nullptr;
+    float* mu[NL] = {};
+    float* rstd[NL] = {};
+    double* tpsum = nullptr;
+    float* tpmax = nullptr;
+    int32_t* tparg = nullptr;
+    float* pooled = nullptr;
+    int32_t* argmax = nullptr;
+    HeadSave hs{};
+    float *dpooled = nullptr, *ghead = nullptr, *dxh = nullptr, *dHa = nullptr, *dHb = nullptr;
+    double* tb = nullptr;
+    float* gmean = nullptr;
+    double* ggb = nullptr;
+    float* wpart = nullptr;
+    double* bpart = nullptr;
+    int64_t ghstride = 0;
+    int last_degree = -1;
+};
+
+namespace {
+
+struct Carve {
+    uintptr_t base;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~static_cast<size_t>(255);
+        T* p = reinterpret_cast<T*>(base + off);
+        off += (count ? count : 1) * sizeof(T);
+        return p;
+    }
+};
+
+size_t layout_batch(gcin_batch* b, uintptr_t base) {
+    Carve cv{base};
+    const size_t G = b->G, N = b->N, E = b->E, T = b->ntiles;
+    b->d_gend = cv.take<int32_t>(G);
+    b->d_gtile = cv.take<int32_t>(G + 1);
+    b->d_tile_graph = cv.take<int32_t>(T);
+    b->d_gcnt = cv.take<float>(G);
+    b->ptr = cv.take<int32_t>(N + 1);
+    b->col = cv.take<int32_t>(E);
+    b->w = cv.take<float>(E);
+    b->x0 = cv.take<float>(2 * N);
+    b->H0 = cv.take<float>(2 * N);
+    for (int l = 0; l < NL; ++l) {
+        b->Y[l] = cv.take<float>(N * HD);
+        b->H[l] = l == 0 ? nullptr : cv.take<float>(N * HD);
+        b->mu[l] = cv.take<float>(G * HD);
+        b->rstd[l] = cv.take<float>(G * HD);
+    }
+    b->tstat = cv.take<double>(T * 2 * HD);
+    b->tpsum = cv.take<double>(T * HD);
+    b->tpmax = cv.take<float>(T * HD);
+    b->tparg = cv.take<int32_t>(T * HD);
+    b->pooled = cv.take<float>(G * NL * 2 * HD);
+    b->argmax = cv.take<int32_t>(G * NL * HD);
+    b->hs.z = cv.take<float>(G * JK);
+    b->hs.ln = cv.take<float>(G * 2);
+    b->hs.s = cv.take<float>(G * JK);
+    b->hs.a1 = cv.take<float>(G * M1);
+    b->hs.a2 = cv.take<float>(G * M2);
+    b->dpooled = cv.take<float>(G * NL * 2 * HD);
+    const Offs o4 = offsets(AMGG_MAX_DEGREE);
+    b->ghstride = ((o4.total - o4.head0) + 63) / 64 * 64;
+    b->ghead = cv.take<float>(G * b->ghstride);
+    b->dxh = cv.take<float>(N * HD);
+    b->dHa = cv.take<float>(N * HD);
+    b->dHb = cv.take<float>(N * HD);
+    b->tb = cv.take<double>(T * 4 * HD);
+    b->gmean = cv.take<float>(G * 2 * HD);
+    b->ggb = cv.take<double>(G * 2 * HD);
+    b->wpart = cv.take<float>(static_cast<size_t>(kWBlocks) * HD * HD);
+    b->bpart = cv.take<double>(static_cast<size_t>(kWBlocks) * HD);
+    return (cv.off + 255) & ~static_cast<size_t>(255);
+}
+
+int plan_batch(gcin_batch* b, int ngraphs, const int32_t* n, const int32_t* nnz) {
+    if (ngraphs < 1 || ngraphs > GCIN_MAX_GRAPHS) return amgg::fail(AMGG_EINVAL, "gcin: ngraphs out of range");
+    b->G = ngraphs;
+    b->goff.assign(ngraphs + 1, 0);
+    b->gend.assign(ngraphs, 0);
+    b->gtile.assign(ngraphs + 1, 0);
+    b->gn.assign(ngraphs, 0);
+    int64_t rows = 0, edges = 0;
+    for (int g = 0; g < ngraphs; ++g) {
+        if (n[g] < 1 || nnz[g] < n[g]) return amgg::fail(AMGG_EINVAL, "gcin: a graph has n < 1 or nnz < n");
+        b->goff[g] = static_cast<int32_t>(rows);
+        b->gend[g] = static_cast<int32_t>(rows + n[g]);
+        b->gtile[g] = static_cast<int32_t>(rows / TILE);
+        b->gn[g] = n[g];
+        rows += (static_cast<int64_t>(n[g]) + TILE - 1) / TILE * TILE;
+        edges += nnz[g];
+        if (rows > INT32_MAX / 2 || edges > INT32_MAX / 2) return amgg::fail(AMGG_EINVAL, "gcin: batch too large");
+    }
+    b->goff[ngraphs] = static_cast<int32_t>(rows);
+    b->gtile[ngraphs] = static_cast<int32_t>(rows / TILE);
+    b->N = rows;
+    b->E = edges;
+    b->ntiles = static_cast<int>(rows / TILE);
+    return AMGG_OK;
+}
+
+int hip_err(hipError_t e, const char* where) {
+    return amgg::fail(AMGG_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" int64_t gcin_param_count(int degree) {
+    if (degree < 1 || degree > AMGG_MAX_DEGREE) return -1;
+    return offsets(degree).total;
+}
+
+extern "C" int gcin_batch_workspace_bytes(int ngraphs, const int32_t* n, const int32_t* nnz, size_t* bytes) {
+    return amgg::guarded([&]() -> int {
+        if (!n || !nnz || !bytes) return amgg::fail(AMGG_EINVAL, "gcin_batch_workspace_bytes: null argument");
+        gcin_batch b;
+        int rc = plan_batch(&b, ngraphs, n, nnz);
+        if (rc) return rc;
+        *bytes = layout_batch(&b, 0);
+        return AMGG_OK;
+    });
+}
+
+extern "C" int gcin_batch_create(int ngraphs, const gcin_graph* graphs, void* workspace, size_t ws_bytes, void* stream,
+                                 gcin_batch** out) {
+    return amgg::guarded([&]() -> int {
+        if (!graphs || !out || !workspace) return amgg::fail(AMGG_EINVAL, "gcin_batch_create: null argument");
+        if (reinterpret_cast<uintptr_t>(workspace) & 255u)
+            return amgg::fail(AMGG_EWORKSPACE, "gcin_batch_create: workspace not 256-byte aligned");
+        if (ngraphs < 1 || ngraphs > GCIN_MAX_GRAPHS) return amgg::fail(AMGG_EINVAL, "gcin_batch_create: ngraphs out of range");
+        std::vector<int32_t> n(ngraphs), z(ngraphs);
+        for (int g = 0; g < ngraphs; ++g) {
+            n[g] = graphs[g].n;
+            z[g] = graphs[g].nnz;
+            if (!graphs[g].rowptr || !graphs[g].col || !graphs[g].val)
+                return amgg::fail(AMGG_EINVAL, "gcin_batch_create: null graph array");
+        }
+        auto* b = new gcin_batch();
+        int rc = plan_batch(b, ngraphs, n.data(), z.data());
+        if (rc) {
+            delete b;
+            return rc;
+        }
+        const size_t need = layout_batch(b, 0);
+        if (ws_bytes < need) {
+            delete b;
+            return amgg::fail(AMGG_EWORKSPACE, "gcin_batch_create: workspace too small");
+        }
+        layout_batch(b, reinterpret_cast<uintptr_t>(workspace));
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        // tables
+        std::vector<int32_t> tile_graph(b->ntiles);
+        std::vector<float> cnt(ngraphs);
+        for (int g = 0; g < ngraphs; ++g) {
+            for (int t = b->gtile[g]; t < b->gtile[g + 1]; ++t) tile_graph[t] = g;
+            cnt[g] = static_cast<float>(b->gn[g]);
+        }
+        hipError_t e = hipMemcpyAsync(b->d_gend, b->gend.data(), sizeof(int32_t) * ngraphs, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->d_gtile, b->gtile.data(), sizeof(int32_t) * (ngraphs + 1), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->d_tile_graph, tile_graph.data(), sizeof(int32_t) * b->ntiles, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(b->d_gcnt, cnt.data(), sizeof(float) * ngraphs, hipMemcpyHostToDevice, st);
+        int64_t e0 = 0;
+        for (int g = 0; g < ngraphs && e == hipSuccess; ++g) {
+            fill_graph_kernel<<<grid_of(n[g], 256), 256, 0, st>>>(n[g], graphs[g].rowptr, graphs[g].col, graphs[g].val,
+                                                                 b->goff[g], static_cast<int32_t>(e0), b->ptr, b->col,
+                                                                 b->w, b->x0);
+            const int32_t from = b->gend[g], to = b->goff[g + 1];
+            e0 += z[g];
+            if (to > from)
+                pad_rows_kernel<<<grid_of(to - from, 256), 256, 0, st>>>(from, to, static_cast<int32_t>(e0), b->ptr, b->x0);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) {
+            set_int_kernel<<<1, 1, 0, st>>>(b->ptr + b->N, static_cast<int32_t>(b->E));
+            e = hipGetLastError();
+        }
+        // the host tables above must stay alive until the copies complete
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            delete b;
+            return hip_err(e, "gcin_batch_create");
+        }
+        *out = b;
+        return AMGG_OK;
+    });
+}
+
+extern "C" int gcin_batch_destroy(gcin_batch* b) {
+    delete b;
+    return AMGG_OK;
+}
+
+extern "C" int gcin_forward(gcin_batch* b, int degree, int precision, const float* P, float* coeffs_out, void* stream) {
+    return amgg::guarded([&]() -> int {
+        if (!b || !P || !coeffs_out) return amgg::fail(AMGG_EINVAL, "gcin_forward: null argument");
+        if (degree < 1 || degree > AMGG_MAX_DEGREE) return amgg::fail(AMGG_EINVAL, "gcin_forward: degree out of range");
+        if (precision < GCIN_FP32 || precision > GCIN_BF16X3) return amgg::fail(AMGG_EINVAL, "gcin_forward: bad precision");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const Offs o = offsets(degree);
+        const int T = b->ntiles, G = b->G;
+        layer0_kernel<<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->x0, b->d_tile_graph, b->d_gend, P + o.convW[0],
+                                        P + o.convb[0], b->H0, b->Y[0], b->tstat);
+        stats_final_kernel<<<G, HD, 0, st>>>(b->tstat, b->d_gtile, b->d_gcnt, b->mu[0], b->rstd[0]);
+        for (int l = 1; l < NL; ++l) {
+            auto kern = precision == GCIN_BF16X3 ? layer_kernel<true, true>
+                        : precision == GCIN_BF16 ? layer_kernel<true, false> : layer_kernel<false, false>;
+            kern<<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->d_tile_graph, b->d_gend, b->Y[l - 1], b->mu[l - 1],
+                                   b->rstd[l - 1], P + o.gam[l - 1], P + o.bet[l - 1], P + o.convW[l], P + o.convb[l],
+                                   b->H[l], b->Y[l], b->tstat);
+            stats_final_kernel<<<G, HD, 0, st>>>(b->tstat, b->d_gtile, b->d_gcnt, b->mu[l], b->rstd[l]);
+        }
+        for (int l = 0; l < NL; ++l) {
+            pool_tile_kernel<<<T, NT, 0, st>>>(b->d_tile_graph, b->d_gend, b->Y[l], b->mu[l], b->rstd[l], P + o.gam[l],
+                                               P + o.bet[l], b->tpsum, b->tpmax, b->tparg);
+            pool_final_kernel<<<G, HD, 0, st>>>(b->tpsum, b->tpmax, b->tparg, b->d_gtile, b->d_gcnt, l, b->pooled,
+                                                b->argmax);
+        }
+        head_fwd_kernel<<<G, 128, 0, st>>>(P, o, b->pooled, b->hs, coeffs_out);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_err(e, "gcin_forward");
+        b->last_degree = degree;
+        return AMGG_OK;
+    });
+}
+
+extern "C" int gcin_backward(gcin_batch* b, int degree, int precision, const float* P, const float* dcoeffs,
+                             float* grads, void* stream) {
+    return amgg::guarded([&]() -> int {
+        if (!b || !P || !dcoeffs || !grads) return amgg::fail(AMGG_EINVAL, "gcin_backward: null argument");
+        if (degree != b->last_degree) return amgg::fail(AMGG_ESTATE, "gcin_backward: no forward pass of this degree");
+        if (precision < GCIN_FP32 || precision > GCIN_BF16X3) return amgg::fail(AMGG_EINVAL, "gcin_backward: bad precision");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const Offs o = offsets(degree);
+        const int T = b->ntiles, G = b->G;
+        head_bwd_kernel<<<G, 128, 0, st>>>(P, o, b->pooled, b->hs, dcoeffs, b->ghead, b->ghstride, b->dpooled);
+        // head parameters: sum over graphs
+        const int64_t nhead = o.total - o.head0;
+        reduce_parts_f32_kernel<<<grid_of(nhead, 256), 256, 0, st>>>(b->ghead, G, b->ghstride, nhead, grads + o.head0);
+        float* dHn = nullptr;  // dH of the layer above (for the aggregation backward)
+        float* bufs[2] = {b->dHa, b->dHb};
+        for (int l = NL - 1; l >= 0; --l) {
+            bwd_a_kernel<<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->d_tile_graph, b->d_gend, b->d_gcnt, b->Y[l], b->mu[l],
+                                           b->rstd[l], P + o.gam[l], P + o.bet[l], b->dpooled, b->argmax, l, dHn,
+                                           b->dxh, b->tb);
+            bwd_final_kernel<<<G, HD, 0, st>>>(b->tb, b->d_gtile, b->d_gcnt, b->gmean, b->ggb);
+            // gamma / beta of this layer
+            reduce_parts_f64_kernel<<<1, HD, 0, st>>>(b->ggb, G, 2 * HD, HD, grads + o.gam[l]);
+            reduce_parts_f64_kernel<<<1, HD, 0, st>>>(b->ggb + HD, G, 2 * HD, HD, grads + o.bet[l]);
+            float* dHout = l > 0 ? bufs[l & 1] : nullptr;
+            const int in_dim = l == 0 ? 2 : HD;
+            const float* Hin = l == 0 ? b->H0 : b->H[l];
+            const int grid = T < kWBlocks ? T : kWBlocks;
+            auto kern = precision == GCIN_FP32 ? bwd_b_kernel<false> : bwd_b_kernel<true>;
+            kern<<<grid, NT, 0, st>>>(T, b->d_tile_graph, b->d_gend, b->Y[l], b->mu[l], b->rstd[l], b->gmean, b->dxh,
+                                      Hin, in_dim, P + o.convW[l], dHout, b->wpart, b->bpart);
+            reduce_parts_f32_kernel<<<grid_of(in_dim * HD, 256), 256, 0, st>>>(b->wpart, grid, HD * HD, in_dim * HD,
+                                                                              grads + o.convW[l]);
+            reduce_parts_f64_kernel<<<1, HD, 0, st>>>(b->bpart, grid, HD, HD, grads + o.convb[l]);
+            dHn = dHout;
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_err(e, "gcin_backward");
+        return AMGG_OK;
+    });
+}
+
+extern "C" int gcin_tile_gemm_check(const float* A, const float* B, float* D_fp32, float* D_bf16, void* stream) {
+    if (!A || !B || !D_fp32 || !D_bf16) return amgg::fail(AMGG_EINVAL, "gcin_tile_gemm_check: null argument");
+    tile_gemm_check_kernel<<<1, NT, 0, static_cast<hipStream_t>(stream)>>>(A, B, D_fp32, D_bf16);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_err(e, "gcin_tile_gemm_check");
+    return AMGG_OK;
+}
+
+extern "C" size_t adam_scratch_bytes(void) { return sizeof(double) * (kAdamBlocks + 8); }
+
+extern "C" int adam_step(float* params, const float* grads, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                         float eps, int step, float clip, float* gnorm_out, void* scratch, void* stream) {
+    return amgg::guarded([&]() -> int {
+        if (!params || !grads || !m || !v || !scratch || n <= 0 || step < 1)
+            return amgg::fail(AMGG_EINVAL, "adam_step: bad argument");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        double* part = static_cast<double*>(scratch);
+        double* scal = part + kAdamBlocks;
+        sumsq_kernel<<<kAdamBlocks, NT, 0, st>>>(grads, n, part);
+        clipcoef_kernel<<<1, 1, 0, st>>>(part, clip, scal, gnorm_out);
+        const float bc1 = 1.0f - std::pow(b1, static_cast<float>(step));
+        const float bc2 = 1.0f - std::pow(b2, static_cast<float>(step));
+        adam_kernel<<<grid_of(n, 256), 256, 0, st>>>(params, grads, m, v, n, lr, b1, b2, eps, bc1, bc2, scal);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_err(e, "adam_step");
+        return AMGG_OK;
+    });
+}

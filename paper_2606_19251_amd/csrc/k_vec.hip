@@ -65,6 +65,11 @@ __global__ void cast_scaled_kernel(int32_t n, const double* __restrict__ x, cons
     if (i < n) y[i] = static_cast<float>(x[i] * scale[0]);
 }
 
+__global__ void cast_scale_kernel(int64_t n, const double* __restrict__ x, double scale, float* __restrict__ y) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < n) y[i] = static_cast<float>(x[i] * scale);
+}
+
 __global__ void cast_d2f_kernel(int32_t n, const double* __restrict__ x, float* __restrict__ y) {
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n) y[i] = static_cast<float>(x[i]);
@@ -237,6 +242,12 @@ hipError_t vec_zero_bytes(void* p, size_t bytes, hipStream_t stream) {
 hipError_t cast_scaled_f64_f32(int32_t n, const double* x, const double* scale, float* y, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     cast_scaled_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, x, scale, y);
+    return hipGetLastError();
+}
+
+hipError_t cast_scale_f64_f32(int64_t n, const double* x, double scale, float* y, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    cast_scale_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, x, scale, y);
     return hipGetLastError();
 }
 

@@ -54,6 +54,7 @@ hipError_t vec_zero_bytes(void* p, size_t bytes, hipStream_t stream);
 // y32 = (float)(x * scale[0]) ; scale on device
 hipError_t cast_scaled_f64_f32(int32_t n, const double* x, const double* scale, float* y, hipStream_t stream);
 hipError_t cast_f64_f32(int32_t n, const double* x, float* y, hipStream_t stream);
+hipError_t cast_scale_f64_f32(int64_t n, const double* x, double scale, float* y, hipStream_t stream);
 hipError_t cast_f32_f64(int32_t n, const float* x, double* y, hipStream_t stream);
 // y = x - mean, mean = sum/n from a device scalar sum
 hipError_t sub_mean(int32_t n, const double* x, const double* sum, double* y, hipStream_t stream);
