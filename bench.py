@@ -174,7 +174,6 @@ def main():
     if os.path.exists(weights):
         from paper_2606_19251_amd import gcin as G
 
-        t0 = time.time()
         pred = G.Predictor.load(weights, dev)
         torch.cuda.synchronize()
         s = torch.cuda.Event(enable_timing=True)

@@ -8,6 +8,9 @@
 
 namespace amgg {
 
+// Rows with at most this many lanes' worth of entries on average use the CSR-stream kernel.
+int kStreamMaxLanes = 8;
+
 int lanes_for(int32_t nrows, int32_t nnz) {
     if (nrows <= 0) return 1;
     const double avg = static_cast<double>(nnz) / nrows;
@@ -55,10 +58,62 @@ __global__ __launch_bounds__(kBlock) void csr_rows_kernel(int32_t nrows, const i
     }
 }
 
+// CSR-stream variant for short rows: a workgroup owns kStreamRows consecutive rows; its
+// threads walk the rows' contiguous nonzeros with unit stride (fully coalesced value and
+// column streams), leave the products a_ij x_j in LDS, and each thread then sums its own
+// row's products in order. Blocks whose nonzeros exceed the LDS capacity fall back to a
+// per-thread row loop from global memory.
+constexpr int kStreamRows = kBlock;
+constexpr int kStreamCap = 2048;
+
+template <typename T, Epi E>
+__global__ __launch_bounds__(kBlock) void csr_stream_kernel(int32_t nrows, const int32_t* __restrict__ ptr,
+                                                           const int32_t* __restrict__ col,
+                                                           const T* __restrict__ val, const T* __restrict__ x,
+                                                           T* __restrict__ y, const T* __restrict__ f,
+                                                           const T* __restrict__ qd, const T* __restrict__ u) {
+    __shared__ T prod[kStreamCap];
+    const int32_t r0 = blockIdx.x * kStreamRows;
+    const int32_t r1 = min(r0 + kStreamRows, nrows);
+    const int32_t e0 = ptr[r0];
+    const int32_t ne = ptr[r1] - e0;
+    const int32_t row = r0 + threadIdx.x;
+    T s = T(0);
+    if (ne <= kStreamCap) {
+        for (int32_t k = threadIdx.x; k < ne; k += kBlock) prod[k] = val[e0 + k] * x[col[e0 + k]];
+        __syncthreads();
+        if (row < r1) {
+            const int32_t end = ptr[row + 1] - e0;
+            for (int32_t k = ptr[row] - e0; k < end; ++k) s += prod[k];
+        }
+    } else if (row < r1) {
+        const int32_t end = ptr[row + 1];
+        for (int32_t k = ptr[row]; k < end; ++k) s += val[k] * x[col[k]];
+    }
+    if (row < r1) {
+        if constexpr (E == Epi::Store) {
+            y[row] = s;
+        } else if constexpr (E == Epi::Resid) {
+            y[row] = f[row] - s;
+        } else if constexpr (E == Epi::Add) {
+            y[row] += s;
+        } else if constexpr (E == Epi::Sub) {
+            y[row] -= s;
+        } else {
+            y[row] = u[row] + qd[row] * (f[row] - s);
+        }
+    }
+}
+
 template <typename T, Epi E>
 hipError_t launch_rows(const CsrView& m, const T* val, const T* x, T* y, const T* f, const T* qd, const T* u,
                        hipStream_t stream) {
     if (m.nrows <= 0) return hipSuccess;
+    if (m.lanes <= kStreamMaxLanes) {
+        const dim3 grid(static_cast<unsigned>((m.nrows + kStreamRows - 1) / kStreamRows));
+        csr_stream_kernel<T, E><<<grid, kBlock, 0, stream>>>(m.nrows, m.ptr, m.col, val, x, y, f, qd, u);
+        return hipGetLastError();
+    }
     const int64_t threads = static_cast<int64_t>(m.nrows) * m.lanes;
     const dim3 grid(static_cast<unsigned>((threads + kBlock - 1) / kBlock));
     switch (m.lanes) {

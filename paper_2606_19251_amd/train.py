@@ -1,0 +1,119 @@
+"""Train the GCIN smoother-coefficient predictor on the GPU (Alg. 1 of the paper).
+
+Training problems are P1 Laplacians on Delaunay meshes of Gaussian-mixture-clustered points
+(2k-16k nodes each, all levels of all meshes of a mini-batch in one GCIN launch). Each step:
+batched GCIN forward, per-problem smoother assembly and nvc V(1,1) cycles from u = 0 with a
+fresh uniform random zero-mean right-hand side, residual-reduction loss (Sec. 3.3, Eq. 11;
+the multi-cycle form when nvc > 1), hand-written adjoint, GCIN backward, clipping at 1.0 and
+Adam (App. B.1, Tab. 7). Every `--val-every` steps the validation metric of Eq. 13 (loss
+relative to omega-Jacobi on held-out meshes) is evaluated and the best parameters are kept
+(the paper's early stopping on the best validation model).
+
+    python -m paper_2606_19251_amd.train --out weights.npz --steps 300
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def build_problems(seed0, count, lo, hi, device, max_coarse=100):
+    import torch
+
+    import workloads as W
+    from .solver import DeviceSolver, HostHierarchy
+
+    rng = np.random.default_rng(seed0)
+    sizes = rng.integers(lo, hi + 1, size=count)
+    out = []
+    for k, npts in enumerate(sizes):
+        A = W.delaunay_p1(W.gmm_points(int(npts), seed0 * 1000 + k))
+        hh = HostHierarchy.build(A.rowptr, A.col, A.val, max_coarse=max_coarse)
+        out.append(DeviceSolver(hh, device.index or 0))
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--degree", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--train-meshes", type=int, default=64)
+    ap.add_argument("--val-meshes", type=int, default=8)
+    ap.add_argument("--nvc", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--val-every", type=int, default=25)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args(argv)
+
+    import torch
+
+    import workloads as W
+    from . import capi
+    from . import gcin as G
+
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    train = build_problems(100 + args.seed, args.train_meshes, 2000, 16000, dev)
+    val = build_problems(900 + args.seed, args.val_meshes, 2000, 16000, dev)
+    print(f"[train] {len(train)} training and {len(val)} validation meshes built in {time.time() - t0:.1f} s", flush=True)
+    rng = np.random.default_rng(args.seed)
+
+    def rhs_for(problems, seed):
+        r = np.random.default_rng(seed)
+        return [torch.from_numpy(W.rhs_uniform(ds.n, int(r.integers(1 << 30)), zero_mean=True)).to(dev) for ds in problems]
+
+    pred = G.Predictor(G.init_flat(args.degree, args.seed), dev, args.degree, capi.GCIN_BF16X3)
+    nb = max(1, len(train) // args.batch)
+    trainers = [G.Trainer(train[b * args.batch:(b + 1) * args.batch], rhs_for(train[b * args.batch:(b + 1) * args.batch], b),
+                          pred, lr=args.lr, nvc=args.nvc) for b in range(nb)]
+    # one optimizer state shared by all mini-batches
+    for tr in trainers[1:]:
+        tr.m, tr.v = trainers[0].m, trainers[0].v
+    val_rhs = rhs_for(val, 12345)
+    val_tr = G.Trainer(val, val_rhs, pred, nvc=args.nvc)
+    jac = torch.zeros(len(val), dtype=torch.float64, device=dev)
+    dc = torch.zeros(16, 2 * args.degree + 1, dtype=torch.float64, device=dev)
+    for p, ds in enumerate(val):
+        ds.set_jacobi(2.0 / 3.0)
+        capi.amgg_vcycle_loss_adjoint(ds.ctx, 1, 1, 32, args.nvc, val_rhs[p].data_ptr(), 0, jac[p:p + 1].data_ptr(),
+                                      dc.data_ptr(), val_tr.batch.stream)
+
+    def validate():
+        val_tr.loss_and_grad()
+        return float((val_tr.losses - jac).mean())  # Eq. 13: log10(||r|| / ||r_Jacobi||), mean over meshes
+
+    best = validate()
+    best_flat = pred.params.cpu().numpy().copy()
+    history = [{"step": 0, "val": best}]
+    print(f"[train] step 0 val {best:+.4f}", flush=True)
+    step = 0
+    t0 = time.time()
+    while step < args.steps:
+        tr = trainers[step % nb]
+        tr.rhs = rhs_for(tr.solvers, int(rng.integers(1 << 30)))
+        tr.step_count = step
+        losses = tr.step()
+        step += 1
+        if step % args.val_every == 0 or step == args.steps:
+            v = validate()
+            rec = {"step": step, "loss": float(losses.mean()), "val": v, "gnorm": float(tr.gnorm.item()),
+                   "s": round(time.time() - t0, 1)}
+            history.append(rec)
+            print(f"[train] {json.dumps(rec)}", flush=True)
+            if v < best:
+                best = v
+                best_flat = pred.params.cpu().numpy().copy()
+    np.savez(args.out, params=best_flat, degree=np.int64(args.degree), nvc=np.int64(args.nvc),
+             history=json.dumps(history))
+    print(f"[train] best validation {best:+.4f}; saved {args.out}", flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
