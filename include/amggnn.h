@@ -193,6 +193,8 @@ typedef struct {
     double div_factor;    /* diverged if ||r|| > div_factor ||b||; <= 0 means 1e3 */
     double stag_ratio;    /* stagnated if ||r_k|| > stag_ratio ||r_{k-w}||; <= 0 means 0.99 */
     int stag_window;      /* w; <= 0 means 10 */
+    int graphs;           /* nonzero: replay each IR / flexible-CG iteration as one captured HIP
+                             graph (captured on first use per configuration, kept in the context) */
 } amgg_solve_opts;
 
 typedef struct {

@@ -46,7 +46,7 @@ class amgg_level_view(C.Structure):
 class amgg_solve_opts(C.Structure):
     _fields_ = [("outer", C.c_int), ("inner_precision", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("maxit", C.c_int), ("tol", C.c_double), ("fallback", C.c_int), ("div_factor", C.c_double),
-                ("stag_ratio", C.c_double), ("stag_window", C.c_int)]
+                ("stag_ratio", C.c_double), ("stag_window", C.c_int), ("graphs", C.c_int)]
 
 
 class amgg_solve_info(C.Structure):

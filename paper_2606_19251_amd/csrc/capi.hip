@@ -84,7 +84,7 @@ size_t layout(amgg_ctx* c, uintptr_t base) {
     }
     const size_t n0 = c->lv[0].n;
     c->scal = b.take<double>(kSlots);
-    c->partial = b.take<double>(kReduceBlocks);
+    c->partial = b.take<double>(std::max(kReduceBlocks, outer_partials(c->lv[0].n, c->lv[0].nnz)));
     c->partial2 = b.take<double>(2 * kReduceBlocks);
     c->flags = b.take<int32_t>(8);
     c->cursor = b.take<int32_t>(max_nc + 1);
@@ -188,7 +188,10 @@ extern "C" int amgg_create(amgg_ctx** out, int device, int nlevels) {
         auto* c = new amgg_ctx();
         c->device = device;
         c->nlevels = nlevels;
-        if ((e = hipSetDevice(device)) != hipSuccess || (e = hipHostMalloc(&c->host_scal, sizeof(double) * kSlots)) != hipSuccess) {
+        if ((e = hipSetDevice(device)) != hipSuccess ||
+            (e = hipHostMalloc(&c->host_scal, sizeof(double) * kSlots)) != hipSuccess ||
+            (e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+            if (c->host_scal) (void)hipHostFree(c->host_scal);
             delete c;
             return hip_fail(e, "amgg_create");
         }
@@ -197,8 +200,15 @@ extern "C" int amgg_create(amgg_ctx** out, int device, int nlevels) {
     });
 }
 
+static void drop_graphs(amgg_ctx* c) {
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+}
+
 extern "C" int amgg_destroy(amgg_ctx* c) {
     if (!c) return AMGG_OK;
+    drop_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->host_scal) (void)hipHostFree(c->host_scal);
     delete c;
     return AMGG_OK;
@@ -280,6 +290,7 @@ extern "C" int amgg_finalize(amgg_ctx* c, int singular, void* workspace, size_t 
                                              std::to_string(need));
         hipError_t e = hipSetDevice(c->device);
         if (e != hipSuccess) return hip_fail(e, "amgg_finalize");
+        drop_graphs(c);
         layout(c, reinterpret_cast<uintptr_t>(workspace));
         c->ws = workspace;
         c->ws_bytes = ws_bytes;

@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 #include <type_traits>
+#include <vector>
 
 #include "amggnn.h"
 #include "kernels.hpp"
@@ -91,6 +93,12 @@ struct amgg_ctx {
     void* ws = nullptr;
     size_t ws_bytes = 0;
     double* host_scal = nullptr;  // pinned host copy of the device scalars
+    hipStream_t cap_stream = nullptr;  // private stream for graph capture
+    struct Graph {
+        std::string key;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;  // captured outer-iteration bodies
     // workspace
     double* scal = nullptr;
     double* partial = nullptr;

@@ -28,11 +28,11 @@ __device__ __forceinline__ void block_partial(double v, double* partial) {
     }
 }
 
-// Sum of kReduceBlocks partials by one workgroup, in a fixed order.
-__device__ __forceinline__ double sum_partials(const double* partial) {
+// Sum of `count` partials by one workgroup, in a fixed order.
+__device__ __forceinline__ double sum_partials(const double* partial, int count = kReduceBlocks) {
     __shared__ double red[kBlock];
     double v = 0.0;
-    for (int k = threadIdx.x; k < kReduceBlocks; k += kBlock) v += partial[k];
+    for (int k = threadIdx.x; k < count; k += kBlock) v += partial[k];
     red[threadIdx.x] = v;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
@@ -107,9 +107,9 @@ __global__ __launch_bounds__(kBlock) void finish_sum_kernel(const double* __rest
     if (threadIdx.x == 0) out[0] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void fcg_finish_pq_kernel(const double* __restrict__ partial,
+__global__ __launch_bounds__(kBlock) void fcg_finish_pq_kernel(const double* __restrict__ partial, int count,
                                                               double* __restrict__ s) {
-    const double pq = sum_partials(partial);
+    const double pq = sum_partials(partial, count);
     if (threadIdx.x == 0) {
         s[kPQ] = pq;
         if (!(pq > 0.0)) s[kFlag] = 1.0;
@@ -135,9 +135,9 @@ __global__ __launch_bounds__(kBlock) void fcg_update_xr_kernel(int32_t n, double
     block_partial(v, partial);
 }
 
-__global__ __launch_bounds__(kBlock) void fcg_finish_rr_kernel(const double* __restrict__ partial,
+__global__ __launch_bounds__(kBlock) void fcg_finish_rr_kernel(const double* __restrict__ partial, int count,
                                                               double* __restrict__ s) {
-    const double rr = sum_partials(partial);
+    const double rr = sum_partials(partial, count);
     if (threadIdx.x == 0) {
         s[kRR] = rr;
         const double nrm = sqrt(rr);
@@ -284,8 +284,8 @@ hipError_t finish_sum(const double* partial, double* out, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t fcg_finish_pq(const double* partial, double* s, hipStream_t stream) {
-    fcg_finish_pq_kernel<<<1, kBlock, 0, stream>>>(partial, s);
+hipError_t fcg_finish_pq(const double* partial, int count, double* s, hipStream_t stream) {
+    fcg_finish_pq_kernel<<<1, kBlock, 0, stream>>>(partial, count, s);
     return hipGetLastError();
 }
 
@@ -295,8 +295,8 @@ hipError_t fcg_update_xr(int32_t n, double* x, const double* p, const double* r,
     return hipGetLastError();
 }
 
-hipError_t fcg_finish_rr(const double* partial, double* s, hipStream_t stream) {
-    fcg_finish_rr_kernel<<<1, kBlock, 0, stream>>>(partial, s);
+hipError_t fcg_finish_rr(const double* partial, int count, double* s, hipStream_t stream) {
+    fcg_finish_rr_kernel<<<1, kBlock, 0, stream>>>(partial, count, s);
     return hipGetLastError();
 }
 

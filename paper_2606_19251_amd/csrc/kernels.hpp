@@ -36,12 +36,14 @@ template <typename T>
 hipError_t csr_apply(const CsrView& m, const T* val, const T* x, T* y, const T* f, const T* qd, const T* u,
                      Epi epi, hipStream_t stream);
 
-// q = A p and per-block partial sums of p_i q_i (FP64 outer loop).
-hipError_t csr_spmv_dot(const CsrView& m, const double* val, const double* p, double* q, double* partial,
+// q = A p and per-workgroup partial sums of p_i q_i (FP64 outer loop); *count = partials written.
+hipError_t csr_spmv_dot(const CsrView& m, const double* val, const double* p, double* q, double* partial, int* count,
                         hipStream_t stream);
-// r = b - A x and per-block partial sums of r_i^2.
+// r = b - A x and per-workgroup partial sums of r_i^2; *count = partials written.
 hipError_t csr_resid_norm(const CsrView& m, const double* val, const double* x, const double* b, double* r,
-                          double* partial, hipStream_t stream);
+                          double* partial, int* count, hipStream_t stream);
+// Number of partial sums the two calls above write for a matrix of this shape.
+int outer_partials(int32_t nrows, int32_t nnz);
 
 // ---------------------------------------------------------------------------------------
 // Vector kernels
@@ -63,7 +65,7 @@ hipError_t sub_mean(int32_t n, const double* x, const double* sum, double* y, hi
 hipError_t partial_dot(int32_t n, const double* a, const double* b, double* partial, hipStream_t stream);
 hipError_t partial_sum(int32_t n, const double* a, double* partial, hipStream_t stream);
 // final: scalars[out] = sum(partial[0..kReduceBlocks))
-hipError_t finish_sum(const double* partial, double* out, hipStream_t stream);
+hipError_t finish_sum(const double* partial, double* out, hipStream_t stream);  // kReduceBlocks partials
 
 // FCG pieces; s = device scalars (see fcg_slot)
 enum FcgSlot : int {
@@ -81,10 +83,10 @@ enum FcgSlot : int {
     kFlag = 11,   // breakdown flag (1.0 = breakdown)
     kSlots = 16
 };
-hipError_t fcg_finish_pq(const double* partial, double* s, hipStream_t stream);       // pq, alpha = gamma/pq
+hipError_t fcg_finish_pq(const double* partial, int count, double* s, hipStream_t stream);  // pq, alpha = gamma/pq
 hipError_t fcg_update_xr(int32_t n, double* x, const double* p, const double* r, const double* q, double* rnew,
                          const double* s, double* partial, hipStream_t stream);      // x += a p ; rnew = r - a q
-hipError_t fcg_finish_rr(const double* partial, double* s, hipStream_t stream);       // rr, norm, invnorm
+hipError_t fcg_finish_rr(const double* partial, int count, double* s, hipStream_t stream);  // rr, norm, invnorm
 // z = (double)u32 * norm and partials of z.rnew, z.rold (2 * kReduceBlocks)
 hipError_t fcg_castback_dots(int32_t n, const float* u32, const double* s, const double* rnew, const double* rold,
                              double* z, double* partial2, hipStream_t stream);

@@ -1,12 +1,17 @@
 // Outer FP64 loops around the V-cycle (paper Sec. 4: V-cycles iterated until the
-// relative residual reaches the tolerance, at most 500 iterations; Sec. 3.4 and App. B:
-// FP32 training and tests on unstructured meshes, FP64 where FP32 stagnates):
+// relative residual reaches the tolerance, at most 500 iterations; Sec. 4.2: FP32 on the
+// unstructured sets, FP64 where FP32 stagnates):
 //   * stationary  u <- V(u, f)                              (FP64 cycle)
 //   * iterative refinement  x <- x + V(0, b - A x)          (FP64 residual, FP32/FP64 cycle)
 //   * flexible CG with z = V(0, r) as preconditioner        (FP64 vectors, FP32/FP64 cycle)
 // The FP32 cycle receives r / ||r|| so that its input is O(1) whatever the residual
 // level; the correction is scaled back in FP64. Scalars live on the device; the host
 // reads one small block of them per iteration to decide on convergence.
+//
+// One outer iteration of IR or flexible CG is a fixed sequence of ~50 kernels (most of
+// them on small coarse levels, where launch latency dominates). With opts.graphs the
+// sequence is captured once per configuration into a HIP graph on the context's private
+// stream and replayed on the caller's stream, one graph launch per iteration.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -24,20 +29,17 @@ namespace {
 
 struct Runner {
     amgg_ctx* c;
-    hipStream_t st;
     int nu1, nu2, prec;
     hipError_t e = hipSuccess;
-    int vcycles = 0;
 
     void ok(hipError_t r) {
         if (r != hipSuccess && e == hipSuccess) e = r;
     }
 
-    // z = V(0, r) on the fine level; returns the device pointer holding z (FP64).
-    // For FP32 the FCG variant also forms the dots z.r_new, z.r_old in the cast-back pass.
-    const double* precondition(const double* r, double* zbuf) {
+    // z = V(0, r) on the fine level. FP64: returns the pointer holding z. FP32: the cycle's
+    // FP32 result pointer is left in `last32` (the caller casts it back, scaled by ||r||).
+    const double* precondition(const double* r, hipStream_t st) {
         Level& L0 = c->lv[0];
-        ++vcycles;
         if (prec == 64) {
             double* res = nullptr;
             ok(vcycle_level<double>(c, 0, r, L0.u64, L0.t64, true, nu1, nu2, st, &res));
@@ -47,12 +49,47 @@ struct Runner {
         ok(cast_scaled_f64_f32(L0.n, r, c->scal + kInvNorm, L0.f32, st));
         ok(vcycle_level<float>(c, 0, L0.f32, L0.u32, L0.t32, true, nu1, nu2, st, &res));
         last32 = res;
-        (void)zbuf;
         return nullptr;
     }
     float* last32 = nullptr;
 
-    bool read_scalars() {
+    // Flexible CG: precondition the latest residual `cur` (prev = the one before, unused on a
+    // (re)start), update p, then q = A p, alpha, x += alpha p, and the next residual into `prev`.
+    void fcg_iteration(bool first, double* x, double* cur, double* prev, hipStream_t st) {
+        Level& L0 = c->lv[0];
+        const int32_t n = L0.n;
+        double* s = c->scal;
+        const double* z = precondition(cur, st);
+        if (prec == 32) {
+            ok(fcg_castback_dots(n, last32, s, cur, first ? nullptr : prev, c->z, c->partial2, st));
+            z = c->z;
+        } else {
+            ok(fcg_dots64(n, z, cur, first ? nullptr : prev, c->partial2, st));
+        }
+        ok(fcg_finish_beta(c->partial2, s, first ? 1 : 0, st));
+        ok(fcg_update_p(n, z, c->p, s, first ? 1 : 0, st));
+        int cnt = 0;
+        ok(csr_spmv_dot(L0.A(), L0.val, c->p, c->q, c->partial, &cnt, st));
+        ok(fcg_finish_pq(c->partial, cnt, s, st));
+        ok(fcg_update_xr(n, x, c->p, cur, c->q, prev, s, c->partial, st));
+        ok(fcg_finish_rr(c->partial, kReduceBlocks, s, st));
+    }
+
+    // Iterative refinement: x += V(0, r); r = b - A x.
+    void ir_iteration(double* x, const double* bb, double* r, hipStream_t st) {
+        Level& L0 = c->lv[0];
+        const int32_t n = L0.n;
+        const double* e64 = precondition(r, st);
+        if (prec == 64)
+            ok(ir_update_f64(n, x, e64, st));
+        else
+            ok(ir_update_f32(n, x, last32, c->scal, st));
+        int cnt = 0;
+        ok(csr_resid_norm(L0.A(), L0.val, x, bb, r, c->partial, &cnt, st));
+        ok(fcg_finish_rr(c->partial, cnt, c->scal, st));
+    }
+
+    bool read_scalars(hipStream_t st) {
         ok(hipMemcpyAsync(c->host_scal, c->scal, sizeof(double) * kSlots, hipMemcpyDeviceToHost, st));
         ok(hipStreamSynchronize(st));
         return e == hipSuccess;
@@ -61,6 +98,44 @@ struct Runner {
 
 void set_all_jacobi(amgg_ctx* c, hipStream_t st) {
     for (int l = 0; l + 1 < c->nlevels; ++l) amgg_set_smoother_jacobi(c, l, 2.0 / 3.0, st);
+}
+
+std::string graph_key(const amgg_ctx* c, const char* what, int prec, int nu1, int nu2, const void* a, const void* b,
+                      const void* d) {
+    std::string k = std::string(what) + ":" + std::to_string(prec) + ":" + std::to_string(nu1) + ":" +
+                    std::to_string(nu2) + ":" + std::to_string(reinterpret_cast<uintptr_t>(a)) + ":" +
+                    std::to_string(reinterpret_cast<uintptr_t>(b)) + ":" +
+                    std::to_string(reinterpret_cast<uintptr_t>(d)) + ":";
+    for (int l = 0; l + 1 < c->nlevels; ++l) k += static_cast<char>('0' + c->lv[l].smoother);
+    return k;
+}
+
+// Run `body(stream)` either directly on `st` or through a cached graph captured on the
+// context's private stream.
+template <class F>
+hipError_t run_body(amgg_ctx* c, bool use_graph, const std::string& key, hipStream_t st, Runner& R, F&& body) {
+    if (!use_graph) {
+        body(st);
+        return R.e;
+    }
+    for (auto& g : c->graphs)
+        if (g.key == key) return hipGraphLaunch(g.exec, st);
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    body(c->cap_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (R.e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return R.e;
+    }
+    if (e != hipSuccess) return e;
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    c->graphs.push_back({key, exec});
+    return hipGraphLaunch(exec, st);
 }
 
 }  // namespace
@@ -82,15 +157,17 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
         const double div_factor = o->div_factor > 0 ? o->div_factor : 1e3;
         const double stag_ratio = o->stag_ratio > 0 ? o->stag_ratio : 0.99;
         const int stag_window = o->stag_window > 0 ? o->stag_window : 10;
+        const bool use_graph = o->graphs != 0 && o->outer != AMGG_OUTER_STATIONARY;
 
         hipStream_t st = static_cast<hipStream_t>(stream);
-        Runner R{c, st, o->nu1, o->nu2, o->inner_precision};
+        Runner R{c, o->nu1, o->nu2, o->inner_precision};
         R.ok(hipSetDevice(c->device));
         Level& L0 = c->lv[0];
         const int32_t n = L0.n;
         const CsrView A = L0.A();
         double* s = c->scal;
         double* hs = c->host_scal;
+        int vcycles = 0;
 
         // right-hand side, projected to zero mean for a singular (all-Neumann) hierarchy
         const double* bb = b;
@@ -104,8 +181,8 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
         R.ok(vec_zero_bytes(x, sizeof(double) * n, st));
         R.ok(vec_copy<double>(n, bb, c->ra, st));
         R.ok(partial_dot(n, bb, bb, c->partial, st));
-        R.ok(fcg_finish_rr(c->partial, s, st));
-        if (!R.read_scalars()) return hip_fail(R.e, "amgg_solve");
+        R.ok(fcg_finish_rr(c->partial, kReduceBlocks, s, st));
+        if (!R.read_scalars(st)) return hip_fail(R.e, "amgg_solve");
         const double nb = std::sqrt(hs[kRR]);
         std::vector<double> hist{1.0};
         amgg_solve_info inf{};
@@ -113,7 +190,7 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
             inf.status = status;
             inf.relres = rel;
             inf.iterations = iters;
-            inf.vcycles = R.vcycles;
+            inf.vcycles = vcycles;
             if (info) *info = inf;
             if (history)
                 for (int k = 0; k < history_cap && k < static_cast<int>(hist.size()); ++k) history[k] = hist[k];
@@ -122,59 +199,44 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
         if (!std::isfinite(nb)) return fail(AMGG_ENONFINITE, "amgg_solve: non-finite right-hand side");
         if (nb == 0.0) return finish(0, 0.0, 0);
 
-        double* r = c->ra;   // current residual
-        double* rn = c->rb;  // next residual
-        bool first = true;   // (re)start of the Krylov recurrence
+        double* cur = c->ra;   // latest residual
+        double* prev = c->rb;  // the one before (flexible CG)
+        bool first = true;     // (re)start of the recurrence
         size_t stag_base = 0;  // stagnation is judged on the history since the last (re)start
         int k = 0;
         for (;;) {
             // ---- one outer iteration ------------------------------------------------
             int outcome = 0;
+            hipError_t e = hipSuccess;
             if (o->outer == AMGG_OUTER_STATIONARY) {
                 double* res = nullptr;
                 R.ok(vec_copy<double>(n, x, L0.u64, st));
-                ++R.vcycles;
                 R.ok(vcycle_level<double>(c, 0, bb, L0.u64, L0.t64, first, o->nu1, o->nu2, st, &res));
                 R.ok(vec_copy<double>(n, res, x, st));
-                R.ok(csr_resid_norm(A, L0.val, x, bb, r, c->partial, st));
-                R.ok(fcg_finish_rr(c->partial, s, st));
-                first = false;
+                int cnt = 0;
+                R.ok(csr_resid_norm(A, L0.val, x, bb, cur, c->partial, &cnt, st));
+                R.ok(fcg_finish_rr(c->partial, cnt, s, st));
+                e = R.e;
             } else if (o->outer == AMGG_OUTER_IR) {
-                const double* e64 = R.precondition(r, nullptr);
-                if (R.prec == 64)
-                    R.ok(ir_update_f64(n, x, e64, st));
-                else
-                    R.ok(ir_update_f32(n, x, R.last32, s, st));
-                R.ok(csr_resid_norm(A, L0.val, x, bb, r, c->partial, st));
-                R.ok(fcg_finish_rr(c->partial, s, st));
+                e = run_body(c, use_graph, graph_key(c, "ir", R.prec, o->nu1, o->nu2, x, bb, cur), st, R,
+                             [&](hipStream_t q) { R.ir_iteration(x, bb, cur, q); });
             } else {
-                if (first) {
-                    // z0 = M r0, p0 = z0, gamma = z0.r0
-                    const double* z = R.precondition(r, c->z);
-                    if (R.prec == 32) {
-                        R.ok(fcg_castback_dots(n, R.last32, s, r, nullptr, c->z, c->partial2, st));
-                        z = c->z;
-                    } else {
-                        R.ok(fcg_dots64(n, z, r, nullptr, c->partial2, st));
-                    }
-                    R.ok(fcg_finish_beta(c->partial2, s, 1, st));
-                    R.ok(fcg_update_p(n, z, c->p, s, 1, st));
-                    first = false;
-                }
-                R.ok(csr_spmv_dot(A, L0.val, c->p, c->q, c->partial, st));
-                R.ok(fcg_finish_pq(c->partial, s, st));
-                R.ok(fcg_update_xr(n, x, c->p, r, c->q, rn, s, c->partial, st));
-                R.ok(fcg_finish_rr(c->partial, s, st));
+                double* cu = cur;
+                double* pv = prev;
+                const bool f0 = first;
+                e = run_body(c, use_graph, graph_key(c, f0 ? "fcg0" : "fcg", R.prec, o->nu1, o->nu2, x, cu, pv), st,
+                             R, [&](hipStream_t q) { R.fcg_iteration(f0, x, cu, pv, q); });
+                std::swap(cur, prev);
             }
+            first = false;
+            ++vcycles;
             ++k;
-            if (!R.read_scalars()) return hip_fail(R.e, "amgg_solve");
+            if (e != hipSuccess) return hip_fail(e, "amgg_solve");
+            if (!R.read_scalars(st)) return hip_fail(R.e, "amgg_solve");
             const double rel = std::sqrt(hs[kRR]) / nb;
             hist.push_back(rel);
             const bool breakdown = hs[kFlag] != 0.0;
-            if (rel <= o->tol && std::isfinite(rel) && !breakdown) {
-                if (o->outer == AMGG_OUTER_FCG) std::swap(r, rn);
-                return finish(0, rel, k);
-            }
+            if (rel <= o->tol && std::isfinite(rel) && !breakdown) return finish(0, rel, k);
             if (!std::isfinite(rel) || rel > div_factor)
                 outcome = AMGG_DIVERGED;
             else if (breakdown)
@@ -193,26 +255,13 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
                 set_all_jacobi(c, st);
                 R.ok(vec_zero_bytes(s + kFlag, sizeof(double), st));
                 if (!std::isfinite(rel)) R.ok(vec_zero_bytes(x, sizeof(double) * n, st));
-                R.ok(csr_resid_norm(A, L0.val, x, bb, c->ra, c->partial, st));
-                R.ok(fcg_finish_rr(c->partial, s, st));
-                r = c->ra;
-                rn = c->rb;
+                int cnt = 0;
+                R.ok(csr_resid_norm(A, L0.val, x, bb, c->ra, c->partial, &cnt, st));
+                R.ok(fcg_finish_rr(c->partial, cnt, s, st));
+                cur = c->ra;
+                prev = c->rb;
                 first = true;
                 stag_base = hist.size() - 1;
-                continue;
-            }
-            if (o->outer == AMGG_OUTER_FCG) {
-                // z = M r_new; beta = z.(r_new - r_old)/gamma; p = z + beta p
-                const double* z = R.precondition(rn, c->z);
-                if (R.prec == 32) {
-                    R.ok(fcg_castback_dots(n, R.last32, s, rn, r, c->z, c->partial2, st));
-                    z = c->z;
-                } else {
-                    R.ok(fcg_dots64(n, z, rn, r, c->partial2, st));
-                }
-                R.ok(fcg_finish_beta(c->partial2, s, 0, st));
-                R.ok(fcg_update_p(n, z, c->p, s, 0, st));
-                std::swap(r, rn);
             }
             if (R.e != hipSuccess) return hip_fail(R.e, "amgg_solve");
         }

@@ -145,11 +145,11 @@ class DeviceSolver:
         return u
 
     def solve(self, b, x=None, outer=capi.AMGG_OUTER_FCG, precision=32, nu1=1, nu2=1, tol=1e-8, maxit=500,
-              fallback=True, history_cap=0, div_factor=0.0, stag_ratio=0.0, stag_window=0):
+              fallback=True, history_cap=0, div_factor=0.0, stag_ratio=0.0, stag_window=0, graphs=True):
         if x is None:
             x = self.torch.empty_like(b)
         o = capi.amgg_solve_opts(outer, precision, nu1, nu2, maxit, tol, int(fallback), div_factor, stag_ratio,
-                                 stag_window)
+                                 stag_window, int(graphs))
         rc, info, hist = capi.amgg_solve(self.ctx, o, b.data_ptr(), x.data_ptr(), history_cap, self.stream)
         return x, rc, info, hist[: max(0, min(history_cap, info.iterations + 1))]
 

@@ -253,3 +253,25 @@ def test_single_level_is_direct_solve():
     ds.vcycle(_dev(f), u, 1, 1, 64)
     ref = sla.solve(amg.to_scipy(A).toarray(), f)
     assert np.linalg.norm(u.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("outer", ["fcg", "ir"])
+@pytest.mark.parametrize("cname", ["jacobi", "poly2"])
+def test_graph_replay_equals_direct_launches(outer, cname):
+    """Outer iterations replayed from captured HIP graphs give bitwise the same iterates as direct
+    launches, over several solves with eager work and synchronisation in between."""
+    from paper_2606_19251_amd import capi
+
+    A, f, ho, hp, ds = _setup("delaunay20k")
+    ds.set_coeffs(*COEFFS[cname])
+    om = capi.AMGG_OUTER_FCG if outer == "fcg" else capi.AMGG_OUTER_IR
+    for seed in range(3):
+        b = _dev(W.rhs_uniform(A.nrows, 50 + seed, zero_mean=True))
+        x1, rc1, i1, h1 = ds.solve(b, outer=om, precision=32, graphs=False, history_cap=600)
+        torch.cuda.synchronize()
+        _ = (b * 2).sum().item()  # unrelated eager work between replays
+        x2, rc2, i2, h2 = ds.solve(b, outer=om, precision=32, graphs=True, history_cap=600)
+        torch.cuda.synchronize()
+        assert rc1 == rc2 == 0 and i1.iterations == i2.iterations
+        assert torch.equal(x1, x2)
+        assert np.array_equal(h1, h2)
