@@ -2,7 +2,7 @@
 flexible CG, GCIN-smoothed vs Jacobi-smoothed AMG, on one MI355X.
 
 Workload (default): P1 finite-element Laplacian on the Delaunay triangulation of 1,000,000
-uniform random points in the unit square (+4 corners), all-Neumann (singular), zero-mean
+points in the unit square (uniform inside, evenly spaced on the boundary), all-Neumann (singular), zero-mean
 U[-1,1] right-hand side; Ruge-Stueben hierarchy (theta 0.25, <= 10 levels, coarsest <= 500
 rows); V(1,1) cycles. One step = one complete solve from x = 0 with the hierarchy, the
 smoother and the right-hand side resident in HBM (setup is reported separately).
@@ -65,6 +65,23 @@ def outer_bytes_fcg(n: int, nnz: int) -> float:
     return spmv_dot + update_xr + cast_in + castback + update_p
 
 
+# Calibrated FETCH_SIZE + WRITE_SIZE bytes per launch of the dominant kernel on the default
+# 1M workload (profiles/traffic_residual_c2_delaunay1M.md), valid only for the kernel source
+# it was measured on: reported as null once that source changes.
+TRAFFIC = {"bytes": 72808345, "npts": 1_000_000, "source": "paper_2606_19251_amd/csrc/k_csr.hip",
+           "sha256_16": "0053aaaa029d245a"}
+
+
+def measured_traffic(npts):
+    import hashlib
+
+    path = os.path.join(ROOT, TRAFFIC["source"])
+    sha = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    if npts != TRAFFIC["npts"] or sha != TRAFFIC["sha256_16"]:
+        return None
+    return TRAFFIC["bytes"]
+
+
 def time_kernel(torch, fn, reps=50):
     """Average duration of one launch of fn() on the current stream, by HIP events."""
     fn()
@@ -118,6 +135,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--npts", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only launch the dominant kernel and a calibration copy (for counter runs)")
     ap.add_argument("--nu", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -168,6 +187,26 @@ def main():
         log(f"{label}: {ms:.3f} ms/solve, {vc} V-cycles, {it} iterations, rc={rc}, rel={true_rel:.2e}")
         return {"ms": ms, "vcycles": vc, "iterations": it, "status": rc, "relres": true_rel}
 
+    if args.profile_kernels:
+        # counter runs: the dominant kernel alone, and a plain copy of known size to calibrate
+        # the byte counters (256 MiB read + 256 MiB written per copy)
+        ds.set_jacobi(2.0 / 3.0)
+        n0 = hh.levels[0].n
+        xs = torch.rand(n0, dtype=torch.float32, device=dev)
+        ys = torch.empty_like(xs)
+        fs = torch.rand(n0, dtype=torch.float32, device=dev)
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(10):
+            capi.amgg_level_apply(ds.ctx, 0, capi.AMGG_OP_RESIDUAL, 32, xs.data_ptr(), ys.data_ptr(), fs.data_ptr(),
+                                  ds.stream)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("profile-kernels: 10 fine-level residual launches, 10 copies of 256 MiB")
+        return
+
     jac = run_solves("jacobi", lambda: ds.set_jacobi(2.0 / 3.0))
     gnn = None  # filled in once a trained predictor is shipped (see below)
     weights = os.path.join(ROOT, "paper_2606_19251_amd", "weights", "gcin_deg2.npz")
@@ -205,9 +244,9 @@ def main():
                                                             ys.data_ptr(), fs.data_ptr(), st))
     k_bytes = z0 * 8 + 4 * (n0 + 1) + 3 * n0 * 4
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
-    roof = {"kernel": "csr_rows_kernel<float, 8, Resid> (fine level r = f - A u, FP32)",
+    roof = {"kernel": "csr_stream_kernel<float, Resid, 256, 0> (fine level r = f - A u, FP32)",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.npts),
             "launch_ms": round(k_ms, 5), "algorithmic_bytes": int(k_bytes)}
 
     out = {

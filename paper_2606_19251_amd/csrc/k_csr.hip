@@ -38,6 +38,17 @@ int stream_rows(int32_t nrows, int32_t nnz) {
     return 0;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on XCD b mod 8), each
+// with its own L2. Renumber them so that every XCD processes one contiguous range of row
+// blocks: neighbouring rows gather neighbouring x entries, which then stay in one L2.
+__device__ __forceinline__ int32_t xcd_block() {
+    constexpr int32_t kXcd = 8;
+    const int32_t b = blockIdx.x, g = gridDim.x;
+    const int32_t q = g / kXcd, r = g % kXcd;
+    const int32_t x = b % kXcd, k = b / kXcd;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 template <typename T, int LANES>
 __device__ __forceinline__ T group_sum(T s) {
 #pragma unroll
@@ -84,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void csr_stream_kernel(int32_t nrows, const
                                                            const T* __restrict__ qd, const T* __restrict__ u,
                                                            double* __restrict__ partial) {
     __shared__ T prod[kStreamCap];
-    const int32_t r0 = blockIdx.x * ROWS;
+    const int32_t r0 = xcd_block() * ROWS;
     const int32_t r1 = min(r0 + ROWS, nrows);
     const int32_t e0 = ptr[r0];
     const int32_t ne = ptr[r1] - e0;
@@ -92,7 +103,23 @@ __global__ __launch_bounds__(kBlock) void csr_stream_kernel(int32_t nrows, const
     const bool mine = threadIdx.x < ROWS && row < r1;
     T s = T(0);
     if (ne <= kStreamCap) {
-        for (int32_t k = threadIdx.x; k < ne; k += kBlock) prod[k] = val[e0 + k] * x[col[e0 + k]];
+        // all column/value loads of this thread first, then the gathers: more loads in flight
+        constexpr int kPer = kStreamCap / kBlock;
+        T v[kPer];
+        int32_t c[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int32_t k = threadIdx.x + q * kBlock;
+            if (k < ne) {
+                v[q] = val[e0 + k];
+                c[q] = col[e0 + k];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int32_t k = threadIdx.x + q * kBlock;
+            if (k < ne) prod[k] = v[q] * x[c[q]];
+        }
         __syncthreads();
         if (mine) {
             const int32_t end = ptr[row + 1] - e0;

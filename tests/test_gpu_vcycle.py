@@ -34,6 +34,12 @@ def _make(kind, seed=0):
     if kind == "gmm5k":
         A = W.delaunay_p1(W.gmm_points(5003, seed))
         return A, W.rhs_uniform(A.nrows, seed + 7, zero_mean=True), dict(max_levels=10, max_coarse=40)
+    if kind == "cmesh32k":
+        A, f = W.airfoil_cmesh_problem(256, 128, seed)
+        return A, f, dict(max_levels=10, max_coarse=200)
+    if kind == "tet30k":
+        A, f = W.tet_fv_problem(17, seed)
+        return A, f, dict(max_levels=10, max_coarse=100)
     if kind == "tiny":
         A = W.grid5(7)
         return A, W.rhs_uniform(49, seed), dict(max_levels=10, max_coarse=10)
@@ -70,7 +76,7 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x, np.float64)).cuda()
 
 
-@pytest.mark.parametrize("kind", ["grid64", "delaunay20k", "tiny"])
+@pytest.mark.parametrize("kind", ["grid64", "delaunay20k", "tiny", "cmesh32k", "tet30k"])
 def test_derived_hierarchy_bitexact(kind):
     A, f, ho, hp, ds = _setup(kind)
     torch.cuda.synchronize()
@@ -114,7 +120,7 @@ def test_smoother_values_bitexact(kind, cname):
         assert np.array_equal(_bits(v["q_val32"].cpu().numpy()), _bits(q.astype(np.float32)))
 
 
-@pytest.mark.parametrize("kind", ["grid64", "grid64_deep", "delaunay20k", "gmm5k", "tiny"])
+@pytest.mark.parametrize("kind", ["grid64", "grid64_deep", "delaunay20k", "gmm5k", "tiny", "cmesh32k", "tet30k"])
 @pytest.mark.parametrize("cname", ["jacobi", "poly2", "poly3"])
 @pytest.mark.parametrize("nu", [(1, 1), (2, 2), (0, 1), (1, 0)])
 def test_vcycle_fp64_matches_oracle(kind, cname, nu):
@@ -166,7 +172,7 @@ def test_stationary_fp64_same_cycle_count(seed):
     assert np.linalg.norm(xe - res.x) <= 1e-10 * np.linalg.norm(res.x)
 
 
-@pytest.mark.parametrize("kind", ["grid64", "delaunay20k", "gmm5k"])
+@pytest.mark.parametrize("kind", ["grid64", "delaunay20k", "gmm5k", "cmesh32k", "tet30k"])
 @pytest.mark.parametrize("outer", ["fcg", "ir"])
 @pytest.mark.parametrize("cname", ["jacobi", "poly2"])
 def test_fp32_cycle_fp64_outer_reaches_tolerance(kind, outer, cname):
@@ -275,3 +281,37 @@ def test_graph_replay_equals_direct_launches(outer, cname):
         assert rc1 == rc2 == 0 and i1.iterations == i2.iterations
         assert torch.equal(x1, x2)
         assert np.array_equal(h1, h2)
+
+
+@pytest.mark.parametrize("kind", ["grid64", "cmesh32k", "tet30k"])
+@pytest.mark.parametrize("cname", ["jacobi", "poly2"])
+def test_level_operators_bitexact(kind, cname):
+    """Every level pass sums each row in stored order with separately rounded products, as the
+    oracle's sparse products do: residual, smoothing, restriction and prolongation in FP64 are
+    bitwise equal to the oracle's."""
+    from paper_2606_19251_amd import capi
+
+    A, f, ho, hp, ds = _setup(kind)
+    c, deg = COEFFS[cname]
+    ds.set_coeffs(c, deg)
+    Qs = amg.smoothers(ho, c, deg)
+    rng = np.random.default_rng(3)
+    st = ds.stream
+    for l in range(ho.nlevels - 1):
+        L = ho.levels[l]
+        n, nc = L.A.shape[0], L.P.shape[1]
+        x, fl, y0 = rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(n)
+        xc = rng.standard_normal(nc)
+        cases = [
+            (capi.AMGG_OP_RESIDUAL, x, fl, None, fl - L.A @ x, n),
+            (capi.AMGG_OP_SMOOTH, x, None, y0, y0 + Qs[l] @ x, n),
+            (capi.AMGG_OP_RESTRICT, x, None, None, L.R @ x, nc),
+            (capi.AMGG_OP_PROLONG, xc, None, y0, y0 + L.P @ xc, n),
+        ]
+        for op, xin, fin, yin, ref, m in cases:
+            xd = _dev(xin)
+            fd = _dev(fin) if fin is not None else xd
+            yd = _dev(yin) if yin is not None else torch.zeros(m, dtype=torch.float64, device="cuda")
+            capi.amgg_level_apply(ds.ctx, l, op, 64, xd.data_ptr(), yd.data_ptr(), fd.data_ptr(), st)
+            torch.cuda.synchronize()
+            assert np.array_equal(_bits(yd.cpu().numpy()), _bits(ref)), (l, op)

@@ -202,6 +202,161 @@ def rhs_uniform(n: int, seed: int, zero_mean: bool = False) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------------------
+# Anisotropic 2D: finite-volume Poisson on a C-mesh around a NACA 4-digit airfoil
+# (stand-in for airfoil RANS meshes with highly stretched inflation layers)
+# --------------------------------------------------------------------------------------
+
+def naca4(code: str, x: np.ndarray):
+    """Upper and lower surface points of a NACA 4-digit section (chord 1) at stations x."""
+    m, p, t = int(code[0]) / 100.0, int(code[1]) / 10.0, int(code[2:]) / 100.0
+    yt = 5 * t * (0.2969 * np.sqrt(x) - 0.1260 * x - 0.3516 * x**2 + 0.2843 * x**3 - 0.1036 * x**4)
+    yc = np.where(x < p, m / p**2 * (2 * p * x - x**2), m / (1 - p) ** 2 * ((1 - 2 * p) + 2 * p * x - x**2))
+    dy = np.where(x < p, 2 * m / p**2 * (p - x), 2 * m / (1 - p) ** 2 * (p - x))
+    th = np.arctan(dy)
+    return (np.stack([x - yt * np.sin(th), yc + yt * np.cos(th)], 1),
+            np.stack([x + yt * np.sin(th), yc - yt * np.cos(th)], 1))
+
+
+def cmesh_nodes(ni: int, nj: int, code: str = "2412", aspect: float = 1e4, radius: float = 20.0, wake: float = 20.0):
+    """Node coordinates [(ni+1), (nj+1), 2] of an algebraic C-mesh.
+
+    i runs along the C: lower wake (downstream to trailing edge), lower surface, upper surface,
+    upper wake; j runs away from the wall with geometric stretching whose first cell has a
+    height of (mean wall spacing)/aspect, so wall cells reach the given aspect ratio.
+    """
+    nw = ni // 4                      # cells on each wake branch
+    na = ni - 2 * nw                  # cells around the airfoil
+    half = na // 2
+    beta = np.linspace(0.0, np.pi, half + 1)
+    xs = 0.5 * (1.0 - np.cos(beta))   # cosine clustering at both edges
+    up, lo = naca4(code, xs)
+    surf = np.concatenate([lo[::-1], up[1:]])                         # TE (lower) -> LE -> TE (upper)
+    surf = surf[: na + 1] if surf.shape[0] >= na + 1 else np.concatenate([surf, surf[-1:]])
+    te = 0.5 * (surf[0] + surf[-1])
+    g = np.geomspace(1e-3, 1.0, nw + 1) * wake                       # wake clustered at the trailing edge
+    wx = te[0] + np.concatenate([[0.0], g[1:]])
+    wake_lo = np.stack([wx[::-1], np.full(nw + 1, te[1])], 1)
+    wake_up = np.stack([wx, np.full(nw + 1, te[1])], 1)
+    curve = np.concatenate([wake_lo[:-1], surf, wake_up[1:]])        # ni + 1 points
+    tang = np.gradient(curve, axis=0)
+    tang /= np.linalg.norm(tang, axis=1, keepdims=True)
+    normal = np.stack([tang[:, 1], -tang[:, 0]], 1)                  # outward of the C
+    normal[: nw] = [0.0, -1.0]
+    normal[-nw:] = [0.0, 1.0]
+    ds = np.mean(np.linalg.norm(np.diff(surf, axis=0), axis=1))
+    h0 = ds / aspect
+    r = 1.0 + 1e-3
+    for _ in range(200):              # solve h0 (r^nj - 1)/(r - 1) = radius for the growth rate
+        r = (1.0 + radius * (r - 1.0) / h0) ** (1.0 / nj)
+    d = np.concatenate([[0.0], h0 * (r ** np.arange(1, nj + 1) - 1.0) / (r - 1.0)])
+    return curve[:, None, :] + d[None, :, None] * normal[:, None, :]
+
+
+def cmesh_fv(ni: int, nj: int, code: str = "2412", aspect: float = 1e4) -> CSRMatrix:
+    """Cell-centred finite-volume Poisson matrix on the C-mesh (two-point flux |face|/|c_i - c_j|).
+
+    Wall faces are Neumann; the outer C and the two downstream boundaries are Dirichlet p = 0
+    (their flux adds to the diagonal), so the matrix is SPD. Across the wake cut, cell (i, 0)
+    of the lower branch neighbours cell (ni-1-i, 0) of the upper branch.
+    """
+    X = cmesh_nodes(ni, nj, code, aspect)
+    C = 0.25 * (X[:-1, :-1] + X[1:, :-1] + X[:-1, 1:] + X[1:, 1:])  # cell centres [ni, nj, 2]
+    idx = np.arange(ni * nj).reshape(ni, nj)
+
+    def flux(face_a, face_b, ca, cb):
+        return np.linalg.norm(face_b - face_a, axis=-1) / np.linalg.norm(cb - ca, axis=-1)
+
+    ii, jj, ww = [], [], []
+    # i-direction neighbours: shared face between nodes (i+1, j) and (i+1, j+1)
+    w = flux(X[1:-1, :-1], X[1:-1, 1:], C[:-1], C[1:])
+    ii.append(idx[:-1].ravel()); jj.append(idx[1:].ravel()); ww.append(w.ravel())
+    # j-direction neighbours: shared face between nodes (i, j+1) and (i+1, j+1)
+    w = flux(X[:-1, 1:-1], X[1:, 1:-1], C[:, :-1], C[:, 1:])
+    ii.append(idx[:, :-1].ravel()); jj.append(idx[:, 1:].ravel()); ww.append(w.ravel())
+    # wake cut: lower-branch cell i and upper-branch cell ni-1-i share the j = 0 face
+    nw = ni // 4
+    lo_i = np.arange(nw)
+    up_i = ni - 1 - lo_i
+    w = np.linalg.norm(X[lo_i + 1, 0] - X[lo_i, 0], axis=-1) / np.linalg.norm(C[up_i, 0] - C[lo_i, 0], axis=-1)
+    ii.append(idx[lo_i, 0]); jj.append(idx[up_i, 0]); ww.append(w)
+    i_all = np.concatenate(ii)
+    j_all = np.concatenate(jj)
+    A = _laplacian_from_edges(np.minimum(i_all, j_all), np.maximum(i_all, j_all), np.concatenate(ww), ni * nj)
+    # Dirichlet outer boundary (j = nj - 1 north faces, i = 0 and i = ni - 1 end faces)
+    bd = np.zeros(ni * nj)
+    far = flux(X[:-1, -1], X[1:, -1], C[:, -1], 2 * 0.5 * (X[:-1, -1] + X[1:, -1]) - C[:, -1])
+    bd[idx[:, -1]] += far
+    for i_end, node in ((0, 0), (ni - 1, ni)):
+        mid = 0.5 * (X[node, :-1] + X[node, 1:])
+        bd[idx[i_end]] += flux(X[node, :-1], X[node, 1:], C[i_end], 2 * mid - C[i_end])
+    rowid = np.repeat(np.arange(ni * nj), np.diff(A.rowptr))
+    isd = A.col == rowid
+    A.val[isd] += bd[rowid[isd]]
+    return A
+
+
+def airfoil_cmesh_problem(ni: int = 4096, nj: int = 1024, seed: int = 0):
+    """C-mesh FV Poisson around NACA 2412 (wall aspect ratio 1e4), f ~ U[-1, 1]."""
+    A = cmesh_fv(ni, nj)
+    return A, rhs_uniform(A.nrows, seed + 3000)
+
+
+# --------------------------------------------------------------------------------------
+# 3D: finite-volume Poisson on a random tetrahedral mesh of the unit cube
+# --------------------------------------------------------------------------------------
+
+def jittered_lattice(m: int, seed: int, jitter: float = 0.3) -> np.ndarray:
+    """m^3 lattice points in the unit cube, interior points moved by U[-jitter h, jitter h]."""
+    h = 1.0 / (m - 1)
+    g = np.arange(m) * h
+    P = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    rng = np.random.default_rng(seed)
+    inner = np.all((P > 0.5 * h) & (P < 1 - 0.5 * h), axis=1)
+    P[inner] += rng.uniform(-jitter * h, jitter * h, size=(int(inner.sum()), 3))
+    return P
+
+
+def tet_fv(points: np.ndarray) -> CSRMatrix:
+    """Cell-centred FV Poisson matrix on the Delaunay tetrahedra of `points`: cells are tets,
+    face-neighbours couple with |face| / |centroid distance|; all-Neumann (zero row sums).
+    Cells are Morton ordered by centroid."""
+    from scipy.spatial import Delaunay
+
+    d = Delaunay(points)
+    tets = d.simplices.astype(np.int64)
+    cent = points[tets].mean(axis=1)
+    vol = np.abs(np.einsum("ij,ij->i", np.cross(points[tets[:, 1]] - points[tets[:, 0]],
+                                               points[tets[:, 2]] - points[tets[:, 0]]),
+                           points[tets[:, 3]] - points[tets[:, 0]])) / 6.0
+    keep = vol > 1e-12 * vol.max()       # drop flat slivers qhull may leave on the boundary
+    order = morton_order((cent - cent.min(0)) / (np.ptp(cent, 0) + 1e-300))
+    remap = -np.ones(tets.shape[0], np.int64)
+    kept = order[keep[order]]
+    remap[kept] = np.arange(kept.size)
+    nb = d.neighbors.astype(np.int64)
+    ii, jj, ww = [], [], []
+    for f in range(4):
+        other = nb[:, f]
+        ok = keep & (other >= 0) & (np.arange(tets.shape[0]) < np.where(other >= 0, other, 0))
+        ok &= np.where(other >= 0, keep[np.where(other >= 0, other, 0)], False)
+        a = np.nonzero(ok)[0]
+        b = other[a]
+        face = np.delete(tets[a], f, axis=1)  # the three vertices opposite vertex f
+        area = 0.5 * np.linalg.norm(np.cross(points[face[:, 1]] - points[face[:, 0]],
+                                             points[face[:, 2]] - points[face[:, 0]]), axis=1)
+        dist = np.linalg.norm(cent[a] - cent[b], axis=1)
+        ii.append(remap[a]); jj.append(remap[b]); ww.append(area / dist)
+    i_all, j_all = np.concatenate(ii), np.concatenate(jj)
+    return _laplacian_from_edges(np.minimum(i_all, j_all), np.maximum(i_all, j_all), np.concatenate(ww), kept.size)
+
+
+def tet_fv_problem(m: int, seed: int = 0):
+    """3D FV Poisson on the tetrahedra of an m^3 jittered lattice, zero-mean RHS."""
+    A = tet_fv(jittered_lattice(m, seed))
+    return A, rhs_uniform(A.nrows, seed + 4000, zero_mean=True)
+
+
+# --------------------------------------------------------------------------------------
 # Named workloads
 # --------------------------------------------------------------------------------------
 
