@@ -82,18 +82,22 @@ def measured_traffic(npts):
     return TRAFFIC["bytes"]
 
 
-def time_kernel(torch, fn, reps=50):
-    """Average duration of one launch of fn() on the current stream, by HIP events."""
-    fn()
+def time_kernel(torch, launch_timed, stream, reps=50):
+    """Average execution time (ms) of one kernel: each of `reps` back-to-back launches records its
+    own pair of HIP events at the kernel's start and end (launch_timed(start, stop)). Also returns
+    the average interval between launches of the same loop (kernel plus launch gap)."""
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for s, e in pairs:  # creates the events
+        s.record(stream)
+        e.record(stream)
+    launch_timed(pairs[0][0].cuda_event, pairs[0][1].cuda_event)  # warm-up
     torch.cuda.synchronize()
-    s = torch.cuda.Event(enable_timing=True)
-    e = torch.cuda.Event(enable_timing=True)
-    s.record()
-    for _ in range(reps):
-        fn()
-    e.record()
-    e.synchronize()
-    return s.elapsed_time(e) / reps  # ms
+    for s, e in pairs:
+        launch_timed(s.cuda_event, e.cuda_event)
+    torch.cuda.synchronize()
+    per = [s.elapsed_time(e) for s, e in pairs]
+    interval = pairs[0][0].elapsed_time(pairs[-1][1]) / reps
+    return sum(per) / reps, interval
 
 
 def cpu_baseline(A, f, gpu_iters, budget_s=20.0):
@@ -240,14 +244,17 @@ def main():
     ys = torch.empty_like(xs)
     fs = torch.rand(n0, dtype=torch.float32, device=dev)
     st = ds.stream
-    k_ms = time_kernel(torch, lambda: capi.amgg_level_apply(ds.ctx, 0, capi.AMGG_OP_RESIDUAL, 32, xs.data_ptr(),
-                                                            ys.data_ptr(), fs.data_ptr(), st))
+    k_ms, k_interval_ms = time_kernel(
+        torch, lambda s0, s1: capi.amgg_level_apply_timed(ds.ctx, 0, capi.AMGG_OP_RESIDUAL, 32, xs.data_ptr(),
+                                                          ys.data_ptr(), fs.data_ptr(), s0, s1, st),
+        torch.cuda.current_stream(dev))
     k_bytes = z0 * 8 + 4 * (n0 + 1) + 3 * n0 * 4
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
     roof = {"kernel": "csr_stream_kernel<float, Resid, 256, 0> (fine level r = f - A u, FP32)",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.npts),
-            "launch_ms": round(k_ms, 5), "algorithmic_bytes": int(k_bytes)}
+            "launch_ms": round(k_ms, 5), "launch_interval_ms": round(k_interval_ms, 5),
+            "algorithmic_bytes": int(k_bytes)}
 
     out = {
         "metric": METRIC,

@@ -127,6 +127,7 @@ typedef struct {
     const double* diag;      /* n */
     const double* scale;     /* 1 value: s_l */
     const double* coarse_inv;/* n*n row-major on the coarsest level, else NULL */
+    int32_t fused_rows;      /* rows per block of the fused smoothing kernels, 0 = not fused */
 } amgg_level_view;
 int amgg_level_view_get(const amgg_ctx* ctx, int lvl, amgg_level_view* out);
 
@@ -177,6 +178,20 @@ int amgg_vcycle(amgg_ctx* ctx, int nu1, int nu2, int precision, const double* f,
 #define AMGG_OP_COARSE 6
 int amgg_level_apply(amgg_ctx* ctx, int lvl, int op, int precision, const void* x, void* y, const void* f,
                      void* stream);
+/* Kernel fusion switch (diagnostics and tests). With enable = 1 (the default) the cycle
+ * fuses, on every level that admits it, the first pre-smoothing step from u = 0 with the
+ * residual after it, and each later smoothing step u <- u + Q^{-1}(f - A u) into one
+ * kernel (the residual of a row block and of its halo rows is kept in LDS). Every row sum
+ * keeps its order, so the results are bitwise the same as with enable = 0, where each
+ * operator is its own pass. Drops the captured solve graphs. */
+int amgg_set_fusion(amgg_ctx* ctx, int enable);
+
+/* The same operator, launched so that the kernel itself records start_event when it begins
+ * and stop_event when it ends (both hipEvent_t created by the caller with timing enabled;
+ * neither may be NULL): hipEventElapsedTime(start, stop) after completion is that kernel's
+ * own execution time, without queueing or launch gaps. Errors as amgg_level_apply. */
+int amgg_level_apply_timed(amgg_ctx* ctx, int lvl, int op, int precision, const void* x, void* y, const void* f,
+                           void* start_event, void* stop_event, void* stream);
 
 #define AMGG_OUTER_STATIONARY 0 /* u <- V(u, f) repeated (FP64 cycles only) */
 #define AMGG_OUTER_IR 1         /* x <- x + V(0, b - A x): iterative refinement, FP64 residual */

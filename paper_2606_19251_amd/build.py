@@ -40,7 +40,7 @@ HIP_SOURCES = {
     "adjoint.hip": [],
     "gcin.hip": [],
 }
-HOST_SOURCES = ["rs_setup.cpp", "errors.cpp"]
+HOST_SOURCES = ["rs_setup.cpp", "errors.cpp", "halo.cpp"]
 
 
 def _run(cmd):

@@ -14,6 +14,7 @@
 #include "amggnn.h"
 #include "ctx.hpp"
 #include "errors.hpp"
+#include "halo.hpp"
 #include "kernels.hpp"
 
 using namespace amgg;
@@ -72,6 +73,22 @@ size_t layout(amgg_ctx* c, uintptr_t base) {
             max_nc = std::max(max_nc, L.nc);
             L.dense = L.inv = nullptr;
             L.piv = nullptr;
+            const int rows = L.n <= kFuseMaxRows ? stream_rows_for(L.n, L.nnz) : 0;
+            if (rows > 0) {
+                const size_t nb = (n + rows - 1) / rows;
+                L.hoff = b.take<int32_t>(nb + 1);
+                L.halo = b.take<int32_t>(z);  // at most one halo row per stored entry
+                L.hend = b.take<uint16_t>(z);
+                L.heoff = b.take<int32_t>(nb + 1);
+                // flat halo-entry arrays; levels whose halos hold more entries are not fused
+                L.hent = b.take<int32_t>(z);
+                L.hcol = b.take<int32_t>(z);
+                L.ha64 = b.take<double>(z);
+                L.ha32 = b.take<float>(z);
+                L.hq64 = b.take<double>(z);
+                L.hq32 = b.take<float>(z);
+                L.hloc = b.take<uint16_t>(z);
+            }
         } else {
             L.dense = b.take<double>(n * n);
             L.inv = b.take<double>(n * n);
@@ -114,6 +131,11 @@ hipError_t smooth_step(Level& L, const T* f, T*& cur, T*& oth, T* r, bool from_z
         return e;
     }
     if (from_zero) return csr_apply<T>(A, L.qval<T>(), f, cur, nullptr, nullptr, nullptr, Epi::Store, st);
+    if (L.fuse && L.hrows > 0) {
+        e = smooth_post_fused<T>(A, L.H(), L.aval<T>(), L.hav<T>(), L.qval<T>(), f, cur, oth, st);
+        std::swap(cur, oth);
+        return e;
+    }
     if ((e = csr_apply<T>(A, L.aval<T>(), cur, r, f, nullptr, nullptr, Epi::Resid, st)) != hipSuccess) return e;
     return csr_apply<T>(A, L.qval<T>(), r, cur, nullptr, nullptr, nullptr, Epi::Add, st);
 }
@@ -132,11 +154,36 @@ hipError_t vcycle_level(amgg_ctx* c, int l, const T* f, T* u, T* t, bool zero, i
     T* cur = u;
     T* oth = t;
     T* r = L.r<T>();
-    for (int k = 0; k < nu1; ++k)
+    // The first pre-smoothing step from u = 0 is fused with the pass after it where the level
+    // allows (same values, one kernel fewer): diagonal smoother u = d f with the residual (or
+    // with the second step), sparse smoother u = Q f with the residual.
+    int k0 = 0;
+    bool have_r = false;
+    if (zero && nu1 >= 1 && L.fuse) {
+        if (L.smoother == kSmootherDiagonal) {
+            if (nu1 == 1) {
+                if ((e = jacobi_pre_resid<T>(L.A(), L.aval<T>(), L.qd<T>(), f, cur, r, st)) != hipSuccess) return e;
+                have_r = true;
+                k0 = 1;
+            } else if (stream_rows_for(L.n, L.nnz) > 0) {
+                if ((e = jacobi_pre_step<T>(L.A(), L.aval<T>(), L.qd<T>(), f, oth, st)) != hipSuccess) return e;
+                std::swap(cur, oth);
+                k0 = 2;
+            }
+        } else if (L.hrows > 0) {
+            if ((e = smooth_pre_fused<T>(L.A(), L.H(), L.aval<T>(), L.qval<T>(), L.hqv<T>(), f, cur, r, st)) != hipSuccess)
+                return e;
+            have_r = nu1 == 1;
+            k0 = 1;
+        }
+    }
+    for (int k = k0; k < nu1; ++k)
         if ((e = smooth_step<T>(L, f, cur, oth, r, zero && k == 0, st)) != hipSuccess) return e;
     const bool still_zero = zero && nu1 == 0;
     const T* res = f;
-    if (!still_zero) {
+    if (!still_zero && have_r) {
+        res = r;
+    } else if (!still_zero) {
         if ((e = csr_apply<T>(L.A(), L.aval<T>(), cur, r, f, nullptr, nullptr, Epi::Resid, st)) != hipSuccess)
             return e;
         res = r;
@@ -276,6 +323,45 @@ extern "C" int amgg_workspace_bytes(const amgg_ctx* c, size_t* bytes) {
     });
 }
 
+// Halo lists of every smoothing level for the fused kernels, built on the host from a copy of
+// the level's pattern (setup only).
+static hipError_t build_halos(amgg_ctx* c, hipStream_t st) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    std::vector<int32_t> ptr, col;
+    HaloLists h;
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        if (e == hipSuccess && bytes > 0) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    for (int l = 0; l + 1 < c->nlevels; ++l) {
+        Level& L = c->lv[l];
+        L.hrows = 0;
+        const int rows = L.n <= kFuseMaxRows ? stream_rows_for(L.n, L.nnz) : 0;
+        if (rows == 0 || L.hoff == nullptr) continue;
+        ptr.resize(static_cast<size_t>(L.n) + 1);
+        col.resize(static_cast<size_t>(L.nnz));
+        if ((e = hipMemcpy(ptr.data(), L.ptr, sizeof(int32_t) * ptr.size(), hipMemcpyDeviceToHost)) != hipSuccess ||
+            (e = hipMemcpy(col.data(), L.col, sizeof(int32_t) * col.size(), hipMemcpyDeviceToHost)) != hipSuccess)
+            return e;
+        if (!build_halo(L.n, ptr.data(), col.data(), rows, kHaloCap, kHaloEntCap, static_cast<size_t>(L.nnz), h))
+            continue;
+        up(L.hoff, h.hoff.data(), sizeof(int32_t) * h.hoff.size());
+        up(L.halo, h.halo.data(), sizeof(int32_t) * h.halo.size());
+        up(L.hend, h.hend.data(), sizeof(uint16_t) * h.hend.size());
+        up(L.heoff, h.heoff.data(), sizeof(int32_t) * h.heoff.size());
+        up(L.hent, h.hent.data(), sizeof(int32_t) * h.hent.size());
+        std::vector<int32_t> hc(h.hent.size());
+        for (size_t k = 0; k < hc.size(); ++k) hc[k] = col[h.hent[k]];
+        up(L.hcol, hc.data(), sizeof(int32_t) * hc.size());
+        up(L.hloc, h.loc.data(), sizeof(uint16_t) * h.loc.size());
+        if (e != hipSuccess) return e;
+        L.nhent = static_cast<int32_t>(h.hent.size());
+        if ((e = gather_values(L.nhent, L.hent, L.val, L.val32, L.ha64, L.ha32, st)) != hipSuccess) return e;
+        L.hrows = rows;
+    }
+    return hipSuccess;
+}
+
 extern "C" int amgg_finalize(amgg_ctx* c, int singular, void* workspace, size_t ws_bytes, void* stream) {
     return guarded([&]() -> int {
         if (!c) return fail(AMGG_EINVAL, "amgg_finalize: null context");
@@ -315,6 +401,7 @@ extern "C" int amgg_finalize(amgg_ctx* c, int singular, void* workspace, size_t 
         ok(dense_from_csr(Lc.n, Lc.ptr, Lc.col, Lc.val, Lc.dense, c->singular, st));
         ok(dense_lu_inverse(Lc.n, Lc.dense, Lc.piv, Lc.inv, c->flags + 1, st));
         if (e != hipSuccess) return hip_fail(e, "amgg_finalize (launch)");
+        if ((e = build_halos(c, st)) != hipSuccess) return hip_fail(e, "amgg_finalize (halo lists)");
         int32_t flags[2] = {0, 0};
         if ((e = hipMemcpyAsync(flags, c->flags, sizeof(flags), hipMemcpyDeviceToHost, st)) != hipSuccess ||
             (e = hipStreamSynchronize(st)) != hipSuccess)
@@ -324,6 +411,13 @@ extern "C" int amgg_finalize(amgg_ctx* c, int singular, void* workspace, size_t 
         c->finalized = true;
         return AMGG_OK;
     });
+}
+
+extern "C" int amgg_set_fusion(amgg_ctx* c, int enable) {
+    if (!c) return fail(AMGG_EINVAL, "amgg_set_fusion: null context");
+    for (int l = 0; l < c->nlevels; ++l) c->lv[l].fuse = enable != 0;
+    drop_graphs(c);
+    return AMGG_OK;
 }
 
 extern "C" int amgg_level_view_get(const amgg_ctx* c, int lvl, amgg_level_view* v) {
@@ -347,6 +441,7 @@ extern "C" int amgg_level_view_get(const amgg_ctx* c, int lvl, amgg_level_view* 
     v->diag = L.diag;
     v->scale = L.scale;
     v->coarse_inv = coarse ? L.inv : nullptr;
+    v->fused_rows = L.hrows;
     return AMGG_OK;
 }
 
@@ -376,6 +471,8 @@ static int set_coeffs_impl(amgg_ctx* c, int lvl, int degree, const double* coeff
     if (e == hipSuccess)
         e = assemble_smoother(L.n, L.ptr, L.col, L.val, L.diag, L.scale, pc, coeffs ? nullptr : dev, L.q64, L.q32,
                               L.qd64, L.qd32, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess && L.hrows > 0)
+        e = gather_values(L.nhent, L.hent, L.q64, L.q32, L.hq64, L.hq32, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "amgg_set_smoother");
     L.smoother = diagonal ? kSmootherDiagonal : kSmootherSparse;
     L.degree = degree;
@@ -456,34 +553,54 @@ hipError_t level_apply_t(amgg_ctx* c, int lvl, int op, const T* x, T* y, const T
 
 }  // namespace
 
-extern "C" int amgg_level_apply(amgg_ctx* c, int lvl, int op, int precision, const void* x, void* y, const void* f,
-                                void* stream) {
+namespace {
+
+int level_apply_checked(amgg_ctx* c, int lvl, int op, int precision, const void* x, void* y, const void* f,
+                        void* stream, void* start_event, void* stop_event, const char* name) {
     return guarded([&]() -> int {
-        if (!c || lvl < 0 || lvl >= c->nlevels) return fail(AMGG_EINVAL, "amgg_level_apply: bad context or level");
-        if (!c->finalized) return fail(AMGG_ESTATE, "amgg_level_apply: hierarchy not finalized");
-        if (op < AMGG_OP_SPMV || op > AMGG_OP_COARSE) return fail(AMGG_EINVAL, "amgg_level_apply: unknown op");
-        if (precision != 32 && precision != 64) return fail(AMGG_EINVAL, "amgg_level_apply: precision must be 32 or 64");
+        if (!c || lvl < 0 || lvl >= c->nlevels) return fail(AMGG_EINVAL, std::string(name) + ": bad context or level");
+        if (!c->finalized) return fail(AMGG_ESTATE, std::string(name) + ": hierarchy not finalized");
+        if (op < AMGG_OP_SPMV || op > AMGG_OP_COARSE) return fail(AMGG_EINVAL, std::string(name) + ": unknown op");
+        if (precision != 32 && precision != 64) return fail(AMGG_EINVAL, std::string(name) + ": precision must be 32 or 64");
         const bool coarsest = lvl == c->nlevels - 1;
         if ((op == AMGG_OP_RESTRICT || op == AMGG_OP_PROLONG) && coarsest)
-            return fail(AMGG_EINVAL, "amgg_level_apply: no transfer below the coarsest level");
-        if (op == AMGG_OP_COARSE && !coarsest) return fail(AMGG_EINVAL, "amgg_level_apply: COARSE needs the coarsest level");
+            return fail(AMGG_EINVAL, std::string(name) + ": no transfer below the coarsest level");
+        if (op == AMGG_OP_COARSE && !coarsest) return fail(AMGG_EINVAL, std::string(name) + ": COARSE needs the coarsest level");
         if ((op == AMGG_OP_SMOOTH || op == AMGG_OP_JACOBI) && c->lv[lvl].smoother == kSmootherNone)
-            return fail(AMGG_ESTATE, "amgg_level_apply: smoother not set");
+            return fail(AMGG_ESTATE, std::string(name) + ": smoother not set");
         if (!x || !y || ((op == AMGG_OP_RESIDUAL || op == AMGG_OP_JACOBI) && !f))
-            return fail(AMGG_EINVAL, "amgg_level_apply: null vector");
+            return fail(AMGG_EINVAL, std::string(name) + ": null vector");
+        if ((start_event == nullptr) != (stop_event == nullptr))
+            return fail(AMGG_EINVAL, std::string(name) + ": give both events or neither");
         hipStream_t st = static_cast<hipStream_t>(stream);
         hipError_t e = hipSetDevice(c->device);
         if (e == hipSuccess) {
+            armed_events() = LaunchEvents{static_cast<hipEvent_t>(start_event), static_cast<hipEvent_t>(stop_event)};
             if (precision == 64)
                 e = level_apply_t<double>(c, lvl, op, static_cast<const double*>(x), static_cast<double*>(y),
                                           static_cast<const double*>(f), st);
             else
                 e = level_apply_t<float>(c, lvl, op, static_cast<const float*>(x), static_cast<float*>(y),
                                          static_cast<const float*>(f), st);
+            armed_events() = LaunchEvents{};
         }
-        if (e != hipSuccess) return hip_fail(e, "amgg_level_apply");
+        if (e != hipSuccess) return hip_fail(e, name);
         return AMGG_OK;
     });
+}
+
+}  // namespace
+
+extern "C" int amgg_level_apply(amgg_ctx* c, int lvl, int op, int precision, const void* x, void* y, const void* f,
+                                void* stream) {
+    return level_apply_checked(c, lvl, op, precision, x, y, f, stream, nullptr, nullptr, "amgg_level_apply");
+}
+
+extern "C" int amgg_level_apply_timed(amgg_ctx* c, int lvl, int op, int precision, const void* x, void* y,
+                                      const void* f, void* start_event, void* stop_event, void* stream) {
+    if (!start_event || !stop_event) return fail(AMGG_EINVAL, "amgg_level_apply_timed: null event");
+    return level_apply_checked(c, lvl, op, precision, x, y, f, stream, start_event, stop_event,
+                               "amgg_level_apply_timed");
 }
 
 extern "C" int amgg_cast_scale_f64_f32(const double* in, float* out, int64_t n, double scale, void* stream) {

@@ -46,6 +46,21 @@ struct Level {
     double* dense = nullptr;
     double* inv = nullptr;
     int32_t* piv = nullptr;
+    // halo lists of the fused smoothing kernels (hrows = rows per block, 0 = not available)
+    int hrows = 0;
+    int32_t nhent = 0;  // halo entries over all blocks
+    int32_t* hoff = nullptr;
+    int32_t* halo = nullptr;
+    uint16_t* hend = nullptr;
+    int32_t* heoff = nullptr;
+    int32_t* hent = nullptr;  // global entry index of each halo entry
+    int32_t* hcol = nullptr;
+    double* ha64 = nullptr;  // A and Q values at the halo entries
+    float* ha32 = nullptr;
+    double* hq64 = nullptr;
+    float* hq32 = nullptr;
+    uint16_t* hloc = nullptr;
+    bool fuse = true;  // use the fused kernels where available
     // adjoint scratch, kAdjVecs vectors of n per precision (see AdjVec)
     double* adj64[8] = {};
     float* adj32[8] = {};
@@ -57,6 +72,9 @@ struct Level {
     CsrView A() const { return {n, nnz, ptr, col, lanes_for(n, nnz)}; }
     CsrView P() const { return {n, pnnz, pptr, pcol, lanes_for(n, pnnz)}; }
     CsrView R() const { return {nc, pnnz, rptr, rcol, lanes_for(nc, pnnz)}; }
+    HaloView H() const { return {hrows, hoff, halo, hend, heoff, hcol, hloc}; }
+    template <typename T> const T* hav() const { if constexpr (std::is_same_v<T, double>) return ha64; else return ha32; }
+    template <typename T> const T* hqv() const { if constexpr (std::is_same_v<T, double>) return hq64; else return hq32; }
 
     template <typename T> const T* aval() const { if constexpr (std::is_same_v<T, double>) return val; else return val32; }
     template <typename T> const T* qval() const { if constexpr (std::is_same_v<T, double>) return q64; else return q32; }

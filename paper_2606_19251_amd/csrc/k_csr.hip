@@ -18,6 +18,11 @@
 
 namespace amgg {
 
+LaunchEvents& armed_events() {
+    static thread_local LaunchEvents ev;
+    return ev;
+}
+
 int lanes_for(int32_t nrows, int32_t nnz) {
     if (nrows <= 0) return 1;
     const double avg = static_cast<double>(nnz) / nrows;
@@ -86,6 +91,60 @@ __device__ __forceinline__ void block_partial(double v, double* partial) {
     }
 }
 
+constexpr int kChunk = 8;  // entries per thread per round of a product stream
+
+// out[k] = m[k] * g(col[k]) for k < ne, where m and col are already offset to the block's first
+// entry and g(j) = x[j] (or d[j] * x[j] with SCALED, rounded as a separate product). Every round
+// gives each thread kChunk entries; a thread past the end re-reads the last entry (same cache
+// line) and stores its unused product past ne instead of branching, so that all value/column
+// loads of a round are issued together and then all of its gathers: each wave keeps many loads
+// in flight. out must hold ne rounded up to a multiple of kChunk * kBlock.
+template <typename T, bool SCALED = false>
+__device__ __forceinline__ void stream_products(int32_t ne, const T* __restrict__ m, const int32_t* __restrict__ col,
+                                                const T* __restrict__ x, const T* __restrict__ d,
+                                                T* __restrict__ out) {
+    for (int32_t base = 0; base < ne; base += kChunk * kBlock) {
+        T v[kChunk];
+        int32_t c[kChunk];
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) {
+            const int32_t k = min(base + static_cast<int32_t>(threadIdx.x) + q * kBlock, ne - 1);
+            v[q] = m[k];
+            c[q] = col[k];
+        }
+        T p[kChunk];
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) {
+            if constexpr (SCALED) {
+                const T g = d[c[q]] * x[c[q]];
+                p[q] = v[q] * g;
+            } else {
+                p[q] = v[q] * x[c[q]];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) out[base + static_cast<int32_t>(threadIdx.x) + q * kBlock] = p[q];
+    }
+}
+static_assert(kStreamCap % (kChunk * kBlock) == 0, "product buffers hold whole rounds");
+
+// Sum of buf[pb..pe) from left to right (the order of the stored row); the LDS reads are
+// issued four at a time ahead of the dependent additions.
+template <typename T>
+__device__ __forceinline__ T row_sum(const T* buf, int32_t pb, int32_t pe) {
+    T s = T(0);
+    int32_t k = pb;
+    for (; k + 4 <= pe; k += 4) {
+        const T a0 = buf[k], a1 = buf[k + 1], a2 = buf[k + 2], a3 = buf[k + 3];
+        s += a0;
+        s += a1;
+        s += a2;
+        s += a3;
+    }
+    for (; k < pe; ++k) s += buf[k];
+    return s;
+}
+
 // DOT: 0 none; 1 partial of x_i y_i (q = A p, p^T q); 2 partial of y_i^2 (r = b - A x, r^T r).
 template <typename T, Epi E, int ROWS, int DOT>
 __global__ __launch_bounds__(kBlock) void csr_stream_kernel(int32_t nrows, const int32_t* __restrict__ ptr,
@@ -101,42 +160,39 @@ __global__ __launch_bounds__(kBlock) void csr_stream_kernel(int32_t nrows, const
     const int32_t ne = ptr[r1] - e0;
     const int32_t row = r0 + static_cast<int32_t>(threadIdx.x);
     const bool mine = threadIdx.x < ROWS && row < r1;
+    // the row's own operands, loaded while the products stream
+    int32_t pb = 0, pe = 0;
+    T fr = T(0), qr = T(0), ur = T(0), yr = T(0), xr = T(0);
+    if (mine) {
+        pb = ptr[row];
+        pe = ptr[row + 1];
+        if constexpr (E == Epi::Resid || E == Epi::Jacobi) fr = f[row];
+        if constexpr (E == Epi::Jacobi) {
+            qr = qd[row];
+            ur = u[row];
+        }
+        if constexpr (E == Epi::Add || E == Epi::Sub) yr = y[row];
+        if constexpr (DOT == 1) xr = x[row];
+    }
     T s = T(0);
     if (ne <= kStreamCap) {
-        // all column/value loads of this thread first, then the gathers: more loads in flight
-        constexpr int kPer = kStreamCap / kBlock;
-        T v[kPer];
-        int32_t c[kPer];
-#pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int32_t k = threadIdx.x + q * kBlock;
-            if (k < ne) {
-                v[q] = val[e0 + k];
-                c[q] = col[e0 + k];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int32_t k = threadIdx.x + q * kBlock;
-            if (k < ne) prod[k] = v[q] * x[c[q]];
-        }
+        stream_products<T>(ne, val + e0, col + e0, x, nullptr, prod);
         __syncthreads();
-        if (mine) {
-            const int32_t end = ptr[row + 1] - e0;
-            for (int32_t k = ptr[row] - e0; k < end; ++k) s += prod[k];
-        }
+        if (mine) s = row_sum(prod, pb - e0, pe - e0);
     } else if (mine) {
-        const int32_t end = ptr[row + 1];
-        for (int32_t k = ptr[row]; k < end; ++k) s += val[k] * x[col[k]];
+        for (int32_t k = pb; k < pe; ++k) s += val[k] * x[col[k]];
     }
     double d = 0.0;
     if (mine) {
-        epilogue<T, E>(row, s, y, f, qd, u);
-        if constexpr (DOT == 1) d = static_cast<double>(x[row]) * static_cast<double>(s);
-        if constexpr (DOT == 2) {
-            const double v = static_cast<double>(y[row]);
-            d = v * v;
-        }
+        T out;
+        if constexpr (E == Epi::Store) out = s;
+        if constexpr (E == Epi::Resid) out = fr - s;
+        if constexpr (E == Epi::Add) out = yr + s;
+        if constexpr (E == Epi::Sub) out = yr - s;
+        if constexpr (E == Epi::Jacobi) out = ur + qr * (fr - s);
+        y[row] = out;
+        if constexpr (DOT == 1) d = static_cast<double>(xr) * static_cast<double>(s);
+        if constexpr (DOT == 2) d = static_cast<double>(out) * static_cast<double>(out);
     }
     if constexpr (DOT != 0) block_partial(d, partial);
 }
@@ -197,21 +253,20 @@ hipError_t launch_stream(int rows, const CsrView& m, const T* val, const T* x, T
     const dim3 grid(static_cast<unsigned>((m.nrows + rows - 1) / rows));
     switch (rows) {
         case 256:
-            csr_stream_kernel<T, E, 256, DOT><<<grid, kBlock, 0, stream>>>(m.nrows, m.ptr, m.col, val, x, y, f, qd, u, partial);
-            break;
+            return launch_kernel(csr_stream_kernel<T, E, 256, DOT>, grid, dim3(kBlock), stream, m.nrows, m.ptr, m.col,
+                                 val, x, y, f, qd, u, partial);
         case 128:
-            csr_stream_kernel<T, E, 128, DOT><<<grid, kBlock, 0, stream>>>(m.nrows, m.ptr, m.col, val, x, y, f, qd, u, partial);
-            break;
+            return launch_kernel(csr_stream_kernel<T, E, 128, DOT>, grid, dim3(kBlock), stream, m.nrows, m.ptr, m.col,
+                                 val, x, y, f, qd, u, partial);
         case 64:
-            csr_stream_kernel<T, E, 64, DOT><<<grid, kBlock, 0, stream>>>(m.nrows, m.ptr, m.col, val, x, y, f, qd, u, partial);
-            break;
+            return launch_kernel(csr_stream_kernel<T, E, 64, DOT>, grid, dim3(kBlock), stream, m.nrows, m.ptr, m.col,
+                                 val, x, y, f, qd, u, partial);
         case 32:
-            csr_stream_kernel<T, E, 32, DOT><<<grid, kBlock, 0, stream>>>(m.nrows, m.ptr, m.col, val, x, y, f, qd, u, partial);
-            break;
+            return launch_kernel(csr_stream_kernel<T, E, 32, DOT>, grid, dim3(kBlock), stream, m.nrows, m.ptr, m.col,
+                                 val, x, y, f, qd, u, partial);
         default:
             return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <typename T, Epi E>
@@ -225,8 +280,8 @@ hipError_t launch_rows(const CsrView& m, const T* val, const T* x, T* y, const T
     switch (m.lanes) {
 #define AMGG_CASE(L)                                                                                        \
     case L:                                                                                                 \
-        csr_rows_kernel<T, L, E><<<grid, kBlock, 0, stream>>>(m.nrows, m.ptr, m.col, val, x, y, f, qd, u); \
-        break;
+        return launch_kernel(csr_rows_kernel<T, L, E>, grid, dim3(kBlock), stream, m.nrows, m.ptr, m.col, val, x, y, \
+                             f, qd, u);
         AMGG_CASE(1)
         AMGG_CASE(2)
         AMGG_CASE(4)
@@ -238,7 +293,6 @@ hipError_t launch_rows(const CsrView& m, const T* val, const T* x, T* y, const T
         default:
             return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <int DOT>
@@ -273,7 +327,241 @@ int launch_outer(const CsrView& m, const double* val, const double* x, const dou
     return kReduceBlocks;
 }
 
+
+// ---------------------------------------------------------------------------------------
+// Fused smoothing steps (one workgroup per block of ROWS rows plus its halo).
+//
+// Phase 1 evaluates z = epi1(M1 x) on the block's own rows and on its halo rows and keeps z
+// in LDS; phase 2 evaluates y = epi2(M2 z) on the own rows, gathering z from LDS through the
+// precomputed slots. The own rows' entries and the halo rows' entries are both read as flat
+// streams shared evenly by the workgroup's threads (all loads issued before the gathers);
+// products go to LDS and every row is then summed by one thread in stored order, so the
+// results are bitwise those of the separate passes.
+//   PRE:  M1 = Q, x = f, z = Q f (also written to u); M2 = A, y = f - A z
+//   POST: M1 = A, x = u, z = f - A u;                 M2 = Q, y = u + Q z
+// ---------------------------------------------------------------------------------------
+enum class Fused : int { Pre = 0, Post = 1 };
+
+template <typename T, int ROWS, Fused M>
+__global__ __launch_bounds__(kBlock) void csr_halo_kernel(int32_t nrows, const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ col, HaloView h,
+                                                         const T* __restrict__ m1, const T* __restrict__ hm1,
+                                                         const T* __restrict__ m2, const T* __restrict__ x,
+                                                         const T* __restrict__ f, T* __restrict__ y,
+                                                         T* __restrict__ uout) {
+    constexpr int kHRows = kHaloCap / kBlock;
+    __shared__ T prod[kStreamCap];
+    __shared__ T hprod[kStreamCap];  // >= kHaloEntCap, whole rounds
+    __shared__ T z[ROWS + kHaloCap];
+    const int32_t b = xcd_block();
+    const int32_t r0 = b * ROWS;
+    const int32_t r1 = min(r0 + ROWS, nrows);
+    const int32_t row = r0 + static_cast<int32_t>(threadIdx.x);
+    const bool mine = threadIdx.x < ROWS && row < r1;
+    const int32_t e0 = ptr[r0];
+    const int32_t ne = ptr[r1] - e0;
+    const int32_t h0 = h.hoff[b];
+    const int32_t nh = h.hoff[b + 1] - h0;
+    const int32_t he0 = h.heoff[b];
+    const int32_t nhe = h.heoff[b + 1] - he0;
+    // operands that do not depend on phase 1: the own row's bounds and f (and u for POST), the
+    // halo rows' entry ranges (and f there for POST), phase 2's first round of values and slots
+    int32_t pb = 0, pe = 0;
+    T fr = T(0), xr = T(0);
+    if (mine) {
+        pb = ptr[row] - e0;
+        pe = ptr[row + 1] - e0;
+        fr = f[row];
+        if constexpr (M == Fused::Post) xr = x[row];
+    }
+    int32_t hb[kHRows], hx[kHRows];
+    T hf[kHRows];
+    if (nh > 0) {  // clamped instead of branching, so the loads are in flight together
+#pragma unroll
+        for (int q = 0; q < kHRows; ++q) {
+            const int32_t hh = min(static_cast<int32_t>(threadIdx.x) + q * kBlock, nh - 1);
+            hb[q] = hh > 0 ? h.hend[h0 + hh - 1] : 0;
+            hx[q] = h.hend[h0 + hh];
+            hf[q] = T(0);
+            if constexpr (M == Fused::Post) hf[q] = f[h.halo[h0 + hh]];
+        }
+    }
+    const bool fits = ne <= kStreamCap;
+    T v2[kChunk];
+    uint16_t l2[kChunk];
+    if (fits && ne > 0) {
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) {
+            const int32_t k = min(static_cast<int32_t>(threadIdx.x) + q * kBlock, ne - 1);
+            v2[q] = m2[e0 + k];
+            l2[q] = h.loc[e0 + k];
+        }
+    }
+    // phase 1: z on the own rows and the halo rows
+    if (fits) stream_products<T>(ne, m1 + e0, col + e0, x, nullptr, prod);
+    stream_products<T>(nhe, hm1 + he0, h.hcol + he0, x, nullptr, hprod);
+    __syncthreads();
+    if (mine) {
+        T s = T(0);
+        if (fits) {
+            s = row_sum(prod, pb, pe);
+        } else {
+            for (int32_t k = pb; k < pe; ++k) s += m1[e0 + k] * x[col[e0 + k]];
+        }
+        if constexpr (M == Fused::Pre) {
+            z[threadIdx.x] = s;
+            uout[row] = s;
+        } else {
+            z[threadIdx.x] = fr - s;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kHRows; ++q) {
+        const int32_t hh = static_cast<int32_t>(threadIdx.x) + q * kBlock;
+        if (hh < nh) {
+            const T s = row_sum(hprod, hb[q], hx[q]);
+            if constexpr (M == Fused::Pre)
+                z[ROWS + hh] = s;
+            else
+                z[ROWS + hh] = hf[q] - s;
+        }
+    }
+    __syncthreads();
+    // phase 2: M2 z on the own rows, z gathered from LDS
+    if (fits) {
+        for (int32_t base = 0; base < ne; base += kChunk * kBlock) {
+            if (base > 0) {
+#pragma unroll
+                for (int q = 0; q < kChunk; ++q) {
+                    const int32_t k = min(base + static_cast<int32_t>(threadIdx.x) + q * kBlock, ne - 1);
+                    v2[q] = m2[e0 + k];
+                    l2[q] = h.loc[e0 + k];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) prod[base + static_cast<int32_t>(threadIdx.x) + q * kBlock] = v2[q] * z[l2[q]];
+        }
+    }
+    __syncthreads();
+    if (mine) {
+        T s = T(0);
+        if (fits) {
+            s = row_sum(prod, pb, pe);
+        } else {
+            for (int32_t k = pb; k < pe; ++k) s += m2[e0 + k] * z[h.loc[e0 + k]];
+        }
+        if constexpr (M == Fused::Pre)
+            y[row] = fr - s;
+        else
+            y[row] = xr + s;
+    }
+}
+
+// First diagonal smoothing step from u = 0 (u = d f) fused with the pass after it: the row
+// products gather d_j f_j, rounded exactly as the separate u = d f pass rounds them.
+//   NEXT_RESID: u_i = d_i f_i, y_i = f_i - (A u)_i
+//   otherwise:  y_i = d_i f_i + d_i (f_i - (A u)_i)
+template <typename T, int ROWS, bool NEXT_RESID>
+__global__ __launch_bounds__(kBlock) void csr_jpre_kernel(int32_t nrows, const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ col,
+                                                         const T* __restrict__ val, const T* __restrict__ d,
+                                                         const T* __restrict__ f, T* __restrict__ y,
+                                                         T* __restrict__ uout) {
+    __shared__ T prod[kStreamCap];
+    const int32_t r0 = xcd_block() * ROWS;
+    const int32_t r1 = min(r0 + ROWS, nrows);
+    const int32_t e0 = ptr[r0];
+    const int32_t ne = ptr[r1] - e0;
+    const int32_t row = r0 + static_cast<int32_t>(threadIdx.x);
+    const bool mine = threadIdx.x < ROWS && row < r1;
+    int32_t pb = 0, pe = 0;
+    T fr = T(0), dr = T(0);
+    if (mine) {
+        pb = ptr[row];
+        pe = ptr[row + 1];
+        fr = f[row];
+        dr = d[row];
+    }
+    T s = T(0);
+    if (ne <= kStreamCap) {
+        stream_products<T, true>(ne, val + e0, col + e0, f, d, prod);
+        __syncthreads();
+        if (mine) s = row_sum(prod, pb - e0, pe - e0);
+    } else if (mine) {
+        for (int32_t k = pb; k < pe; ++k) {
+            const T uj = d[col[k]] * f[col[k]];
+            s += val[k] * uj;
+        }
+    }
+    if (mine) {
+        const T ui = dr * fr;
+        if constexpr (NEXT_RESID) {
+            uout[row] = ui;
+            y[row] = fr - s;
+        } else {
+            y[row] = ui + dr * (fr - s);
+        }
+    }
+}
+
+template <typename T, Fused M>
+hipError_t launch_halo(const CsrView& m, const HaloView& h, const T* m1, const T* hm1, const T* m2, const T* x,
+                       const T* f, T* y, T* uout, hipStream_t stream) {
+    if (m.nrows <= 0) return hipSuccess;
+    const dim3 grid(static_cast<unsigned>((m.nrows + h.rows - 1) / h.rows));
+    switch (h.rows) {
+#define AMGG_CASE(R)                                                                                              \
+    case R:                                                                                                       \
+        return launch_kernel(csr_halo_kernel<T, R, M>, grid, dim3(kBlock), stream, m.nrows, m.ptr, m.col, h, m1, hm1, \
+                             m2, x, f, y, uout);
+        AMGG_CASE(256)
+        AMGG_CASE(128)
+        AMGG_CASE(64)
+        AMGG_CASE(32)
+#undef AMGG_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+__global__ void gather_kernel(int32_t n, const int32_t* __restrict__ idx, const double* __restrict__ s64,
+                              const float* __restrict__ s32, double* __restrict__ d64, float* __restrict__ d32) {
+    const int32_t k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const int32_t i = idx[k];
+    if (d64) d64[k] = s64[i];
+    if (d32) d32[k] = s32[i];
+}
+
+template <typename T, bool NEXT_RESID>
+hipError_t launch_jpre(const CsrView& m, const T* a, const T* d, const T* f, T* y, T* u, hipStream_t stream) {
+    if (m.nrows <= 0) return hipSuccess;
+    const int rows = stream_rows(m.nrows, m.nnz);
+    if (rows == 0) {  // long rows: the separate passes (u = d f, then r = f - A u)
+        if constexpr (!NEXT_RESID) return hipErrorInvalidValue;  // would need a third buffer
+        hipError_t e = vec_mul<T>(m.nrows, d, f, u, stream);
+        if (e != hipSuccess) return e;
+        return csr_apply<T>(m, a, u, y, f, nullptr, nullptr, Epi::Resid, stream);
+    }
+    const dim3 grid(static_cast<unsigned>((m.nrows + rows - 1) / rows));
+    switch (rows) {
+#define AMGG_CASE(R)                                                                                               \
+    case R:                                                                                                        \
+        return launch_kernel(csr_jpre_kernel<T, R, NEXT_RESID>, grid, dim3(kBlock), stream, m.nrows, m.ptr, m.col, \
+                             a, d, f, y, u);
+        AMGG_CASE(256)
+        AMGG_CASE(128)
+        AMGG_CASE(64)
+        AMGG_CASE(32)
+#undef AMGG_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
+
+int stream_rows_for(int32_t nrows, int32_t nnz) { return stream_rows(nrows, nnz); }
 
 int outer_partials(int32_t nrows, int32_t nnz) {
     const int rows = stream_rows(nrows, nnz);
@@ -316,5 +604,40 @@ hipError_t csr_resid_norm(const CsrView& m, const double* val, const double* x, 
     *count = launch_outer<2>(m, val, x, b, r, partial, stream, &e);
     return e;
 }
+
+template <typename T>
+hipError_t smooth_pre_fused(const CsrView& m, const HaloView& h, const T* a, const T* q, const T* hq, const T* f,
+                            T* u, T* r, hipStream_t stream) {
+    return launch_halo<T, Fused::Pre>(m, h, q, hq, a, f, f, r, u, stream);
+}
+template <typename T>
+hipError_t smooth_post_fused(const CsrView& m, const HaloView& h, const T* a, const T* ha, const T* q, const T* f,
+                             const T* u, T* y, hipStream_t stream) {
+    return launch_halo<T, Fused::Post>(m, h, a, ha, q, u, f, y, nullptr, stream);
+}
+hipError_t gather_values(int32_t n, const int32_t* idx, const double* src64, const float* src32, double* dst64,
+                         float* dst32, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    gather_kernel<<<(n + kBlock - 1) / kBlock, kBlock, 0, stream>>>(n, idx, src64, src32, dst64, dst32);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t jacobi_pre_resid(const CsrView& m, const T* a, const T* d, const T* f, T* u, T* r, hipStream_t stream) {
+    return launch_jpre<T, true>(m, a, d, f, r, u, stream);
+}
+template <typename T>
+hipError_t jacobi_pre_step(const CsrView& m, const T* a, const T* d, const T* f, T* y, hipStream_t stream) {
+    return launch_jpre<T, false>(m, a, d, f, y, nullptr, stream);
+}
+#define AMGG_INST(T)                                                                                                \
+    template hipError_t smooth_pre_fused<T>(const CsrView&, const HaloView&, const T*, const T*, const T*, const T*, \
+                                            T*, T*, hipStream_t);                                                  \
+    template hipError_t smooth_post_fused<T>(const CsrView&, const HaloView&, const T*, const T*, const T*,         \
+                                             const T*, const T*, T*, hipStream_t);                                 \
+    template hipError_t jacobi_pre_resid<T>(const CsrView&, const T*, const T*, const T*, T*, T*, hipStream_t);     \
+    template hipError_t jacobi_pre_step<T>(const CsrView&, const T*, const T*, const T*, T*, hipStream_t);
+AMGG_INST(float)
+AMGG_INST(double)
+#undef AMGG_INST
 
 }  // namespace amgg

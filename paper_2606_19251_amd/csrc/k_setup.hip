@@ -318,8 +318,7 @@ template <typename T>
 hipError_t dense_gemv(int32_t n, const double* inv, const T* x, T* y, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     const dim3 grid(static_cast<unsigned>((n + kBlock / 64 - 1) / (kBlock / 64)));
-    dense_gemv_kernel<T><<<grid, kBlock, 0, stream>>>(n, inv, x, y);
-    return hipGetLastError();
+    return launch_kernel(dense_gemv_kernel<T>, grid, dim3(kBlock), stream, n, inv, x, y);
 }
 template hipError_t dense_gemv<float>(int32_t, const double*, const float*, float*, hipStream_t);
 template hipError_t dense_gemv<double>(int32_t, const double*, const double*, double*, hipStream_t);

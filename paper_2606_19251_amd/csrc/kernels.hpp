@@ -2,11 +2,37 @@
 // `stream` and returns hipSuccess or the launch error; none synchronises.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 namespace amgg {
+
+// ---------------------------------------------------------------------------------------
+// Launch helper. When a pair of events is armed on the calling thread, the next kernel
+// launched through launch_kernel records them at its own start and end (hipExtLaunchKernel)
+// and disarms them; otherwise it is a plain launch.
+// ---------------------------------------------------------------------------------------
+struct LaunchEvents {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
+LaunchEvents& armed_events();  // per host thread
+
+template <typename... KArgs, typename... Args>
+inline hipError_t launch_kernel(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t stream,
+                                Args... args) {
+    LaunchEvents& ev = armed_events();
+    if (ev.start != nullptr) {
+        const hipEvent_t s = ev.start, e = ev.stop;
+        ev = LaunchEvents{};
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, s, e, 0, static_cast<KArgs>(args)...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, stream, static_cast<KArgs>(args)...);
+    }
+    return hipGetLastError();
+}
 
 constexpr int kBlock = 256;         // threads per workgroup (4 wavefronts of 64)
 constexpr int kReduceBlocks = 1024; // fixed partial count: reductions are deterministic
@@ -35,6 +61,47 @@ int lanes_for(int32_t nrows, int32_t nnz);
 template <typename T>
 hipError_t csr_apply(const CsrView& m, const T* val, const T* x, T* y, const T* f, const T* qd, const T* u,
                      Epi epi, hipStream_t stream);
+
+// Rows per workgroup of the CSR-stream kernels for a matrix of this shape (0: lane kernel).
+int stream_rows_for(int32_t nrows, int32_t nnz);
+
+// Fused smoothing steps on a level (Q values on A's pattern). Rows are grouped in blocks of
+// h.rows consecutive rows (= stream_rows_for(A)); each block has at most kHaloCap halo rows
+// with at most kHaloEntCap stored entries between them (lists built on the host, halo.hpp).
+// Levels with more rows than this stay with separate passes: there the halo rows' extra
+// traffic (about 0.4-0.9 of the block's own entries) costs more than the saved launch.
+constexpr int32_t kFuseMaxRows = 65536;
+constexpr int kHaloCap = 1024;
+constexpr int kHaloEntCap = 3072;  // <= the kernels' LDS product buffer (4096)
+struct HaloView {
+    int rows;
+    const int32_t* hoff;   // [blocks + 1] into halo / hend
+    const int32_t* halo;   // halo row ids
+    const uint16_t* hend;  // end of each halo row's entries within its block's flat list
+    const int32_t* heoff;  // [blocks + 1] into the flat halo-entry arrays
+    const int32_t* hcol;   // column of each halo entry
+    const uint16_t* loc;   // [nnz] block-local slot of each stored entry's column
+};
+// first pre-smoothing step from u = 0 and the residual after it: u = Q f, r = f - A u
+// (hq: Q's values at the halo entries, in flat halo-entry order)
+template <typename T>
+hipError_t smooth_pre_fused(const CsrView& m, const HaloView& h, const T* a, const T* q, const T* hq, const T* f,
+                            T* u, T* r, hipStream_t stream);
+// one smoothing step into another buffer: y = u + Q (f - A u)   (y must not alias u;
+// ha: A's values at the halo entries)
+template <typename T>
+hipError_t smooth_post_fused(const CsrView& m, const HaloView& h, const T* a, const T* ha, const T* q, const T* f,
+                             const T* u, T* y, hipStream_t stream);
+// dst[k] = src[idx[k]] for k < n, in both precisions (either pair may be null)
+hipError_t gather_values(int32_t n, const int32_t* idx, const double* src64, const float* src32, double* dst64,
+                         float* dst32, hipStream_t stream);
+// Diagonal smoother d: first step from u = 0 fused with what follows it.
+//   jacobi_pre_resid: u = d f and r = f - A u
+//   jacobi_pre_step:  y = d f + d (f - A (d f))   (two steps)
+template <typename T>
+hipError_t jacobi_pre_resid(const CsrView& m, const T* a, const T* d, const T* f, T* u, T* r, hipStream_t stream);
+template <typename T>
+hipError_t jacobi_pre_step(const CsrView& m, const T* a, const T* d, const T* f, T* y, hipStream_t stream);
 
 // q = A p and per-workgroup partial sums of p_i q_i (FP64 outer loop); *count = partials written.
 hipError_t csr_spmv_dot(const CsrView& m, const double* val, const double* p, double* q, double* partial, int* count,

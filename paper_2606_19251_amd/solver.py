@@ -109,6 +109,9 @@ class DeviceSolver:
     def stream(self):
         return _stream_ptr(self.torch, self.device)
 
+    def set_fusion(self, enable: bool):
+        capi.amgg_set_fusion(self.ctx, enable)
+
     def close(self):
         if self.ctx:
             capi.amgg_destroy(self.ctx)
@@ -178,4 +181,5 @@ class DeviceSolver:
             "diag": s(v.diag, v.n, torch.float64),
             "scale": s(v.scale, 1, torch.float64),
             "coarse_inv": s(v.coarse_inv, v.n * v.n, torch.float64),
+            "fused_rows": int(v.fused_rows),
         }

@@ -315,3 +315,58 @@ def test_level_operators_bitexact(kind, cname):
             capi.amgg_level_apply(ds.ctx, l, op, 64, xd.data_ptr(), yd.data_ptr(), fd.data_ptr(), st)
             torch.cuda.synchronize()
             assert np.array_equal(_bits(yd.cpu().numpy()), _bits(ref)), (l, op)
+
+
+@pytest.mark.parametrize("kind", ["grid64", "delaunay20k", "gmm5k", "tiny", "cmesh32k", "tet30k"])
+@pytest.mark.parametrize("cname", ["jacobi", "poly2"])
+@pytest.mark.parametrize("prec", [64, 32])
+def test_fused_kernels_equal_separate_passes(kind, cname, prec):
+    """The fused kernels (first pre-smoothing step with the residual; halo-fused sparse smoothing
+    steps) give bitwise the iterates of the separate passes, for several (nu1, nu2)."""
+    A, f, ho, hp, ds = _setup(kind)
+    c, deg = COEFFS[cname]
+    ds.set_coeffs(c, deg)
+    if kind != "tiny":  # the fused kernels are in use on some level
+        assert any(ds.level_view(l)["fused_rows"] > 0 for l in range(hp.nlevels - 1))
+    rng = np.random.default_rng(5)
+    u0 = rng.standard_normal(A.nrows)
+    fd = _dev(f)
+    try:
+        for nu in [(1, 1), (2, 2), (2, 1), (0, 1), (3, 0)]:
+            for start in (np.zeros(A.nrows), u0):
+                out = []
+                for fuse in (True, False):
+                    ds.set_fusion(fuse)
+                    u = _dev(start)
+                    ds.vcycle(fd, u, nu[0], nu[1], prec)
+                    out.append(u)
+                torch.cuda.synchronize()
+                assert torch.equal(out[0], out[1]), (nu, float((out[0] - out[1]).abs().max()))
+    finally:
+        ds.set_fusion(True)
+
+
+def test_timed_level_operator_records_kernel_time():
+    from paper_2606_19251_amd import capi
+
+    A, f, ho, hp, ds = _setup("delaunay20k")
+    ds.set_jacobi()
+    x = _dev(np.random.default_rng(1).standard_normal(A.nrows))
+    y1 = torch.zeros_like(x)
+    y2 = torch.zeros_like(x)
+    fd = _dev(f)
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    s1.record()
+    torch.cuda.synchronize()
+    capi.amgg_level_apply(ds.ctx, 0, capi.AMGG_OP_RESIDUAL, 64, x.data_ptr(), y1.data_ptr(), fd.data_ptr(),
+                          ds.stream)
+    capi.amgg_level_apply_timed(ds.ctx, 0, capi.AMGG_OP_RESIDUAL, 64, x.data_ptr(), y2.data_ptr(), fd.data_ptr(),
+                                s0.cuda_event, s1.cuda_event, ds.stream)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    ms = s0.elapsed_time(s1)
+    assert 0.0 < ms < 10.0
+    with pytest.raises(capi.AmggError):
+        capi.amgg_level_apply_timed(ds.ctx, 0, capi.AMGG_OP_RESIDUAL, 64, x.data_ptr(), y2.data_ptr(),
+                                    fd.data_ptr(), 0, 0, ds.stream)

@@ -350,6 +350,61 @@ def tet_fv(points: np.ndarray) -> CSRMatrix:
     return _laplacian_from_edges(np.minimum(i_all, j_all), np.maximum(i_all, j_all), np.concatenate(ww), kept.size)
 
 
+def kuhn_tets(m: int, seed: int, jitter: float = 0.15):
+    """Tetrahedral mesh of the unit cube: an m^3 lattice, interior points moved by
+    U[-jitter h, jitter h], each lattice cube split into the 6 tetrahedra around its main
+    diagonal (the Freudenthal/Kuhn split, conforming across cubes). With jitter <= 0.15 every
+    tetrahedron keeps its orientation (each vertex-to-face distance is at least h/sqrt(2), and
+    a jitter of 0.15 h per coordinate moves a vertex and its opposite face by at most 0.21 h
+    each along the face normal). Returns (points[m^3, 3], tets[6 (m-1)^3, 4])."""
+    P = jittered_lattice(m, seed, jitter)
+    g = np.arange(m - 1)
+    I, J, K = np.meshgrid(g, g, g, indexing="ij")
+    base = (I * m * m + J * m + K).ravel().astype(np.int64)
+    step = {0: m * m, 1: m, 2: 1}
+    tets = []
+    for a, b, c in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        v1 = base + step[a]
+        v2 = v1 + step[b]
+        v3 = v2 + step[c]
+        tets.append(np.stack([base, v1, v2, v3], axis=1))
+    return P, np.concatenate(tets)
+
+
+def tet_fv_mesh(points: np.ndarray, tets: np.ndarray) -> CSRMatrix:
+    """Cell-centred FV Poisson matrix on a conforming tetrahedral mesh (cells = tets, face
+    neighbours couple with |face| / |centroid distance|, all-Neumann), face neighbours found by
+    matching the sorted vertex triples of the faces. Cells are Morton ordered by centroid."""
+    nt = tets.shape[0]
+    npnt = np.int64(points.shape[0])
+    cent = points[tets].mean(axis=1)
+    order = morton_order((cent - cent.min(0)) / (np.ptp(cent, 0) + 1e-300))
+    remap = np.empty(nt, np.int64)
+    remap[order] = np.arange(nt)
+    faces = np.concatenate([np.sort(np.delete(tets, f, axis=1), axis=1) for f in range(4)])
+    owner = np.tile(np.arange(nt, dtype=np.int64), 4)
+    key = (faces[:, 0] * npnt + faces[:, 1]) * npnt + faces[:, 2]
+    srt = np.argsort(key, kind="stable")
+    ks = key[srt]
+    pair = np.nonzero(ks[1:] == ks[:-1])[0]
+    fa = srt[pair]
+    a, b = owner[fa], owner[srt[pair + 1]]
+    fv = faces[fa]
+    area = 0.5 * np.linalg.norm(np.cross(points[fv[:, 1]] - points[fv[:, 0]], points[fv[:, 2]] - points[fv[:, 0]]),
+                                axis=1)
+    dist = np.linalg.norm(cent[a] - cent[b], axis=1)
+    i_all, j_all = remap[a], remap[b]
+    return _laplacian_from_edges(np.minimum(i_all, j_all), np.maximum(i_all, j_all), area / dist, nt)
+
+
+def tet_kuhn_problem(m: int, seed: int = 0):
+    """3D FV Poisson on the Kuhn tetrahedra of an m^3 jittered lattice (6 (m-1)^3 cells; m = 111
+    gives 7,986,000 cells), zero-mean RHS."""
+    P, T = kuhn_tets(m, seed)
+    A = tet_fv_mesh(P, T)
+    return A, rhs_uniform(A.nrows, seed + 5000, zero_mean=True)
+
+
 def tet_fv_problem(m: int, seed: int = 0):
     """3D FV Poisson on the tetrahedra of an m^3 jittered lattice, zero-mean RHS."""
     A = tet_fv(jittered_lattice(m, seed))
