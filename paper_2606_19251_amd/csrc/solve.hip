@@ -233,9 +233,20 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
             ++k;
             if (e != hipSuccess) return hip_fail(e, "amgg_solve");
             if (!R.read_scalars(st)) return hip_fail(R.e, "amgg_solve");
-            const double rel = std::sqrt(hs[kRR]) / nb;
-            hist.push_back(rel);
+            double rel = std::sqrt(hs[kRR]) / nb;
             const bool breakdown = hs[kFlag] != 0.0;
+            if (o->outer == AMGG_OUTER_FCG && rel <= o->tol && std::isfinite(rel) && !breakdown) {
+                // The CG residual is updated by recurrence and drifts from b - A x on badly
+                // conditioned problems: confirm with the true residual; if it is still above the
+                // tolerance, restart the recurrence from it.
+                int cnt = 0;
+                R.ok(csr_resid_norm(A, L0.val, x, bb, cur, c->partial, &cnt, st));
+                R.ok(fcg_finish_rr(c->partial, cnt, s, st));
+                if (!R.read_scalars(st)) return hip_fail(R.e, "amgg_solve");
+                rel = std::sqrt(hs[kRR]) / nb;
+                if (!(rel <= o->tol)) first = true;
+            }
+            hist.push_back(rel);
             if (rel <= o->tol && std::isfinite(rel) && !breakdown) return finish(0, rel, k);
             if (!std::isfinite(rel) || rel > div_factor)
                 outcome = AMGG_DIVERGED;

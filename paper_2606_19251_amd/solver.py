@@ -79,6 +79,7 @@ class DeviceSolver:
         self.device = torch.device("cuda", device)
         self.nlevels = hier.nlevels
         self.n = hier.levels[0].n
+        self.singular = bool(hier.singular)
         self._keep = []
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(self.device)
         self.ctx = capi.amgg_create(device, self.nlevels)

@@ -1,7 +1,11 @@
 """Train the GCIN smoother-coefficient predictor on the GPU (Alg. 1 of the paper).
 
-Training problems are P1 Laplacians on Delaunay meshes of Gaussian-mixture-clustered points
-(2k-16k nodes each, all levels of all meshes of a mini-batch in one GCIN launch). Each step:
+Training problems (all levels of all meshes of a mini-batch in one GCIN launch), by family:
+  delaunay  P1 Laplacians on Delaunay meshes of Gaussian-mixture-clustered points, 2k-16k nodes;
+  cmesh     finite-volume C-meshes around random NACA 4-digit sections, ~24k-41k cells, wall
+            aspect ratios 1e3-1e4 (for the 4M-cell airfoil mesh, 128 times larger);
+  tet       finite-volume Poisson on jittered Kuhn tetrahedral meshes, ~8k-55k cells.
+Each step:
 batched GCIN forward, per-problem smoother assembly and nvc V(1,1) cycles from u = 0 with a
 fresh uniform random zero-mean right-hand side, residual-reduction loss (Sec. 3.3, Eq. 11;
 the multi-cycle form when nvc > 1), hand-written adjoint, GCIN backward, clipping at 1.0 and
@@ -22,17 +26,30 @@ import time
 import numpy as np
 
 
-def build_problems(seed0, count, lo, hi, device, max_coarse=100):
-    import torch
-
+def make_matrix(family, rng, seed):
+    """One training matrix of the given family, drawn from rng."""
     import workloads as W
+
+    if family == "delaunay":
+        return W.delaunay_p1(W.gmm_points(int(rng.integers(2000, 16001)), seed))
+    if family == "cmesh":
+        code = f"{int(rng.integers(0, 5))}{int(rng.integers(2, 6))}{int(rng.integers(9, 16)):02d}"
+        ni = int(rng.choice([224, 256, 288]))
+        aspect = float(10 ** rng.uniform(3.0, 4.0))
+        return W.cmesh_fv(ni, ni // 2, code, aspect)
+    if family == "tet":
+        P, T = W.kuhn_tets(int(rng.integers(12, 23)), seed, float(rng.uniform(0.05, 0.15)))
+        return W.tet_fv_mesh(P, T)
+    raise ValueError(family)
+
+
+def build_problems(family, seed0, count, device, max_coarse=100):
     from .solver import DeviceSolver, HostHierarchy
 
     rng = np.random.default_rng(seed0)
-    sizes = rng.integers(lo, hi + 1, size=count)
     out = []
-    for k, npts in enumerate(sizes):
-        A = W.delaunay_p1(W.gmm_points(int(npts), seed0 * 1000 + k))
+    for k in range(count):
+        A = make_matrix(family, rng, seed0 * 1000 + k)
         hh = HostHierarchy.build(A.rowptr, A.col, A.val, max_coarse=max_coarse)
         out.append(DeviceSolver(hh, device.index or 0))
     return out
@@ -50,6 +67,7 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--val-every", type=int, default=25)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--family", choices=["delaunay", "cmesh", "tet"], default="delaunay")
     args = ap.parse_args(argv)
 
     import torch
@@ -60,14 +78,15 @@ def main(argv=None):
 
     dev = torch.device("cuda", 0)
     t0 = time.time()
-    train = build_problems(100 + args.seed, args.train_meshes, 2000, 16000, dev)
-    val = build_problems(900 + args.seed, args.val_meshes, 2000, 16000, dev)
+    train = build_problems(args.family, 100 + args.seed, args.train_meshes, dev)
+    val = build_problems(args.family, 900 + args.seed, args.val_meshes, dev)
     print(f"[train] {len(train)} training and {len(val)} validation meshes built in {time.time() - t0:.1f} s", flush=True)
     rng = np.random.default_rng(args.seed)
 
     def rhs_for(problems, seed):
         r = np.random.default_rng(seed)
-        return [torch.from_numpy(W.rhs_uniform(ds.n, int(r.integers(1 << 30)), zero_mean=True)).to(dev) for ds in problems]
+        return [torch.from_numpy(W.rhs_uniform(ds.n, int(r.integers(1 << 30)), zero_mean=bool(ds.singular))).to(dev)
+                for ds in problems]
 
     pred = G.Predictor(G.init_flat(args.degree, args.seed), dev, args.degree, capi.GCIN_BF16X3)
     nb = max(1, len(train) // args.batch)
@@ -111,7 +130,7 @@ def main(argv=None):
                 best = v
                 best_flat = pred.params.cpu().numpy().copy()
     np.savez(args.out, params=best_flat, degree=np.int64(args.degree), nvc=np.int64(args.nvc),
-             history=json.dumps(history))
+             family=args.family, history=json.dumps(history))
     print(f"[train] best validation {best:+.4f}; saved {args.out}", flush=True)
 
 

@@ -1,0 +1,208 @@
+"""Parity at full size on the two other fine-level workloads.
+
+Airfoil C-mesh, 4096 x 1024 = 4,194,304 cells (finite-volume Poisson, wall aspect ratio 1e4,
+Dirichlet far field): the oracle builds its own hierarchy, compared bit for bit with the
+product's; one FP64 V-cycle from the same (u, f) within 1e-12 of the oracle's; FP32-cycle /
+FP64 flexible-CG solves with the Jacobi smoother and with the GCIN trained on 25k-41k-cell
+C-meshes (applied unchanged, about 128 times larger) reach 1e-8, residual recomputed in FP64.
+
+3D tetrahedral mesh, 7,986,000 cells (finite-volume Poisson on the Kuhn tetrahedra of a
+jittered 111^3 lattice, all-Neumann): the oracle's full setup takes minutes at this size, so
+the hierarchy is checked through properties that hold at any size (exact transpose, constant
+preservation of P, symmetry and zero row sums of every Galerkin product, sampled Galerkin rows
+against a sparse triple product), the level operators bitwise against the oracle's sparse
+products, the FP64 cycle through exact linearity, and the solves through the FP64 residual;
+the GCIN trained on 8k-55k-cell tetrahedral meshes needs fewer V-cycles than Jacobi.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import amg
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+torch = pytest.importorskip("torch")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bits(a):
+    a = np.ascontiguousarray(a)
+    return a.view(np.uint64 if a.dtype == np.float64 else np.uint32)
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, np.float64)).cuda()
+
+
+def _predictor(name):
+    from paper_2606_19251_amd import gcin as G
+
+    return G.Predictor.load(os.path.join(ROOT, "paper_2606_19251_amd", "weights", name), torch.device("cuda", 0))
+
+
+def _solve(ds, f, smoother, weights, precision=32):
+    from paper_2606_19251_amd import capi
+
+    if smoother == "jacobi":
+        ds.set_jacobi(2 / 3)
+    else:
+        pred = _predictor(weights)
+        ds.set_coeffs_device(pred.predict(ds.hier, ds), pred.degree)
+    x, rc, info, _ = ds.solve(_dev(f), outer=capi.AMGG_OUTER_FCG, precision=precision, tol=1e-8, fallback=False)
+    return x.cpu().numpy(), rc, info
+
+
+# ---------------------------------------------------------------------------- C-mesh
+@pytest.fixture(scope="module")
+def cmesh():
+    from paper_2606_19251_amd.solver import DeviceSolver, HostHierarchy
+
+    print("[gpu] full-size workload: airfoil C-mesh 4096 x 1024", flush=True)
+    A, f = W.airfoil_cmesh_problem(4096, 1024, 0)
+    An, fn, sing = amg.normalize(A, f)
+    ho = amg.setup(An, singular=sing, max_levels=10, max_coarse=500)
+    hp = HostHierarchy.build(A.rowptr, A.col, A.val, max_levels=10, max_coarse=500)
+    print(f"[gpu] levels {[L.n for L in hp.levels]}", flush=True)
+    return A, fn, ho, hp, DeviceSolver(hp, 0)
+
+
+def test_cmesh_hierarchy_bitexact(cmesh):
+    A, f, ho, hp, ds = cmesh
+    assert not ho.singular and hp.nlevels == ho.nlevels
+    for l in range(ho.nlevels):
+        assert np.array_equal(ho.levels[l].A.indptr, hp.levels[l].rowptr)
+        assert np.array_equal(ho.levels[l].A.indices, hp.levels[l].col)
+        assert np.array_equal(_bits(ho.levels[l].A.data), _bits(hp.levels[l].val))
+        if l + 1 < ho.nlevels:
+            assert np.array_equal(ho.levels[l].P.indices, hp.levels[l].p_col)
+            assert np.array_equal(_bits(ho.levels[l].P.data), _bits(hp.levels[l].p_val))
+
+
+def test_cmesh_vcycle_fp64(cmesh):
+    A, f, ho, hp, ds = cmesh
+    c = np.array([0.6, 0.01, -0.001, 0.12, 0.01])
+    ds.set_coeffs(c, 2)
+    u0 = np.random.default_rng(4).standard_normal(A.nrows)
+    ref = amg.vcycle(ho, amg.smoothers(ho, c, 2), u0, f)
+    u = _dev(u0)
+    ds.vcycle(_dev(f), u, 1, 1, 64)
+    err = np.linalg.norm(u.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= 1e-12, err
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "gcin"])
+def test_cmesh_solve_reaches_tolerance(cmesh, smoother):
+    A, f, ho, hp, ds = cmesh
+    x, rc, info = _solve(ds, f, smoother, "gcin_cmesh_deg2.npz")
+    assert rc == 0, (rc, info.relres)
+    rel = np.linalg.norm(f - ho.levels[0].A @ x) / np.linalg.norm(f)
+    print(f"[gpu] C-mesh {smoother}: {info.vcycles} cycles, oracle residual {rel:.2e}", flush=True)
+    assert rel <= 1e-8 * 1.01
+
+
+# ---------------------------------------------------------------------------- 3D tetrahedra
+@pytest.fixture(scope="module")
+def tet():
+    from paper_2606_19251_amd.solver import DeviceSolver, HostHierarchy
+
+    print("[gpu] full-size workload: Kuhn tetrahedra of a jittered 111^3 lattice", flush=True)
+    A, f = W.tet_kuhn_problem(111, 0)
+    hp = HostHierarchy.build(A.rowptr, A.col, A.val, max_levels=10, max_coarse=500)
+    print(f"[gpu] levels {[L.n for L in hp.levels]}", flush=True)
+    return A, f, hp, DeviceSolver(hp, 0)
+
+
+def _level_mats(hp, l):
+    L = hp.levels[l]
+    Al = sp.csr_matrix((L.val, L.col, L.rowptr), shape=(L.n, L.n))
+    if l + 1 == hp.nlevels:
+        return Al, None
+    P = sp.csr_matrix((L.p_val, L.p_col, L.p_rowptr), shape=(L.n, L.p_ncols))
+    return Al, P
+
+
+def test_tet_hierarchy_properties(tet):
+    A, f, hp, ds = tet
+    assert hp.singular and hp.nlevels >= 5
+    rng = np.random.default_rng(0)
+    for l in range(hp.nlevels - 1):
+        Al, P = _level_mats(hp, l)
+        Ac, _ = _level_mats(hp, l + 1)
+        d = Al.diagonal()
+        # zero row sums (all-Neumann) and symmetry of every Galerkin product
+        assert np.abs(np.asarray(Al.sum(axis=1)).ravel()).max() <= 1e-12 * d.max()
+        assert abs(Ac - Ac.T).max() <= 1e-14 * Ac.diagonal().max()
+        # direct interpolation preserves constants on zero-row-sum rows (rows with weights)
+        has = np.diff(P.indptr) > 0
+        assert has.mean() > 0.99
+        assert np.abs((P @ np.ones(P.shape[1]) - 1.0)[has]).max() <= 1e-12
+        # sampled Galerkin rows against the sparse triple product (summation order differs)
+        rows = np.sort(rng.choice(Ac.shape[0], size=min(200, Ac.shape[0]), replace=False))
+        ref = ((Al @ P[:, rows].tocsc()).T @ P).toarray()  # rows of P^T A P (A symmetric)
+        got = Ac[rows].toarray()
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_tet_level_operators_bitexact(tet):
+    """Fine and first coarse level: residual, restriction and prolongation in FP64 are bitwise
+    the oracle's sparse products (rows summed in stored order, products rounded separately)."""
+    from paper_2606_19251_amd import capi
+
+    A, f, hp, ds = tet
+    ds.set_jacobi(2 / 3)
+    rng = np.random.default_rng(1)
+    for l in (0, 1):
+        Al, P = _level_mats(hp, l)
+        n, nc = P.shape
+        x, fl, y0, xc = rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(nc)
+        R = amg.transpose_exact(P)
+        cases = [
+            (capi.AMGG_OP_RESIDUAL, x, fl, None, fl - Al @ x, n),
+            (capi.AMGG_OP_RESTRICT, x, None, None, R @ x, nc),
+            (capi.AMGG_OP_PROLONG, xc, None, y0, y0 + P @ xc, n),
+        ]
+        for op, xin, fin, yin, ref, m in cases:
+            xd = _dev(xin)
+            fd = _dev(fin) if fin is not None else xd
+            yd = _dev(yin) if yin is not None else torch.zeros(m, dtype=torch.float64, device="cuda")
+            capi.amgg_level_apply(ds.ctx, l, op, 64, xd.data_ptr(), yd.data_ptr(), fd.data_ptr(), ds.stream)
+            torch.cuda.synchronize()
+            assert np.array_equal(_bits(yd.cpu().numpy()), _bits(ref)), (l, op)
+
+
+def test_tet_vcycle_fp64_linear(tet):
+    A, f, hp, ds = tet
+    ds.set_coeffs(np.array([0.6, 0.01, -0.001, 0.12, 0.01]), 2)
+    rng = np.random.default_rng(2)
+    n = A.nrows
+    u1, u2, f1, f2 = (rng.standard_normal(n) for _ in range(4))
+    f1 -= f1.mean()
+    f2 -= f2.mean()
+    a, b = 0.75, -1.25
+
+    def cyc(u, ff):
+        ud = _dev(u)
+        ds.vcycle(_dev(ff), ud, 1, 1, 64)
+        return ud.cpu().numpy()
+
+    lhs = cyc(a * u1 + b * u2, a * f1 + b * f2)
+    rhs = a * cyc(u1, f1) + b * cyc(u2, f2)
+    assert np.linalg.norm(lhs - rhs) <= 1e-12 * np.linalg.norm(rhs)
+
+
+def test_tet_solves_and_learned_gain(tet):
+    A, f, hp, ds = tet
+    Al, _ = _level_mats(hp, 0)
+    out = {}
+    for smoother in ("jacobi", "gcin"):
+        x, rc, info = _solve(ds, f, smoother, "gcin_tet_deg2.npz")
+        assert rc == 0, (smoother, rc, info.relres)
+        rel = np.linalg.norm(f - Al @ x) / np.linalg.norm(f)
+        print(f"[gpu] tet {smoother}: {info.vcycles} cycles, FP64 residual {rel:.2e}", flush=True)
+        assert rel <= 1e-8 * 1.01
+        out[smoother] = info.vcycles
+    assert out["gcin"] < out["jacobi"], out

@@ -1,0 +1,71 @@
+"""What the trained GCIN gains over the method without it (the omega-Jacobi smoother, the
+paper's baseline and fallback), on meshes none of the training or validation sets contained.
+
+For each mesh family the shipped weights were trained on (Sec. 3.3-3.4, Alg. 1), held-out
+meshes are solved with FP32 V(1,1) cycles inside FP64 flexible CG, once with omega-Jacobi and
+once with the GCIN-predicted coefficients; the learned smoother must not need more V-cycles in
+total, and its validation metric (Eq. 13: log10 of the residual after the trained number of
+cycles relative to omega-Jacobi's, averaged over the meshes as in validation) must be negative. The cycle counts of FP64
+iterative refinement are reported too: the loss rewards the first cycles' reduction, and on
+small hierarchies the learned smoother's asymptotic stationary rate can be the slower one.
+The quality of learned coefficients has no value in the paper to compare with; omega-Jacobi on
+the same meshes is the reference.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _meshes(family):
+    if family == "delaunay":
+        return [W.delaunay_p1(W.gmm_points(n, 70_000 + k)) for k, n in enumerate((9000, 12000, 15000))]
+    if family == "tet":
+        return [W.tet_fv_mesh(*W.kuhn_tets(m, 71_000 + m, 0.12)) for m in (16, 19, 22)]
+    return [W.cmesh_fv(256, 128, code, 1e4) for code in ("2412", "0012", "4415")]
+
+
+@pytest.mark.parametrize("family,weights", [("delaunay", "gcin_deg2.npz"), ("tet", "gcin_tet_deg2.npz"),
+                                            ("cmesh", "gcin_cmesh_deg2.npz")])
+def test_trained_gcin_beats_jacobi_on_held_out_meshes(family, weights):
+    from paper_2606_19251_amd import capi
+    from paper_2606_19251_amd import gcin as G
+    from paper_2606_19251_amd.solver import DeviceSolver, HostHierarchy
+
+    pred = G.Predictor.load(os.path.join(ROOT, "paper_2606_19251_amd", "weights", weights), torch.device("cuda", 0))
+    cycles = {("jacobi", "fcg"): 0, ("gcin", "fcg"): 0, ("jacobi", "ir"): 0, ("gcin", "ir"): 0}
+    metric = []
+    for k, A in enumerate(_meshes(family)):
+        hh = HostHierarchy.build(A.rowptr, A.col, A.val, max_levels=10, max_coarse=100)
+        ds = DeviceSolver(hh, 0)
+        f = W.rhs_uniform(A.nrows, 72_000 + k, zero_mean=hh.singular)
+        b = torch.from_numpy(f).cuda()
+        coeffs = pred.predict(hh, ds)
+        losses = {}
+        for name in ("jacobi", "gcin"):
+            if name == "jacobi":
+                ds.set_jacobi(2 / 3)
+            else:
+                ds.set_coeffs_device(coeffs, pred.degree)
+            for outer, key in ((capi.AMGG_OUTER_FCG, "fcg"), (capi.AMGG_OUTER_IR, "ir")):
+                _, rc, info, _ = ds.solve(b, outer=outer, precision=32, tol=1e-8, fallback=False)
+                assert rc == 0, (family, k, name, key, rc)
+                cycles[(name, key)] += info.vcycles
+            loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+            dc = torch.zeros(hh.nlevels, 2 * pred.degree + 1, dtype=torch.float64, device="cuda")
+            capi.amgg_vcycle_loss_adjoint(ds.ctx, 1, 1, 32, 4, b.data_ptr(), 0, loss.data_ptr(), dc.data_ptr(),
+                                          ds.stream)
+            torch.cuda.synchronize()
+            losses[name] = float(loss.item())
+        metric.append(losses["gcin"] - losses["jacobi"])
+        ds.close()
+    print(f"[gpu] {family}: V-cycles {cycles}, Eq. 13 metric {np.round(metric, 3)}", flush=True)
+    assert float(np.mean(metric)) < 0.0
+    assert cycles[("gcin", "fcg")] <= cycles[("jacobi", "fcg")]

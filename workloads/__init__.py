@@ -210,8 +210,11 @@ def naca4(code: str, x: np.ndarray):
     """Upper and lower surface points of a NACA 4-digit section (chord 1) at stations x."""
     m, p, t = int(code[0]) / 100.0, int(code[1]) / 10.0, int(code[2:]) / 100.0
     yt = 5 * t * (0.2969 * np.sqrt(x) - 0.1260 * x - 0.3516 * x**2 + 0.2843 * x**3 - 0.1036 * x**4)
-    yc = np.where(x < p, m / p**2 * (2 * p * x - x**2), m / (1 - p) ** 2 * ((1 - 2 * p) + 2 * p * x - x**2))
-    dy = np.where(x < p, 2 * m / p**2 * (p - x), 2 * m / (1 - p) ** 2 * (p - x))
+    if m == 0.0 or p == 0.0:  # symmetric section (00xx): no camber line
+        yc = dy = np.zeros_like(x)
+    else:
+        yc = np.where(x < p, m / p**2 * (2 * p * x - x**2), m / (1 - p) ** 2 * ((1 - 2 * p) + 2 * p * x - x**2))
+        dy = np.where(x < p, 2 * m / p**2 * (p - x), 2 * m / (1 - p) ** 2 * (p - x))
     th = np.arctan(dy)
     return (np.stack([x - yt * np.sin(th), yc + yt * np.cos(th)], 1),
             np.stack([x + yt * np.sin(th), yc - yt * np.cos(th)], 1))
@@ -381,17 +384,23 @@ def tet_fv_mesh(points: np.ndarray, tets: np.ndarray) -> CSRMatrix:
     order = morton_order((cent - cent.min(0)) / (np.ptp(cent, 0) + 1e-300))
     remap = np.empty(nt, np.int64)
     remap[order] = np.arange(nt)
-    faces = np.concatenate([np.sort(np.delete(tets, f, axis=1), axis=1) for f in range(4)])
-    owner = np.tile(np.arange(nt, dtype=np.int64), 4)
-    key = (faces[:, 0] * npnt + faces[:, 1]) * npnt + faces[:, 2]
-    srt = np.argsort(key, kind="stable")
+    keys, owners = [], []
+    for f in range(4):
+        a, b, c = (tets[:, k] for k in range(4) if k != f)
+        lo = np.minimum(np.minimum(a, b), c)
+        hi = np.maximum(np.maximum(a, b), c)
+        mid = a + b + c - lo - hi
+        keys.append((lo * npnt + mid) * npnt + hi)
+        owners.append(np.arange(nt, dtype=np.int64))
+    key = np.concatenate(keys)
+    owner = np.concatenate(owners)
+    srt = np.argsort(key)
     ks = key[srt]
     pair = np.nonzero(ks[1:] == ks[:-1])[0]
-    fa = srt[pair]
-    a, b = owner[fa], owner[srt[pair + 1]]
-    fv = faces[fa]
-    area = 0.5 * np.linalg.norm(np.cross(points[fv[:, 1]] - points[fv[:, 0]], points[fv[:, 2]] - points[fv[:, 0]]),
-                                axis=1)
+    a, b = owner[srt[pair]], owner[srt[pair + 1]]
+    fk = ks[pair]
+    v0, v1, v2 = fk // (npnt * npnt), (fk // npnt) % npnt, fk % npnt
+    area = 0.5 * np.linalg.norm(np.cross(points[v1] - points[v0], points[v2] - points[v0]), axis=1)
     dist = np.linalg.norm(cent[a] - cent[b], axis=1)
     i_all, j_all = remap[a], remap[b]
     return _laplacian_from_edges(np.minimum(i_all, j_all), np.maximum(i_all, j_all), area / dist, nt)
