@@ -1,11 +1,21 @@
 """Benchmark: time to solve to 1e-8 relative residual with FP32 V-cycles inside FP64
 flexible CG, GCIN-smoothed vs Jacobi-smoothed AMG, on one MI355X.
 
-Workload (default): P1 finite-element Laplacian on the Delaunay triangulation of 1,000,000
-points in the unit square (uniform inside, evenly spaced on the boundary), all-Neumann (singular), zero-mean
-U[-1,1] right-hand side; Ruge-Stueben hierarchy (theta 0.25, <= 10 levels, coarsest <= 500
-rows); V(1,1) cycles. One step = one complete solve from x = 0 with the hierarchy, the
-smoother and the right-hand side resident in HBM (setup is reported separately).
+Workloads (--workload):
+  delaunay1m (default)  P1 finite-element Laplacian on the Delaunay triangulation of 1,000,000
+                        points in the unit square (uniform inside, evenly spaced on the boundary),
+                        all-Neumann (singular), zero-mean U[-1,1] right-hand side;
+  tet8m                 finite-volume Poisson on the Kuhn tetrahedra of a jittered 111^3 lattice
+                        (7,986,000 cells, all-Neumann), zero-mean U[-1,1] right-hand side;
+  cmesh4m               finite-volume Poisson on a 4096 x 1024 C-mesh around a NACA 2412 section
+                        (wall aspect ratio 1e4, Dirichlet far field), U[-1,1] right-hand side.
+Ruge-Stueben hierarchy (theta 0.25, <= 10 levels, coarsest <= 500 rows); V(1,1) cycles; each
+mesh family uses the GCIN weights trained on small meshes of that family. One step = one
+complete solve from x = 0 with the hierarchy, the smoother and the right-hand side resident in
+HBM (setup is reported separately). The same solves with FP64 iterative refinement as the
+outer loop (the paper's stationary V-cycle iteration with an FP64 residual) are reported too,
+and with the default workload the fine-level residual kernel of tet8m (whose matrix does not
+fit the 256 MB last-level cache) is timed as a second roofline point.
 
 Prints one JSON line. With --gpus N > 1 it exits: the build runs on one GPU.
 """
@@ -31,7 +41,8 @@ def log(msg):
 
 
 def level_bytes_vcycle(h, smoother_sparse: bool, bv: int = 4, bi: int = 4) -> float:
-    """Algorithmic HBM bytes of one V(1,1) preconditioner cycle (u = 0 on entry) on the hierarchy."""
+    """Algorithmic HBM bytes of one V(1,1) preconditioner cycle (u = 0 on entry) on the hierarchy:
+    every matrix entry read once per pass, every vector once per pass (gathers counted once)."""
     total = 0.0
     L = h.nlevels
     for l, lev in enumerate(h.levels):
@@ -48,10 +59,11 @@ def level_bytes_vcycle(h, smoother_sparse: bool, bv: int = 4, bi: int = 4) -> fl
         if smoother_sparse:
             pre = apass + 2 * n * bv                 # u = Q f
             post = resid + apass + 3 * n * bv         # r = f - A u ; u += Q r
+            total += pre + resid + restrict + prolong + post
         else:
-            pre = 3 * n * bv                          # u = qd * f
+            pre = apass + 4 * n * bv                  # u = qd f and r = f - A u in one pass
             post = apass + 4 * n * bv                 # u' = u + qd (f - A u)
-        total += pre + resid + restrict + prolong + post
+            total += pre + restrict + prolong + post
     return total
 
 
@@ -65,21 +77,23 @@ def outer_bytes_fcg(n: int, nnz: int) -> float:
     return spmv_dot + update_xr + cast_in + castback + update_p
 
 
-# Calibrated FETCH_SIZE + WRITE_SIZE bytes per launch of the dominant kernel on the default
-# 1M workload (profiles/traffic_residual_c2_delaunay1M.md), valid only for the kernel source
-# it was measured on: reported as null once that source changes.
-TRAFFIC = {"bytes": 72808345, "npts": 1_000_000, "source": "paper_2606_19251_amd/csrc/k_csr.hip",
-           "sha256_16": "0053aaaa029d245a"}
+# Calibrated FETCH_SIZE + WRITE_SIZE bytes per launch of the dominant kernel (the fine-level
+# FP32 residual) per workload, valid only for the kernel source they were measured on: reported
+# as null once that source changes (summaries under profiles/).
+TRAFFIC_SOURCE = "paper_2606_19251_amd/csrc/k_csr.hip"
+TRAFFIC = {  # workload -> (sha256 prefix of TRAFFIC_SOURCE, bytes per launch)
+    "delaunay1m": ("9d877287f5853bf5", 72729001),
+    "tet8m": ("9d877287f5853bf5", 462801860),
+}
 
 
-def measured_traffic(npts):
+def measured_traffic(workload):
     import hashlib
 
-    path = os.path.join(ROOT, TRAFFIC["source"])
-    sha = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
-    if npts != TRAFFIC["npts"] or sha != TRAFFIC["sha256_16"]:
+    if workload not in TRAFFIC:
         return None
-    return TRAFFIC["bytes"]
+    sha = hashlib.sha256(open(os.path.join(ROOT, TRAFFIC_SOURCE), "rb").read()).hexdigest()[:16]
+    return TRAFFIC[workload][1] if sha == TRAFFIC[workload][0] else None
 
 
 def time_kernel(torch, launch_timed, stream, reps=50):
@@ -101,7 +115,9 @@ def time_kernel(torch, launch_timed, stream, reps=50):
 
 
 def cpu_baseline(A, f, gpu_iters, budget_s=20.0):
-    """The oracle's FP64 flexible-CG solve timed on the host for a bounded number of iterations."""
+    """The oracle's FP64 flexible-CG solve timed on the host for a bounded number of iterations
+    (one thread; the smoother has A's pattern whatever its coefficients, so the cost per
+    iteration is that of the GCIN-smoothed solve too)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import amg
@@ -132,13 +148,122 @@ def cpu_baseline(A, f, gpu_iters, budget_s=20.0):
     }
 
 
+WORKLOADS = {
+    "delaunay1m": ("gcin_deg2.npz", "P1 Laplacian on the Delaunay mesh of 1,000,000 points in the unit square, "
+                                    "all-Neumann"),
+    "tet8m": ("gcin_tet_deg2.npz", "FV Poisson on the Kuhn tetrahedra of a jittered 111^3 lattice "
+                                   "(7,986,000 cells), all-Neumann"),
+    "cmesh4m": ("gcin_cmesh_deg2.npz", "FV Poisson on a 4096 x 1024 C-mesh around NACA 2412, wall aspect 1e4"),
+}
+
+
+def make_workload(name):
+    import workloads as W
+
+    if name == "delaunay1m":
+        return W.delaunay_p1_problem(1_000_000, 0)
+    if name == "tet8m":
+        return W.tet_kuhn_problem(111, 0)
+    return W.airfoil_cmesh_problem(4096, 1024, 0)
+
+
+class Case:
+    """One workload on the device: hierarchy, solver, right-hand side, trained predictor."""
+
+    def __init__(self, torch, name):
+        from paper_2606_19251_amd import gcin as G
+        from paper_2606_19251_amd.solver import DeviceSolver, HostHierarchy
+
+        self.torch, self.name = torch, name
+        t0 = time.time()
+        self.A, self.f = make_workload(name)
+        log(f"{name}: n={self.A.nrows} nnz={self.A.nnz} ({time.time() - t0:.1f} s)")
+        t0 = time.time()
+        self.hh = HostHierarchy.build(self.A.rowptr, self.A.col, self.A.val, theta=0.25, max_levels=10,
+                                      max_coarse=500)
+        self.host_setup_ms = (time.time() - t0) * 1e3
+        log(f"{name}: host RS setup {self.host_setup_ms:.0f} ms, levels {[L.n for L in self.hh.levels]}")
+        self.ds = DeviceSolver(self.hh, 0)
+        self.dev = self.ds.device
+        self.b = torch.from_numpy(self.f).to(self.dev)
+        self.x = torch.empty_like(self.b)
+        self.pred = G.Predictor.load(os.path.join(ROOT, "paper_2606_19251_amd", "weights", WORKLOADS[name][0]),
+                                     self.dev)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        self.coeffs = self.pred.predict(self.hh, self.ds)
+        e.record()
+        torch.cuda.synchronize()
+        self.gnn_setup_ms = s.elapsed_time(e)
+
+    def set(self, smoother):
+        if smoother == "jacobi":
+            self.ds.set_jacobi(2.0 / 3.0)
+        else:
+            self.ds.set_coeffs_device(self.coeffs, self.pred.degree)
+
+    def solves(self, smoother, outer, steps, warmup, nu=1):
+        from paper_2606_19251_amd import capi
+
+        torch = self.torch
+        self.set(smoother)
+        kw = dict(outer=outer, precision=32, nu1=nu, nu2=nu, tol=1e-8)
+        for _ in range(warmup):
+            self.ds.solve(self.b, self.x, **kw)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(steps):
+            _, rc, info, _ = self.ds.solve(self.b, self.x, **kw)
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / steps
+        # residual recomputed in FP64 on the host from the returned x
+        xh = self.x.cpu().numpy()
+        fb = self.f - self.f.mean() if self.hh.singular else self.f
+        true_rel = float(np.linalg.norm(fb - self.A.to_scipy() @ xh) / np.linalg.norm(fb))
+        tag = "FCG" if outer == capi.AMGG_OUTER_FCG else "IR"
+        log(f"{self.name} {smoother} {tag}: {ms:.3f} ms/solve, {info.vcycles} V-cycles, rc={rc}, "
+            f"fell_back={info.fell_back}, rel={true_rel:.2e}")
+        return {"ms": round(ms, 4), "vcycles": info.vcycles, "iterations": info.iterations, "status": rc,
+                "fell_back": info.fell_back, "relres": true_rel}
+
+    def roofline(self):
+        """Fine-level FP32 residual r = f - A u: algorithmic bytes / kernel time from HIP events
+        recorded by the kernel itself on the solve stream."""
+        from paper_2606_19251_amd import capi
+
+        torch = self.torch
+        n0, z0 = self.hh.levels[0].n, self.hh.levels[0].nnz
+        self.ds.set_jacobi(2.0 / 3.0)
+        xs = torch.rand(n0, dtype=torch.float32, device=self.dev)
+        ys = torch.empty_like(xs)
+        fs = torch.rand(n0, dtype=torch.float32, device=self.dev)
+        st = self.ds.stream
+        k_ms, k_interval_ms = time_kernel(
+            torch, lambda s0, s1: capi.amgg_level_apply_timed(self.ds.ctx, 0, capi.AMGG_OP_RESIDUAL, 32, xs.data_ptr(),
+                                                              ys.data_ptr(), fs.data_ptr(), s0, s1, st),
+            torch.cuda.current_stream(self.dev))
+        rows = 256 if z0 / n0 * 256 * 1.25 <= 4096 else 128
+        k_bytes = z0 * 8 + 4 * (n0 + 1) + 3 * n0 * 4
+        achieved = k_bytes / (k_ms * 1e-3) / 1e9
+        return {"kernel": f"csr_stream_kernel<float, Resid, {rows}, 0> (fine level r = f - A u, FP32, {self.name})",
+                "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(self.name),
+                "launch_ms": round(k_ms, 5), "launch_interval_ms": round(k_interval_ms, 5),
+                "algorithmic_bytes": int(k_bytes)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--npts", type=int, default=1_000_000)
+    ap.add_argument("--workload", choices=list(WORKLOADS), default="delaunay1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-second-roofline", action="store_true",
+                    help="skip the tet8m fine-level kernel timing that follows the default workload")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch the dominant kernel and a calibration copy (for counter runs)")
     ap.add_argument("--nu", type=int, default=1)
@@ -150,56 +275,19 @@ def main():
 
     import torch
 
-    import workloads as W
     from paper_2606_19251_amd import capi
-    from paper_2606_19251_amd.solver import DeviceSolver, HostHierarchy
 
-    t0 = time.time()
-    A, f = W.delaunay_p1_problem(args.npts, 0)
-    log(f"workload n={A.nrows} nnz={A.nnz} ({time.time() - t0:.1f} s)")
-    t0 = time.time()
-    hh = HostHierarchy.build(A.rowptr, A.col, A.val, theta=0.25, max_levels=10, max_coarse=500)
-    host_setup_ms = (time.time() - t0) * 1e3
-    log(f"host RS setup {host_setup_ms:.0f} ms, levels {[L.n for L in hh.levels]}")
-    ds = DeviceSolver(hh, 0)
-    dev = ds.device
-    b = torch.from_numpy(f).to(dev)
-    x = torch.empty_like(b)
-
-    def run_solves(label, set_smoother):
-        set_smoother()
-        for _ in range(args.warmup):
-            ds.solve(b, x, outer=capi.AMGG_OUTER_FCG, precision=32, nu1=args.nu, nu2=args.nu, tol=1e-8)
-        torch.cuda.synchronize()
-        s = torch.cuda.Event(enable_timing=True)
-        e = torch.cuda.Event(enable_timing=True)
-        infos = []
-        s.record()
-        for _ in range(args.steps):
-            _, rc, info, _ = ds.solve(b, x, outer=capi.AMGG_OUTER_FCG, precision=32, nu1=args.nu, nu2=args.nu,
-                                      tol=1e-8)
-            infos.append((rc, info.iterations, info.vcycles, info.relres))
-        e.record()
-        torch.cuda.synchronize()
-        ms = s.elapsed_time(e) / args.steps
-        rc, it, vc, rel = infos[-1]
-        # residual recomputed in FP64 on the host from the returned x
-        xh = x.cpu().numpy()
-        fb = f - f.mean()
-        Aop = A.to_scipy()
-        true_rel = float(np.linalg.norm(fb - Aop @ xh) / np.linalg.norm(fb))
-        log(f"{label}: {ms:.3f} ms/solve, {vc} V-cycles, {it} iterations, rc={rc}, rel={true_rel:.2e}")
-        return {"ms": ms, "vcycles": vc, "iterations": it, "status": rc, "relres": true_rel}
-
+    case = Case(torch, args.workload)
+    ds, hh = case.ds, case.hh
     if args.profile_kernels:
         # counter runs: the dominant kernel alone, and a plain copy of known size to calibrate
         # the byte counters (256 MiB read + 256 MiB written per copy)
         ds.set_jacobi(2.0 / 3.0)
         n0 = hh.levels[0].n
-        xs = torch.rand(n0, dtype=torch.float32, device=dev)
+        xs = torch.rand(n0, dtype=torch.float32, device=case.dev)
         ys = torch.empty_like(xs)
-        fs = torch.rand(n0, dtype=torch.float32, device=dev)
-        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        fs = torch.rand(n0, dtype=torch.float32, device=case.dev)
+        src = torch.ones(64 << 20, dtype=torch.float32, device=case.dev)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         for _ in range(10):
@@ -211,79 +299,54 @@ def main():
         log("profile-kernels: 10 fine-level residual launches, 10 copies of 256 MiB")
         return
 
-    jac = run_solves("jacobi", lambda: ds.set_jacobi(2.0 / 3.0))
-    gnn = None  # filled in once a trained predictor is shipped (see below)
-    weights = os.path.join(ROOT, "paper_2606_19251_amd", "weights", "gcin_deg2.npz")
-    if os.path.exists(weights):
-        from paper_2606_19251_amd import gcin as G
+    fcg, ir = capi.AMGG_OUTER_FCG, capi.AMGG_OUTER_IR
+    jac = case.solves("jacobi", fcg, args.steps, args.warmup, args.nu)
+    gnn = case.solves("gnn", fcg, args.steps, args.warmup, args.nu)
+    gnn["setup_ms"] = round(case.gnn_setup_ms, 3)
+    ir_res = {"jacobi": case.solves("jacobi", ir, 2, 1, args.nu), "gnn": case.solves("gnn", ir, 2, 1, args.nu)}
 
-        pred = G.Predictor.load(weights, dev)
-        torch.cuda.synchronize()
-        s = torch.cuda.Event(enable_timing=True)
-        e = torch.cuda.Event(enable_timing=True)
-        s.record()
-        coeffs = pred.predict(hh, ds)
-        ds.set_coeffs_device(coeffs, pred.degree)
-        e.record()
-        torch.cuda.synchronize()
-        gnn_setup_ms = s.elapsed_time(e)
-        gnn = run_solves("gnn", lambda: ds.set_coeffs_device(coeffs, pred.degree))
-        gnn["setup_ms"] = gnn_setup_ms
-
-    # ---- V-cycle bytes and throughput
     n0, z0 = hh.levels[0].n, hh.levels[0].nnz
-    ref = gnn if gnn is not None else jac
-    vbytes = level_bytes_vcycle(hh, smoother_sparse=gnn is not None)
+    vbytes = level_bytes_vcycle(hh, smoother_sparse=True)
     obytes = outer_bytes_fcg(n0, z0)
-    solve_bytes = ref["vcycles"] * vbytes + ref["iterations"] * obytes
-    solve_gbs = solve_bytes / (ref["ms"] * 1e-3) / 1e9
-
-    # ---- dominant kernel: fine-level FP32 CSR pass, timed live with HIP events on the solve stream
-    ds.set_jacobi(2.0 / 3.0)
-    xs = torch.rand(n0, dtype=torch.float32, device=dev)
-    ys = torch.empty_like(xs)
-    fs = torch.rand(n0, dtype=torch.float32, device=dev)
-    st = ds.stream
-    k_ms, k_interval_ms = time_kernel(
-        torch, lambda s0, s1: capi.amgg_level_apply_timed(ds.ctx, 0, capi.AMGG_OP_RESIDUAL, 32, xs.data_ptr(),
-                                                          ys.data_ptr(), fs.data_ptr(), s0, s1, st),
-        torch.cuda.current_stream(dev))
-    k_bytes = z0 * 8 + 4 * (n0 + 1) + 3 * n0 * 4
-    achieved = k_bytes / (k_ms * 1e-3) / 1e9
-    roof = {"kernel": "csr_stream_kernel<float, Resid, 256, 0> (fine level r = f - A u, FP32)",
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.npts),
-            "launch_ms": round(k_ms, 5), "launch_interval_ms": round(k_interval_ms, 5),
-            "algorithmic_bytes": int(k_bytes)}
-
+    solve_gbs = (gnn["vcycles"] * vbytes + gnn["iterations"] * obytes) / (gnn["ms"] * 1e-3) / 1e9
+    roof = case.roofline()
     out = {
         "metric": METRIC,
-        "value": round(ref["ms"], 4),
+        "value": gnn["ms"],
         "unit": "ms",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ref["ms"], 4),
+        "ms_per_step": gnn["ms"],
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 cycle / f64 outer",
         "data": "synthetic",
-        "config": {"workload": f"P1 Laplacian, Delaunay of {args.npts} uniform points (n={n0}, nnz={z0}), "
+        "config": {"workload": f"{WORKLOADS[args.workload][1]} (n={n0}, nnz={z0}); GCIN-smoothed AMG, "
                                f"FCG(FP64) + FP32 V({args.nu},{args.nu}) to 1e-8",
-                   "levels": [L.n for L in hh.levels], "smoother": "gnn" if gnn is not None else "jacobi"},
-        "vcycles": ref["vcycles"],
+                   "levels": [L.n for L in hh.levels], "smoother": "gnn"},
+        "vcycles": gnn["vcycles"],
         "jacobi": jac,
         "gnn": gnn,
+        "gnn_over_jacobi_time": round(gnn["ms"] / jac["ms"], 4),
+        "ir": ir_res,
         "vcycle_bytes": int(vbytes),
         "solve_gbs_algorithmic": round(solve_gbs, 1),
-        "host_setup_ms": round(host_setup_ms, 1),
+        "host_setup_ms": round(case.host_setup_ms, 1),
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(A, f, ref["iterations"])
-    print(json.dumps(out), flush=True)
+    if args.workload == "delaunay1m" and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case.A, case.f, gnn["iterations"])
     ds.close()
+    if args.workload == "delaunay1m" and not args.no_second_roofline:
+        del case
+        second = Case(torch, "tet8m")
+        out["roofline_tet8m"] = second.roofline()
+        out["tet8m"] = {"jacobi": second.solves("jacobi", fcg, 3, 1, args.nu),
+                        "gnn": second.solves("gnn", fcg, 3, 1, args.nu)}
+        second.ds.close()
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -327,15 +327,53 @@ __global__ __launch_bounds__(NT) void layer_kernel(const int32_t* __restrict__ p
     }
 }
 
-// Per graph and channel: mean and 1/sqrt(biased variance + eps) from the tile sums.
-__global__ void stats_final_kernel(const double* __restrict__ tstat, const int32_t* __restrict__ gtile,
-                                   const float* __restrict__ gcnt, float* __restrict__ mu, float* __restrict__ rstd) {
-    const int g = blockIdx.x, c = threadIdx.x;
+// Per-graph reductions over tiles run in two fixed-order stages so that large graphs (the fine
+// level has n/64 tiles) are spread over many workgroups: stage 1 sums the tiles of each chunk
+// (at most kChunkTiles consecutive tiles of one graph, chunks counted from the graph's first
+// tile), stage 2 the chunks of each graph. In both, wave w of the workgroup sums items w, w+4,
+// w+8, ... in order and the four wave sums are added in wave order: deterministic, and a
+// graph's result does not depend on the other graphs of the batch.
+constexpr int kChunkTiles = 256;
+
+// out[k][j][c] = sum over items i in [bounds[k], bounds[k+1]) of in[i][j][c], j < K, c < HD
+template <int K>
+__global__ __launch_bounds__(NT) void chunk_sum_kernel(const double* __restrict__ in, const int32_t* __restrict__ bounds,
+                                                       double* __restrict__ out) {
+    __shared__ double sh[4][K][HD];
+    const int k = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
+    double s[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) s[j] = 0.0;
+    for (int32_t i = bounds[k] + wv; i < bounds[k + 1]; i += 4)
+#pragma unroll
+        for (int j = 0; j < K; ++j) s[j] += in[(static_cast<int64_t>(i) * K + j) * HD + c];
+#pragma unroll
+    for (int j = 0; j < K; ++j) sh[wv][j][c] = s[j];
+    __syncthreads();
+    if (wv == 0)
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            out[(static_cast<int64_t>(k) * K + j) * HD + c] = ((sh[0][j][c] + sh[1][j][c]) + sh[2][j][c]) + sh[3][j][c];
+}
+
+// Per graph and channel: mean and 1/sqrt(biased variance + eps) from the chunk sums.
+__global__ __launch_bounds__(NT) void stats_final_kernel(const double* __restrict__ cstat,
+                                                         const int32_t* __restrict__ gchunk,
+                                                         const float* __restrict__ gcnt, float* __restrict__ mu,
+                                                         float* __restrict__ rstd) {
+    __shared__ double sh[4][2][HD];
+    const int g = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
     double s1 = 0.0, s2 = 0.0;
-    for (int t = gtile[g]; t < gtile[g + 1]; ++t) {
-        s1 += tstat[t * 2 * HD + c];
-        s2 += tstat[t * 2 * HD + HD + c];
+    for (int32_t k = gchunk[g] + wv; k < gchunk[g + 1]; k += 4) {
+        s1 += cstat[static_cast<int64_t>(k) * 2 * HD + c];
+        s2 += cstat[static_cast<int64_t>(k) * 2 * HD + HD + c];
     }
+    sh[wv][0][c] = s1;
+    sh[wv][1][c] = s2;
+    __syncthreads();
+    if (wv != 0) return;
+    s1 = ((sh[0][0][c] + sh[1][0][c]) + sh[2][0][c]) + sh[3][0][c];
+    s2 = ((sh[0][1][c] + sh[1][1][c]) + sh[2][1][c]) + sh[3][1][c];
     const double n = gcnt[g];
     const double m = s1 / n;
     double var = s2 / n - m * m;
@@ -387,21 +425,64 @@ __global__ __launch_bounds__(NT) void pool_tile_kernel(const int32_t* __restrict
     }
 }
 
-__global__ void pool_final_kernel(const double* __restrict__ tsum, const float* __restrict__ tmax,
-                                  const int32_t* __restrict__ targ, const int32_t* __restrict__ gtile,
-                                  const float* __restrict__ gcnt, int layer, float* __restrict__ pooled,
-                                  int32_t* __restrict__ argmax) {
-    const int g = blockIdx.x, c = threadIdx.x;
+// Max with its arg-max, ties to the lowest node index (any combination order gives the same).
+__device__ __forceinline__ void max_merge(float& mx, int32_t& am, float m2, int32_t a2) {
+    if (m2 > mx || (m2 == mx && a2 < am)) {
+        mx = m2;
+        am = a2;
+    }
+}
+
+// Stage 1 of the pooling reduction (see chunk_sum_kernel): per chunk, sum, max and arg-max.
+__global__ __launch_bounds__(NT) void pool_chunk_kernel(const double* __restrict__ tsum, const float* __restrict__ tmax,
+                                                        const int32_t* __restrict__ targ,
+                                                        const int32_t* __restrict__ bounds, double* __restrict__ csum,
+                                                        float* __restrict__ cmax, int32_t* __restrict__ carg) {
+    __shared__ double ss[4][HD];
+    __shared__ float sm[4][HD];
+    __shared__ int32_t sa[4][HD];
+    const int k = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
     double s = 0.0;
     float mx = -INFINITY;
     int32_t am = INT32_MAX;
-    for (int t = gtile[g]; t < gtile[g + 1]; ++t) {
-        s += tsum[t * HD + c];
-        if (tmax[t * HD + c] > mx) {
-            mx = tmax[t * HD + c];
-            am = targ[t * HD + c];
-        }
+    for (int32_t t = bounds[k] + wv; t < bounds[k + 1]; t += 4) {
+        s += tsum[static_cast<int64_t>(t) * HD + c];
+        max_merge(mx, am, tmax[static_cast<int64_t>(t) * HD + c], targ[static_cast<int64_t>(t) * HD + c]);
     }
+    ss[wv][c] = s;
+    sm[wv][c] = mx;
+    sa[wv][c] = am;
+    __syncthreads();
+    if (wv != 0) return;
+    for (int w = 1; w < 4; ++w) max_merge(mx, am, sm[w][c], sa[w][c]);
+    csum[static_cast<int64_t>(k) * HD + c] = ((ss[0][c] + ss[1][c]) + ss[2][c]) + ss[3][c];
+    cmax[static_cast<int64_t>(k) * HD + c] = mx;
+    carg[static_cast<int64_t>(k) * HD + c] = am;
+}
+
+__global__ __launch_bounds__(NT) void pool_final_kernel(const double* __restrict__ csum, const float* __restrict__ cmax,
+                                                        const int32_t* __restrict__ carg,
+                                                        const int32_t* __restrict__ gchunk,
+                                                        const float* __restrict__ gcnt, int layer,
+                                                        float* __restrict__ pooled, int32_t* __restrict__ argmax) {
+    __shared__ double ss[4][HD];
+    __shared__ float sm[4][HD];
+    __shared__ int32_t sa[4][HD];
+    const int g = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
+    double s = 0.0;
+    float mx = -INFINITY;
+    int32_t am = INT32_MAX;
+    for (int32_t k = gchunk[g] + wv; k < gchunk[g + 1]; k += 4) {
+        s += csum[static_cast<int64_t>(k) * HD + c];
+        max_merge(mx, am, cmax[static_cast<int64_t>(k) * HD + c], carg[static_cast<int64_t>(k) * HD + c]);
+    }
+    ss[wv][c] = s;
+    sm[wv][c] = mx;
+    sa[wv][c] = am;
+    __syncthreads();
+    if (wv != 0) return;
+    for (int w = 1; w < 4; ++w) max_merge(mx, am, sm[w][c], sa[w][c]);
+    s = ((ss[0][c] + ss[1][c]) + ss[2][c]) + ss[3][c];
     pooled[(g * NL + layer) * 2 * HD + c] = static_cast<float>(s / gcnt[g]);
     pooled[(g * NL + layer) * 2 * HD + HD + c] = mx;
     argmax[(g * NL + layer) * HD + c] = am;
@@ -593,21 +674,27 @@ __global__ __launch_bounds__(NT) void bwd_a_kernel(const int32_t* __restrict__ p
     }
 }
 
-// Per graph: means of dxhat and dxhat*xhat; gamma/beta gradients of the graph.
-__global__ void bwd_final_kernel(const double* __restrict__ tb, const int32_t* __restrict__ gtile,
-                                 const float* __restrict__ gcnt, float* __restrict__ gmean, double* __restrict__ ggb) {
-    const int g = blockIdx.x, c = threadIdx.x;
-    double sa = 0.0, sb = 0.0, sg = 0.0, sbe = 0.0;
-    for (int t = gtile[g]; t < gtile[g + 1]; ++t) {
-        sa += tb[t * 4 * HD + c];
-        sb += tb[t * 4 * HD + HD + c];
-        sg += tb[t * 4 * HD + 2 * HD + c];
-        sbe += tb[t * 4 * HD + 3 * HD + c];
-    }
-    gmean[g * 2 * HD + c] = static_cast<float>(sa / gcnt[g]);
-    gmean[g * 2 * HD + HD + c] = static_cast<float>(sb / gcnt[g]);
-    ggb[g * 2 * HD + c] = sg;
-    ggb[g * 2 * HD + HD + c] = sbe;
+// Per graph: means of dxhat and dxhat*xhat; gamma/beta gradients of the graph (from the chunk
+// sums of the four per-tile quantities, as in stats_final_kernel).
+__global__ __launch_bounds__(NT) void bwd_final_kernel(const double* __restrict__ ctb, const int32_t* __restrict__ gchunk,
+                                                       const float* __restrict__ gcnt, float* __restrict__ gmean,
+                                                       double* __restrict__ ggb) {
+    __shared__ double sh[4][4][HD];
+    const int g = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int32_t k = gchunk[g] + wv; k < gchunk[g + 1]; k += 4)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s[j] += ctb[(static_cast<int64_t>(k) * 4 + j) * HD + c];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) sh[wv][j][c] = s[j];
+    __syncthreads();
+    if (wv != 0) return;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] = ((sh[0][j][c] + sh[1][j][c]) + sh[2][j][c]) + sh[3][j][c];
+    gmean[g * 2 * HD + c] = static_cast<float>(s[0] / gcnt[g]);
+    gmean[g * 2 * HD + HD + c] = static_cast<float>(s[1] / gcnt[g]);
+    ggb[g * 2 * HD + c] = s[2];
+    ggb[g * 2 * HD + HD + c] = s[3];
 }
 
 // Layer backward, second half. dY = rstd (dxhat - mean(dxhat) - xhat mean(dxhat xhat));
@@ -841,8 +928,14 @@ struct gcin_batch {
     int64_t N = 0, E = 0;
     int ntiles = 0;
     std::vector<int32_t> goff, gend, gtile, gn;
+    std::vector<int32_t> cbound, gchunk;  // chunk tile bounds [nchunks + 1], graph chunk bounds [G + 1]
+    int nchunks = 0;
     // device
     int32_t *d_gend = nullptr, *d_gtile = nullptr, *d_tile_graph = nullptr;
+    int32_t *d_cbound = nullptr, *d_gchunk = nullptr;
+    double* cbuf = nullptr;  // chunk partial sums (up to 4 HD doubles per chunk)
+    float* cmax = nullptr;
+    int32_t* carg = nullptr;
     float* d_gcnt = nullptr;
     int32_t *ptr = nullptr, *col = nullptr;
     float *w = nullptr, *x0 = nullptr, *H0 = nullptr;
@@ -888,6 +981,11 @@ size_t layout_batch(gcin_batch* b, uintptr_t base) {
     b->d_gtile = cv.take<int32_t>(G + 1);
     b->d_tile_graph = cv.take<int32_t>(T);
     b->d_gcnt = cv.take<float>(G);
+    b->d_cbound = cv.take<int32_t>(static_cast<size_t>(b->nchunks) + 1);
+    b->d_gchunk = cv.take<int32_t>(G + 1);
+    b->cbuf = cv.take<double>(static_cast<size_t>(b->nchunks) * 4 * HD);
+    b->cmax = cv.take<float>(static_cast<size_t>(b->nchunks) * HD);
+    b->carg = cv.take<int32_t>(static_cast<size_t>(b->nchunks) * HD);
     b->ptr = cv.take<int32_t>(N + 1);
     b->col = cv.take<int32_t>(E);
     b->w = cv.take<float>(E);
@@ -945,6 +1043,15 @@ int plan_batch(gcin_batch* b, int ngraphs, const int32_t* n, const int32_t* nnz)
     }
     b->goff[ngraphs] = static_cast<int32_t>(rows);
     b->gtile[ngraphs] = static_cast<int32_t>(rows / TILE);
+    b->cbound.clear();
+    b->gchunk.assign(ngraphs + 1, 0);
+    for (int g = 0; g < ngraphs; ++g) {
+        b->gchunk[g] = static_cast<int32_t>(b->cbound.size());
+        for (int32_t t = b->gtile[g]; t < b->gtile[g + 1]; t += kChunkTiles) b->cbound.push_back(t);
+    }
+    b->gchunk[ngraphs] = static_cast<int32_t>(b->cbound.size());
+    b->nchunks = static_cast<int>(b->cbound.size());
+    b->cbound.push_back(b->gtile[ngraphs]);
     b->N = rows;
     b->E = edges;
     b->ntiles = static_cast<int>(rows / TILE);
@@ -1013,6 +1120,12 @@ extern "C" int gcin_batch_create(int ngraphs, const gcin_graph* graphs, void* wo
         if (e == hipSuccess)
             e = hipMemcpyAsync(b->d_tile_graph, tile_graph.data(), sizeof(int32_t) * b->ntiles, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(b->d_gcnt, cnt.data(), sizeof(float) * ngraphs, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->d_cbound, b->cbound.data(), sizeof(int32_t) * b->cbound.size(), hipMemcpyHostToDevice,
+                               st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->d_gchunk, b->gchunk.data(), sizeof(int32_t) * b->gchunk.size(), hipMemcpyHostToDevice,
+                               st);
         int64_t e0 = 0;
         for (int g = 0; g < ngraphs && e == hipSuccess; ++g) {
             fill_graph_kernel<<<grid_of(n[g], 256), 256, 0, st>>>(n[g], graphs[g].rowptr, graphs[g].col, graphs[g].val,
@@ -1054,19 +1167,23 @@ extern "C" int gcin_forward(gcin_batch* b, int degree, int precision, const floa
         const int T = b->ntiles, G = b->G;
         layer0_kernel<<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->x0, b->d_tile_graph, b->d_gend, P + o.convW[0],
                                         P + o.convb[0], b->H0, b->Y[0], b->tstat);
-        stats_final_kernel<<<G, HD, 0, st>>>(b->tstat, b->d_gtile, b->d_gcnt, b->mu[0], b->rstd[0]);
+        const int C = b->nchunks;
+        chunk_sum_kernel<2><<<C, NT, 0, st>>>(b->tstat, b->d_cbound, b->cbuf);
+        stats_final_kernel<<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->mu[0], b->rstd[0]);
         for (int l = 1; l < NL; ++l) {
             auto kern = precision == GCIN_BF16X3 ? layer_kernel<true, true>
                         : precision == GCIN_BF16 ? layer_kernel<true, false> : layer_kernel<false, false>;
             kern<<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->d_tile_graph, b->d_gend, b->Y[l - 1], b->mu[l - 1],
                                    b->rstd[l - 1], P + o.gam[l - 1], P + o.bet[l - 1], P + o.convW[l], P + o.convb[l],
                                    b->H[l], b->Y[l], b->tstat);
-            stats_final_kernel<<<G, HD, 0, st>>>(b->tstat, b->d_gtile, b->d_gcnt, b->mu[l], b->rstd[l]);
+            chunk_sum_kernel<2><<<C, NT, 0, st>>>(b->tstat, b->d_cbound, b->cbuf);
+            stats_final_kernel<<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->mu[l], b->rstd[l]);
         }
         for (int l = 0; l < NL; ++l) {
             pool_tile_kernel<<<T, NT, 0, st>>>(b->d_tile_graph, b->d_gend, b->Y[l], b->mu[l], b->rstd[l], P + o.gam[l],
                                                P + o.bet[l], b->tpsum, b->tpmax, b->tparg);
-            pool_final_kernel<<<G, HD, 0, st>>>(b->tpsum, b->tpmax, b->tparg, b->d_gtile, b->d_gcnt, l, b->pooled,
+            pool_chunk_kernel<<<C, NT, 0, st>>>(b->tpsum, b->tpmax, b->tparg, b->d_cbound, b->cbuf, b->cmax, b->carg);
+            pool_final_kernel<<<G, NT, 0, st>>>(b->cbuf, b->cmax, b->carg, b->d_gchunk, b->d_gcnt, l, b->pooled,
                                                 b->argmax);
         }
         head_fwd_kernel<<<G, 128, 0, st>>>(P, o, b->pooled, b->hs, coeffs_out);
@@ -1096,7 +1213,8 @@ extern "C" int gcin_backward(gcin_batch* b, int degree, int precision, const flo
             bwd_a_kernel<<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->d_tile_graph, b->d_gend, b->d_gcnt, b->Y[l], b->mu[l],
                                            b->rstd[l], P + o.gam[l], P + o.bet[l], b->dpooled, b->argmax, l, dHn,
                                            b->dxh, b->tb);
-            bwd_final_kernel<<<G, HD, 0, st>>>(b->tb, b->d_gtile, b->d_gcnt, b->gmean, b->ggb);
+            chunk_sum_kernel<4><<<b->nchunks, NT, 0, st>>>(b->tb, b->d_cbound, b->cbuf);
+            bwd_final_kernel<<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->gmean, b->ggb);
             // gamma / beta of this layer
             reduce_parts_f64_kernel<<<1, HD, 0, st>>>(b->ggb, G, 2 * HD, HD, grads + o.gam[l]);
             reduce_parts_f64_kernel<<<1, HD, 0, st>>>(b->ggb + HD, G, 2 * HD, HD, grads + o.bet[l]);
