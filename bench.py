@@ -266,6 +266,8 @@ def main():
                     help="skip the tet8m fine-level kernel timing that follows the default workload")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch the dominant kernel and a calibration copy (for counter runs)")
+    ap.add_argument("--profile-gcin", action="store_true",
+                    help="only run the GCIN inference (BF16 MFMA) on the workload's hierarchy, 5 times (for counter runs)")
     ap.add_argument("--nu", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -279,6 +281,13 @@ def main():
 
     case = Case(torch, args.workload)
     ds, hh = case.ds, case.hh
+    if args.profile_gcin:
+        for _ in range(5):
+            case.pred.predict(hh, ds)
+        torch.cuda.synchronize()
+        log(f"profile-gcin: 5 GCIN forward passes over {hh.nlevels} levels "
+            f"({sum(L.n for L in hh.levels)} nodes, {sum(L.nnz for L in hh.levels)} entries)")
+        return
     if args.profile_kernels:
         # counter runs: the dominant kernel alone, and a plain copy of known size to calibrate
         # the byte counters (256 MiB read + 256 MiB written per copy)

@@ -89,6 +89,48 @@ __device__ __forceinline__ float normrelu(float y, float mu, float rs, float ga,
     return fmaxf((y - mu) * rs * ga + be, 0.0f);
 }
 
+// Aggregation over the stored entries of a wavefront's rows [r0, r1) of the batched graph (the
+// row index is uniform over the wavefront, lane = channel). Entries are visited in stored order,
+// kAggBatch at a time: the batch's column indices and weights are loaded first, then all of its
+// gathers load(j), so that each wavefront keeps kAggBatch gathers in flight; use(w, v) is then
+// applied in entry order and done(row) is called once per row after its last entry (rows
+// without entries included).
+constexpr int kAggBatch = 8;
+
+template <typename V, class Load, class Use, class Done>
+__device__ __forceinline__ void visit_rows(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                           const float* __restrict__ w, int32_t r0, int32_t r1, Load load, Use use,
+                                           Done done) {
+    const int32_t kend = ptr[r1];
+    int32_t r = r0;
+    int32_t rnext = ptr[r0 + 1];
+    for (int32_t k = ptr[r0]; k < kend; k += kAggBatch) {
+        int32_t cj[kAggBatch];
+        float wj[kAggBatch];
+        V vj[kAggBatch];
+#pragma unroll
+        for (int q = 0; q < kAggBatch; ++q) {
+            const int32_t kk = min(k + q, kend - 1);
+            cj[q] = col[kk];
+            wj[q] = w[kk];
+        }
+#pragma unroll
+        for (int q = 0; q < kAggBatch; ++q) vj[q] = load(cj[q]);
+#pragma unroll
+        for (int q = 0; q < kAggBatch; ++q) {
+            if (k + q < kend) {
+                while (k + q >= rnext) {
+                    done(r);
+                    ++r;
+                    rnext = ptr[r + 1];
+                }
+                use(wj[q], vj[q]);
+            }
+        }
+    }
+    for (; r < r1; ++r) done(r);
+}
+
 // Sum over the 4 wavefronts of a workgroup, per channel (lane), into out[c] (thread wave 0).
 __device__ __forceinline__ double wave4_sum(double v, double (*sh)[HD]) {
     const int wv = threadIdx.x / HD, c = threadIdx.x % HD;
@@ -150,26 +192,29 @@ __global__ __launch_bounds__(NT) void layer0_kernel(const int32_t* __restrict__ 
     const int32_t end = gend[tile_graph[tile]];
     const float w0 = W0[c], w1 = W0[HD + c], bb = b0[c];
     double s1 = 0.0, s2 = 0.0;
-    for (int r = 0; r < 16; ++r) {
-        const int32_t row = tile * TILE + wv * 16 + r;
-        float y = 0.0f;
-        if (row < end) {
-            float h0 = 0.0f, h1 = 0.0f;
-            for (int32_t p = ptr[row]; p < ptr[row + 1]; ++p) {
-                const int32_t j = col[p];
-                h0 += w[p] * x0[2 * j];
-                h1 += w[p] * x0[2 * j + 1];
+    float h0 = 0.0f, h1 = 0.0f;
+    const int32_t r0 = tile * TILE + wv * 16;
+    visit_rows<float2>(
+        ptr, col, w, r0, r0 + 16,
+        [&](int32_t j) { return make_float2(x0[2 * j], x0[2 * j + 1]); },
+        [&](float wp, float2 v) {
+            h0 += wp * v.x;
+            h1 += wp * v.y;
+        },
+        [&](int32_t row) {
+            float y = 0.0f;
+            if (row < end) {
+                y = bb + h0 * w0 + h1 * w1;
+                if (c == 0) {
+                    H0[2 * row] = h0;
+                    H0[2 * row + 1] = h1;
+                }
+                s1 += y;
+                s2 += static_cast<double>(y) * y;
             }
-            y = bb + h0 * w0 + h1 * w1;
-            if (c == 0) {
-                H0[2 * row] = h0;
-                H0[2 * row + 1] = h1;
-            }
-            s1 += y;
-            s2 += static_cast<double>(y) * y;
-        }
-        Y[static_cast<int64_t>(row) * HD + c] = y;
-    }
+            Y[static_cast<int64_t>(row) * HD + c] = y;
+            h0 = h1 = 0.0f;
+        });
     s1 = wave4_sum(s1, sh);
     s2 = wave4_sum(s2, sh);
     if (wv == 0) {
@@ -293,16 +338,17 @@ __global__ __launch_bounds__(NT) void layer_kernel(const int32_t* __restrict__ p
         stage_bf16_split_t(W, Bt, Btlo);
     else if constexpr (MFMA)
         stage_bf16(W, true, Bt);
-    for (int r = 0; r < 16; ++r) {
-        const int lr = wv * 16 + r;
-        const int32_t row = tile * TILE + lr;
-        float h = 0.0f;
-        if (row < end)
-            for (int32_t p = ptr[row]; p < ptr[row + 1]; ++p)
-                h += w[p] * normrelu(Yp[static_cast<int64_t>(col[p]) * HD + c], mu, rs, ga, be);
-        Hs[lr][c] = h;
-        Hout[static_cast<int64_t>(row) * HD + c] = h;
-    }
+    float h = 0.0f;
+    const int32_t r0 = tile * TILE + wv * 16;
+    visit_rows<float>(
+        ptr, col, w, r0, r0 + 16, [&](int32_t j) { return Yp[static_cast<int64_t>(j) * HD + c]; },
+        [&](float wp, float v) { h += wp * normrelu(v, mu, rs, ga, be); },
+        [&](int32_t row) {
+            const float hv = row < end ? h : 0.0f;
+            Hs[row - tile * TILE][c] = hv;
+            Hout[static_cast<int64_t>(row) * HD + c] = hv;
+            h = 0.0f;
+        });
     __syncthreads();
     tile_gemm<MFMA, true, X3>(Hs, W, Bt, Ds, Btlo);
     __syncthreads();
@@ -644,13 +690,11 @@ __global__ __launch_bounds__(NT) void bwd_a_kernel(const int32_t* __restrict__ p
     const float dmax = dpooled[(g * NL + layer) * 2 * HD + HD + c];
     const int32_t am = argmax[(g * NL + layer) * HD + c];
     double sa = 0.0, sb = 0.0, sg = 0.0, sbe = 0.0;
-    for (int r = 0; r < 16; ++r) {
-        const int32_t row = tile * TILE + wv * 16 + r;
+    float acc = 0.0f;  // sum over the row of w * dH of the layer above (A_hat^T = A_hat)
+    auto row_done = [&](int32_t row) {
         float d = 0.0f;
         if (row < end) {
-            float dx = dmean + (row == am ? dmax : 0.0f);
-            if (dHn)
-                for (int32_t p = ptr[row]; p < ptr[row + 1]; ++p) dx += w[p] * dHn[static_cast<int64_t>(col[p]) * HD + c];
+            const float dx = dmean + (row == am ? dmax : 0.0f) + acc;
             const float xh = (Y[static_cast<int64_t>(row) * HD + c] - m) * rs;
             const float xn = xh * ga + be;
             const float dxn = xn > 0.0f ? dx : 0.0f;
@@ -661,7 +705,15 @@ __global__ __launch_bounds__(NT) void bwd_a_kernel(const int32_t* __restrict__ p
             sbe += dxn;
         }
         dxh[static_cast<int64_t>(row) * HD + c] = d;
-    }
+        acc = 0.0f;
+    };
+    const int32_t r0 = tile * TILE + wv * 16;
+    if (dHn)
+        visit_rows<float>(
+            ptr, col, w, r0, r0 + 16, [&](int32_t j) { return dHn[static_cast<int64_t>(j) * HD + c]; },
+            [&](float wp, float v) { acc += wp * v; }, row_done);
+    else
+        for (int32_t row = r0; row < r0 + 16; ++row) row_done(row);
     sa = wave4_sum(sa, sh);
     sb = wave4_sum(sb, sh);
     sg = wave4_sum(sg, sh);
