@@ -95,7 +95,7 @@ __device__ __forceinline__ float normrelu(float y, float mu, float rs, float ga,
 // gathers load(j), so that each wavefront keeps kAggBatch gathers in flight; use(w, v) is then
 // applied in entry order and done(row) is called once per row after its last entry (rows
 // without entries included).
-constexpr int kAggBatch = 8;
+constexpr int kAggBatch = 16;
 
 template <typename V, class Load, class Use, class Done>
 __device__ __forceinline__ void visit_rows(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
