@@ -71,3 +71,38 @@ def test_generators_are_deterministic():
     t1 = W.tet_fv(W.jittered_lattice(7, 1))
     t2 = W.tet_fv(W.jittered_lattice(7, 1))
     assert np.array_equal(t1.col, t2.col) and np.array_equal(t1.val, t2.val)
+
+
+def test_kuhn_tetrahedra_keep_orientation_and_fill_the_cube():
+    m = 9
+    P0, T = W.kuhn_tets(m, 0, jitter=0.0)
+    P, T2 = W.kuhn_tets(m, 0, jitter=0.15)
+    assert np.array_equal(T, T2) and T.shape == (6 * (m - 1) ** 3, 4)
+
+    def vol(P):
+        a, b, c, d = (P[T[:, k]] for k in range(4))
+        return np.einsum("ij,ij->i", np.cross(b - a, c - a), d - a) / 6.0
+
+    v0, v = vol(P0), vol(P)
+    assert np.all(np.sign(v) == np.sign(v0)) and np.all(np.abs(v) > 0)
+    assert abs(np.abs(v0).sum() - 1.0) < 1e-12 and abs(np.abs(v).sum() - 1.0) < 1e-12  # a partition of the cube
+
+
+def test_tet_fv_mesh_face_neighbours():
+    A = W.tet_fv_mesh(*W.kuhn_tets(7, 3))
+    deg = np.diff(A.rowptr) - 1
+    assert deg.max() == 4 and deg.min() >= 1
+    # interior cells have four face neighbours; boundary faces (2 per boundary square) are open
+    n_bdry_faces = 6 * 2 * 6 ** 2
+    assert (4 * A.nrows - deg.sum()) == n_bdry_faces
+    S = A.to_scipy()
+    assert abs(S - S.T).max() == 0.0
+    assert np.abs(np.asarray(S.sum(axis=1))).max() <= 1e-12 * S.diagonal().max()
+
+
+def test_symmetric_naca_section_has_no_camber():
+    x = np.linspace(0.0, 1.0, 41)
+    up, lo = W.naca4("0012", x)
+    assert np.allclose(up[:, 0], x) and np.allclose(lo[:, 0], x)
+    assert np.allclose(up[:, 1], -lo[:, 1])
+    assert abs(up[:, 1].max() - 0.06) < 2e-3  # 12 % thickness, half above the chord
