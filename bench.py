@@ -82,8 +82,8 @@ def outer_bytes_fcg(n: int, nnz: int) -> float:
 # as null once that source changes (summaries under profiles/).
 TRAFFIC_SOURCE = "paper_2606_19251_amd/csrc/k_csr.hip"
 TRAFFIC = {  # workload -> (sha256 prefix of TRAFFIC_SOURCE, bytes per launch)
-    "delaunay1m": ("9d877287f5853bf5", 72729001),
-    "tet8m": ("9d877287f5853bf5", 462801860),
+    "delaunay1m": ("0a5b7f02c26dffaa", 72729049),
+    "tet8m": ("0a5b7f02c26dffaa", 462842842),
 }
 
 

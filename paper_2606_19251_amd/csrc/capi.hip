@@ -236,8 +236,13 @@ extern "C" int amgg_create(amgg_ctx** out, int device, int nlevels) {
         c->device = device;
         c->nlevels = nlevels;
         if ((e = hipSetDevice(device)) != hipSuccess ||
-            (e = hipHostMalloc(&c->host_scal, sizeof(double) * kSlots)) != hipSuccess ||
-            (e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+            (e = hipHostMalloc(&c->host_scal, sizeof(double) * kSlots * 3)) != hipSuccess ||
+            (e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming)) != hipSuccess) {
+            for (hipEvent_t ev : c->ev)
+                if (ev) (void)hipEventDestroy(ev);
+            if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
             if (c->host_scal) (void)hipHostFree(c->host_scal);
             delete c;
             return hip_fail(e, "amgg_create");
@@ -256,6 +261,8 @@ extern "C" int amgg_destroy(amgg_ctx* c) {
     if (!c) return AMGG_OK;
     drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (hipEvent_t ev : c->ev)
+        if (ev) (void)hipEventDestroy(ev);
     if (c->host_scal) (void)hipHostFree(c->host_scal);
     delete c;
     return AMGG_OK;

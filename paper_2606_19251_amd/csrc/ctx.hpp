@@ -110,8 +110,9 @@ struct amgg_ctx {
     int singular = 0;
     void* ws = nullptr;
     size_t ws_bytes = 0;
-    double* host_scal = nullptr;  // pinned host copy of the device scalars
+    double* host_scal = nullptr;  // pinned host copies of the device scalars: 3 slots of kSlots
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
+    hipEvent_t ev[2] = {nullptr, nullptr};  // completion of the two pipelined scalar copies
     struct Graph {
         std::string key;
         hipGraphExec_t exec;

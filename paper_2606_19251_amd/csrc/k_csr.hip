@@ -99,10 +99,9 @@ constexpr int kChunk = 8;  // entries per thread per round of a product stream
 // line) and stores its unused product past ne instead of branching, so that all value/column
 // loads of a round are issued together and then all of its gathers: each wave keeps many loads
 // in flight. out must hold ne rounded up to a multiple of kChunk * kBlock.
-template <typename T, bool SCALED = false>
-__device__ __forceinline__ void stream_products(int32_t ne, const T* __restrict__ m, const int32_t* __restrict__ col,
-                                                const T* __restrict__ x, const T* __restrict__ d,
-                                                T* __restrict__ out) {
+template <typename T, class Gather>
+__device__ __forceinline__ void stream_products_g(int32_t ne, const T* __restrict__ m,
+                                                  const int32_t* __restrict__ col, Gather gather, T* __restrict__ out) {
     for (int32_t base = 0; base < ne; base += kChunk * kBlock) {
         T v[kChunk];
         int32_t c[kChunk];
@@ -114,17 +113,20 @@ __device__ __forceinline__ void stream_products(int32_t ne, const T* __restrict_
         }
         T p[kChunk];
 #pragma unroll
-        for (int q = 0; q < kChunk; ++q) {
-            if constexpr (SCALED) {
-                const T g = d[c[q]] * x[c[q]];
-                p[q] = v[q] * g;
-            } else {
-                p[q] = v[q] * x[c[q]];
-            }
-        }
+        for (int q = 0; q < kChunk; ++q) p[q] = v[q] * gather(c[q]);
 #pragma unroll
         for (int q = 0; q < kChunk; ++q) out[base + static_cast<int32_t>(threadIdx.x) + q * kBlock] = p[q];
     }
+}
+
+template <typename T, bool SCALED = false>
+__device__ __forceinline__ void stream_products(int32_t ne, const T* __restrict__ m, const int32_t* __restrict__ col,
+                                                const T* __restrict__ x, const T* __restrict__ d,
+                                                T* __restrict__ out) {
+    if constexpr (SCALED)
+        stream_products_g<T>(ne, m, col, [&](int32_t j) { return d[j] * x[j]; }, out);
+    else
+        stream_products_g<T>(ne, m, col, [&](int32_t j) { return x[j]; }, out);
 }
 static_assert(kStreamCap % (kChunk * kBlock) == 0, "product buffers hold whole rounds");
 

@@ -124,6 +124,7 @@ __global__ __launch_bounds__(kBlock) void fcg_update_xr_kernel(int32_t n, double
                                                               double* __restrict__ rnew,
                                                               const double* __restrict__ s,
                                                               double* __restrict__ partial) {
+    if (s[kHalt] != 0.0 || s[kFlag] != 0.0) return;  // uniform over the grid
     const double a = s[kAlpha];
     double v = 0.0;
     for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += kReduceBlocks * kBlock) {
@@ -201,13 +202,45 @@ __global__ void fcg_update_p_kernel(int32_t n, const double* __restrict__ z, dou
 
 __global__ void ir_update_f32_kernel(int32_t n, double* __restrict__ x, const float* __restrict__ u32,
                                      const double* __restrict__ s) {
+    if (s[kHalt] != 0.0) return;
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n) x[i] += static_cast<double>(u32[i]) * s[kNorm];
 }
 
-__global__ void ir_update_f64_kernel(int32_t n, double* __restrict__ x, const double* __restrict__ e) {
+__global__ void ir_update_f64_kernel(int32_t n, double* __restrict__ x, const double* __restrict__ e,
+                                     const double* __restrict__ s) {
+    if (s[kHalt] != 0.0) return;
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n) x[i] += e[i];
+}
+
+__global__ void fcg_set_limits_kernel(double* __restrict__ s, double tol2, double div2) {
+    if (threadIdx.x == 0) {
+        s[kTolRR] = tol2 * s[kRR];
+        s[kDivRR] = div2 * s[kRR];
+        s[kHalt] = 0.0;
+        s[kFlag] = 0.0;
+    }
+}
+
+__global__ void fcg_clear_halt_kernel(double* __restrict__ s) {
+    if (threadIdx.x == 0) {
+        s[kHalt] = 0.0;
+        s[kFlag] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void fcg_finish_rr_guarded_kernel(const double* __restrict__ partial, int count,
+                                                                      double* __restrict__ s) {
+    if (s[kHalt] != 0.0 || s[kFlag] != 0.0) return;
+    const double rr = sum_partials(partial, count);
+    if (threadIdx.x == 0) {
+        s[kRR] = rr;
+        const double nrm = sqrt(rr);
+        s[kNorm] = nrm;
+        s[kInvNorm] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        if (rr <= s[kTolRR] || !(rr <= s[kDivRR])) s[kHalt] = 1.0;
+    }
 }
 
 }  // namespace
@@ -329,9 +362,24 @@ hipError_t ir_update_f32(int32_t n, double* x, const float* u32, const double* s
     return hipGetLastError();
 }
 
-hipError_t ir_update_f64(int32_t n, double* x, const double* e, hipStream_t stream) {
+hipError_t fcg_set_limits(double* s, double tol, double div, hipStream_t stream) {
+    fcg_set_limits_kernel<<<1, 64, 0, stream>>>(s, tol * tol, div * div);
+    return hipGetLastError();
+}
+
+hipError_t fcg_clear_halt(double* s, hipStream_t stream) {
+    fcg_clear_halt_kernel<<<1, 64, 0, stream>>>(s);
+    return hipGetLastError();
+}
+
+hipError_t fcg_finish_rr_guarded(const double* partial, int count, double* s, hipStream_t stream) {
+    fcg_finish_rr_guarded_kernel<<<1, kBlock, 0, stream>>>(partial, count, s);
+    return hipGetLastError();
+}
+
+hipError_t ir_update_f64(int32_t n, double* x, const double* e, const double* s, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
-    ir_update_f64_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, x, e);
+    ir_update_f64_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, x, e, s);
     return hipGetLastError();
 }
 

@@ -148,11 +148,23 @@ enum FcgSlot : int {
     kBB = 9,      // ||b||^2
     kSum = 10,    // scratch sum (mean projection)
     kFlag = 11,   // breakdown flag (1.0 = breakdown)
+    kTolRR = 12,  // tol^2 ||b||^2: the guarded steps halt below it
+    kDivRR = 13,  // div^2 ||b||^2: ... and above it (or on a non-finite norm)
+    kHalt = 14,   // 1.0 once a guarded step has halted the iteration
     kSlots = 16
 };
+// Halting. An outer iteration may be enqueued before the host has read the previous one's
+// residual; the guarded steps below then leave x and the residual norm unchanged once the
+// iteration has converged, diverged or broken down (kHalt or kFlag set).
+// s[kTolRR] = tol^2 s[kRR], s[kDivRR] = div^2 s[kRR], s[kHalt] = s[kFlag] = 0 (from the initial residual)
+hipError_t fcg_set_limits(double* s, double tol, double div, hipStream_t stream);
+hipError_t fcg_clear_halt(double* s, hipStream_t stream);  // s[kHalt] = s[kFlag] = 0
+// guarded fcg_finish_rr: skipped when halted; sets kHalt when rr <= s[kTolRR] or !(rr <= s[kDivRR])
+hipError_t fcg_finish_rr_guarded(const double* partial, int count, double* s, hipStream_t stream);
 hipError_t fcg_finish_pq(const double* partial, int count, double* s, hipStream_t stream);  // pq, alpha = gamma/pq
+// x += a p ; rnew = r - a q (skipped, partials included, when halted)
 hipError_t fcg_update_xr(int32_t n, double* x, const double* p, const double* r, const double* q, double* rnew,
-                         const double* s, double* partial, hipStream_t stream);      // x += a p ; rnew = r - a q
+                         const double* s, double* partial, hipStream_t stream);
 hipError_t fcg_finish_rr(const double* partial, int count, double* s, hipStream_t stream);  // rr, norm, invnorm
 // z = (double)u32 * norm and partials of z.rnew, z.rold (2 * kReduceBlocks)
 hipError_t fcg_castback_dots(int32_t n, const float* u32, const double* s, const double* rnew, const double* rold,
@@ -161,9 +173,9 @@ hipError_t fcg_dots64(int32_t n, const double* z, const double* rnew, const doub
                       hipStream_t stream);
 hipError_t fcg_finish_beta(const double* partial2, double* s, int first, hipStream_t stream);
 hipError_t fcg_update_p(int32_t n, const double* z, double* p, const double* s, int first, hipStream_t stream);
-// IR: x += (double)u32 * norm  (or x += e64)
+// IR: x += (double)u32 * norm  (or x += e64); skipped when halted
 hipError_t ir_update_f32(int32_t n, double* x, const float* u32, const double* s, hipStream_t stream);
-hipError_t ir_update_f64(int32_t n, double* x, const double* e, hipStream_t stream);
+hipError_t ir_update_f64(int32_t n, double* x, const double* e, const double* s, hipStream_t stream);
 
 // ---------------------------------------------------------------------------------------
 // Setup kernels

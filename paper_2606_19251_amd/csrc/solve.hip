@@ -6,7 +6,10 @@
 //   * flexible CG with z = V(0, r) as preconditioner        (FP64 vectors, FP32/FP64 cycle)
 // The FP32 cycle receives r / ||r|| so that its input is O(1) whatever the residual
 // level; the correction is scaled back in FP64. Scalars live on the device; the host
-// reads one small block of them per iteration to decide on convergence.
+// reads one small block of them per iteration to decide on convergence, one iteration late
+// while convergence is not in sight: iteration k + 1 is already enqueued while the host waits
+// for iteration k's block, and the guarded steps leave x unchanged once the device has seen
+// convergence, divergence or a breakdown, so an extra iteration is a no-op for the result.
 //
 // One outer iteration of IR or flexible CG is a fixed sequence of ~50 kernels (most of
 // them on small coarse levels, where launch latency dominates). With opts.graphs the
@@ -14,6 +17,7 @@
 // stream and replayed on the caller's stream, one graph launch per iteration.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -54,7 +58,9 @@ struct Runner {
     float* last32 = nullptr;
 
     // Flexible CG: precondition the latest residual `cur` (prev = the one before, unused on a
-    // (re)start), update p, then q = A p, alpha, x += alpha p, and the next residual into `prev`.
+    // (re)start), update p, then q = A p, alpha, x += alpha p and the next residual into `prev`.
+    // (Forming p inside the product, from z and the previous p, saves a pass but gathers from
+    // two vectors: slower once the vectors no longer fit the last-level cache, 8M rows.)
     void fcg_iteration(bool first, double* x, double* cur, double* prev, hipStream_t st) {
         Level& L0 = c->lv[0];
         const int32_t n = L0.n;
@@ -72,7 +78,7 @@ struct Runner {
         ok(csr_spmv_dot(L0.A(), L0.val, c->p, c->q, c->partial, &cnt, st));
         ok(fcg_finish_pq(c->partial, cnt, s, st));
         ok(fcg_update_xr(n, x, c->p, cur, c->q, prev, s, c->partial, st));
-        ok(fcg_finish_rr(c->partial, kReduceBlocks, s, st));
+        ok(fcg_finish_rr_guarded(c->partial, kReduceBlocks, s, st));
     }
 
     // Iterative refinement: x += V(0, r); r = b - A x.
@@ -81,12 +87,12 @@ struct Runner {
         const int32_t n = L0.n;
         const double* e64 = precondition(r, st);
         if (prec == 64)
-            ok(ir_update_f64(n, x, e64, st));
+            ok(ir_update_f64(n, x, e64, c->scal, st));
         else
             ok(ir_update_f32(n, x, last32, c->scal, st));
         int cnt = 0;
         ok(csr_resid_norm(L0.A(), L0.val, x, bb, r, c->partial, &cnt, st));
-        ok(fcg_finish_rr(c->partial, cnt, c->scal, st));
+        ok(fcg_finish_rr_guarded(c->partial, cnt, c->scal, st));
     }
 
     bool read_scalars(hipStream_t st) {
@@ -203,12 +209,9 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
         double* prev = c->rb;  // the one before (flexible CG)
         bool first = true;     // (re)start of the recurrence
         size_t stag_base = 0;  // stagnation is judged on the history since the last (re)start
-        int k = 0;
-        for (;;) {
-            // ---- one outer iteration ------------------------------------------------
-            int outcome = 0;
-            hipError_t e = hipSuccess;
-            if (o->outer == AMGG_OUTER_STATIONARY) {
+        int k = 0;             // iterations processed
+        if (o->outer == AMGG_OUTER_STATIONARY) {
+            for (;;) {
                 double* res = nullptr;
                 R.ok(vec_copy<double>(n, x, L0.u64, st));
                 R.ok(vcycle_level<double>(c, 0, bb, L0.u64, L0.t64, first, o->nu1, o->nu2, st, &res));
@@ -216,64 +219,164 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
                 int cnt = 0;
                 R.ok(csr_resid_norm(A, L0.val, x, bb, cur, c->partial, &cnt, st));
                 R.ok(fcg_finish_rr(c->partial, cnt, s, st));
-                e = R.e;
-            } else if (o->outer == AMGG_OUTER_IR) {
-                e = run_body(c, use_graph, graph_key(c, "ir", R.prec, o->nu1, o->nu2, x, bb, cur), st, R,
-                             [&](hipStream_t q) { R.ir_iteration(x, bb, cur, q); });
-            } else {
-                double* cu = cur;
-                double* pv = prev;
-                const bool f0 = first;
-                e = run_body(c, use_graph, graph_key(c, f0 ? "fcg0" : "fcg", R.prec, o->nu1, o->nu2, x, cu, pv), st,
-                             R, [&](hipStream_t q) { R.fcg_iteration(f0, x, cu, pv, q); });
-                std::swap(cur, prev);
-            }
-            first = false;
-            ++vcycles;
-            ++k;
-            if (e != hipSuccess) return hip_fail(e, "amgg_solve");
-            if (!R.read_scalars(st)) return hip_fail(R.e, "amgg_solve");
-            double rel = std::sqrt(hs[kRR]) / nb;
-            const bool breakdown = hs[kFlag] != 0.0;
-            if (o->outer == AMGG_OUTER_FCG && rel <= o->tol && std::isfinite(rel) && !breakdown) {
-                // The CG residual is updated by recurrence and drifts from b - A x on badly
-                // conditioned problems: confirm with the true residual; if it is still above the
-                // tolerance, restart the recurrence from it.
-                int cnt = 0;
-                R.ok(csr_resid_norm(A, L0.val, x, bb, cur, c->partial, &cnt, st));
-                R.ok(fcg_finish_rr(c->partial, cnt, s, st));
+                first = false;
+                ++vcycles;
+                ++k;
                 if (!R.read_scalars(st)) return hip_fail(R.e, "amgg_solve");
-                rel = std::sqrt(hs[kRR]) / nb;
-                if (!(rel <= o->tol)) first = true;
-            }
-            hist.push_back(rel);
-            if (rel <= o->tol && std::isfinite(rel) && !breakdown) return finish(0, rel, k);
-            if (!std::isfinite(rel) || rel > div_factor)
-                outcome = AMGG_DIVERGED;
-            else if (breakdown)
-                outcome = AMGG_BREAKDOWN;
-            else if (hist.size() - stag_base > static_cast<size_t>(stag_window) &&
-                     rel > stag_ratio * hist[hist.size() - 1 - stag_window])
-                outcome = AMGG_STAGNATED;
-            if (outcome == 0 && k >= o->maxit) return finish(AMGG_MAXIT, rel, k);
-            if (outcome != 0) {
+                const double rel = std::sqrt(hs[kRR]) / nb;
+                hist.push_back(rel);
+                if (rel <= o->tol && std::isfinite(rel)) return finish(0, rel, k);
+                int outcome = 0;
+                if (!std::isfinite(rel) || rel > div_factor)
+                    outcome = AMGG_DIVERGED;
+                else if (hist.size() - stag_base > static_cast<size_t>(stag_window) &&
+                         rel > stag_ratio * hist[hist.size() - 1 - stag_window])
+                    outcome = AMGG_STAGNATED;
+                if (outcome == 0) {
+                    if (k >= o->maxit) return finish(AMGG_MAXIT, rel, k);
+                    continue;
+                }
                 bool learned = false;
                 for (int l = 0; l + 1 < c->nlevels; ++l) learned |= !c->lv[l].baseline;
                 if (!o->fallback || inf.fell_back || !learned || k >= o->maxit) return finish(outcome, rel, k);
-                // Jacobi fallback: the cycle stays a linear operator, so the iteration may
-                // continue from the current x with the paper's baseline smoother.
+                // Jacobi fallback from the current x (from zero if it is not finite)
                 inf.fell_back = 1;
                 set_all_jacobi(c, st);
-                R.ok(vec_zero_bytes(s + kFlag, sizeof(double), st));
-                if (!std::isfinite(rel)) R.ok(vec_zero_bytes(x, sizeof(double) * n, st));
-                int cnt = 0;
-                R.ok(csr_resid_norm(A, L0.val, x, bb, c->ra, c->partial, &cnt, st));
-                R.ok(fcg_finish_rr(c->partial, cnt, s, st));
-                cur = c->ra;
-                prev = c->rb;
-                first = true;
+                first = !std::isfinite(rel);
+                if (first) R.ok(vec_zero_bytes(x, sizeof(double) * n, st));
                 stag_base = hist.size() - 1;
+                if (R.e != hipSuccess) return hip_fail(R.e, "amgg_solve");
             }
+        }
+
+        // IR and flexible CG: each iteration is enqueued (a graph launch) together with an
+        // asynchronous copy of the scalar block into one of two pinned slots; the host keeps
+        // one iteration in flight while it inspects the previous one.
+        R.ok(fcg_set_limits(s, o->tol, div_factor, st));
+        struct InFlight {
+            double* cu;
+            double* pv;
+        };
+        std::vector<InFlight> q;  // enqueued, not yet inspected (at most two)
+        int launched = 0;
+        bool more = true;  // false once a stop is decided and only the in-flight one remains
+        auto launch = [&]() -> hipError_t {
+            double* cu = cur;
+            double* pv = prev;
+            const bool f0 = first;
+            hipError_t e;
+            if (o->outer == AMGG_OUTER_IR) {
+                e = run_body(c, use_graph, graph_key(c, "ir", R.prec, o->nu1, o->nu2, x, bb, cu), st, R,
+                             [&](hipStream_t qs) { R.ir_iteration(x, bb, cu, qs); });
+            } else {
+                e = run_body(c, use_graph, graph_key(c, f0 ? "fcg0" : "fcg", R.prec, o->nu1, o->nu2, x, cu, pv), st,
+                             R, [&](hipStream_t qs) { R.fcg_iteration(f0, x, cu, pv, qs); });
+                std::swap(cur, prev);
+            }
+            first = false;
+            if (e != hipSuccess) return e;
+            const int slot = launched % 2;
+            if ((e = hipMemcpyAsync(hs + (1 + slot) * kSlots, s, sizeof(double) * kSlots, hipMemcpyDeviceToHost,
+                                    st)) != hipSuccess ||
+                (e = hipEventRecord(c->ev[slot], st)) != hipSuccess)
+                return e;
+            q.push_back({cu, pv});
+            ++launched;
+            return hipSuccess;
+        };
+        // back to a state where nothing is in flight (a masked or superseded iteration is dropped)
+        auto settle = [&]() -> bool {
+            q.clear();
+            launched = k;
+            R.ok(hipStreamSynchronize(st));
+            return R.e == hipSuccess;
+        };
+        // Enqueue ahead only while the in-flight iteration is not expected to converge (its
+        // residual predicted from the last ratio stays above twice the tolerance): an iteration
+        // enqueued after the converging one would run its whole cycle for nothing.
+        auto ahead = [&]() {
+            if (hist.size() < 3) return true;
+            const double last = hist[hist.size() - 1], ratio = std::min(1.0, last / hist[hist.size() - 2]);
+            return last * ratio > 2.0 * o->tol;
+        };
+        for (;;) {
+            hipError_t e = hipSuccess;
+            if (q.empty()) e = launch();
+            if (e == hipSuccess && more && q.size() == 1 && launched < o->maxit && ahead()) e = launch();
+            if (e != hipSuccess) return hip_fail(e, "amgg_solve");
+            const int slot = k % 2;
+            if ((e = hipEventSynchronize(c->ev[slot])) != hipSuccess) return hip_fail(e, "amgg_solve");
+            const double* hk = hs + (1 + slot) * kSlots;
+            const InFlight it = q.front();
+            q.erase(q.begin());
+            ++k;
+            ++vcycles;
+            double rel = std::sqrt(hk[kRR]) / nb;
+            const bool breakdown = hk[kFlag] != 0.0;
+            const bool halted = hk[kHalt] != 0.0;  // converged or diverged, as the device saw it
+            int outcome = 0;
+            if (!std::isfinite(rel) || rel > div_factor || (halted && !(rel <= o->tol * (1.0 + 1e-9)))) {
+                outcome = AMGG_DIVERGED;
+            } else if (breakdown) {
+                outcome = AMGG_BREAKDOWN;
+            } else if (halted) {
+                // converged: the in-flight iteration (if any) left x unchanged
+                if (!settle()) return hip_fail(R.e, "amgg_solve");
+                if (o->outer == AMGG_OUTER_FCG) {
+                    // The CG residual is updated by recurrence and drifts from b - A x on badly
+                    // conditioned problems: confirm with the true residual; if it is still above
+                    // the tolerance, restart the recurrence from it.
+                    cur = it.pv;
+                    prev = it.cu;
+                    int cnt = 0;
+                    R.ok(csr_resid_norm(A, L0.val, x, bb, cur, c->partial, &cnt, st));
+                    R.ok(fcg_finish_rr(c->partial, cnt, s, st));
+                    if (!R.read_scalars(st)) return hip_fail(R.e, "amgg_solve");
+                    rel = std::sqrt(hs[kRR]) / nb;
+                    hist.push_back(rel);
+                    if (rel <= o->tol) return finish(0, rel, k);
+                    if (k >= o->maxit) return finish(AMGG_MAXIT, rel, k);
+                    R.ok(fcg_clear_halt(s, st));
+                    first = true;
+                    more = true;
+                    continue;
+                }
+                hist.push_back(rel);
+                return finish(0, rel, k);
+            }
+            hist.push_back(rel);
+            if (outcome == 0 && hist.size() - stag_base > static_cast<size_t>(stag_window) &&
+                rel > stag_ratio * hist[hist.size() - 1 - stag_window]) {
+                if (!q.empty()) {  // judge again on the iteration already in flight
+                    more = false;
+                    continue;
+                }
+                outcome = AMGG_STAGNATED;
+            }
+            if (outcome == 0) {
+                if (k >= o->maxit && q.empty()) return finish(AMGG_MAXIT, rel, k);
+                more = true;
+                continue;
+            }
+            // divergence, breakdown or stagnation
+            if (!settle()) return hip_fail(R.e, "amgg_solve");
+            bool learned = false;
+            for (int l = 0; l + 1 < c->nlevels; ++l) learned |= !c->lv[l].baseline;
+            if (!o->fallback || inf.fell_back || !learned || k >= o->maxit) return finish(outcome, rel, k);
+            // Jacobi fallback: the cycle stays a linear operator, so the iteration may
+            // continue from the current x with the paper's baseline smoother.
+            inf.fell_back = 1;
+            set_all_jacobi(c, st);
+            R.ok(fcg_clear_halt(s, st));
+            if (!std::isfinite(rel)) R.ok(vec_zero_bytes(x, sizeof(double) * n, st));
+            int cnt = 0;
+            R.ok(csr_resid_norm(A, L0.val, x, bb, c->ra, c->partial, &cnt, st));
+            R.ok(fcg_finish_rr(c->partial, cnt, s, st));
+            cur = c->ra;
+            prev = c->rb;
+            first = true;
+            more = true;
+            stag_base = hist.size() - 1;
             if (R.e != hipSuccess) return hip_fail(R.e, "amgg_solve");
         }
     });
