@@ -255,6 +255,45 @@ class Case:
                 "algorithmic_bytes": int(k_bytes)}
 
 
+def training_step(torch, steps=10, warmup=3):
+    """One training step of Alg. 1 on the 32-mesh training batch (2k-16k nodes each, Gaussian-
+    mixture clustered Delaunay P1): batched GCIN forward over all levels (BF16 MFMA, split
+    operands), smoother assembly and one FP32 V(1,1) cycle per mesh with the loss, the
+    hand-written adjoint, the GCIN backward and Adam with clipping; degree-3 coefficients."""
+    import workloads as W
+    from paper_2606_19251_amd import capi
+    from paper_2606_19251_amd import gcin as G
+    from paper_2606_19251_amd.solver import DeviceSolver, HostHierarchy
+
+    t0 = time.time()
+    meshes = W.training_batch(32, seed=0)
+    solvers = [DeviceSolver(HostHierarchy.build(A.rowptr, A.col, A.val, max_coarse=100), 0) for A, _ in meshes]
+    dev = solvers[0].device
+    rhs = [torch.from_numpy(f).to(dev) for _, f in meshes]
+    pred = G.Predictor(G.init_flat(3, 0), dev, 3, capi.GCIN_BF16X3)
+    tr = G.Trainer(solvers, rhs, pred, nvc=1)
+    log(f"training batch: 32 meshes, {sum(ds.n for ds in solvers)} fine nodes, "
+        f"{tr.batch.ngraphs} graphs ({time.time() - t0:.1f} s)")
+    for _ in range(warmup):
+        tr.step()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(steps):
+        losses = tr.step()
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / steps
+    log(f"training step: {ms:.2f} ms (loss {float(losses.mean()):.4f})")
+    out = {"ms_per_step": round(ms, 3), "meshes": 32, "fine_nodes": int(sum(ds.n for ds in solvers)),
+           "graphs": int(tr.batch.ngraphs), "nodes": int(tr.batch.n.sum()), "degree": 3, "nvc": 1,
+           "gcin": "BF16 MFMA with split operands (FP32-accurate products), FP32 accumulation",
+           "cycles": "FP32 V(1,1), one per mesh, hand-written adjoint"}
+    for ds in solvers:
+        ds.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -262,6 +301,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=list(WORKLOADS), default="delaunay1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-training", action="store_true", help="skip the training-step timing")
     ap.add_argument("--no-second-roofline", action="store_true",
                     help="skip the tet8m fine-level kernel timing that follows the default workload")
     ap.add_argument("--profile-kernels", action="store_true",
@@ -348,6 +388,8 @@ def main():
     if args.workload == "delaunay1m" and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case.A, case.f, gnn["iterations"])
     ds.close()
+    if args.workload == "delaunay1m" and not args.no_training:
+        out["training"] = training_step(torch)
     if args.workload == "delaunay1m" and not args.no_second_roofline:
         del case
         second = Case(torch, "tet8m")
