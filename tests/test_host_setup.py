@@ -117,3 +117,11 @@ def test_one_level_hierarchy_when_small():
     A = W.grid5(10)
     h = HostHierarchy.build(A.rowptr, A.col, A.val, max_coarse=500)
     assert h.nlevels == 1 and h.levels[0].p_rowptr is None
+
+
+def test_rs_bitexact_airfoil_cmesh():
+    _compare(W.cmesh_fv(96, 48, "4415", 1e4), max_coarse=60)
+
+
+def test_rs_bitexact_kuhn_tetrahedra():
+    _compare(W.tet_fv_mesh(*W.kuhn_tets(10, 1)), singular=True, max_coarse=60)
