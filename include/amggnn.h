@@ -84,6 +84,50 @@ int amgg_rs_copy_level(const amgg_rs* h, int lvl, int32_t* rowptr, int32_t* col,
                        int32_t* p_rowptr, int32_t* p_col, double* p_val, int8_t* cf);
 void amgg_rs_free(amgg_rs* h);
 
+/* Stepwise form of amgg_rs_setup for callers that form the Galerkin products elsewhere
+ * (amgg_galerkin_device). amgg_rs_begin validates the matrix as amgg_rs_setup does and
+ * holds it as level 0. amgg_rs_coarsen works on the last level: it applies the stopping
+ * rules and, unless coarsening stops (*more = 0; further calls keep returning 0), computes
+ * the level's C/F split and interpolation P (*more = 1; amgg_rs_level_size and
+ * amgg_rs_copy_level then report P). The next level's matrix must then be supplied,
+ * either by amgg_rs_galerkin (host product, as in amgg_rs_setup) or by amgg_rs_push_level
+ * (host CSR arrays, n = P's column count, validated like the input), before coarsening
+ * again. With host products throughout the result equals amgg_rs_setup's.
+ * Errors: AMGG_EINVAL (bad argument or pattern), AMGG_ESTATE (call out of sequence). */
+int amgg_rs_begin(const int32_t* rowptr, const int32_t* col, const double* val, int32_t n,
+                  double theta, int max_levels, int32_t max_coarse, amgg_rs** out);
+int amgg_rs_coarsen(amgg_rs* h, int* more);
+int amgg_rs_galerkin(amgg_rs* h);
+int amgg_rs_push_level(amgg_rs* h, int32_t n, const int32_t* rowptr, const int32_t* col, const double* val);
+
+/* ------------------------------------------------------------------------------------
+ * Device Galerkin product of one level (paper Sec. 2.2: the coarse operator is R A P with
+ * R = P^T; Alg. 1, step 2).
+ * ------------------------------------------------------------------------------------ */
+typedef void* (*amgg_alloc_fn)(size_t bytes, void* user); /* device memory, or NULL */
+typedef void (*amgg_release_fn)(void* ptr, void* user);
+
+/* A_c = P^T (A P) on device `device`, bitwise equal to the host product of amgg_rs_setup:
+ * R = P^T is the exact transpose, and each entry of A P and of R (A P) is accumulated over
+ * the left operand's row in ascending column order, starting from 0.0, with products and
+ * sums rounded separately; exact zeros off the diagonal are then dropped (zeros of A P are
+ * kept). A (n x n, a_nnz entries) and P (n x nc, p_nnz entries) are device CSR arrays
+ * with int32 strictly ascending columns and FP64 values, read only; their patterns are
+ * checked on the device before use. Device memory comes from alloc(bytes, user); temporaries are
+ * handed back through release(ptr, user) before the call returns, also on error. On
+ * success *ac_rowptr (nc + 1 entries), *ac_col and *ac_val (*ac_nnz entries) were obtained
+ * from alloc and belong to the caller. chunk_products bounds the expanded products sorted
+ * at once, which sets the temporary memory (about 24 bytes per product); 0 selects 2^27.
+ * Work is queued on `stream` (hipStream_t), which the call synchronises to read sizes.
+ * Errors: AMGG_EINVAL (NULL, bad sizes or pattern, more than 2^31 - 1 result entries),
+ * AMGG_EWORKSPACE (alloc returned NULL), AMGG_EHIP (runtime error). */
+int amgg_galerkin_device(int device, int32_t n, int32_t nc, const int32_t* a_rowptr, const int32_t* a_col,
+                         const double* a_val, int32_t a_nnz, const int32_t* p_rowptr, const int32_t* p_col,
+                         const double* p_val, int32_t p_nnz, amgg_alloc_fn alloc, amgg_release_fn release,
+                         void* user, int64_t chunk_products, int32_t** ac_rowptr, int32_t** ac_col,
+                         double** ac_val, int32_t* ac_nnz, void* stream);
+
+
 /* ------------------------------------------------------------------------------------
  * Device context: hierarchy load (Alg. 1, step 2) and derived data.
  * ------------------------------------------------------------------------------------ */

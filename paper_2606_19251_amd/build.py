@@ -39,6 +39,7 @@ HIP_SOURCES = {
     "solve.hip": [],
     "adjoint.hip": [],
     "gcin.hip": [],
+    "galerkin.hip": ["-ffp-contract=off"],  # same rounding as the host Galerkin product
 }
 HOST_SOURCES = ["rs_setup.cpp", "errors.cpp", "halo.cpp"]
 

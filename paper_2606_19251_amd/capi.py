@@ -72,6 +72,12 @@ SIGNATURES = {
     "amgg_rs_level_size": (_I, [_VP, _I, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32)]),
     "amgg_rs_copy_level": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "amgg_rs_free": (None, [_VP]),
+    "amgg_rs_begin": (_I, [_VP, _VP, _VP, _I32, C.c_double, _I, _I32, C.POINTER(_VP)]),
+    "amgg_rs_coarsen": (_I, [_VP, C.POINTER(_I)]),
+    "amgg_rs_galerkin": (_I, [_VP]),
+    "amgg_rs_push_level": (_I, [_VP, _I32, _VP, _VP, _VP]),
+    "amgg_galerkin_device": (_I, [_I, _I32, _I32, _VP, _VP, _VP, _I32, _VP, _VP, _VP, _I32, _VP, _VP, _VP,
+                                  C.c_int64, C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_I32), _VP]),
     "amgg_create": (_I, [C.POINTER(_VP), _I, _I]),
     "amgg_destroy": (_I, [_VP]),
     "amgg_last_error": (C.c_char_p, []),
@@ -171,6 +177,86 @@ def amgg_rs_copy_level(h: int, lvl: int, rowptr, col, val, p_rowptr=None, p_col=
 
 def amgg_rs_free(h: int):
     lib().amgg_rs_free(h)
+
+
+def amgg_rs_begin(rowptr: np.ndarray, col: np.ndarray, val: np.ndarray, n: int, theta: float,
+                  max_levels: int, max_coarse: int) -> int:
+    rowptr = np.ascontiguousarray(rowptr, np.int32)
+    col = np.ascontiguousarray(col, np.int32)
+    val = np.ascontiguousarray(val, np.float64)
+    h = _VP()
+    _check(lib().amgg_rs_begin(_np_ptr(rowptr), _np_ptr(col), _np_ptr(val), n, theta, max_levels, max_coarse,
+                               C.byref(h)), "amgg_rs_begin")
+    return h.value
+
+
+def amgg_rs_coarsen(h: int) -> bool:
+    more = _I()
+    _check(lib().amgg_rs_coarsen(h, C.byref(more)), "amgg_rs_coarsen")
+    return bool(more.value)
+
+
+def amgg_rs_galerkin(h: int):
+    _check(lib().amgg_rs_galerkin(h), "amgg_rs_galerkin")
+
+
+def amgg_rs_push_level(h: int, n: int, rowptr: np.ndarray, col: np.ndarray, val: np.ndarray):
+    rowptr = np.ascontiguousarray(rowptr, np.int32)
+    col = np.ascontiguousarray(col, np.int32)
+    val = np.ascontiguousarray(val, np.float64)
+    _check(lib().amgg_rs_push_level(h, n, _np_ptr(rowptr), _np_ptr(col), _np_ptr(val)), "amgg_rs_push_level")
+
+
+# ---------------------------------------------------------------------------- device Galerkin product
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class TorchDeviceAllocator:
+    """Allocator callbacks backed by torch tensors on one device (stream-ordered on torch's
+    current stream, which is the stream the library is given)."""
+
+    def __init__(self, torch, device):
+        self.torch = torch
+        self.device = device
+        self.live = {}
+        self.alloc = ALLOC_FN(self._alloc)
+        self.release = RELEASE_FN(self._release)
+
+    def _alloc(self, nbytes, user):
+        try:
+            t = self.torch.empty(max(int(nbytes), 1), dtype=self.torch.uint8, device=self.device)
+        except RuntimeError:
+            return None
+        self.live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _release(self, ptr, user):
+        self.live.pop(ptr, None)
+
+    def take(self, ptr, dtype, count):
+        """The allocation at ptr as a tensor of `count` elements of `dtype`, owned by the caller."""
+        t = self.live.pop(ptr)
+        return t[: count * self.torch.empty(0, dtype=dtype).element_size()].view(dtype)
+
+
+def amgg_galerkin_device(device: int, n: int, nc: int, a_rowptr, a_col, a_val, p_rowptr, p_col, p_val,
+                         chunk_products: int = 0, allocator: TorchDeviceAllocator | None = None):
+    """A_c = P^T A P of device CSR tensors (int32 / float64); returns (rowptr, col, val) tensors."""
+    import torch
+
+    dev = torch.device("cuda", device)
+    al = allocator if allocator is not None else TorchDeviceAllocator(torch, dev)
+    rp, cl, vl, nnz = _VP(), _VP(), _VP(), _I32()
+    _check(lib().amgg_galerkin_device(device, n, nc, a_rowptr.data_ptr(), a_col.data_ptr(), a_val.data_ptr(),
+                                      int(a_col.numel()), p_rowptr.data_ptr(), p_col.data_ptr(), p_val.data_ptr(),
+                                      int(p_col.numel()), al.alloc, al.release, None, int(chunk_products),
+                                      C.byref(rp), C.byref(cl), C.byref(vl), C.byref(nnz),
+                                      torch.cuda.current_stream(dev).cuda_stream), "amgg_galerkin_device")
+    out = (al.take(rp.value, torch.int32, nc + 1), al.take(cl.value, torch.int32, nnz.value),
+           al.take(vl.value, torch.float64, nnz.value))
+    assert not al.live, "temporaries left allocated"
+    return out
 
 
 # ---------------------------------------------------------------------------- device context

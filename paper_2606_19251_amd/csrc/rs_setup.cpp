@@ -281,50 +281,138 @@ bool check_pattern(const int32_t* rowptr, const int32_t* col, const double* val,
 struct amgg_rs {
     std::vector<RsLevel> levels;
     int singular = 0;
+    double theta = 0.25;
+    int max_levels = 1;
+    int32_t max_coarse = 1;
+    bool open = false;  // the last level has P and awaits its Galerkin product
+    bool done = false;  // coarsening stopped: the last level is the coarsest
 };
+
+namespace {
+
+int begin_impl(const char* who, const int32_t* rowptr, const int32_t* col, const double* val, int32_t n,
+               double theta, int max_levels, int32_t max_coarse, amgg_rs** out) {
+    const std::string w(who);
+    if (!out || !rowptr || n <= 0 || (!col && rowptr[n] > 0) || (!val && rowptr[n] > 0))
+        return amgg::fail(AMGG_EINVAL, w + ": null argument or n <= 0");
+    if (!(theta > 0.0 && theta < 1.0) || max_levels < 1 || max_levels > AMGG_MAX_LEVELS || max_coarse < 1)
+        return amgg::fail(AMGG_EINVAL, w + ": theta, max_levels or max_coarse out of range");
+    std::string why;
+    if (!check_pattern(rowptr, col, val, n, &why)) return amgg::fail(AMGG_EINVAL, w + ": " + why);
+    auto* h = new amgg_rs();
+    h->theta = theta;
+    h->max_levels = max_levels;
+    h->max_coarse = max_coarse;
+    RsLevel top;
+    top.A.nrows = top.A.ncols = n;
+    top.A.ptr.assign(rowptr, rowptr + n + 1);
+    top.A.idx.assign(col, col + rowptr[n]);
+    top.A.val.assign(val, val + rowptr[n]);
+    // all-Neumann detection: every row sums to zero relative to its diagonal
+    h->singular = 1;
+    for (int32_t i = 0; i < n && h->singular; ++i) {
+        double s = 0.0, d = 0.0;
+        for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            s += val[p];
+            if (col[p] == i) d = val[p];
+        }
+        if (!(std::fabs(s) <= 1e-12 * d)) h->singular = 0;
+    }
+    h->levels.push_back(std::move(top));
+    *out = h;
+    return AMGG_OK;
+}
+
+// Strength, C/F split and interpolation of the last level, or the decision to stop there.
+bool coarsen_last(amgg_rs* h) {
+    RsLevel& cur = h->levels.back();
+    const int32_t nl = cur.A.nrows;
+    if (static_cast<int>(h->levels.size()) >= h->max_levels || nl <= h->max_coarse) return false;
+    Csr S = strong_couplings(cur.A, h->theta);
+    std::vector<int8_t> cf = first_pass_split(S);
+    int64_t nc = 0;
+    for (int8_t c : cf) nc += c;
+    if (nc == 0 || 10 * nc > 9 * static_cast<int64_t>(nl)) return false;
+    cur.P = direct_interp(cur.A, S, cf);
+    cur.cf = std::move(cf);
+    return true;
+}
+
+}  // namespace
 
 extern "C" int amgg_rs_setup(const int32_t* rowptr, const int32_t* col, const double* val, int32_t n,
                              double theta, int max_levels, int32_t max_coarse, amgg_rs** out) {
     return amgg::guarded([&]() -> int {
-        if (!out || !rowptr || n <= 0 || (!col && rowptr[n] > 0) || (!val && rowptr[n] > 0))
-            return amgg::fail(AMGG_EINVAL, "amgg_rs_setup: null argument or n <= 0");
-        if (!(theta > 0.0 && theta < 1.0) || max_levels < 1 || max_levels > AMGG_MAX_LEVELS || max_coarse < 1)
-            return amgg::fail(AMGG_EINVAL, "amgg_rs_setup: theta, max_levels or max_coarse out of range");
-        std::string why;
-        if (!check_pattern(rowptr, col, val, n, &why)) return amgg::fail(AMGG_EINVAL, "amgg_rs_setup: " + why);
-        auto* h = new amgg_rs();
-        RsLevel top;
-        top.A.nrows = top.A.ncols = n;
-        top.A.ptr.assign(rowptr, rowptr + n + 1);
-        top.A.idx.assign(col, col + rowptr[n]);
-        top.A.val.assign(val, val + rowptr[n]);
-        // all-Neumann detection: every row sums to zero relative to its diagonal
-        h->singular = 1;
-        for (int32_t i = 0; i < n && h->singular; ++i) {
-            double s = 0.0, d = 0.0;
-            for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-                s += val[p];
-                if (col[p] == i) d = val[p];
+        amgg_rs* h = nullptr;
+        const int rc = begin_impl("amgg_rs_setup", rowptr, col, val, n, theta, max_levels, max_coarse, &h);
+        if (rc != AMGG_OK) return rc;
+        try {
+            while (coarsen_last(h)) {
+                RsLevel next;
+                next.A = galerkin_product(h->levels.back().A, h->levels.back().P);
+                h->levels.push_back(std::move(next));
             }
-            if (!(std::fabs(s) <= 1e-12 * d)) h->singular = 0;
+        } catch (...) {
+            delete h;
+            throw;
         }
-        h->levels.push_back(std::move(top));
-        for (;;) {
-            RsLevel& cur = h->levels.back();
-            const int32_t nl = cur.A.nrows;
-            if (static_cast<int>(h->levels.size()) >= max_levels || nl <= max_coarse) break;
-            Csr S = strong_couplings(cur.A, theta);
-            std::vector<int8_t> cf = first_pass_split(S);
-            int64_t nc = 0;
-            for (int8_t c : cf) nc += c;
-            if (nc == 0 || 10 * nc > 9 * static_cast<int64_t>(nl)) break;
-            cur.P = direct_interp(cur.A, S, cf);
-            cur.cf = std::move(cf);
-            RsLevel next;
-            next.A = galerkin_product(cur.A, cur.P);
-            h->levels.push_back(std::move(next));
-        }
+        h->done = true;
         *out = h;
+        return AMGG_OK;
+    });
+}
+
+extern "C" int amgg_rs_begin(const int32_t* rowptr, const int32_t* col, const double* val, int32_t n,
+                             double theta, int max_levels, int32_t max_coarse, amgg_rs** out) {
+    return amgg::guarded(
+        [&]() -> int { return begin_impl("amgg_rs_begin", rowptr, col, val, n, theta, max_levels, max_coarse, out); });
+}
+
+extern "C" int amgg_rs_coarsen(amgg_rs* h, int* more) {
+    return amgg::guarded([&]() -> int {
+        if (!h || !more) return amgg::fail(AMGG_EINVAL, "amgg_rs_coarsen: null argument");
+        if (h->open) return amgg::fail(AMGG_ESTATE, "amgg_rs_coarsen: the last level still needs its coarse matrix");
+        if (h->done) {
+            *more = 0;
+            return AMGG_OK;
+        }
+        h->open = coarsen_last(h);
+        h->done = !h->open;
+        *more = h->open ? 1 : 0;
+        return AMGG_OK;
+    });
+}
+
+extern "C" int amgg_rs_galerkin(amgg_rs* h) {
+    return amgg::guarded([&]() -> int {
+        if (!h) return amgg::fail(AMGG_EINVAL, "amgg_rs_galerkin: null handle");
+        if (!h->open) return amgg::fail(AMGG_ESTATE, "amgg_rs_galerkin: no level awaits its coarse matrix");
+        RsLevel next;
+        next.A = galerkin_product(h->levels.back().A, h->levels.back().P);
+        h->levels.push_back(std::move(next));
+        h->open = false;
+        return AMGG_OK;
+    });
+}
+
+extern "C" int amgg_rs_push_level(amgg_rs* h, int32_t n, const int32_t* rowptr, const int32_t* col,
+                                  const double* val) {
+    return amgg::guarded([&]() -> int {
+        if (!h || !rowptr || n <= 0) return amgg::fail(AMGG_EINVAL, "amgg_rs_push_level: null argument or n <= 0");
+        if (!h->open) return amgg::fail(AMGG_ESTATE, "amgg_rs_push_level: no level awaits its coarse matrix");
+        if (n != h->levels.back().P.ncols)
+            return amgg::fail(AMGG_EINVAL, "amgg_rs_push_level: row count differs from the coarse point count");
+        const int32_t nnz = rowptr[n];
+        if ((!col || !val) && nnz > 0) return amgg::fail(AMGG_EINVAL, "amgg_rs_push_level: null col or val");
+        std::string why;
+        if (!check_pattern(rowptr, col, val, n, &why)) return amgg::fail(AMGG_EINVAL, "amgg_rs_push_level: " + why);
+        RsLevel next;
+        next.A.nrows = next.A.ncols = n;
+        next.A.ptr.assign(rowptr, rowptr + n + 1);
+        next.A.idx.assign(col, col + nnz);
+        next.A.val.assign(val, val + nnz);
+        h->levels.push_back(std::move(next));
+        h->open = false;
         return AMGG_OK;
     });
 }
@@ -356,7 +444,7 @@ extern "C" int amgg_rs_copy_level(const amgg_rs* h, int lvl, int32_t* rowptr, in
     if (rowptr) std::memcpy(rowptr, L.A.ptr.data(), sizeof(int32_t) * L.A.ptr.size());
     if (col) std::memcpy(col, L.A.idx.data(), sizeof(int32_t) * L.A.idx.size());
     if (val) std::memcpy(val, L.A.val.data(), sizeof(double) * L.A.val.size());
-    const bool has_p = lvl + 1 < static_cast<int>(h->levels.size());
+    const bool has_p = !L.P.ptr.empty();
     if (has_p) {
         if (p_rowptr) std::memcpy(p_rowptr, L.P.ptr.data(), sizeof(int32_t) * L.P.ptr.size());
         if (p_col) std::memcpy(p_col, L.P.idx.data(), sizeof(int32_t) * L.P.idx.size());

@@ -37,31 +37,70 @@ class HostHierarchy:
     singular: bool = False
 
     @classmethod
-    def build(cls, rowptr, col, val, theta=0.25, max_levels=10, max_coarse=500):
+    def build(cls, rowptr, col, val, theta=0.25, max_levels=10, max_coarse=500, galerkin="host", device=0,
+              chunk_products=0):
+        """RS hierarchy of a host CSR matrix. galerkin="host" forms every coarse matrix in the
+        host setup; galerkin="device" forms them with amgg_galerkin_device on GPU `device`
+        (strength, C/F split and interpolation stay on the host; the results are bitwise
+        the same)."""
         rowptr = np.ascontiguousarray(rowptr, np.int32)
         n = rowptr.size - 1
-        h = capi.amgg_rs_setup(rowptr, col, val, n, theta, max_levels, max_coarse)
+        if galerkin == "host":
+            h = capi.amgg_rs_setup(rowptr, col, val, n, theta, max_levels, max_coarse)
+        elif galerkin == "device":
+            h = _rs_with_device_galerkin(rowptr, col, val, n, theta, max_levels, max_coarse, device, chunk_products)
+        else:
+            raise ValueError(f"galerkin must be 'host' or 'device', not {galerkin!r}")
         try:
-            nl, sing = capi.amgg_rs_info(h)
-            out = cls([], bool(sing))
-            for l in range(nl):
-                n_l, nnz, pnc, pnnz = capi.amgg_rs_level_size(h, l)
-                L = HostLevel(n_l, np.empty(n_l + 1, np.int32), np.empty(nnz, np.int32), np.empty(nnz, np.float64))
-                L.cf = np.empty(n_l, np.int8)
-                if l + 1 < nl:
-                    L.p_ncols = pnc
-                    L.p_rowptr = np.empty(n_l + 1, np.int32)
-                    L.p_col = np.empty(pnnz, np.int32)
-                    L.p_val = np.empty(pnnz, np.float64)
-                capi.amgg_rs_copy_level(h, l, L.rowptr, L.col, L.val, L.p_rowptr, L.p_col, L.p_val, L.cf)
-                out.levels.append(L)
-            return out
+            return cls.from_handle(h)
         finally:
             capi.amgg_rs_free(h)
+
+    @classmethod
+    def from_handle(cls, h):
+        """Copy the levels held by an amgg_rs handle (which stays owned by the caller)."""
+        nl, sing = capi.amgg_rs_info(h)
+        out = cls([], bool(sing))
+        for l in range(nl):
+            n_l, nnz, pnc, pnnz = capi.amgg_rs_level_size(h, l)
+            L = HostLevel(n_l, np.empty(n_l + 1, np.int32), np.empty(nnz, np.int32), np.empty(nnz, np.float64))
+            L.cf = np.empty(n_l, np.int8)
+            if l + 1 < nl:
+                L.p_ncols = pnc
+                L.p_rowptr = np.empty(n_l + 1, np.int32)
+                L.p_col = np.empty(pnnz, np.int32)
+                L.p_val = np.empty(pnnz, np.float64)
+            capi.amgg_rs_copy_level(h, l, L.rowptr, L.col, L.val, L.p_rowptr, L.p_col, L.p_val, L.cf)
+            out.levels.append(L)
+        return out
 
     @property
     def nlevels(self):
         return len(self.levels)
+
+
+def _rs_with_device_galerkin(rowptr, col, val, n, theta, max_levels, max_coarse, device, chunk_products):
+    """Stepwise RS setup whose Galerkin products run on the GPU; returns the host handle."""
+    import torch
+
+    dev = torch.device("cuda", device)
+    h = capi.amgg_rs_begin(rowptr, col, val, n, theta, max_levels, max_coarse)
+    try:
+        A = (torch.from_numpy(rowptr).to(dev), torch.from_numpy(np.ascontiguousarray(col, np.int32)).to(dev),
+             torch.from_numpy(np.ascontiguousarray(val, np.float64)).to(dev))
+        lvl = 0
+        while capi.amgg_rs_coarsen(h):
+            n_l, _, nc, pnnz = capi.amgg_rs_level_size(h, lvl)
+            prp, pcl, pvl = np.empty(n_l + 1, np.int32), np.empty(pnnz, np.int32), np.empty(pnnz, np.float64)
+            capi.amgg_rs_copy_level(h, lvl, None, None, None, prp, pcl, pvl, None)
+            P = tuple(torch.from_numpy(a).to(dev) for a in (prp, pcl, pvl))
+            A = capi.amgg_galerkin_device(device, n_l, nc, *A, *P, chunk_products=chunk_products)
+            capi.amgg_rs_push_level(h, nc, *(a.cpu().numpy() for a in A))
+            lvl += 1
+        return h
+    except BaseException:
+        capi.amgg_rs_free(h)
+        raise
 
 
 def _stream_ptr(torch, device):

@@ -125,3 +125,69 @@ def test_rs_bitexact_airfoil_cmesh():
 
 def test_rs_bitexact_kuhn_tetrahedra():
     _compare(W.tet_fv_mesh(*W.kuhn_tets(10, 1)), singular=True, max_coarse=60)
+
+
+def _levels_equal(ha, hb):
+    assert ha.nlevels == hb.nlevels and ha.singular == hb.singular
+    for La, Lb in zip(ha.levels, hb.levels):
+        assert np.array_equal(La.rowptr, Lb.rowptr) and np.array_equal(La.col, Lb.col)
+        assert np.array_equal(_bits(La.val), _bits(Lb.val))
+        assert np.array_equal(La.cf, Lb.cf)
+        if La.p_rowptr is not None:
+            assert np.array_equal(La.p_rowptr, Lb.p_rowptr) and np.array_equal(La.p_col, Lb.p_col)
+            assert np.array_equal(_bits(La.p_val), _bits(Lb.p_val))
+
+
+@pytest.mark.parametrize("source", ["host", "oracle"])
+def test_stepwise_setup_equals_one_call_setup(source):
+    """amgg_rs_begin / coarsen / galerkin (or push_level of the oracle's Galerkin products)
+    gives the hierarchy of amgg_rs_setup bit for bit."""
+    from paper_2606_19251_amd.solver import HostHierarchy
+
+    capi = _capi()
+    A = W.delaunay_p1(W.gmm_points(5000, 4))
+    ref = HostHierarchy.build(A.rowptr, A.col, A.val, max_coarse=60)
+    ho = amg.setup(amg.to_scipy(A), singular=True, max_coarse=60) if source == "oracle" else None
+    h = capi.amgg_rs_begin(A.rowptr, A.col, A.val, A.nrows, 0.25, 10, 60)
+    try:
+        lvl = 0
+        while capi.amgg_rs_coarsen(h):
+            if source == "host":
+                capi.amgg_rs_galerkin(h)
+            else:
+                Ac = ho.levels[lvl + 1].A
+                capi.amgg_rs_push_level(h, Ac.shape[0], Ac.indptr, Ac.indices, Ac.data)
+            lvl += 1
+        assert not capi.amgg_rs_coarsen(h)  # stays stopped
+        got = HostHierarchy.from_handle(h)
+    finally:
+        capi.amgg_rs_free(h)
+    assert lvl == ref.nlevels - 1
+    _levels_equal(ref, got)
+
+
+def test_stepwise_setup_rejects_calls_out_of_sequence():
+    capi = _capi()
+    A = W.grid5(30)
+    h = capi.amgg_rs_begin(A.rowptr, A.col, A.val, A.nrows, 0.25, 10, 20)
+    try:
+        with pytest.raises(capi.AmggError) as e:
+            capi.amgg_rs_galerkin(h)  # nothing to coarsen yet
+        assert e.value.code == capi.AMGG_ESTATE
+        assert capi.amgg_rs_coarsen(h)
+        with pytest.raises(capi.AmggError) as e:
+            capi.amgg_rs_coarsen(h)  # the open level needs its coarse matrix first
+        assert e.value.code == capi.AMGG_ESTATE
+        _, _, nc, _ = capi.amgg_rs_level_size(h, 0)
+        B = W.grid5(int(np.sqrt(nc)) + 1)
+        with pytest.raises(capi.AmggError) as e:
+            capi.amgg_rs_push_level(h, B.nrows, B.rowptr, B.col, B.val)  # wrong size
+        assert e.value.code == capi.AMGG_EINVAL
+        G = W.grid5(30)
+        with pytest.raises(capi.AmggError) as e:
+            capi.amgg_rs_push_level(h, G.nrows, G.rowptr, G.col, G.val)
+        assert e.value.code == capi.AMGG_EINVAL
+        capi.amgg_rs_galerkin(h)
+        assert capi.amgg_rs_info(h)[0] == 2
+    finally:
+        capi.amgg_rs_free(h)
