@@ -167,10 +167,31 @@ def make_workload(name):
     return W.airfoil_cmesh_problem(4096, 1024, 0)
 
 
+def _tiny_matrix():
+    import workloads as W
+
+    A = W.grid5(40)
+    return A.rowptr, A.col, A.val
+
+
+def same_hierarchy(ha, hb):
+    """Same levels, patterns and FP64 bits."""
+    if ha.nlevels != hb.nlevels:
+        return False
+    for La, Lb in zip(ha.levels, hb.levels):
+        if not (np.array_equal(La.rowptr, Lb.rowptr) and np.array_equal(La.col, Lb.col)
+                and np.array_equal(La.val.view(np.uint64), Lb.val.view(np.uint64))):
+            return False
+        if La.p_col is not None and not (np.array_equal(La.p_col, Lb.p_col)
+                                         and np.array_equal(La.p_val.view(np.uint64), Lb.p_val.view(np.uint64))):
+            return False
+    return True
+
+
 class Case:
     """One workload on the device: hierarchy, solver, right-hand side, trained predictor."""
 
-    def __init__(self, torch, name):
+    def __init__(self, torch, name, with_host_setup=False):
         from paper_2606_19251_amd import gcin as G
         from paper_2606_19251_amd.solver import DeviceSolver, HostHierarchy
 
@@ -178,11 +199,25 @@ class Case:
         t0 = time.time()
         self.A, self.f = make_workload(name)
         log(f"{name}: n={self.A.nrows} nnz={self.A.nnz} ({time.time() - t0:.1f} s)")
+        # RS setup with the Galerkin products on the GPU (a warm-up call loads the sort kernels)
+        HostHierarchy.build(*_tiny_matrix(), max_coarse=10, galerkin="device")
+        tm = {}
         t0 = time.time()
         self.hh = HostHierarchy.build(self.A.rowptr, self.A.col, self.A.val, theta=0.25, max_levels=10,
-                                      max_coarse=500)
-        self.host_setup_ms = (time.time() - t0) * 1e3
-        log(f"{name}: host RS setup {self.host_setup_ms:.0f} ms, levels {[L.n for L in self.hh.levels]}")
+                                      max_coarse=500, galerkin="device", timings=tm)
+        torch.cuda.synchronize()
+        self.setup = {"device_galerkin_build_ms": round((time.time() - t0) * 1e3, 1),
+                      **{k.replace("_s", "_ms"): round(v * 1e3, 1) for k, v in tm.items()}}
+        log(f"{name}: RS setup with device Galerkin {self.setup}, levels {[L.n for L in self.hh.levels]}")
+        if with_host_setup:
+            t0 = time.time()
+            hh = HostHierarchy.build(self.A.rowptr, self.A.col, self.A.val, theta=0.25, max_levels=10,
+                                     max_coarse=500)
+            self.setup["host_build_ms"] = round((time.time() - t0) * 1e3, 1)
+            self.setup["bitwise_equal"] = bool(same_hierarchy(hh, self.hh))
+            log(f"{name}: host RS setup {self.setup['host_build_ms']:.0f} ms, "
+                f"bitwise equal: {self.setup['bitwise_equal']}")
+            del hh
         self.ds = DeviceSolver(self.hh, 0)
         self.dev = self.ds.device
         self.b = torch.from_numpy(self.f).to(self.dev)
@@ -258,8 +293,10 @@ class Case:
 def training_step(torch, steps=10, warmup=3):
     """One training step of Alg. 1 on the 32-mesh training batch (2k-16k nodes each, Gaussian-
     mixture clustered Delaunay P1): batched GCIN forward over all levels (BF16 MFMA, split
-    operands), smoother assembly and one FP32 V(1,1) cycle per mesh with the loss, the
-    hand-written adjoint, the GCIN backward and Adam with clipping; degree-3 coefficients."""
+    operands), smoother assembly and FP32 V(1,1) cycles of every mesh with the loss, the
+    hand-written adjoint, the GCIN backward and Adam with clipping; degree-3 coefficients.
+    The cycles run as one block-diagonal hierarchy (the default); the same step with the
+    meshes cycled one after the other is timed for comparison."""
     import workloads as W
     from paper_2606_19251_amd import capi
     from paper_2606_19251_amd import gcin as G
@@ -270,25 +307,35 @@ def training_step(torch, steps=10, warmup=3):
     solvers = [DeviceSolver(HostHierarchy.build(A.rowptr, A.col, A.val, max_coarse=100), 0) for A, _ in meshes]
     dev = solvers[0].device
     rhs = [torch.from_numpy(f).to(dev) for _, f in meshes]
-    pred = G.Predictor(G.init_flat(3, 0), dev, 3, capi.GCIN_BF16X3)
-    tr = G.Trainer(solvers, rhs, pred, nvc=1)
+
+    def timed(nvc, batched):
+        pred = G.Predictor(G.init_flat(3, 0), dev, 3, capi.GCIN_BF16X3)
+        tr = G.Trainer(solvers, rhs, pred, nvc=nvc, batched=batched)
+        for _ in range(warmup):
+            tr.step()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(steps):
+            losses = tr.step()
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / steps
+        log(f"training step (nvc {nvc}, {'batched' if batched else 'one mesh at a time'}): {ms:.2f} ms "
+            f"(loss {float(losses.mean()):.4f})")
+        return round(ms, 3), tr
+
+    ms, tr = timed(1, True)
+    ms4, _ = timed(4, True)
+    seq, _ = timed(1, False)
     log(f"training batch: 32 meshes, {sum(ds.n for ds in solvers)} fine nodes, "
         f"{tr.batch.ngraphs} graphs ({time.time() - t0:.1f} s)")
-    for _ in range(warmup):
-        tr.step()
-    torch.cuda.synchronize()
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.record()
-    for _ in range(steps):
-        losses = tr.step()
-    e.record()
-    torch.cuda.synchronize()
-    ms = s.elapsed_time(e) / steps
-    log(f"training step: {ms:.2f} ms (loss {float(losses.mean()):.4f})")
-    out = {"ms_per_step": round(ms, 3), "meshes": 32, "fine_nodes": int(sum(ds.n for ds in solvers)),
-           "graphs": int(tr.batch.ngraphs), "nodes": int(tr.batch.n.sum()), "degree": 3, "nvc": 1,
+    out = {"ms_per_step": ms, "ms_per_step_nvc4": ms4, "ms_per_step_one_mesh_at_a_time": seq, "meshes": 32,
+           "fine_nodes": int(sum(ds.n for ds in solvers)), "graphs": int(tr.batch.ngraphs),
+           "nodes": int(tr.batch.n.sum()), "degree": 3, "nvc": 1,
            "gcin": "BF16 MFMA with split operands (FP32-accurate products), FP32 accumulation",
-           "cycles": "FP32 V(1,1), one per mesh, hand-written adjoint"}
+           "cycles": "FP32 V(1,1) of all 32 meshes in one block-diagonal hierarchy, hand-written adjoint"}
+    tr.bsolver.close()
     for ds in solvers:
         ds.close()
     return out
@@ -319,7 +366,7 @@ def main():
 
     from paper_2606_19251_amd import capi
 
-    case = Case(torch, args.workload)
+    case = Case(torch, args.workload, with_host_setup=not (args.profile_gcin or args.profile_kernels))
     ds, hh = case.ds, case.hh
     if args.profile_gcin:
         for _ in range(5):
@@ -382,7 +429,7 @@ def main():
         "ir": ir_res,
         "vcycle_bytes": int(vbytes),
         "solve_gbs_algorithmic": round(solve_gbs, 1),
-        "host_setup_ms": round(case.host_setup_ms, 1),
+        "setup": case.setup,
         "roofline": roof,
     }
     if args.workload == "delaunay1m" and not args.no_cpu_baseline:

@@ -286,6 +286,41 @@ int amgg_vcycle_loss_adjoint(amgg_ctx* ctx, int nu1, int nu2, int precision, int
                              const double* f, const double* u0, double* loss_dev,
                              double* dcoeffs_dev, void* stream);
 
+/* ------------------------------------------------------------------------------------
+ * Block-diagonal (batched) hierarchies: the independent problems of a training mini-batch
+ * (Sec. 3.3-3.4; Alg. 1, steps 7-12) in one context, so that each kernel of a V-cycle and
+ * of its adjoint serves all of them at once.
+ * ------------------------------------------------------------------------------------ */
+/* Declare level lvl (loaded, before amgg_finalize) block-diagonal with nblk blocks: block b
+ * holds rows [offsets[b], offsets[b+1]) (host array of nblk+1 entries from 0 to n, no empty
+ * block) and is coupled to no other block. Every level needs the same nblk, and P_l must map
+ * block b of level l into block b of level l+1 (amgg_finalize checks both). coeff_rows
+ * (host, nblk entries; NULL means 0..nblk-1): the row of the coefficient array that block
+ * b reads in amgg_set_smoother_coeffs_blocks and whose gradient it receives in
+ * amgg_vcycle_loss_adjoint_blocks; -1 means no smoother on that block (Q = 0: with an
+ * identity P this passes a problem whose own hierarchy is shallower through the level
+ * unchanged). Rows >= 0 must differ within a level. singular (host, nblk entries, may be
+ * NULL): on the coarsest level, the blocks whose dense solve takes the rank-one fix of an
+ * all-Neumann problem. Each block gets its own off-diagonal scale s of Eq. 5 and its own
+ * dense coarsest inverse; amgg_set_smoother_coeffs / _jacobi apply the same coefficients to
+ * every block with a coefficient row. amgg_solve is not available on such a context. */
+int amgg_set_level_blocks(amgg_ctx* ctx, int lvl, int32_t nblk, const int32_t* offsets,
+                          const int32_t* coeff_rows, const int32_t* singular);
+/* Eq. 5 smoother of a block-diagonal level: block b uses the degree-`degree` coefficients at
+ * coeffs_dev + coeff_rows[b] * stride (device FP32, e.g. the GCIN output for all levels of
+ * all problems, one row per level graph; stride >= 2*degree+1). */
+int amgg_set_smoother_coeffs_blocks(amgg_ctx* ctx, int lvl, int degree, const float* coeffs_dev,
+                                    int32_t stride, void* stream);
+/* amgg_vcycle_loss_adjoint of every block at once: loss_dev[b] (device FP64, nblk) is block
+ * b's loss, and the gradient of block b's loss with respect to the coefficients of level l
+ * is added to row coeff_rows_l[b] of dcoeffs_dev (device FP64, dcoeff_rows x (2*degree+1),
+ * zeroed first; rows no block uses stay 0). f and u0 (may be NULL) hold the blocks' fine
+ * vectors one after the other. Sums over a block run in a different order than in
+ * amgg_vcycle_loss_adjoint (differences at rounding level). No host synchronisation. */
+int amgg_vcycle_loss_adjoint_blocks(amgg_ctx* ctx, int nu1, int nu2, int precision, int nvc,
+                                    const double* f, const double* u0, double* loss_dev,
+                                    double* dcoeffs_dev, int32_t dcoeff_rows, void* stream);
+
 /* out[i] = (float)(in[i] * scale) for i < n (device arrays): hands the FP64 coefficient
  * gradients of amgg_vcycle_loss_adjoint, scaled by 1/|batch| (Alg. 1, step 12: batch-mean
  * loss), to the FP32 predictor backward. */

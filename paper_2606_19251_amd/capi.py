@@ -95,6 +95,9 @@ SIGNATURES = {
     "amgg_level_apply_timed": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP]),
     "amgg_solve": (_I, [_VP, C.POINTER(amgg_solve_opts), _VP, _VP, C.POINTER(amgg_solve_info), _VP, _I, _VP]),
     "amgg_vcycle_loss_adjoint": (_I, [_VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _VP]),
+    "amgg_set_level_blocks": (_I, [_VP, _I, _I32, _VP, _VP, _VP]),
+    "amgg_set_smoother_coeffs_blocks": (_I, [_VP, _I, _I, _VP, _I32, _VP]),
+    "amgg_vcycle_loss_adjoint_blocks": (_I, [_VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _I32, _VP]),
     "amgg_cast_scale_f64_f32": (_I, [_VP, _VP, C.c_int64, C.c_double, _VP]),
     "gcin_param_count": (C.c_int64, [_I]),
     "gcin_batch_workspace_bytes": (_I, [_I, _VP, _VP, C.POINTER(C.c_size_t)]),
@@ -336,6 +339,25 @@ def amgg_solve(ctx, opts: amgg_solve_opts, b, x, history_cap: int, stream):
 def amgg_vcycle_loss_adjoint(ctx, nu1, nu2, precision, nvc, f, u0, loss_dev, dcoeffs_dev, stream):
     return _check(lib().amgg_vcycle_loss_adjoint(ctx, nu1, nu2, precision, nvc, f, u0, loss_dev, dcoeffs_dev,
                                                  stream), "amgg_vcycle_loss_adjoint")
+
+
+def amgg_set_level_blocks(ctx, lvl, offsets, coeff_rows=None, singular=None):
+    offsets = np.ascontiguousarray(offsets, np.int32)
+    rows = None if coeff_rows is None else np.ascontiguousarray(coeff_rows, np.int32)
+    sing = None if singular is None else np.ascontiguousarray(singular, np.int32)
+    return _check(lib().amgg_set_level_blocks(ctx, lvl, offsets.size - 1, _np_ptr(offsets), _np_ptr(rows),
+                                              _np_ptr(sing)), "amgg_set_level_blocks")
+
+
+def amgg_set_smoother_coeffs_blocks(ctx, lvl, degree, coeffs_dev, stride, stream):
+    return _check(lib().amgg_set_smoother_coeffs_blocks(ctx, lvl, degree, coeffs_dev, stride, stream),
+                  "amgg_set_smoother_coeffs_blocks")
+
+
+def amgg_vcycle_loss_adjoint_blocks(ctx, nu1, nu2, precision, nvc, f, u0, loss_dev, dcoeffs_dev, dcoeff_rows,
+                                    stream):
+    return _check(lib().amgg_vcycle_loss_adjoint_blocks(ctx, nu1, nu2, precision, nvc, f, u0, loss_dev, dcoeffs_dev,
+                                                        dcoeff_rows, stream), "amgg_vcycle_loss_adjoint_blocks")
 
 
 def amgg_cast_scale_f64_f32(src, dst, n, scale, stream):

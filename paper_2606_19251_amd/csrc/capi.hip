@@ -44,7 +44,9 @@ struct Bump {
 // Carve the workspace; with base == 0 only the size is computed.
 size_t layout(amgg_ctx* c, uintptr_t base) {
     Bump b{base};
+    c->nblk = c->lv[0].nblk;
     int32_t max_nc = 1;
+    int32_t max_chunks = 1;
     for (int l = 0; l < c->nlevels; ++l) {
         Level& L = c->lv[l];
         const size_t n = L.n, z = L.nnz;
@@ -89,10 +91,24 @@ size_t layout(amgg_ctx* c, uintptr_t base) {
                 L.hq32 = b.take<float>(z);
                 L.hloc = b.take<uint16_t>(z);
             }
+        } else if (L.nblk > 0) {
+            const size_t dz = static_cast<size_t>(L.dense_off_h.back());
+            L.dense = b.take<double>(dz);
+            L.inv = b.take<double>(dz);
+            L.piv = b.take<int32_t>(n);
+            L.dense_off = b.take<int64_t>(L.nblk + 1);
         } else {
             L.dense = b.take<double>(n * n);
             L.inv = b.take<double>(n * n);
             L.piv = b.take<int32_t>(n);
+        }
+        if (L.nblk > 0) {
+            L.blk_off = b.take<int32_t>(L.nblk + 1);
+            L.blk_crow = b.take<int32_t>(L.nblk);
+            L.blk_scale = b.take<double>(L.nblk);
+            L.chunk_row = b.take<int32_t>(L.nchunk() + 1);
+            L.blk_chunk = b.take<int32_t>(L.nblk + 1);
+            max_chunks = std::max(max_chunks, L.nchunk());
         }
         for (int k = 0; k < kAdjVecs; ++k) {
             L.adj64[k] = b.take<double>(n);
@@ -114,12 +130,24 @@ size_t layout(amgg_ctx* c, uintptr_t base) {
     c->adj_partial = b.take<double>(static_cast<size_t>(2 * AMGG_MAX_DEGREE + 1) * kReduceBlocks);
     c->adj_scal = b.take<double>(64);
     c->adj_f32 = b.take<float>(n0);
+    if (c->nblk > 0) {
+        c->blk_scal = b.take<double>(4 * static_cast<size_t>(c->nblk));
+        c->blk_partial = b.take<double>(static_cast<size_t>(kMaxCoef) * max_chunks);
+    }
     return (b.off + 255) & ~static_cast<size_t>(255);
 }
 
 // ------------------------------------------------------------------------------------
 // V-cycle
 // ------------------------------------------------------------------------------------
+template <typename T>
+hipError_t coarse_solve(const Level& L, const T* f, T* u, hipStream_t st) {
+    if (L.nblk > 0) return block_dense_gemv<T>(L.n, L.nblk, L.blk_off, L.dense_off, L.inv, f, u, st);
+    return dense_gemv<T>(L.n, L.inv, f, u, st);
+}
+template hipError_t coarse_solve<float>(const Level&, const float*, float*, hipStream_t);
+template hipError_t coarse_solve<double>(const Level&, const double*, double*, hipStream_t);
+
 template <typename T>
 hipError_t smooth_step(Level& L, const T* f, T*& cur, T*& oth, T* r, bool from_zero, hipStream_t st) {
     const CsrView A = L.A();
@@ -149,7 +177,7 @@ hipError_t vcycle_level(amgg_ctx* c, int l, const T* f, T* u, T* t, bool zero, i
     hipError_t e;
     if (l == c->nlevels - 1) {
         *result = u;
-        return dense_gemv<T>(L.n, L.inv, f, u, st);
+        return coarse_solve<T>(L, f, u, st);
     }
     T* cur = u;
     T* oth = t;
@@ -312,7 +340,20 @@ static int check_loaded(const amgg_ctx* c, const char* where) {
                                              " does not match the level sizes");
         }
     }
-    const int32_t nL = c->lv[c->nlevels - 1].n;
+    const Level& Lc = c->lv[c->nlevels - 1];
+    int32_t nL = Lc.n;
+    if (Lc.nblk > 0) {
+        nL = 0;
+        for (int32_t b = 0; b < Lc.nblk; ++b) nL = std::max(nL, Lc.blk_off_h[b + 1] - Lc.blk_off_h[b]);
+    }
+    int32_t nblk = -1;
+    for (int l = 0; l < c->nlevels; ++l) {
+        const int32_t k = c->lv[l].nblk;
+        if (nblk < 0) nblk = k;
+        if (k != nblk)
+            return fail(AMGG_EINVAL, std::string(where) + ": every level needs the same block count (level " +
+                                         std::to_string(l) + " has " + std::to_string(k) + ")");
+    }
     if (nL > AMGG_MAX_COARSE_DENSE)
         return fail(AMGG_EINVAL, std::string(where) + ": coarsest level has " + std::to_string(nL) +
                                      " rows, more than the dense limit " + std::to_string(AMGG_MAX_COARSE_DENSE));
@@ -384,6 +425,7 @@ extern "C" int amgg_finalize(amgg_ctx* c, int singular, void* workspace, size_t 
         hipError_t e = hipSetDevice(c->device);
         if (e != hipSuccess) return hip_fail(e, "amgg_finalize");
         drop_graphs(c);
+        c->nblk = c->lv[0].nblk;
         layout(c, reinterpret_cast<uintptr_t>(workspace));
         c->ws = workspace;
         c->ws_bytes = ws_bytes;
@@ -405,16 +447,44 @@ extern "C" int amgg_finalize(amgg_ctx* c, int singular, void* workspace, size_t 
             }
         }
         Level& Lc = c->lv[c->nlevels - 1];
-        ok(dense_from_csr(Lc.n, Lc.ptr, Lc.col, Lc.val, Lc.dense, c->singular, st));
-        ok(dense_lu_inverse(Lc.n, Lc.dense, Lc.piv, Lc.inv, c->flags + 1, st));
+        if (c->nblk > 0) {
+            auto up = [&](void* dst, const void* src, size_t bytes) {
+                ok(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+            };
+            for (int l = 0; l < c->nlevels; ++l) {
+                Level& L = c->lv[l];
+                up(L.blk_off, L.blk_off_h.data(), sizeof(int32_t) * L.blk_off_h.size());
+                up(L.blk_crow, L.blk_crow_h.data(), sizeof(int32_t) * L.blk_crow_h.size());
+                up(L.chunk_row, L.chunk_row_h.data(), sizeof(int32_t) * L.chunk_row_h.size());
+                up(L.blk_chunk, L.blk_chunk_h.data(), sizeof(int32_t) * L.blk_chunk_h.size());
+            }
+            for (int l = 0; l < c->nlevels; ++l) {  // after every level's tables are on the device
+                Level& L = c->lv[l];
+                ok(block_absmax(L.nblk, L.blk_off, L.ptr, L.col, L.val, L.blk_scale, st));
+                if (l + 1 < c->nlevels)
+                    ok(prolong_blocks_check(L.n, L.pptr, L.pcol, L.nblk, L.blk_off, c->lv[l + 1].blk_off,
+                                            c->flags + 2, st));
+            }
+            up(Lc.dense_off, Lc.dense_off_h.data(), sizeof(int64_t) * Lc.dense_off_h.size());
+            for (int32_t b = 0; b < Lc.nblk; ++b) {
+                const int32_t o = Lc.blk_off_h[b], nb = Lc.blk_off_h[b + 1] - o;
+                double* M = Lc.dense + Lc.dense_off_h[b];
+                ok(dense_from_csr(nb, Lc.ptr + o, Lc.col, Lc.val, M, Lc.blk_sing_h[b], st, o));
+                ok(dense_lu_inverse(nb, M, Lc.piv + o, Lc.inv + Lc.dense_off_h[b], c->flags + 1, st));
+            }
+        } else {
+            ok(dense_from_csr(Lc.n, Lc.ptr, Lc.col, Lc.val, Lc.dense, c->singular, st));
+            ok(dense_lu_inverse(Lc.n, Lc.dense, Lc.piv, Lc.inv, c->flags + 1, st));
+        }
         if (e != hipSuccess) return hip_fail(e, "amgg_finalize (launch)");
         if ((e = build_halos(c, st)) != hipSuccess) return hip_fail(e, "amgg_finalize (halo lists)");
-        int32_t flags[2] = {0, 0};
+        int32_t flags[3] = {0, 0, 0};
         if ((e = hipMemcpyAsync(flags, c->flags, sizeof(flags), hipMemcpyDeviceToHost, st)) != hipSuccess ||
             (e = hipStreamSynchronize(st)) != hipSuccess)
             return hip_fail(e, "amgg_finalize (sync)");
         if (flags[0]) return fail(AMGG_EINVAL, "amgg_finalize: a level matrix has a missing or non-positive diagonal");
         if (flags[1]) return fail(AMGG_EINVAL, "amgg_finalize: coarsest matrix is singular (zero pivot)");
+        if (flags[2]) return fail(AMGG_EINVAL, "amgg_finalize: a prolongation couples different blocks");
         c->finalized = true;
         return AMGG_OK;
     });
@@ -475,7 +545,11 @@ static int set_coeffs_impl(amgg_ctx* c, int lvl, int degree, const double* coeff
     }
     Level& L = c->lv[lvl];
     hipError_t e = hipSetDevice(c->device);
-    if (e == hipSuccess)
+    if (e == hipSuccess && L.nblk > 0)  // the same coefficients on every block, each with its own scale
+        e = assemble_smoother_blocks(L.n, L.ptr, L.col, L.val, L.diag, L.nblk, L.blk_off, L.blk_scale, L.blk_crow, pc,
+                                     coeffs ? nullptr : dev, 0, L.q64, L.q32, L.qd64, L.qd32,
+                                     static_cast<hipStream_t>(stream));
+    else if (e == hipSuccess)
         e = assemble_smoother(L.n, L.ptr, L.col, L.val, L.diag, L.scale, pc, coeffs ? nullptr : dev, L.q64, L.q32,
                               L.qd64, L.qd32, static_cast<hipStream_t>(stream));
     if (e == hipSuccess && L.hrows > 0)
@@ -499,6 +573,74 @@ extern "C" int amgg_set_smoother_coeffs_device(amgg_ctx* c, int lvl, int degree,
 extern "C" int amgg_set_smoother_jacobi(amgg_ctx* c, int lvl, double omega, void* stream) {
     double cf[3] = {omega, 0.0, 0.0};
     return guarded([&] { return set_coeffs_impl(c, lvl, 1, cf, nullptr, stream); });
+}
+
+extern "C" int amgg_set_smoother_coeffs_blocks(amgg_ctx* c, int lvl, int degree, const float* coeffs_dev,
+                                               int32_t stride, void* stream) {
+    return guarded([&]() -> int {
+        if (!c || lvl < 0 || lvl >= c->nlevels) return fail(AMGG_EINVAL, "amgg_set_smoother_coeffs_blocks: bad level");
+        if (!c->finalized) return fail(AMGG_ESTATE, "amgg_set_smoother_coeffs_blocks: hierarchy not finalized");
+        Level& L = c->lv[lvl];
+        if (L.nblk == 0) return fail(AMGG_ESTATE, "amgg_set_smoother_coeffs_blocks: level has no blocks");
+        if (degree < 1 || degree > AMGG_MAX_DEGREE || !coeffs_dev || stride < 2 * degree + 1)
+            return fail(AMGG_EINVAL, "amgg_set_smoother_coeffs_blocks: bad degree, stride or null coefficients");
+        PolyCoeffs pc{};
+        pc.degree = degree;
+        const hipStream_t st = static_cast<hipStream_t>(stream);
+        hipError_t e = hipSetDevice(c->device);
+        if (e == hipSuccess)
+            e = assemble_smoother_blocks(L.n, L.ptr, L.col, L.val, L.diag, L.nblk, L.blk_off, L.blk_scale, L.blk_crow,
+                                         pc, coeffs_dev, stride, L.q64, L.q32, L.qd64, L.qd32, st);
+        if (e == hipSuccess && L.hrows > 0) e = gather_values(L.nhent, L.hent, L.q64, L.q32, L.hq64, L.hq32, st);
+        if (e != hipSuccess) return hip_fail(e, "amgg_set_smoother_coeffs_blocks");
+        L.smoother = kSmootherSparse;
+        L.degree = degree;
+        L.baseline = false;
+        return AMGG_OK;
+    });
+}
+
+extern "C" int amgg_set_level_blocks(amgg_ctx* c, int lvl, int32_t nblk, const int32_t* offsets,
+                                     const int32_t* coeff_rows, const int32_t* singular) {
+    return guarded([&]() -> int {
+        if (!c || lvl < 0 || lvl >= c->nlevels) return fail(AMGG_EINVAL, "amgg_set_level_blocks: bad context or level");
+        Level& L = c->lv[lvl];
+        if (!L.loaded) return fail(AMGG_ESTATE, "amgg_set_level_blocks: load the level first");
+        if (nblk < 1 || !offsets) return fail(AMGG_EINVAL, "amgg_set_level_blocks: nblk < 1 or null offsets");
+        if (offsets[0] != 0 || offsets[nblk] != L.n)
+            return fail(AMGG_EINVAL, "amgg_set_level_blocks: offsets must run from 0 to the level's row count");
+        for (int32_t b = 0; b < nblk; ++b)
+            if (offsets[b + 1] <= offsets[b]) return fail(AMGG_EINVAL, "amgg_set_level_blocks: empty or unordered block");
+        std::vector<int32_t> rows(nblk);
+        for (int32_t b = 0; b < nblk; ++b) rows[b] = coeff_rows ? coeff_rows[b] : b;
+        std::vector<int32_t> used;
+        for (int32_t r : rows)
+            if (r >= 0) used.push_back(r);
+        std::sort(used.begin(), used.end());
+        if (std::adjacent_find(used.begin(), used.end()) != used.end())
+            return fail(AMGG_EINVAL, "amgg_set_level_blocks: two blocks share a coefficient row");
+        L.nblk = nblk;
+        L.blk_off_h.assign(offsets, offsets + nblk + 1);
+        L.blk_crow_h = rows;
+        L.blk_sing_h.assign(nblk, 0);
+        if (singular)
+            for (int32_t b = 0; b < nblk; ++b) L.blk_sing_h[b] = singular[b] ? 1 : 0;
+        L.chunk_row_h.clear();
+        L.blk_chunk_h.assign(nblk + 1, 0);
+        for (int32_t b = 0; b < nblk; ++b) {
+            L.blk_chunk_h[b] = static_cast<int32_t>(L.chunk_row_h.size());
+            for (int32_t r = offsets[b]; r < offsets[b + 1]; r += kChunkRows) L.chunk_row_h.push_back(r);
+        }
+        L.blk_chunk_h[nblk] = static_cast<int32_t>(L.chunk_row_h.size());
+        L.chunk_row_h.push_back(L.n);
+        L.dense_off_h.assign(nblk + 1, 0);
+        for (int32_t b = 0; b < nblk; ++b) {
+            const int64_t nb = offsets[b + 1] - offsets[b];
+            L.dense_off_h[b + 1] = L.dense_off_h[b] + nb * nb;
+        }
+        c->finalized = false;
+        return AMGG_OK;
+    });
 }
 
 // ------------------------------------------------------------------------------------
@@ -553,7 +695,7 @@ hipError_t level_apply_t(amgg_ctx* c, int lvl, int op, const T* x, T* y, const T
         case AMGG_OP_PROLONG:
             return csr_apply<T>(L.P(), L.pv<T>(), x, y, nullptr, nullptr, nullptr, Epi::Add, st);
         case AMGG_OP_COARSE:
-            return dense_gemv<T>(L.n, L.inv, x, y, st);
+            return coarse_solve<T>(L, x, y, st);
     }
     return hipErrorInvalidValue;
 }

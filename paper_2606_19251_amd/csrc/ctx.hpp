@@ -15,6 +15,8 @@
 namespace amgg {
 
 enum : int { kSmootherNone = 0, kSmootherDiagonal = 1, kSmootherSparse = 2 };
+constexpr int kChunkRows = 256;  // rows per workgroup of the segmented (per-block) sums
+constexpr int kMaxCoef = 2 * AMGG_MAX_DEGREE + 1;
 
 struct Level {
     bool loaded = false, p_loaded = false;
@@ -64,6 +66,20 @@ struct Level {
     // adjoint scratch, kAdjVecs vectors of n per precision (see AdjVec)
     double* adj64[8] = {};
     float* adj32[8] = {};
+    // block-diagonal (batched) level: nblk independent problems, rows of block b are
+    // [blk_off[b], blk_off[b+1]); host copies are kept for the device tables and the chunks
+    // of at most kChunkRows rows (never spanning two blocks) that segmented sums use
+    int32_t nblk = 0;
+    std::vector<int32_t> blk_off_h, blk_crow_h, chunk_row_h, blk_chunk_h;
+    std::vector<int32_t> blk_sing_h;
+    std::vector<int64_t> dense_off_h;
+    int32_t* blk_off = nullptr;
+    int32_t* blk_crow = nullptr;  // coefficient row of each block (-1: no smoother)
+    double* blk_scale = nullptr;
+    int32_t* chunk_row = nullptr;  // nchunk + 1 row starts
+    int32_t* blk_chunk = nullptr;  // nblk + 1 chunk offsets
+    int64_t* dense_off = nullptr;  // coarsest level: offset of each block's dense inverse
+    int32_t nchunk() const { return static_cast<int32_t>(chunk_row_h.empty() ? 0 : chunk_row_h.size() - 1); }
     // smoother state
     int smoother = kSmootherNone;
     int degree = 0;
@@ -128,6 +144,10 @@ struct amgg_ctx {
     double* adj_partial = nullptr;
     double* adj_scal = nullptr;
     float* adj_f32 = nullptr;
+    // block-diagonal contexts (every level split into nblk blocks)
+    int32_t nblk = 0;
+    double* blk_scal = nullptr;     // per-block loss scalars, 4 x nblk
+    double* blk_partial = nullptr;  // per-chunk partial sums, kMaxCoef x (most chunks of a level)
 };
 
 namespace amgg {
@@ -140,5 +160,8 @@ hipError_t vcycle_level(amgg_ctx* c, int l, const T* f, T* u, T* t, bool zero, i
                         T** result, bool store = false);
 template <typename T>
 hipError_t smooth_step(Level& L, const T* f, T*& cur, T*& oth, T* r, bool from_zero, hipStream_t st);
+// Coarsest-level solve: the dense inverse, or the block inverses of a block-diagonal level.
+template <typename T>
+hipError_t coarse_solve(const Level& L, const T* f, T* u, hipStream_t st);
 
 }  // namespace amgg

@@ -1,5 +1,6 @@
 // Setup-side kernels: diagonal and off-diagonal scale of each level, the exact transpose
 // R = P^T, and the dense coarsest-level factorisation, inverse and per-cycle product.
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.hpp"
@@ -68,29 +69,69 @@ __global__ void count_cols_kernel(int32_t nnz, const int32_t* __restrict__ col, 
     if (p < nnz) atomicAdd(&cnt[col[p] + 1], 1);
 }
 
-// In-place inclusive scan of a[1..m] by one workgroup of 1024 threads (setup only).
-__global__ __launch_bounds__(1024) void scan_kernel(int32_t m, int32_t* __restrict__ a) {
-    __shared__ int32_t part[1024];
-    const int32_t chunk = (m + 1023) / 1024;
-    const int32_t lo = 1 + threadIdx.x * chunk;
-    const int32_t hi = min(lo + chunk, m + 1);
-    int32_t s = 0;
-    for (int32_t k = lo; k < hi; ++k) s += a[k];
-    part[threadIdx.x] = s;
+// In-place inclusive scan of a[1..m] (setup only): the range is cut into at most
+// kScanParts contiguous pieces; pass 1 sums each piece, pass 2 scans the piece sums, pass 3
+// scans each piece from its offset. Integer sums: the result does not depend on the order.
+constexpr int kScanBlock = 1024;  // 16 wavefronts
+constexpr int64_t kScanParts = 1024;  // at most ceil(m / kScanBlock) <= m pieces
+
+__device__ int32_t block_inclusive_scan(int32_t v, int32_t* lds, int32_t* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    if (lane == 63) lds[wave] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t run = 0;
-        for (int k = 0; k < 1024; ++k) {
-            const int32_t v = part[k];
-            part[k] = run;
-            run += v;
+    if (wave == 0) {
+        int32_t w = lane < kScanBlock / 64 ? lds[lane] : 0;
+        for (int o = 1; o < kScanBlock / 64; o <<= 1) {
+            const int32_t t = __shfl_up(w, o, 64);
+            if (lane >= o) w += t;
         }
+        if (lane < kScanBlock / 64) lds[lane] = w;
     }
     __syncthreads();
-    int32_t run = part[threadIdx.x];
-    for (int32_t k = lo; k < hi; ++k) {
-        run += a[k];
-        a[k] = run;
+    if (wave > 0) v += lds[wave - 1];
+    *total = lds[kScanBlock / 64 - 1];
+    __syncthreads();
+    return v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void scan_reduce_kernel(int32_t m, int32_t piece,
+                                                                 const int32_t* __restrict__ a,
+                                                                 int32_t* __restrict__ parts) {
+    __shared__ int32_t lds[kScanBlock / 64];
+    const int64_t lo = 1 + static_cast<int64_t>(blockIdx.x) * piece;
+    const int64_t hi = min(lo + piece, static_cast<int64_t>(m) + 1);
+    int32_t s = 0;
+    for (int64_t k = lo + threadIdx.x; k < hi; k += kScanBlock) s += a[k];
+    int32_t total;
+    block_inclusive_scan(s, lds, &total);
+    if (threadIdx.x == 0) parts[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanBlock) void scan_parts_kernel(int32_t nparts, int32_t* __restrict__ parts) {
+    __shared__ int32_t lds[kScanBlock / 64];
+    const int32_t v = threadIdx.x < nparts ? parts[threadIdx.x] : 0;
+    int32_t total;
+    const int32_t incl = block_inclusive_scan(v, lds, &total);
+    if (threadIdx.x < nparts) parts[threadIdx.x] = incl - v;  // exclusive
+}
+
+__global__ __launch_bounds__(kScanBlock) void scan_apply_kernel(int32_t m, int32_t piece, int32_t* __restrict__ a,
+                                                                const int32_t* __restrict__ parts) {
+    __shared__ int32_t lds[kScanBlock / 64];
+    const int64_t lo = 1 + static_cast<int64_t>(blockIdx.x) * piece;
+    const int64_t hi = min(lo + piece, static_cast<int64_t>(m) + 1);
+    int32_t carry = parts[blockIdx.x];
+    for (int64_t base = lo; base < hi; base += kScanBlock) {
+        const int64_t k = base + threadIdx.x;
+        const int32_t v = k < hi ? a[k] : 0;
+        int32_t total;
+        const int32_t incl = block_inclusive_scan(v, lds, &total);
+        if (k < hi) a[k] = carry + incl;
+        carry += total;
     }
 }
 
@@ -134,11 +175,12 @@ __global__ void dense_zero_kernel(int64_t total, double* __restrict__ M) {
     if (k < total) M[k] = 0.0;
 }
 
+// Rows [0, n) of ptr (columns shifted by -col0) into the dense n x n matrix M.
 __global__ void dense_scatter_kernel(int32_t n, const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                                     const double* __restrict__ val, double* __restrict__ M) {
+                                     const double* __restrict__ val, int32_t col0, double* __restrict__ M) {
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p) M[static_cast<int64_t>(i) * n + col[p]] = val[p];
+    for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p) M[static_cast<int64_t>(i) * n + (col[p] - col0)] = val[p];
 }
 
 // A_L + alpha 1 1^T with alpha = mean(diag)/n (constant null space of all-Neumann problems).
@@ -270,6 +312,75 @@ __global__ __launch_bounds__(kBlock) void dense_gemv_kernel(int32_t n, const dou
     if (row < n && lane == 0) y[row] = static_cast<T>(s);
 }
 
+
+// --- block-diagonal levels ---------------------------------------------------------------
+__device__ __forceinline__ int32_t block_of(int32_t i, int32_t nblk, const int32_t* __restrict__ off) {
+    int32_t lo = 0, hi = nblk - 1;  // largest b with off[b] <= i
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) / 2;
+        if (off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// scale[b] = max |a_ij| over the off-diagonal entries of block b's rows (1 if none), one
+// workgroup per block; a maximum does not depend on the order.
+__global__ __launch_bounds__(kBlock) void block_absmax_kernel(const int32_t* __restrict__ off,
+                                                             const int32_t* __restrict__ ptr,
+                                                             const int32_t* __restrict__ col,
+                                                             const double* __restrict__ val,
+                                                             double* __restrict__ scale) {
+    __shared__ double red[kBlock];
+    const int32_t b = blockIdx.x;
+    double m = -1.0;
+    for (int32_t i = off[b] + threadIdx.x; i < off[b + 1]; i += kBlock)
+        for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p)
+            if (col[p] != i) m = fmax(m, fabs(val[p]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) scale[b] = red[0] <= 0.0 ? 1.0 : red[0];
+}
+
+// bad = 1 if an entry of P couples fine block b with another coarse block.
+__global__ void prolong_blocks_kernel(int32_t n, const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                      int32_t nblk, const int32_t* __restrict__ foff,
+                                      const int32_t* __restrict__ coff, int32_t* __restrict__ bad) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int32_t b = block_of(i, nblk, foff);
+    for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p)
+        if (col[p] < coff[b] || col[p] >= coff[b + 1]) bad[0] = 1;
+}
+
+// y = blockdiag(inv_b) x: row i of block b is a dot product with row (i - off[b]) of inv_b,
+// summed exactly as dense_gemv_kernel sums a row of a single inverse.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void block_dense_gemv_kernel(int32_t n, int32_t nblk,
+                                                                 const int32_t* __restrict__ off,
+                                                                 const int64_t* __restrict__ doff,
+                                                                 const double* __restrict__ inv,
+                                                                 const T* __restrict__ x, T* __restrict__ y) {
+    const int32_t row = blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    double s = 0.0;
+    if (row < n) {
+        const int32_t b = block_of(row, nblk, off);
+        const int32_t o = off[b], nb = off[b + 1] - o;
+        const double* a = inv + doff[b] + static_cast<int64_t>(row - o) * nb;
+        for (int32_t j = lane; j < nb; j += 64) s += a[j] * static_cast<double>(x[o + j]);
+    }
+#pragma unroll
+    for (int off2 = 32; off2 > 0; off2 >>= 1) s += __shfl_xor(s, off2, 64);
+    if (row < n && lane == 0) y[row] = static_cast<T>(s);
+}
+
 }  // namespace
 
 hipError_t extract_diag(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, double* diag,
@@ -292,7 +403,12 @@ hipError_t transpose_csr(int32_t nf, int32_t nc, int32_t nnz, const int32_t* p_p
     hipError_t e = vec_zero_bytes(r_ptr, sizeof(int32_t) * (nc + 1), stream);
     if (e != hipSuccess) return e;
     if (nnz > 0) count_cols_kernel<<<grid_for(nnz), kBlock, 0, stream>>>(nnz, p_col, r_ptr);
-    scan_kernel<<<1, 1024, 0, stream>>>(nc, r_ptr);
+    // piece sums live in `cursor`, which is free until the scatter below
+    const int32_t nparts = static_cast<int32_t>(std::min<int64_t>(kScanParts, (static_cast<int64_t>(nc) + kScanBlock - 1) / kScanBlock));
+    const int32_t piece = static_cast<int32_t>((static_cast<int64_t>(nc) + nparts - 1) / nparts);
+    scan_reduce_kernel<<<nparts, kScanBlock, 0, stream>>>(nc, piece, r_ptr, cursor);
+    scan_parts_kernel<<<1, kScanBlock, 0, stream>>>(nparts, cursor);
+    scan_apply_kernel<<<nparts, kScanBlock, 0, stream>>>(nc, piece, r_ptr, cursor);
     if ((e = vec_copy<int32_t>(nc, r_ptr, cursor, stream)) != hipSuccess) return e;
     scatter_transpose_kernel<<<grid_for(nf), kBlock, 0, stream>>>(nf, p_ptr, p_col, p_val, cursor, r_col, r_val);
     sort_rows_kernel<<<grid_for(nc), kBlock, 0, stream>>>(nc, r_ptr, r_col, r_val);
@@ -300,10 +416,10 @@ hipError_t transpose_csr(int32_t nf, int32_t nc, int32_t nnz, const int32_t* p_p
 }
 
 hipError_t dense_from_csr(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, double* M,
-                          int singular, hipStream_t stream) {
+                          int singular, hipStream_t stream, int32_t col0) {
     const int64_t total = static_cast<int64_t>(n) * n;
     dense_zero_kernel<<<grid_for(total), kBlock, 0, stream>>>(total, M);
-    dense_scatter_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, ptr, col, val, M);
+    dense_scatter_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, ptr, col, val, col0, M);
     if (singular) dense_rank_one_kernel<<<1, 1024, 0, stream>>>(n, M);
     return hipGetLastError();
 }
@@ -322,5 +438,31 @@ hipError_t dense_gemv(int32_t n, const double* inv, const T* x, T* y, hipStream_
 }
 template hipError_t dense_gemv<float>(int32_t, const double*, const float*, float*, hipStream_t);
 template hipError_t dense_gemv<double>(int32_t, const double*, const double*, double*, hipStream_t);
+
+hipError_t block_absmax(int32_t nblk, const int32_t* off, const int32_t* ptr, const int32_t* col, const double* val,
+                        double* scale, hipStream_t stream) {
+    if (nblk <= 0) return hipSuccess;
+    block_absmax_kernel<<<nblk, kBlock, 0, stream>>>(off, ptr, col, val, scale);
+    return hipGetLastError();
+}
+
+hipError_t prolong_blocks_check(int32_t n, const int32_t* ptr, const int32_t* col, int32_t nblk, const int32_t* foff,
+                                const int32_t* coff, int32_t* bad, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    prolong_blocks_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, ptr, col, nblk, foff, coff, bad);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t block_dense_gemv(int32_t n, int32_t nblk, const int32_t* off, const int64_t* doff, const double* inv,
+                            const T* x, T* y, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const dim3 grid(static_cast<unsigned>((n + kBlock / 64 - 1) / (kBlock / 64)));
+    return launch_kernel(block_dense_gemv_kernel<T>, grid, dim3(kBlock), stream, n, nblk, off, doff, inv, x, y);
+}
+template hipError_t block_dense_gemv<float>(int32_t, int32_t, const int32_t*, const int64_t*, const double*,
+                                            const float*, float*, hipStream_t);
+template hipError_t block_dense_gemv<double>(int32_t, int32_t, const int32_t*, const int64_t*, const double*,
+                                             const double*, double*, hipStream_t);
 
 }  // namespace amgg

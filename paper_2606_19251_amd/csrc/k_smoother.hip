@@ -27,21 +27,13 @@ __device__ __forceinline__ double horner_off(double x, const double* o, int deg)
     return x * t;
 }
 
-__global__ __launch_bounds__(kBlock) void assemble_kernel(int32_t n, const int32_t* __restrict__ ptr,
-                                                         const int32_t* __restrict__ col,
-                                                         const double* __restrict__ val,
-                                                         const double* __restrict__ diag,
-                                                         const double* __restrict__ scale, PolyCoeffs pc,
-                                                         const float* __restrict__ coeffs_dev,
-                                                         double* __restrict__ q64, float* __restrict__ q32,
-                                                         double* __restrict__ qd64, float* __restrict__ qd32) {
+// Row i of Q and of its diagonal with coefficients c[0..2deg] and scale s.
+__device__ __forceinline__ void assemble_row(int32_t i, const int32_t* __restrict__ ptr,
+                                             const int32_t* __restrict__ col, const double* __restrict__ val,
+                                             const double* __restrict__ diag, const double* c, int deg, double s,
+                                             double* __restrict__ q64, float* __restrict__ q32,
+                                             double* __restrict__ qd64, float* __restrict__ qd32) {
 #pragma clang fp contract(off)
-    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int deg = pc.degree;
-    double c[2 * 4 + 1];
-    for (int k = 0; k < 2 * deg + 1; ++k) c[k] = coeffs_dev ? static_cast<double>(coeffs_dev[k]) : pc.c[k];
-    const double s = scale[0];
     const double aii = diag[i];
     for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p) {
         const int32_t j = col[p];
@@ -60,6 +52,45 @@ __global__ __launch_bounds__(kBlock) void assemble_kernel(int32_t n, const int32
     }
 }
 
+__global__ __launch_bounds__(kBlock) void assemble_kernel(int32_t n, const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ col,
+                                                         const double* __restrict__ val,
+                                                         const double* __restrict__ diag,
+                                                         const double* __restrict__ scale, PolyCoeffs pc,
+                                                         const float* __restrict__ coeffs_dev,
+                                                         double* __restrict__ q64, float* __restrict__ q32,
+                                                         double* __restrict__ qd64, float* __restrict__ qd32) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int deg = pc.degree;
+    double c[2 * 4 + 1];
+    for (int k = 0; k < 2 * deg + 1; ++k) c[k] = coeffs_dev ? static_cast<double>(coeffs_dev[k]) : pc.c[k];
+    assemble_row(i, ptr, col, val, diag, c, deg, scale[0], q64, q32, qd64, qd32);
+}
+
+__global__ __launch_bounds__(kBlock) void assemble_blocks_kernel(
+    int32_t n, const int32_t* __restrict__ ptr, const int32_t* __restrict__ col, const double* __restrict__ val,
+    const double* __restrict__ diag, int32_t nblk, const int32_t* __restrict__ off, const double* __restrict__ scale,
+    const int32_t* __restrict__ crow, PolyCoeffs pc, const float* __restrict__ coeffs_dev, int32_t stride,
+    double* __restrict__ q64, float* __restrict__ q32, double* __restrict__ qd64, float* __restrict__ qd32) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int32_t lo = 0, hi = nblk - 1;  // block of row i
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) / 2;
+        if (off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int deg = pc.degree;
+    const int32_t r = crow[lo];
+    double c[2 * 4 + 1];
+    for (int k = 0; k < 2 * deg + 1; ++k)
+        c[k] = r < 0 ? 0.0 : coeffs_dev ? static_cast<double>(coeffs_dev[static_cast<int64_t>(r) * stride + k]) : pc.c[k];
+    assemble_row(i, ptr, col, val, diag, c, deg, scale[lo], q64, q32, qd64, qd32);
+}
+
 }  // namespace
 
 hipError_t assemble_smoother(int32_t n, const int32_t* ptr, const int32_t* col, const double* val,
@@ -71,6 +102,19 @@ hipError_t assemble_smoother(int32_t n, const int32_t* ptr, const int32_t* col, 
     const dim3 grid(static_cast<unsigned>((n + kBlock - 1) / kBlock));
     assemble_kernel<<<grid, kBlock, 0, stream>>>(n, ptr, col, val, diag, scale, pc, coeffs_dev, q64, q32, qd64,
                                                   qd32);
+    return hipGetLastError();
+}
+
+hipError_t assemble_smoother_blocks(int32_t n, const int32_t* ptr, const int32_t* col, const double* val,
+                                    const double* diag, int32_t nblk, const int32_t* off, const double* scale,
+                                    const int32_t* crow, const PolyCoeffs& pc, const float* coeffs_dev,
+                                    int32_t stride, double* q64, float* q32, double* qd64, float* qd32,
+                                    hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    if (pc.degree < 1 || pc.degree > 4 || nblk < 1) return hipErrorInvalidValue;
+    const dim3 grid(static_cast<unsigned>((n + kBlock - 1) / kBlock));
+    assemble_blocks_kernel<<<grid, kBlock, 0, stream>>>(n, ptr, col, val, diag, nblk, off, scale, crow, pc, coeffs_dev,
+                                                         stride, q64, q32, qd64, qd32);
     return hipGetLastError();
 }
 

@@ -186,7 +186,8 @@ hipError_t extract_diag(int32_t n, const int32_t* ptr, const int32_t* col, const
 // scale[0] = max |a_ij| over off-diagonal entries, or 1 when there are none
 hipError_t offdiag_absmax(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, double* partial,
                           double* scale, hipStream_t stream);
-// R = P^T: counts (r_ptr must be zeroed, size n_c + 1), scan, scatter, per-row sort
+// R = P^T (rows in ascending fine index): counts, scan, scatter, per-row sort; r_ptr has
+// n_c + 1 entries, cursor n_c + 1 entries of scratch
 hipError_t transpose_csr(int32_t nf, int32_t nc, int32_t nnz, const int32_t* p_ptr, const int32_t* p_col,
                          const double* p_val, int32_t* r_ptr, int32_t* r_col, double* r_val, int32_t* cursor,
                          hipStream_t stream);
@@ -200,12 +201,28 @@ hipError_t assemble_smoother(int32_t n, const int32_t* ptr, const int32_t* col, 
                              const double* diag, const double* scale, const PolyCoeffs& pc,
                              const float* coeffs_dev, double* q64, float* q32, double* qd64, float* qd32,
                              hipStream_t stream);
+// The same values on a block-diagonal level: block b (rows off[b]..off[b+1]) uses scale[b]
+// and the coefficients coeffs_dev + crow[b] * stride (or pc when coeffs_dev is null);
+// crow[b] < 0 gives Q = 0 on that block.
+hipError_t assemble_smoother_blocks(int32_t n, const int32_t* ptr, const int32_t* col, const double* val,
+                                    const double* diag, int32_t nblk, const int32_t* off, const double* scale,
+                                    const int32_t* crow, const PolyCoeffs& pc, const float* coeffs_dev,
+                                    int32_t stride, double* q64, float* q32, double* qd64, float* qd32,
+                                    hipStream_t stream);
 
-// Dense coarse solve
+// Dense coarse solve (rows [0, n) of ptr; columns shifted by -col0 for a diagonal block)
 hipError_t dense_from_csr(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, double* M,
-                          int singular, hipStream_t stream);
+                          int singular, hipStream_t stream, int32_t col0 = 0);
 hipError_t dense_lu_inverse(int32_t n, double* M, int32_t* piv, double* inv, int32_t* bad, hipStream_t stream);
 template <typename T>
 hipError_t dense_gemv(int32_t n, const double* inv, const T* x, T* y, hipStream_t stream);
+// Block-diagonal levels: off[nblk+1] row offsets; inverse of block b at inv + doff[b].
+hipError_t block_absmax(int32_t nblk, const int32_t* off, const int32_t* ptr, const int32_t* col, const double* val,
+                        double* scale, hipStream_t stream);
+hipError_t prolong_blocks_check(int32_t n, const int32_t* ptr, const int32_t* col, int32_t nblk, const int32_t* foff,
+                                const int32_t* coff, int32_t* bad, hipStream_t stream);
+template <typename T>
+hipError_t block_dense_gemv(int32_t n, int32_t nblk, const int32_t* off, const int64_t* doff, const double* inv,
+                            const T* x, T* y, hipStream_t stream);
 
 }  // namespace amgg

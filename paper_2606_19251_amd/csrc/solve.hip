@@ -151,6 +151,8 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
     return guarded([&]() -> int {
         int rc = check_ready(c, "amgg_solve");
         if (rc) return rc;
+        if (c->nblk > 0)
+            return fail(AMGG_ESTATE, "amgg_solve: not available on a block-diagonal (batched) hierarchy");
         if (!o || !b || !x) return fail(AMGG_EINVAL, "amgg_solve: null argument");
         if (o->outer < AMGG_OUTER_STATIONARY || o->outer > AMGG_OUTER_FCG)
             return fail(AMGG_EINVAL, "amgg_solve: unknown outer method");

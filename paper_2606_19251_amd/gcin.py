@@ -151,11 +151,15 @@ class Trainer:
     hand-written adjoint, GCIN backward, gradient clipping and Adam."""
 
     def __init__(self, solvers, rhs, predictor: Predictor, lr=1e-3, clip=1.0, nu=(1, 1), nvc=1,
-                 cycle_precision=32):
+                 cycle_precision=32, streams=1, batched=True):
+        """batched: cycle every problem in one block-diagonal context (one launch per level
+        operation for the whole mini-batch); otherwise problem by problem, spread over
+        `streams` streams."""
         import torch
 
         self.torch = torch
         self.solvers = solvers
+        self.batched = batched
         self.rhs = rhs
         self.pred = predictor
         self.lr, self.clip, self.nu, self.nvc = lr, clip, nu, nvc
@@ -177,18 +181,57 @@ class Trainer:
         self.dc64 = torch.zeros(self.batch.ngraphs, 2 * d + 1, dtype=torch.float64, device=dev)
         self.dc32 = torch.zeros(self.batch.ngraphs, 2 * d + 1, dtype=torch.float32, device=dev)
         self.step_count = 0
+        # the problems' cycles and adjoints are independent: with streams > 1 they are spread
+        # over that many streams (default priority) between two event joins
+        self.side = [torch.cuda.Stream(device=dev) for _ in range(streams)] if streams > 1 and not batched else []
+        self.bsolver = None
+        if batched:
+            from .solver import BatchSolver
+
+            self.bsolver = BatchSolver([ds.hier for ds in solvers], dev.index or 0)
+            assert self.bsolver.ngraphs == self.batch.ngraphs
+        # fork / join events live as long as the trainer: an event must outlive the waits
+        # queued on it
+        self.fork = torch.cuda.Event()
+        self.joins = [torch.cuda.Event() for _ in self.side]
+
+    @property
+    def rhs(self):
+        return self._rhs
+
+    @rhs.setter
+    def rhs(self, value):
+        self._rhs = list(value)
+        self.f_cat = self.torch.cat(self._rhs) if self.batched else None
 
     def loss_and_grad(self):
         """Batch-mean loss (device tensor of per-problem losses) and d loss / d coefficients."""
+        torch = self.torch
         d = self.pred.degree
         coeffs = self.batch.forward(self.pred.params, d, self.pred.precision)
         stream = self.batch.stream
+        if self.bsolver is not None:
+            self.bsolver.set_coeffs_device(coeffs, d, stream)
+            self.bsolver.loss_adjoint(self.f_cat, self.losses, self.dc64, self.nu, self.cycle_precision, self.nvc,
+                                      stream)
+            capi.amgg_cast_scale_f64_f32(self.dc64.data_ptr(), self.dc32.data_ptr(), self.dc64.numel(),
+                                         1.0 / len(self.solvers), stream)
+            return coeffs
+        if self.side:
+            main = torch.cuda.current_stream(self.pred.device)  # the stream `stream` names
+            self.fork.record(main)
+            for s in self.side:
+                s.wait_event(self.fork)
         for p, ds in enumerate(self.solvers):
             a, b = self.slices[p]
-            ds.set_coeffs_device(coeffs[a:b], d)
+            st = self.side[p % len(self.side)].cuda_stream if self.side else stream
+            ds.set_coeffs_device(coeffs[a:b], d, stream=st)
             capi.amgg_vcycle_loss_adjoint(ds.ctx, self.nu[0], self.nu[1], self.cycle_precision, self.nvc,
                                           self.rhs[p].data_ptr(), 0, self.losses[p:p + 1].data_ptr(),
-                                          self.dc64[a:b].data_ptr(), stream)
+                                          self.dc64[a:b].data_ptr(), st)
+        for s, join in zip(self.side, self.joins):
+            join.record(s)
+            main.wait_event(join)
         capi.amgg_cast_scale_f64_f32(self.dc64.data_ptr(), self.dc32.data_ptr(), self.dc64.numel(),
                                      1.0 / len(self.solvers), stream)
         return coeffs

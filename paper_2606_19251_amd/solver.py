@@ -38,17 +38,19 @@ class HostHierarchy:
 
     @classmethod
     def build(cls, rowptr, col, val, theta=0.25, max_levels=10, max_coarse=500, galerkin="host", device=0,
-              chunk_products=0):
+              chunk_products=0, timings=None):
         """RS hierarchy of a host CSR matrix. galerkin="host" forms every coarse matrix in the
         host setup; galerkin="device" forms them with amgg_galerkin_device on GPU `device`
         (strength, C/F split and interpolation stay on the host; the results are bitwise
-        the same)."""
+        the same). With galerkin="device", `timings` (a dict) receives the seconds spent in
+        the host coarsening, the device products and the transfers between them."""
         rowptr = np.ascontiguousarray(rowptr, np.int32)
         n = rowptr.size - 1
         if galerkin == "host":
             h = capi.amgg_rs_setup(rowptr, col, val, n, theta, max_levels, max_coarse)
         elif galerkin == "device":
-            h = _rs_with_device_galerkin(rowptr, col, val, n, theta, max_levels, max_coarse, device, chunk_products)
+            h = _rs_with_device_galerkin(rowptr, col, val, n, theta, max_levels, max_coarse, device, chunk_products,
+                                         timings if timings is not None else {})
         else:
             raise ValueError(f"galerkin must be 'host' or 'device', not {galerkin!r}")
         try:
@@ -79,23 +81,41 @@ class HostHierarchy:
         return len(self.levels)
 
 
-def _rs_with_device_galerkin(rowptr, col, val, n, theta, max_levels, max_coarse, device, chunk_products):
+def _rs_with_device_galerkin(rowptr, col, val, n, theta, max_levels, max_coarse, device, chunk_products, timings):
     """Stepwise RS setup whose Galerkin products run on the GPU; returns the host handle."""
+    import time
+
     import torch
 
     dev = torch.device("cuda", device)
+    clock = time.perf_counter
+    for k in ("coarsen_s", "galerkin_s", "transfer_s"):
+        timings.setdefault(k, 0.0)
     h = capi.amgg_rs_begin(rowptr, col, val, n, theta, max_levels, max_coarse)
     try:
+        t0 = clock()
         A = (torch.from_numpy(rowptr).to(dev), torch.from_numpy(np.ascontiguousarray(col, np.int32)).to(dev),
              torch.from_numpy(np.ascontiguousarray(val, np.float64)).to(dev))
+        timings["transfer_s"] += clock() - t0
         lvl = 0
-        while capi.amgg_rs_coarsen(h):
+        while True:
+            t0 = clock()
+            more = capi.amgg_rs_coarsen(h)
+            timings["coarsen_s"] += clock() - t0
+            if not more:
+                break
+            t0 = clock()
             n_l, _, nc, pnnz = capi.amgg_rs_level_size(h, lvl)
             prp, pcl, pvl = np.empty(n_l + 1, np.int32), np.empty(pnnz, np.int32), np.empty(pnnz, np.float64)
             capi.amgg_rs_copy_level(h, lvl, None, None, None, prp, pcl, pvl, None)
             P = tuple(torch.from_numpy(a).to(dev) for a in (prp, pcl, pvl))
+            torch.cuda.synchronize(dev)
+            t1 = clock()
             A = capi.amgg_galerkin_device(device, n_l, nc, *A, *P, chunk_products=chunk_products)
+            t2 = clock()
             capi.amgg_rs_push_level(h, nc, *(a.cpu().numpy() for a in A))
+            timings["galerkin_s"] += t2 - t1
+            timings["transfer_s"] += (t1 - t0) + (clock() - t2)
             lvl += 1
         return h
     except BaseException:
@@ -110,7 +130,9 @@ def _stream_ptr(torch, device):
 class DeviceSolver:
     """A finalized solver context on one GPU; owns the device copies and the workspace."""
 
-    def __init__(self, hier: HostHierarchy, device: int = 0):
+    def __init__(self, hier: HostHierarchy, device: int = 0, blocks=None):
+        """blocks: for a block-diagonal hierarchy, (row offsets per level, coefficient rows per
+        level, singular flag per block) as made by block_diagonal()."""
         import torch
 
         self.torch = torch
@@ -134,6 +156,11 @@ class DeviceSolver:
                     self._keep += [pr, pc, pv]
                     capi.amgg_load_prolong(self.ctx, l, L.n, L.p_ncols, int(L.p_col.size), pr.data_ptr(),
                                            pc.data_ptr() if L.p_col.size else 0, pv.data_ptr() if L.p_col.size else 0)
+            if blocks is not None:
+                offsets, rows, sing = blocks
+                for l in range(self.nlevels):
+                    capi.amgg_set_level_blocks(self.ctx, l, offsets[l], rows[l],
+                                               sing if l == self.nlevels - 1 else None)
             self.ws_bytes = capi.amgg_workspace_bytes(self.ctx)
             raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
             off = (-raw.data_ptr()) % 256
@@ -171,12 +198,14 @@ class DeviceSolver:
         for l in (range(self.nlevels) if levels is None else levels):
             capi.amgg_set_smoother_coeffs(self.ctx, l, degree, coeffs[l], self.stream)
 
-    def set_coeffs_device(self, coeffs_dev, degree):
-        """coeffs_dev: float32 CUDA tensor [nlevels, 2*degree+1]."""
+    def set_coeffs_device(self, coeffs_dev, degree, stream=None):
+        """coeffs_dev: float32 CUDA tensor [nlevels, 2*degree+1]; queued on `stream` (a raw
+        hipStream_t, default: the solver's stream)."""
         assert coeffs_dev.dtype == self.torch.float32 and coeffs_dev.is_contiguous()
         stride = coeffs_dev.shape[1] * 4
+        st = self.stream if stream is None else stream
         for l in range(self.nlevels):
-            capi.amgg_set_smoother_coeffs_device(self.ctx, l, degree, coeffs_dev.data_ptr() + l * stride, self.stream)
+            capi.amgg_set_smoother_coeffs_device(self.ctx, l, degree, coeffs_dev.data_ptr() + l * stride, st)
 
     def set_jacobi(self, omega=2.0 / 3.0):
         for l in range(self.nlevels):
@@ -223,3 +252,89 @@ class DeviceSolver:
             "coarse_inv": s(v.coarse_inv, v.n * v.n, torch.float64),
             "fused_rows": int(v.fused_rows),
         }
+
+
+# ------------------------------------------------------------------------------------------
+# Block-diagonal (batched) hierarchies
+# ------------------------------------------------------------------------------------------
+def block_diagonal(hiers):
+    """One block-diagonal hierarchy holding several problems' hierarchies.
+
+    Super level l holds, for each problem p (block p), its level min(l, L_p - 1): a problem
+    with fewer levels repeats its coarsest matrix, with the identity as P and no smoother
+    there, so that a V-cycle passes its residual down unchanged to the coarsest super level,
+    whose block solve is the problem's own coarsest solve. Returns (HostHierarchy, offsets,
+    coeff_rows, singular): per level the blocks' row offsets and coefficient rows, where the
+    coefficient row of (p, l) is p's level-l graph in the order of all problems' levels
+    (problem-major), or -1 for repeated and coarsest levels."""
+    depth = max(h.nlevels for h in hiers)
+    first = np.cumsum([0] + [h.nlevels for h in hiers])[:-1]
+    levels, offsets, rows = [], [], []
+    for l in range(depth):
+        mats = [h.levels[min(l, h.nlevels - 1)] for h in hiers]
+        off = np.cumsum([0] + [m.n for m in mats]).astype(np.int32)
+        nnz = np.cumsum([0] + [m.nnz for m in mats])
+        rowptr = np.concatenate([m.rowptr[:-1].astype(np.int64) + nnz[b] for b, m in enumerate(mats)] + [[nnz[-1]]])
+        col = np.concatenate([m.col.astype(np.int64) + off[b] for b, m in enumerate(mats)])
+        val = np.concatenate([m.val for m in mats])
+        L = HostLevel(int(off[-1]), rowptr.astype(np.int32), col.astype(np.int32), val.astype(np.float64))
+        if l + 1 < depth:
+            cmats = [h.levels[min(l + 1, h.nlevels - 1)] for h in hiers]
+            coff = np.cumsum([0] + [m.n for m in cmats])
+            prp, pcl, pvl = [], [], []
+            pnnz = 0
+            for b, h in enumerate(hiers):
+                if l + 1 < h.nlevels:
+                    F = h.levels[l]
+                    r, c, v = F.p_rowptr.astype(np.int64), F.p_col.astype(np.int64), F.p_val
+                else:  # identity on the repeated coarsest level
+                    k = mats[b].n
+                    r, c, v = np.arange(k + 1, dtype=np.int64), np.arange(k, dtype=np.int64), np.ones(k)
+                prp.append(r[:-1] + pnnz)
+                pcl.append(c + coff[b])
+                pvl.append(v)
+                pnnz += int(r[-1])
+            L.p_ncols = int(coff[-1])
+            L.p_rowptr = np.concatenate(prp + [[pnnz]]).astype(np.int32)
+            L.p_col = np.concatenate(pcl).astype(np.int32)
+            L.p_val = np.concatenate(pvl).astype(np.float64)
+        levels.append(L)
+        offsets.append(off)
+        rows.append(np.array([first[b] + l if l + 1 < h.nlevels else -1 for b, h in enumerate(hiers)], np.int32))
+    sing = np.array([int(h.singular) for h in hiers], np.int32)
+    return HostHierarchy(levels, False), offsets, rows, sing
+
+
+class BatchSolver:
+    """Several problems' hierarchies in one block-diagonal context on one GPU: one launch per
+    level operation serves every problem of the batch."""
+
+    def __init__(self, hiers, device: int = 0):
+        self.hiers = list(hiers)
+        bh, self.offsets, self.rows, self.sing = block_diagonal(self.hiers)
+        self.ds = DeviceSolver(bh, device, blocks=(self.offsets, self.rows, self.sing))
+        self.nblk = len(self.hiers)
+        self.ngraphs = int(sum(h.nlevels for h in self.hiers))
+        self.depth = bh.nlevels
+
+    @property
+    def ctx(self):
+        return self.ds.ctx
+
+    def set_coeffs_device(self, coeffs_dev, degree, stream=None):
+        """coeffs_dev: float32 CUDA tensor [ngraphs, 2*degree+1], one row per level graph of
+        every problem (problem-major), as the batched GCIN forward returns them."""
+        assert coeffs_dev.dtype == self.ds.torch.float32 and coeffs_dev.is_contiguous()
+        assert coeffs_dev.shape[0] == self.ngraphs
+        st = self.ds.stream if stream is None else stream
+        for l in range(self.depth - 1):
+            capi.amgg_set_smoother_coeffs_blocks(self.ctx, l, degree, coeffs_dev.data_ptr(), coeffs_dev.shape[1], st)
+
+    def loss_adjoint(self, f_cat, losses, dcoeffs, nu=(1, 1), precision=32, nvc=1, stream=None):
+        """Per-problem losses [nblk] and coefficient gradients [ngraphs, 2*degree+1] (FP64)."""
+        st = self.ds.stream if stream is None else stream
+        capi.amgg_vcycle_loss_adjoint_blocks(self.ctx, nu[0], nu[1], precision, nvc, f_cat.data_ptr(), 0,
+                                             losses.data_ptr(), dcoeffs.data_ptr(), self.ngraphs, st)
+
+    def close(self):
+        self.ds.close()

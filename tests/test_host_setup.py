@@ -191,3 +191,35 @@ def test_stepwise_setup_rejects_calls_out_of_sequence():
         assert capi.amgg_rs_info(h)[0] == 2
     finally:
         capi.amgg_rs_free(h)
+
+
+def test_block_diagonal_hierarchy_layout():
+    """The batched hierarchy: super level l is the block diagonal of each problem's level
+    min(l, L_p - 1); repeated coarsest levels get an identity P and no coefficient row."""
+    import scipy.sparse as sp
+
+    from paper_2606_19251_amd.solver import HostHierarchy, block_diagonal
+
+    mats = [W.grid5(30), W.grid5(8), W.delaunay_p1(W.gmm_points(3000, 1))]
+    hs = [HostHierarchy.build(A.rowptr, A.col, A.val, max_coarse=100) for A in mats]
+    depths = [h.nlevels for h in hs]
+    assert depths[1] == 1 and max(depths) >= 3
+    bh, offsets, rows, sing = block_diagonal(hs)
+    assert bh.nlevels == max(depths) and list(sing) == [int(h.singular) for h in hs]
+    csr = lambda L: sp.csr_matrix((L.val, L.col, L.rowptr), shape=(L.n, L.n))
+    first = np.cumsum([0] + depths)
+    for l, L in enumerate(bh.levels):
+        ref = sp.block_diag([csr(h.levels[min(l, h.nlevels - 1)]) for h in hs]).tocsr()
+        assert (csr(L) != ref).nnz == 0
+        assert list(offsets[l]) == list(np.cumsum([0] + [h.levels[min(l, h.nlevels - 1)].n for h in hs]))
+        assert list(rows[l]) == [first[p] + l if l + 1 < h.nlevels else -1 for p, h in enumerate(hs)]
+        if l + 1 < bh.nlevels:
+            P = sp.csr_matrix((L.p_val, L.p_col, L.p_rowptr), shape=(L.n, L.p_ncols))
+            parts = []
+            for h in hs:
+                if l + 1 < h.nlevels:
+                    F = h.levels[l]
+                    parts.append(sp.csr_matrix((F.p_val, F.p_col, F.p_rowptr), shape=(F.n, F.p_ncols)))
+                else:
+                    parts.append(sp.identity(h.levels[h.nlevels - 1].n, format="csr"))
+            assert (P != sp.block_diag(parts).tocsr()).nnz == 0
