@@ -29,13 +29,25 @@ __device__ __forceinline__ void block_partial(double v, double* partial) {
 }
 
 // Sum of `count` partials by one workgroup, in a fixed order.
+// Sum of count partials by one workgroup of kFinish threads: each thread keeps eight
+// independent accumulators (eight loads in flight) over a fixed strided subset, then a
+// fixed-order tree; the result does not depend on timing.
+constexpr int kFinish = 1024;
+
 __device__ __forceinline__ double sum_partials(const double* partial, int count = kReduceBlocks) {
-    __shared__ double red[kBlock];
-    double v = 0.0;
-    for (int k = threadIdx.x; k < count; k += kBlock) v += partial[k];
-    red[threadIdx.x] = v;
+    __shared__ double red[kFinish];
+    double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int k = threadIdx.x;
+    for (; k + 7 * kFinish < count; k += 8 * kFinish) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] += partial[k + q * kFinish];
+    }
+#pragma unroll
+    for (int q = 0; q < 7; ++q)
+        if (k + q * kFinish < count) v[q] += partial[k + q * kFinish];
+    red[threadIdx.x] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
+    for (int w = kFinish / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
@@ -101,13 +113,13 @@ __global__ __launch_bounds__(kBlock) void partial_sum_kernel(int32_t n, const do
     block_partial(v, partial);
 }
 
-__global__ __launch_bounds__(kBlock) void finish_sum_kernel(const double* __restrict__ partial,
+__global__ __launch_bounds__(kFinish) void finish_sum_kernel(const double* __restrict__ partial,
                                                            double* __restrict__ out) {
     const double s = sum_partials(partial);
     if (threadIdx.x == 0) out[0] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void fcg_finish_pq_kernel(const double* __restrict__ partial, int count,
+__global__ __launch_bounds__(kFinish) void fcg_finish_pq_kernel(const double* __restrict__ partial, int count,
                                                               double* __restrict__ s) {
     const double pq = sum_partials(partial, count);
     if (threadIdx.x == 0) {
@@ -136,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void fcg_update_xr_kernel(int32_t n, double
     block_partial(v, partial);
 }
 
-__global__ __launch_bounds__(kBlock) void fcg_finish_rr_kernel(const double* __restrict__ partial, int count,
+__global__ __launch_bounds__(kFinish) void fcg_finish_rr_kernel(const double* __restrict__ partial, int count,
                                                               double* __restrict__ s) {
     const double rr = sum_partials(partial, count);
     if (threadIdx.x == 0) {
@@ -180,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void fcg_dots64_kernel(int32_t n, const dou
     block_partial(b, partial2 + kReduceBlocks);
 }
 
-__global__ __launch_bounds__(kBlock) void fcg_finish_beta_kernel(const double* __restrict__ partial2,
+__global__ __launch_bounds__(kFinish) void fcg_finish_beta_kernel(const double* __restrict__ partial2,
                                                                 double* __restrict__ s, int first) {
     const double zr = sum_partials(partial2);
     __syncthreads();
@@ -230,7 +242,7 @@ __global__ void fcg_clear_halt_kernel(double* __restrict__ s) {
     }
 }
 
-__global__ __launch_bounds__(kBlock) void fcg_finish_rr_guarded_kernel(const double* __restrict__ partial, int count,
+__global__ __launch_bounds__(kFinish) void fcg_finish_rr_guarded_kernel(const double* __restrict__ partial, int count,
                                                                       double* __restrict__ s) {
     if (s[kHalt] != 0.0 || s[kFlag] != 0.0) return;
     const double rr = sum_partials(partial, count);
@@ -313,12 +325,12 @@ hipError_t partial_sum(int32_t n, const double* a, double* partial, hipStream_t 
 }
 
 hipError_t finish_sum(const double* partial, double* out, hipStream_t stream) {
-    finish_sum_kernel<<<1, kBlock, 0, stream>>>(partial, out);
+    finish_sum_kernel<<<1, kFinish, 0, stream>>>(partial, out);
     return hipGetLastError();
 }
 
 hipError_t fcg_finish_pq(const double* partial, int count, double* s, hipStream_t stream) {
-    fcg_finish_pq_kernel<<<1, kBlock, 0, stream>>>(partial, count, s);
+    fcg_finish_pq_kernel<<<1, kFinish, 0, stream>>>(partial, count, s);
     return hipGetLastError();
 }
 
@@ -329,7 +341,7 @@ hipError_t fcg_update_xr(int32_t n, double* x, const double* p, const double* r,
 }
 
 hipError_t fcg_finish_rr(const double* partial, int count, double* s, hipStream_t stream) {
-    fcg_finish_rr_kernel<<<1, kBlock, 0, stream>>>(partial, count, s);
+    fcg_finish_rr_kernel<<<1, kFinish, 0, stream>>>(partial, count, s);
     return hipGetLastError();
 }
 
@@ -346,7 +358,7 @@ hipError_t fcg_dots64(int32_t n, const double* z, const double* rnew, const doub
 }
 
 hipError_t fcg_finish_beta(const double* partial2, double* s, int first, hipStream_t stream) {
-    fcg_finish_beta_kernel<<<1, kBlock, 0, stream>>>(partial2, s, first);
+    fcg_finish_beta_kernel<<<1, kFinish, 0, stream>>>(partial2, s, first);
     return hipGetLastError();
 }
 
@@ -373,7 +385,7 @@ hipError_t fcg_clear_halt(double* s, hipStream_t stream) {
 }
 
 hipError_t fcg_finish_rr_guarded(const double* partial, int count, double* s, hipStream_t stream) {
-    fcg_finish_rr_guarded_kernel<<<1, kBlock, 0, stream>>>(partial, count, s);
+    fcg_finish_rr_guarded_kernel<<<1, kFinish, 0, stream>>>(partial, count, s);
     return hipGetLastError();
 }
 
