@@ -36,6 +36,7 @@ Csr strong_couplings(const Csr& A, double theta) {
     Csr S;
     S.nrows = S.ncols = A.nrows;
     S.ptr.assign(A.nrows + 1, 0);
+    S.idx.reserve(A.idx.size());
     for (int32_t i = 0; i < A.nrows; ++i) {
         double big = -INFINITY;
         bool any_off = false;
@@ -74,36 +75,44 @@ Csr pattern_transpose(const Csr& S) {
     return T;
 }
 
-// Max tournament tree over the undecided points: each node keeps the leftmost index of
-// the largest measure in its range, so the root answers "largest lambda, smallest index".
+// Max tournament tree over the undecided points. A node holds the packed maximum
+// (measure << 32 | ~index) of its range, so the root answers "largest lambda, smallest
+// index" without looking anything up, and an update stops climbing as soon as a node keeps
+// its value.
 class ArgmaxTree {
   public:
     explicit ArgmaxTree(const std::vector<int64_t>& key) {
         n_ = static_cast<int32_t>(key.size());
         size_ = 1;
         while (size_ < n_) size_ <<= 1;
-        key_.assign(size_, kDecided);
-        std::copy(key.begin(), key.end(), key_.begin());
-        node_.assign(2 * size_, -1);
-        for (int32_t i = 0; i < size_; ++i) node_[size_ + i] = i;
-        for (int32_t v = size_ - 1; v >= 1; --v) node_[v] = better(node_[2 * v], node_[2 * v + 1]);
+        node_.assign(2 * static_cast<size_t>(size_), kEmpty);
+        for (int32_t i = 0; i < n_; ++i) node_[size_ + i] = pack(key[i], i);
+        for (int32_t v = size_ - 1; v >= 1; --v) node_[v] = std::max(node_[2 * v], node_[2 * v + 1]);
     }
     static constexpr int64_t kDecided = INT64_MIN;
-    int32_t top() const { return key_[node_[1]] == kDecided ? -1 : node_[1]; }
-    int64_t key(int32_t i) const { return key_[i]; }
+    int32_t top() const {
+        const int64_t t = node_[1];
+        return t == kEmpty ? -1 : static_cast<int32_t>(~static_cast<uint32_t>(t & 0xFFFFFFFFu));
+    }
     void set(int32_t i, int64_t k) {
-        key_[i] = k;
-        for (int32_t v = (size_ + i) >> 1; v >= 1; v >>= 1) node_[v] = better(node_[2 * v], node_[2 * v + 1]);
+        size_t v = static_cast<size_t>(size_) + i;
+        node_[v] = pack(k, i);
+        for (v >>= 1; v >= 1; v >>= 1) {
+            const int64_t m = std::max(node_[2 * v], node_[2 * v + 1]);
+            if (node_[v] == m) break;
+            node_[v] = m;
+        }
     }
 
   private:
-    int32_t better(int32_t a, int32_t b) const {
-        // a < b always holds for the two children of a node: prefer a on ties
-        return key_[b] > key_[a] ? b : a;
+    // measures are counts (|lambda| < 2^31); a decided point is below every measure
+    static constexpr int64_t kEmpty = INT64_MIN;
+    static int64_t pack(int64_t k, int32_t i) {
+        if (k == kDecided) return kEmpty;
+        return static_cast<int64_t>(static_cast<uint64_t>(k) << 32) | static_cast<int64_t>(~static_cast<uint32_t>(i));
     }
     int32_t n_ = 0, size_ = 1;
-    std::vector<int64_t> key_;
-    std::vector<int32_t> node_;
+    std::vector<int64_t> node_;
 };
 
 // Ruge-Stueben first pass. Returns cf[i] = 1 for C points, 0 for F points.
@@ -161,6 +170,8 @@ Csr direct_interp(const Csr& A, const Csr& S, const std::vector<int8_t>& cf) {
     P.nrows = n;
     P.ncols = nc;
     P.ptr.assign(n + 1, 0);
+    P.idx.reserve(S.idx.size() + n);
+    P.val.reserve(S.idx.size() + n);
     std::vector<char> in_ci(n, 0);
     for (int32_t i = 0; i < n; ++i) {
         if (cf[i]) {
