@@ -154,6 +154,8 @@ WORKLOADS = {
     "tet8m": ("gcin_tet_deg2.npz", "FV Poisson on the Kuhn tetrahedra of a jittered 111^3 lattice "
                                    "(7,986,000 cells), all-Neumann"),
     "cmesh4m": ("gcin_cmesh_deg2.npz", "FV Poisson on a 4096 x 1024 C-mesh around NACA 2412, wall aspect 1e4"),
+    "grid1m": ("gcin_grid_h32_deg2.npz", "5-point Laplacian on a 1024 x 1024 structured grid, Dirichlet "
+                                         "(32-channel GCIN)"),
 }
 
 
@@ -164,6 +166,9 @@ def make_workload(name):
         return W.delaunay_p1_problem(1_000_000, 0)
     if name == "tet8m":
         return W.tet_kuhn_problem(111, 0)
+    if name == "grid1m":
+        A = W.grid5(1024)
+        return A, W.rhs_uniform(A.nrows, 0)
     return W.airfoil_cmesh_problem(4096, 1024, 0)
 
 
@@ -341,6 +346,40 @@ def training_step(torch, steps=10, warmup=3):
     return out
 
 
+def structured_case(torch, nu=1):
+    """The structured case: a 1024 x 1024 5-point Laplacian, omega-Jacobi against the 32-channel
+    GCIN trained on structured grids (FCG(FP64) + FP32 V-cycles to 1e-8), and the GCIN setup
+    time (inference + smoother assembly) of the 32- and 64-channel networks on its hierarchy."""
+    from paper_2606_19251_amd import capi
+    from paper_2606_19251_amd import gcin as G
+
+    case = Case(torch, "grid1m")
+    fcg = capi.AMGG_OUTER_FCG
+    res = {"workload": WORKLOADS["grid1m"][1], "levels": [L.n for L in case.hh.levels],
+           "jacobi": case.solves("jacobi", fcg, 5, 1, nu), "gnn_hidden32": case.solves("gnn", fcg, 5, 1, nu)}
+    setup = {}
+    for name, fn in (("hidden32", "gcin_grid_h32_deg2.npz"), ("hidden64", "gcin_grid_deg2.npz")):
+        pred = G.Predictor.load(os.path.join(ROOT, "paper_2606_19251_amd", "weights", fn), case.dev)
+        for _ in range(2):
+            pred.predict(case.hh, case.ds)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(5):
+            c = pred.predict(case.hh, case.ds)
+            case.ds.set_coeffs_device(c, pred.degree)
+        e.record()
+        torch.cuda.synchronize()
+        setup[name] = round(s.elapsed_time(e) / 5, 3)
+        if name == "hidden64":  # the same solves with the 64-channel network's coefficients
+            case.coeffs, case.pred = c, pred
+            res["gnn_hidden64"] = case.solves("gnn", fcg, 5, 1, nu)
+    res["gcin_setup_ms"] = setup
+    log(f"structured: GCIN setup {setup}")
+    case.ds.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -349,6 +388,8 @@ def main():
     ap.add_argument("--workload", choices=list(WORKLOADS), default="delaunay1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-training", action="store_true", help="skip the training-step timing")
+    ap.add_argument("--no-structured", action="store_true",
+                    help="skip the structured-grid comparison (32-channel GCIN) that follows the default workload")
     ap.add_argument("--no-second-roofline", action="store_true",
                     help="skip the tet8m fine-level kernel timing that follows the default workload")
     ap.add_argument("--profile-kernels", action="store_true",
@@ -437,6 +478,8 @@ def main():
     ds.close()
     if args.workload == "delaunay1m" and not args.no_training:
         out["training"] = training_step(torch)
+    if args.workload == "delaunay1m" and not args.no_structured:
+        out["structured"] = structured_case(torch, args.nu)
     if args.workload == "delaunay1m" and not args.no_second_roofline:
         del case
         second = Case(torch, "tet8m")

@@ -29,6 +29,13 @@
  * for training, where ReLU masks and arg-max pooling make gradients sensitive to activation
  * rounding. Activations, normalisation, pooling and the head stay FP32 in every mode.
  *
+ * Hidden width: the functions without a width argument build the 64-channel network above.
+ * The *_hidden variants also build the 32-channel variant that the paper proposes for
+ * structured meshes, where the smaller network costs less setup time (Sec. 5): every 64
+ * above that counts GCIN channels becomes 32 (conv_l.W [in_l x 32], readout_l.W [64 x 32]);
+ * the readout width, the head and the coefficient count are unchanged. Its tile products
+ * run in FP32 whatever the precision argument (the MFMA tiling is written for 64 channels).
+ *
  * Memory and streams as in amggnn.h: device pointers are caller-owned, the batch
  * lives in one caller-allocated workspace, every call is ordered on `stream`; 0 =
  * success, negative = error with the message in amgg_last_error(). Reductions use a
@@ -51,6 +58,8 @@ extern "C" {
 
 /* Trainable parameter count for polynomial degree d (1..4): 55,045 for d = 2. */
 int64_t gcin_param_count(int degree);
+/* The same for hidden width 64 or 32 (-1 for another width or degree). */
+int64_t gcin_param_count_hidden(int degree, int hidden);
 
 /* One graph of the batch: a level matrix in device CSR (diagonal stored). */
 typedef struct {
@@ -70,6 +79,11 @@ int gcin_batch_workspace_bytes(int ngraphs, const int32_t* n, const int32_t* nnz
  * The views are read during this call only. */
 int gcin_batch_create(int ngraphs, const gcin_graph* graphs, void* workspace, size_t ws_bytes, void* stream,
                       gcin_batch** out);
+/* The same for hidden width 64 or 32 (AMGG_EINVAL otherwise); forward and backward then use
+ * the parameter layout of gcin_param_count_hidden(d, hidden). */
+int gcin_batch_workspace_bytes_hidden(int hidden, int ngraphs, const int32_t* n, const int32_t* nnz, size_t* bytes);
+int gcin_batch_create_hidden(int hidden, int ngraphs, const gcin_graph* graphs, void* workspace, size_t ws_bytes,
+                             void* stream, gcin_batch** out);
 int gcin_batch_destroy(gcin_batch* b);
 
 /* Forward pass (Alg. 1, step 6): coeffs_out is device FP32 [ngraphs][2d+1], raw

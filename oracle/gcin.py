@@ -50,15 +50,15 @@ def param_shapes(degree: int = 2, in_dim: int = 2, hidden: int = HIDDEN, layers:
     return shapes
 
 
-def param_count(degree: int = 2) -> int:
-    return int(sum(np.prod(s) for _, s in param_shapes(degree)))
+def param_count(degree: int = 2, hidden: int = HIDDEN) -> int:
+    return int(sum(np.prod(s) for _, s in param_shapes(degree, hidden=hidden)))
 
 
-def init_params(degree: int = 2, seed: int = 0) -> dict:
+def init_params(degree: int = 2, seed: int = 0, hidden: int = HIDDEN) -> dict:
     """Uniform(+-1/sqrt(fan_in)) weights, zero biases, unit/zero norm affines (FP64 numpy)."""
     rng = np.random.default_rng(seed)
     p = {}
-    for name, shape in param_shapes(degree):
+    for name, shape in param_shapes(degree, hidden=hidden):
         if name.endswith(".W"):
             bound = 1.0 / np.sqrt(shape[0])
             p[name] = rng.uniform(-bound, bound, size=shape)

@@ -100,8 +100,11 @@ SIGNATURES = {
     "amgg_vcycle_loss_adjoint_blocks": (_I, [_VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _I32, _VP]),
     "amgg_cast_scale_f64_f32": (_I, [_VP, _VP, C.c_int64, C.c_double, _VP]),
     "gcin_param_count": (C.c_int64, [_I]),
+    "gcin_param_count_hidden": (C.c_int64, [_I, _I]),
     "gcin_batch_workspace_bytes": (_I, [_I, _VP, _VP, C.POINTER(C.c_size_t)]),
+    "gcin_batch_workspace_bytes_hidden": (_I, [_I, _I, _VP, _VP, C.POINTER(C.c_size_t)]),
     "gcin_batch_create": (_I, [_I, C.POINTER(gcin_graph), _VP, C.c_size_t, _VP, C.POINTER(_VP)]),
+    "gcin_batch_create_hidden": (_I, [_I, _I, C.POINTER(gcin_graph), _VP, C.c_size_t, _VP, C.POINTER(_VP)]),
     "gcin_batch_destroy": (_I, [_VP]),
     "gcin_forward": (_I, [_VP, _I, _I, _VP, _VP, _VP]),
     "gcin_backward": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP]),
@@ -365,26 +368,28 @@ def amgg_cast_scale_f64_f32(src, dst, n, scale, stream):
 
 
 # ---------------------------------------------------------------------------- GCIN predictor
-def gcin_param_count(degree: int) -> int:
-    v = lib().gcin_param_count(degree)
+def gcin_param_count(degree: int, hidden: int = 64) -> int:
+    v = lib().gcin_param_count_hidden(degree, hidden)
     if v < 0:
-        raise AmggError(AMGG_EINVAL, "gcin_param_count: degree out of range")
+        raise AmggError(AMGG_EINVAL, "gcin_param_count: degree or hidden width out of range")
     return v
 
 
-def gcin_batch_workspace_bytes(n, nnz) -> int:
+def gcin_batch_workspace_bytes(n, nnz, hidden: int = 64) -> int:
     n = np.ascontiguousarray(n, np.int32)
     nnz = np.ascontiguousarray(nnz, np.int32)
     b = C.c_size_t()
-    _check(lib().gcin_batch_workspace_bytes(n.size, _np_ptr(n), _np_ptr(nnz), C.byref(b)), "gcin_batch_workspace_bytes")
+    _check(lib().gcin_batch_workspace_bytes_hidden(hidden, n.size, _np_ptr(n), _np_ptr(nnz), C.byref(b)),
+           "gcin_batch_workspace_bytes")
     return b.value
 
 
-def gcin_batch_create(graphs, workspace, ws_bytes, stream) -> int:
+def gcin_batch_create(graphs, workspace, ws_bytes, stream, hidden: int = 64) -> int:
     """graphs: list of (n, nnz, rowptr_ptr, col_ptr, val_ptr) device CSR views."""
     arr = (gcin_graph * len(graphs))(*[gcin_graph(*g) for g in graphs])
     h = _VP()
-    _check(lib().gcin_batch_create(len(graphs), arr, workspace, ws_bytes, stream, C.byref(h)), "gcin_batch_create")
+    _check(lib().gcin_batch_create_hidden(hidden, len(graphs), arr, workspace, ws_bytes, stream, C.byref(h)),
+           "gcin_batch_create")
     return h.value
 
 

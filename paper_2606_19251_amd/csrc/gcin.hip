@@ -26,13 +26,14 @@
 
 namespace {
 
-constexpr int HD = 64;     // hidden width
+// The hidden width HD (64, or 32 for the smaller variant) is a template parameter of every
+// kernel below; a workgroup has 4 HD threads (4 groups of HD lanes, lane = channel).
 constexpr int NL = 4;      // GCIN layers
 constexpr int RO = 32;     // readout width per layer
 constexpr int JK = RO * NL;
 constexpr int M1 = 128, M2 = 64;
 constexpr int TILE = 64;
-constexpr int NT = 256;       // threads per workgroup
+constexpr int kAdamThreads = 256;
 constexpr int kWBlocks = 512; // fixed grid of the weight-gradient reductions
 constexpr int kMaxOut = 9;    // 2 d + 1 for d <= 4
 constexpr float kEps = 1e-5f;
@@ -50,7 +51,7 @@ struct Offs {
     int nout;
 };
 
-Offs offsets(int d) {
+Offs offsets(int d, int HD) {
     Offs o{};
     int64_t k = 0;
     for (int l = 0; l < NL; ++l) {
@@ -132,6 +133,7 @@ __device__ __forceinline__ void visit_rows(const int32_t* __restrict__ ptr, cons
 }
 
 // Sum over the 4 wavefronts of a workgroup, per channel (lane), into out[c] (thread wave 0).
+template <int HD>
 __device__ __forceinline__ double wave4_sum(double v, double (*sh)[HD]) {
     const int wv = threadIdx.x / HD, c = threadIdx.x % HD;
     sh[wv][c] = v;
@@ -181,7 +183,8 @@ __global__ void pad_rows_kernel(int32_t from, int32_t to, int32_t eptr, int32_t*
 // ------------------------------------------------------------------------------------------
 // forward
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void layer0_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+template <int HD>
+__global__ __launch_bounds__(4 * HD) void layer0_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                                     const float* __restrict__ w, const float* __restrict__ x0,
                                                     const int32_t* __restrict__ tile_graph,
                                                     const int32_t* __restrict__ gend, const float* __restrict__ W0,
@@ -242,10 +245,11 @@ __device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned
 // a_lo b_lo term is below FP32 resolution): an FP32-accurate product on the BF16 MFMA
 // units, used where the result feeds non-smooth operations (ReLU masks, arg-max pooling)
 // whose gradients must match an FP32/FP64 evaluation.
-template <bool MFMA, bool SPLIT = false, bool SPLITB = false>
+template <int HD, bool MFMA, bool SPLIT = false, bool SPLITB = false>
 __device__ __forceinline__ void tile_gemm(const float (*A)[HD + 1], const float* __restrict__ Bf,
                                           const unsigned short (*Bt)[HD + 8], float (*D)[HD + 1],
                                           const unsigned short (*Btlo)[HD + 8] = nullptr) {
+    static_assert(!MFMA || HD == 64, "the MFMA tiling is written for 64 channels");
     const int wv = threadIdx.x / HD, lane = threadIdx.x % HD;
     if constexpr (!MFMA) {
         for (int r = 0; r < 16; ++r) {
@@ -294,8 +298,9 @@ __device__ __forceinline__ void tile_gemm(const float (*A)[HD + 1], const float*
 
 // Stage a 64 x 64 FP32 matrix M (row-major [k][c]) for tile_gemm: bf16 copy as Bt[c][k] when
 // `transpose`, else as Bt[k'][c'] = M[k'][c'] (used for products with M^T).
+template <int HD>
 __device__ __forceinline__ void stage_bf16(const float* __restrict__ M, bool transpose, unsigned short (*Bt)[HD + 8]) {
-    for (int e = threadIdx.x; e < HD * HD; e += NT) {
+    for (int e = threadIdx.x; e < HD * HD; e += 4 * HD) {
         const int k = e / HD, c = e % HD;
         if (transpose)
             Bt[c][k] = f2bf(M[e]);
@@ -305,9 +310,10 @@ __device__ __forceinline__ void stage_bf16(const float* __restrict__ M, bool tra
 }
 
 // hi/lo bf16 pair of M^T (Bt[c][k] = hi, Btlo[c][k] = lo of M[k][c]).
+template <int HD>
 __device__ __forceinline__ void stage_bf16_split_t(const float* __restrict__ M, unsigned short (*Bt)[HD + 8],
                                                    unsigned short (*Btlo)[HD + 8]) {
-    for (int e = threadIdx.x; e < HD * HD; e += NT) {
+    for (int e = threadIdx.x; e < HD * HD; e += 4 * HD) {
         const int k = e / HD, c = e % HD;
         unsigned short h, l;
         split_bf16(M[e], h, l);
@@ -316,8 +322,8 @@ __device__ __forceinline__ void stage_bf16_split_t(const float* __restrict__ M, 
     }
 }
 
-template <bool MFMA, bool X3>
-__global__ __launch_bounds__(NT) void layer_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+template <int HD, bool MFMA, bool X3>
+__global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                                    const float* __restrict__ w, const int32_t* __restrict__ tile_graph,
                                                    const int32_t* __restrict__ gend, const float* __restrict__ Yp,
                                                    const float* __restrict__ mup, const float* __restrict__ rsp,
@@ -334,10 +340,10 @@ __global__ __launch_bounds__(NT) void layer_kernel(const int32_t* __restrict__ p
     const int g = tile_graph[tile];
     const int32_t end = gend[g];
     const float mu = mup[g * HD + c], rs = rsp[g * HD + c], ga = gam[c], be = bet[c];
-    if constexpr (X3)
-        stage_bf16_split_t(W, Bt, Btlo);
+    if constexpr (X3 && MFMA)
+        stage_bf16_split_t<HD>(W, Bt, Btlo);
     else if constexpr (MFMA)
-        stage_bf16(W, true, Bt);
+        stage_bf16<HD>(W, true, Bt);
     float h = 0.0f;
     const int32_t r0 = tile * TILE + wv * 16;
     visit_rows<float>(
@@ -350,7 +356,7 @@ __global__ __launch_bounds__(NT) void layer_kernel(const int32_t* __restrict__ p
             h = 0.0f;
         });
     __syncthreads();
-    tile_gemm<MFMA, true, X3>(Hs, W, Bt, Ds, Btlo);
+    tile_gemm<HD, MFMA, true, X3>(Hs, W, Bt, Ds, Btlo);
     __syncthreads();
     const float bc = b[c];
     double s1 = 0.0, s2 = 0.0;
@@ -382,8 +388,8 @@ __global__ __launch_bounds__(NT) void layer_kernel(const int32_t* __restrict__ p
 constexpr int kChunkTiles = 256;
 
 // out[k][j][c] = sum over items i in [bounds[k], bounds[k+1]) of in[i][j][c], j < K, c < HD
-template <int K>
-__global__ __launch_bounds__(NT) void chunk_sum_kernel(const double* __restrict__ in, const int32_t* __restrict__ bounds,
+template <int HD, int K>
+__global__ __launch_bounds__(4 * HD) void chunk_sum_kernel(const double* __restrict__ in, const int32_t* __restrict__ bounds,
                                                        double* __restrict__ out) {
     __shared__ double sh[4][K][HD];
     const int k = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
@@ -403,7 +409,8 @@ __global__ __launch_bounds__(NT) void chunk_sum_kernel(const double* __restrict_
 }
 
 // Per graph and channel: mean and 1/sqrt(biased variance + eps) from the chunk sums.
-__global__ __launch_bounds__(NT) void stats_final_kernel(const double* __restrict__ cstat,
+template <int HD>
+__global__ __launch_bounds__(4 * HD) void stats_final_kernel(const double* __restrict__ cstat,
                                                          const int32_t* __restrict__ gchunk,
                                                          const float* __restrict__ gcnt, float* __restrict__ mu,
                                                          float* __restrict__ rstd) {
@@ -429,7 +436,8 @@ __global__ __launch_bounds__(NT) void stats_final_kernel(const double* __restric
 }
 
 // Per tile: sum, max and first arg-max of x = ReLU(IN(y)) per channel.
-__global__ __launch_bounds__(NT) void pool_tile_kernel(const int32_t* __restrict__ tile_graph,
+template <int HD>
+__global__ __launch_bounds__(4 * HD) void pool_tile_kernel(const int32_t* __restrict__ tile_graph,
                                                        const int32_t* __restrict__ gend, const float* __restrict__ Y,
                                                        const float* __restrict__ mu, const float* __restrict__ rstd,
                                                        const float* __restrict__ gam, const float* __restrict__ bet,
@@ -480,7 +488,8 @@ __device__ __forceinline__ void max_merge(float& mx, int32_t& am, float m2, int3
 }
 
 // Stage 1 of the pooling reduction (see chunk_sum_kernel): per chunk, sum, max and arg-max.
-__global__ __launch_bounds__(NT) void pool_chunk_kernel(const double* __restrict__ tsum, const float* __restrict__ tmax,
+template <int HD>
+__global__ __launch_bounds__(4 * HD) void pool_chunk_kernel(const double* __restrict__ tsum, const float* __restrict__ tmax,
                                                         const int32_t* __restrict__ targ,
                                                         const int32_t* __restrict__ bounds, double* __restrict__ csum,
                                                         float* __restrict__ cmax, int32_t* __restrict__ carg) {
@@ -506,7 +515,8 @@ __global__ __launch_bounds__(NT) void pool_chunk_kernel(const double* __restrict
     carg[static_cast<int64_t>(k) * HD + c] = am;
 }
 
-__global__ __launch_bounds__(NT) void pool_final_kernel(const double* __restrict__ csum, const float* __restrict__ cmax,
+template <int HD>
+__global__ __launch_bounds__(4 * HD) void pool_final_kernel(const double* __restrict__ csum, const float* __restrict__ cmax,
                                                         const int32_t* __restrict__ carg,
                                                         const int32_t* __restrict__ gchunk,
                                                         const float* __restrict__ gcnt, int layer,
@@ -556,6 +566,7 @@ struct HeadSave {
 };
 
 // Readout, LayerNorm, sigmoid and predictive MLP of one graph per workgroup (128 threads).
+template <int HD>
 __global__ __launch_bounds__(128) void head_fwd_kernel(const float* __restrict__ P, Offs o,
                                                        const float* __restrict__ pooled, HeadSave hs,
                                                        float* __restrict__ out) {
@@ -609,6 +620,7 @@ __global__ __launch_bounds__(128) void head_fwd_kernel(const float* __restrict__
 // ------------------------------------------------------------------------------------------
 // Head backward of one graph; writes this graph's head-parameter gradients (relative to
 // o.head0) into gh[g][*] and the pooled-feature gradients into dpooled[g].
+template <int HD>
 __global__ __launch_bounds__(128) void head_bwd_kernel(const float* __restrict__ P, Offs o,
                                                        const float* __restrict__ pooled, HeadSave hs,
                                                        const float* __restrict__ dout, float* __restrict__ gh,
@@ -661,10 +673,10 @@ __global__ __launch_bounds__(128) void head_bwd_kernel(const float* __restrict__
     for (int l = 0; l < NL; ++l) {
         if (t < RO) G(o.rob[l] + t) = dzv[l * RO + t];
         for (int e = t; e < 2 * HD * RO; e += 128) G(o.roW[l] + e) = p[l * 2 * HD + e / RO] * dzv[l * RO + e % RO];
-        {
+        for (int k = t; k < 2 * HD; k += 128) {
             float acc = 0.0f;
-            for (int q = 0; q < RO; ++q) acc += dzv[l * RO + q] * P[o.roW[l] + t * RO + q];
-            dpooled[(g * NL + l) * 2 * HD + t] = acc;
+            for (int q = 0; q < RO; ++q) acc += dzv[l * RO + q] * P[o.roW[l] + k * RO + q];
+            dpooled[(g * NL + l) * 2 * HD + k] = acc;
         }
     }
 }
@@ -672,7 +684,8 @@ __global__ __launch_bounds__(128) void head_bwd_kernel(const float* __restrict__
 // Layer backward, first half, per tile: dX from pooling (mean and arg-max) and, below the last
 // layer, from the next layer's aggregation (A_hat^T dH = A_hat dH, A symmetric); ReLU and the
 // affine part of InstanceNorm; per-tile sums for the normalisation backward and gamma/beta.
-__global__ __launch_bounds__(NT) void bwd_a_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+template <int HD>
+__global__ __launch_bounds__(4 * HD) void bwd_a_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                                    const float* __restrict__ w, const int32_t* __restrict__ tile_graph,
                                                    const int32_t* __restrict__ gend, const float* __restrict__ gcnt,
                                                    const float* __restrict__ Y, const float* __restrict__ mu,
@@ -728,7 +741,8 @@ __global__ __launch_bounds__(NT) void bwd_a_kernel(const int32_t* __restrict__ p
 
 // Per graph: means of dxhat and dxhat*xhat; gamma/beta gradients of the graph (from the chunk
 // sums of the four per-tile quantities, as in stats_final_kernel).
-__global__ __launch_bounds__(NT) void bwd_final_kernel(const double* __restrict__ ctb, const int32_t* __restrict__ gchunk,
+template <int HD>
+__global__ __launch_bounds__(4 * HD) void bwd_final_kernel(const double* __restrict__ ctb, const int32_t* __restrict__ gchunk,
                                                        const float* __restrict__ gcnt, float* __restrict__ gmean,
                                                        double* __restrict__ ggb) {
     __shared__ double sh[4][4][HD];
@@ -752,8 +766,8 @@ __global__ __launch_bounds__(NT) void bwd_final_kernel(const double* __restrict_
 // Layer backward, second half. dY = rstd (dxhat - mean(dxhat) - xhat mean(dxhat xhat));
 // dH = dY W^T (stored for the layer below unless first); partial dW = H^T dY and db = sum dY
 // accumulated over the tiles a workgroup visits (fixed grid of kWBlocks, fixed order).
-template <bool MFMA>
-__global__ __launch_bounds__(NT) void bwd_b_kernel(int ntiles, const int32_t* __restrict__ tile_graph,
+template <int HD, bool MFMA>
+__global__ __launch_bounds__(4 * HD) void bwd_b_kernel(int ntiles, const int32_t* __restrict__ tile_graph,
                                                    const int32_t* __restrict__ gend, const float* __restrict__ Y,
                                                    const float* __restrict__ mu, const float* __restrict__ rstd,
                                                    const float* __restrict__ gmean, const float* __restrict__ dxh,
@@ -766,12 +780,14 @@ __global__ __launch_bounds__(NT) void bwd_b_kernel(int ntiles, const int32_t* __
     __shared__ unsigned short Bt[HD][HD + 8];
     __shared__ double sh[4][HD];
     const int wv = threadIdx.x / HD, c = threadIdx.x % HD;
+    static_assert(!MFMA || HD == 64, "the MFMA tiling is written for 64 channels");
+    constexpr int NT = 4 * HD, NW = HD / 4;  // threads; dW entries per thread (in_dim <= HD)
     if constexpr (MFMA) {
-        if (dH) stage_bf16(W, false, Bt);  // dH = dY W^T: B[c'][k] = W[k][c'] read as rows of W
+        if (dH) stage_bf16<HD>(W, false, Bt);  // dH = dY W^T: B[c'][k] = W[k][c'] read as rows of W
     }
-    // dW accumulator: thread owns W entries e = threadIdx.x + q*NT (in_dim*64 entries)
-    float accw[16];
-    for (int q = 0; q < 16; ++q) accw[q] = 0.0f;
+    // dW accumulator: thread owns W entries e = threadIdx.x + q*NT (in_dim*HD entries)
+    float accw[NW];
+    for (int q = 0; q < NW; ++q) accw[q] = 0.0f;
     double accb = 0.0;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int g = tile_graph[tile];
@@ -803,7 +819,7 @@ __global__ __launch_bounds__(NT) void bwd_b_kernel(int ntiles, const int32_t* __
                     Ds[lr][c] = acc;
                 }
             } else {
-                tile_gemm<true>(dYs, W, Bt, Ds);
+                tile_gemm<HD, true>(dYs, W, Bt, Ds);
             }
             __syncthreads();
             for (int r = 0; r < 16; ++r) {
@@ -814,7 +830,7 @@ __global__ __launch_bounds__(NT) void bwd_b_kernel(int ntiles, const int32_t* __
         }
         // dW[k][c'] += sum_rows H[row][k] dY[row][c']
         if constexpr (!MFMA) {
-            for (int q = 0; q < 16; ++q) {
+            for (int q = 0; q < NW; ++q) {
                 const int e = threadIdx.x + q * NT;
                 if (e < in_dim * HD) {
                     const int k = e / HD, cc = e % HD;
@@ -852,7 +868,7 @@ __global__ __launch_bounds__(NT) void bwd_b_kernel(int ntiles, const int32_t* __
                 for (int nb = 0; nb < 4; ++nb)
                     for (int e = 0; e < 4; ++e) accw[nb * 4 + e] += acc[nb][e];
             } else {
-                for (int q = 0; q < 16; ++q) {
+                for (int q = 0; q < NW; ++q) {
                     const int e = threadIdx.x + q * NT;
                     if (e < in_dim * HD) {
                         const int k = e / HD, cc = e % HD;
@@ -874,7 +890,7 @@ __global__ __launch_bounds__(NT) void bwd_b_kernel(int ntiles, const int32_t* __
                 wpart[static_cast<int64_t>(blockIdx.x) * HD * HD + k * HD + cc] = accw[nb * 4 + e];
             }
     } else {
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < NW; ++q) {
             const int e = threadIdx.x + q * NT;
             if (e < in_dim * HD) wpart[static_cast<int64_t>(blockIdx.x) * HD * HD + e] = accw[q];
         }
@@ -884,19 +900,20 @@ __global__ __launch_bounds__(NT) void bwd_b_kernel(int ntiles, const int32_t* __
 }
 
 // One workgroup: D1 = A B by the FP32 path and D2 = A B by the BF16 MFMA path of tile_gemm.
-__global__ __launch_bounds__(NT) void tile_gemm_check_kernel(const float* __restrict__ A, const float* __restrict__ B,
-                                                             float* __restrict__ D1, float* __restrict__ D2) {
+__global__ __launch_bounds__(256) void tile_gemm_check_kernel(const float* __restrict__ A, const float* __restrict__ B,
+                                                              float* __restrict__ D1, float* __restrict__ D2) {
+    constexpr int HD = 64, NT = 256;
     __shared__ float As[TILE][HD + 1];
     __shared__ float Ds[TILE][HD + 1];
     __shared__ unsigned short Bt[HD][HD + 8];
     for (int e = threadIdx.x; e < TILE * HD; e += NT) As[e / HD][e % HD] = A[e];
-    stage_bf16(B, true, Bt);
+    stage_bf16<HD>(B, true, Bt);
     __syncthreads();
-    tile_gemm<false>(As, B, Bt, Ds);
+    tile_gemm<HD, false>(As, B, Bt, Ds);
     __syncthreads();
     for (int e = threadIdx.x; e < TILE * HD; e += NT) D1[e] = Ds[e / HD][e % HD];
     __syncthreads();
-    tile_gemm<true, true>(As, B, Bt, Ds);
+    tile_gemm<HD, true, true>(As, B, Bt, Ds);
     __syncthreads();
     for (int e = threadIdx.x; e < TILE * HD; e += NT) D2[e] = Ds[e / HD][e % HD];
 }
@@ -925,7 +942,9 @@ __global__ void reduce_parts_f64_kernel(const double* __restrict__ part, int par
 // ------------------------------------------------------------------------------------------
 constexpr int kAdamBlocks = 256;
 
-__global__ __launch_bounds__(NT) void sumsq_kernel(const float* __restrict__ g, int64_t n, double* __restrict__ part) {
+__global__ __launch_bounds__(kAdamThreads) void sumsq_kernel(const float* __restrict__ g, int64_t n,
+                                                             double* __restrict__ part) {
+    constexpr int NT = kAdamThreads;
     __shared__ double red[NT];
     double s = 0.0;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; i < n; i += static_cast<int64_t>(gridDim.x) * NT)
@@ -1010,6 +1029,7 @@ struct gcin_batch {
     double* bpart = nullptr;
     int64_t ghstride = 0;
     int last_degree = -1;
+    int hd = 64;  // hidden width
 };
 
 namespace {
@@ -1028,7 +1048,7 @@ struct Carve {
 
 size_t layout_batch(gcin_batch* b, uintptr_t base) {
     Carve cv{base};
-    const size_t G = b->G, N = b->N, E = b->E, T = b->ntiles;
+    const size_t G = b->G, N = b->N, E = b->E, T = b->ntiles, HD = b->hd;
     b->d_gend = cv.take<int32_t>(G);
     b->d_gtile = cv.take<int32_t>(G + 1);
     b->d_tile_graph = cv.take<int32_t>(T);
@@ -1061,7 +1081,7 @@ size_t layout_batch(gcin_batch* b, uintptr_t base) {
     b->hs.a1 = cv.take<float>(G * M1);
     b->hs.a2 = cv.take<float>(G * M2);
     b->dpooled = cv.take<float>(G * NL * 2 * HD);
-    const Offs o4 = offsets(AMGG_MAX_DEGREE);
+    const Offs o4 = offsets(AMGG_MAX_DEGREE, b->hd);
     b->ghstride = ((o4.total - o4.head0) + 63) / 64 * 64;
     b->ghead = cv.take<float>(G * b->ghstride);
     b->dxh = cv.take<float>(N * HD);
@@ -1116,15 +1136,22 @@ int hip_err(hipError_t e, const char* where) {
 
 }  // namespace
 
-extern "C" int64_t gcin_param_count(int degree) {
-    if (degree < 1 || degree > AMGG_MAX_DEGREE) return -1;
-    return offsets(degree).total;
+static bool hidden_ok(int hidden) { return hidden == 64 || hidden == 32; }
+
+extern "C" int64_t gcin_param_count_hidden(int degree, int hidden) {
+    if (degree < 1 || degree > AMGG_MAX_DEGREE || !hidden_ok(hidden)) return -1;
+    return offsets(degree, hidden).total;
 }
 
-extern "C" int gcin_batch_workspace_bytes(int ngraphs, const int32_t* n, const int32_t* nnz, size_t* bytes) {
+extern "C" int64_t gcin_param_count(int degree) { return gcin_param_count_hidden(degree, 64); }
+
+extern "C" int gcin_batch_workspace_bytes_hidden(int hidden, int ngraphs, const int32_t* n, const int32_t* nnz,
+                                                 size_t* bytes) {
     return amgg::guarded([&]() -> int {
         if (!n || !nnz || !bytes) return amgg::fail(AMGG_EINVAL, "gcin_batch_workspace_bytes: null argument");
+        if (!hidden_ok(hidden)) return amgg::fail(AMGG_EINVAL, "gcin_batch_workspace_bytes: hidden must be 64 or 32");
         gcin_batch b;
+        b.hd = hidden;
         int rc = plan_batch(&b, ngraphs, n, nnz);
         if (rc) return rc;
         *bytes = layout_batch(&b, 0);
@@ -1132,9 +1159,14 @@ extern "C" int gcin_batch_workspace_bytes(int ngraphs, const int32_t* n, const i
     });
 }
 
-extern "C" int gcin_batch_create(int ngraphs, const gcin_graph* graphs, void* workspace, size_t ws_bytes, void* stream,
-                                 gcin_batch** out) {
+extern "C" int gcin_batch_workspace_bytes(int ngraphs, const int32_t* n, const int32_t* nnz, size_t* bytes) {
+    return gcin_batch_workspace_bytes_hidden(64, ngraphs, n, nnz, bytes);
+}
+
+extern "C" int gcin_batch_create_hidden(int hidden, int ngraphs, const gcin_graph* graphs, void* workspace,
+                                        size_t ws_bytes, void* stream, gcin_batch** out) {
     return amgg::guarded([&]() -> int {
+        if (!hidden_ok(hidden)) return amgg::fail(AMGG_EINVAL, "gcin_batch_create: hidden must be 64 or 32");
         if (!graphs || !out || !workspace) return amgg::fail(AMGG_EINVAL, "gcin_batch_create: null argument");
         if (reinterpret_cast<uintptr_t>(workspace) & 255u)
             return amgg::fail(AMGG_EWORKSPACE, "gcin_batch_create: workspace not 256-byte aligned");
@@ -1147,6 +1179,7 @@ extern "C" int gcin_batch_create(int ngraphs, const gcin_graph* graphs, void* wo
                 return amgg::fail(AMGG_EINVAL, "gcin_batch_create: null graph array");
         }
         auto* b = new gcin_batch();
+        b->hd = hidden;
         int rc = plan_batch(b, ngraphs, n.data(), z.data());
         if (rc) {
             delete b;
@@ -1204,10 +1237,88 @@ extern "C" int gcin_batch_create(int ngraphs, const gcin_graph* graphs, void* wo
     });
 }
 
+extern "C" int gcin_batch_create(int ngraphs, const gcin_graph* graphs, void* workspace, size_t ws_bytes, void* stream,
+                                 gcin_batch** out) {
+    return gcin_batch_create_hidden(64, ngraphs, graphs, workspace, ws_bytes, stream, out);
+}
+
 extern "C" int gcin_batch_destroy(gcin_batch* b) {
     delete b;
     return AMGG_OK;
 }
+
+namespace {
+
+// The tile products run on MFMA for 64 channels; the 32-channel variant keeps them in FP32.
+template <int HD>
+void forward_impl(gcin_batch* b, int degree, int precision, const float* P, float* coeffs_out, hipStream_t st) {
+    constexpr int NT = 4 * HD;
+    const Offs o = offsets(degree, HD);
+    const int T = b->ntiles, G = b->G;
+    layer0_kernel<HD><<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->x0, b->d_tile_graph, b->d_gend, P + o.convW[0],
+                                        P + o.convb[0], b->H0, b->Y[0], b->tstat);
+    const int C = b->nchunks;
+    chunk_sum_kernel<HD, 2><<<C, NT, 0, st>>>(b->tstat, b->d_cbound, b->cbuf);
+    stats_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->mu[0], b->rstd[0]);
+    for (int l = 1; l < NL; ++l) {
+        auto kern = layer_kernel<HD, false, false>;
+        if constexpr (HD == 64)
+            kern = precision == GCIN_BF16X3 ? layer_kernel<HD, true, true>
+                   : precision == GCIN_BF16 ? layer_kernel<HD, true, false> : layer_kernel<HD, false, false>;
+        kern<<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->d_tile_graph, b->d_gend, b->Y[l - 1], b->mu[l - 1],
+                               b->rstd[l - 1], P + o.gam[l - 1], P + o.bet[l - 1], P + o.convW[l], P + o.convb[l],
+                               b->H[l], b->Y[l], b->tstat);
+        chunk_sum_kernel<HD, 2><<<C, NT, 0, st>>>(b->tstat, b->d_cbound, b->cbuf);
+        stats_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->mu[l], b->rstd[l]);
+    }
+    for (int l = 0; l < NL; ++l) {
+        pool_tile_kernel<HD><<<T, NT, 0, st>>>(b->d_tile_graph, b->d_gend, b->Y[l], b->mu[l], b->rstd[l], P + o.gam[l],
+                                               P + o.bet[l], b->tpsum, b->tpmax, b->tparg);
+        pool_chunk_kernel<HD><<<C, NT, 0, st>>>(b->tpsum, b->tpmax, b->tparg, b->d_cbound, b->cbuf, b->cmax, b->carg);
+        pool_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->cmax, b->carg, b->d_gchunk, b->d_gcnt, l, b->pooled,
+                                                b->argmax);
+    }
+    head_fwd_kernel<HD><<<G, 128, 0, st>>>(P, o, b->pooled, b->hs, coeffs_out);
+}
+
+template <int HD>
+void backward_impl(gcin_batch* b, int degree, int precision, const float* P, const float* dcoeffs, float* grads,
+                   hipStream_t st) {
+    constexpr int NT = 4 * HD;
+    const Offs o = offsets(degree, HD);
+    const int T = b->ntiles, G = b->G;
+    head_bwd_kernel<HD><<<G, 128, 0, st>>>(P, o, b->pooled, b->hs, dcoeffs, b->ghead, b->ghstride, b->dpooled);
+    // head parameters: sum over graphs
+    const int64_t nhead = o.total - o.head0;
+    reduce_parts_f32_kernel<<<grid_of(nhead, 256), 256, 0, st>>>(b->ghead, G, b->ghstride, nhead, grads + o.head0);
+    float* dHn = nullptr;  // dH of the layer above (for the aggregation backward)
+    float* bufs[2] = {b->dHa, b->dHb};
+    for (int l = NL - 1; l >= 0; --l) {
+        bwd_a_kernel<HD><<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->d_tile_graph, b->d_gend, b->d_gcnt, b->Y[l],
+                                           b->mu[l], b->rstd[l], P + o.gam[l], P + o.bet[l], b->dpooled, b->argmax, l,
+                                           dHn, b->dxh, b->tb);
+        chunk_sum_kernel<HD, 4><<<b->nchunks, NT, 0, st>>>(b->tb, b->d_cbound, b->cbuf);
+        bwd_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->gmean, b->ggb);
+        // gamma / beta of this layer
+        reduce_parts_f64_kernel<<<1, HD, 0, st>>>(b->ggb, G, 2 * HD, HD, grads + o.gam[l]);
+        reduce_parts_f64_kernel<<<1, HD, 0, st>>>(b->ggb + HD, G, 2 * HD, HD, grads + o.bet[l]);
+        float* dHout = l > 0 ? bufs[l & 1] : nullptr;
+        const int in_dim = l == 0 ? 2 : HD;
+        const float* Hin = l == 0 ? b->H0 : b->H[l];
+        const int grid = T < kWBlocks ? T : kWBlocks;
+        auto kern = bwd_b_kernel<HD, false>;
+        if constexpr (HD == 64)
+            if (precision != GCIN_FP32) kern = bwd_b_kernel<HD, true>;
+        kern<<<grid, NT, 0, st>>>(T, b->d_tile_graph, b->d_gend, b->Y[l], b->mu[l], b->rstd[l], b->gmean, b->dxh, Hin,
+                                  in_dim, P + o.convW[l], dHout, b->wpart, b->bpart);
+        reduce_parts_f32_kernel<<<grid_of(in_dim * HD, 256), 256, 0, st>>>(b->wpart, grid, HD * HD, in_dim * HD,
+                                                                          grads + o.convW[l]);
+        reduce_parts_f64_kernel<<<1, HD, 0, st>>>(b->bpart, grid, HD, HD, grads + o.convb[l]);
+        dHn = dHout;
+    }
+}
+
+}  // namespace
 
 extern "C" int gcin_forward(gcin_batch* b, int degree, int precision, const float* P, float* coeffs_out, void* stream) {
     return amgg::guarded([&]() -> int {
@@ -1215,30 +1326,10 @@ extern "C" int gcin_forward(gcin_batch* b, int degree, int precision, const floa
         if (degree < 1 || degree > AMGG_MAX_DEGREE) return amgg::fail(AMGG_EINVAL, "gcin_forward: degree out of range");
         if (precision < GCIN_FP32 || precision > GCIN_BF16X3) return amgg::fail(AMGG_EINVAL, "gcin_forward: bad precision");
         hipStream_t st = static_cast<hipStream_t>(stream);
-        const Offs o = offsets(degree);
-        const int T = b->ntiles, G = b->G;
-        layer0_kernel<<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->x0, b->d_tile_graph, b->d_gend, P + o.convW[0],
-                                        P + o.convb[0], b->H0, b->Y[0], b->tstat);
-        const int C = b->nchunks;
-        chunk_sum_kernel<2><<<C, NT, 0, st>>>(b->tstat, b->d_cbound, b->cbuf);
-        stats_final_kernel<<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->mu[0], b->rstd[0]);
-        for (int l = 1; l < NL; ++l) {
-            auto kern = precision == GCIN_BF16X3 ? layer_kernel<true, true>
-                        : precision == GCIN_BF16 ? layer_kernel<true, false> : layer_kernel<false, false>;
-            kern<<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->d_tile_graph, b->d_gend, b->Y[l - 1], b->mu[l - 1],
-                                   b->rstd[l - 1], P + o.gam[l - 1], P + o.bet[l - 1], P + o.convW[l], P + o.convb[l],
-                                   b->H[l], b->Y[l], b->tstat);
-            chunk_sum_kernel<2><<<C, NT, 0, st>>>(b->tstat, b->d_cbound, b->cbuf);
-            stats_final_kernel<<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->mu[l], b->rstd[l]);
-        }
-        for (int l = 0; l < NL; ++l) {
-            pool_tile_kernel<<<T, NT, 0, st>>>(b->d_tile_graph, b->d_gend, b->Y[l], b->mu[l], b->rstd[l], P + o.gam[l],
-                                               P + o.bet[l], b->tpsum, b->tpmax, b->tparg);
-            pool_chunk_kernel<<<C, NT, 0, st>>>(b->tpsum, b->tpmax, b->tparg, b->d_cbound, b->cbuf, b->cmax, b->carg);
-            pool_final_kernel<<<G, NT, 0, st>>>(b->cbuf, b->cmax, b->carg, b->d_gchunk, b->d_gcnt, l, b->pooled,
-                                                b->argmax);
-        }
-        head_fwd_kernel<<<G, 128, 0, st>>>(P, o, b->pooled, b->hs, coeffs_out);
+        if (b->hd == 32)
+            forward_impl<32>(b, degree, precision, P, coeffs_out, st);
+        else
+            forward_impl<64>(b, degree, precision, P, coeffs_out, st);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_err(e, "gcin_forward");
         b->last_degree = degree;
@@ -1253,35 +1344,10 @@ extern "C" int gcin_backward(gcin_batch* b, int degree, int precision, const flo
         if (degree != b->last_degree) return amgg::fail(AMGG_ESTATE, "gcin_backward: no forward pass of this degree");
         if (precision < GCIN_FP32 || precision > GCIN_BF16X3) return amgg::fail(AMGG_EINVAL, "gcin_backward: bad precision");
         hipStream_t st = static_cast<hipStream_t>(stream);
-        const Offs o = offsets(degree);
-        const int T = b->ntiles, G = b->G;
-        head_bwd_kernel<<<G, 128, 0, st>>>(P, o, b->pooled, b->hs, dcoeffs, b->ghead, b->ghstride, b->dpooled);
-        // head parameters: sum over graphs
-        const int64_t nhead = o.total - o.head0;
-        reduce_parts_f32_kernel<<<grid_of(nhead, 256), 256, 0, st>>>(b->ghead, G, b->ghstride, nhead, grads + o.head0);
-        float* dHn = nullptr;  // dH of the layer above (for the aggregation backward)
-        float* bufs[2] = {b->dHa, b->dHb};
-        for (int l = NL - 1; l >= 0; --l) {
-            bwd_a_kernel<<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->d_tile_graph, b->d_gend, b->d_gcnt, b->Y[l], b->mu[l],
-                                           b->rstd[l], P + o.gam[l], P + o.bet[l], b->dpooled, b->argmax, l, dHn,
-                                           b->dxh, b->tb);
-            chunk_sum_kernel<4><<<b->nchunks, NT, 0, st>>>(b->tb, b->d_cbound, b->cbuf);
-            bwd_final_kernel<<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->gmean, b->ggb);
-            // gamma / beta of this layer
-            reduce_parts_f64_kernel<<<1, HD, 0, st>>>(b->ggb, G, 2 * HD, HD, grads + o.gam[l]);
-            reduce_parts_f64_kernel<<<1, HD, 0, st>>>(b->ggb + HD, G, 2 * HD, HD, grads + o.bet[l]);
-            float* dHout = l > 0 ? bufs[l & 1] : nullptr;
-            const int in_dim = l == 0 ? 2 : HD;
-            const float* Hin = l == 0 ? b->H0 : b->H[l];
-            const int grid = T < kWBlocks ? T : kWBlocks;
-            auto kern = precision == GCIN_FP32 ? bwd_b_kernel<false> : bwd_b_kernel<true>;
-            kern<<<grid, NT, 0, st>>>(T, b->d_tile_graph, b->d_gend, b->Y[l], b->mu[l], b->rstd[l], b->gmean, b->dxh,
-                                      Hin, in_dim, P + o.convW[l], dHout, b->wpart, b->bpart);
-            reduce_parts_f32_kernel<<<grid_of(in_dim * HD, 256), 256, 0, st>>>(b->wpart, grid, HD * HD, in_dim * HD,
-                                                                              grads + o.convW[l]);
-            reduce_parts_f64_kernel<<<1, HD, 0, st>>>(b->bpart, grid, HD, HD, grads + o.convb[l]);
-            dHn = dHout;
-        }
+        if (b->hd == 32)
+            backward_impl<32>(b, degree, precision, P, dcoeffs, grads, st);
+        else
+            backward_impl<64>(b, degree, precision, P, dcoeffs, grads, st);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_err(e, "gcin_backward");
         return AMGG_OK;
@@ -1290,7 +1356,7 @@ extern "C" int gcin_backward(gcin_batch* b, int degree, int precision, const flo
 
 extern "C" int gcin_tile_gemm_check(const float* A, const float* B, float* D_fp32, float* D_bf16, void* stream) {
     if (!A || !B || !D_fp32 || !D_bf16) return amgg::fail(AMGG_EINVAL, "gcin_tile_gemm_check: null argument");
-    tile_gemm_check_kernel<<<1, NT, 0, static_cast<hipStream_t>(stream)>>>(A, B, D_fp32, D_bf16);
+    tile_gemm_check_kernel<<<1, 256, 0, static_cast<hipStream_t>(stream)>>>(A, B, D_fp32, D_bf16);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_err(e, "gcin_tile_gemm_check");
     return AMGG_OK;
@@ -1306,7 +1372,7 @@ extern "C" int adam_step(float* params, const float* grads, float* m, float* v, 
         hipStream_t st = static_cast<hipStream_t>(stream);
         double* part = static_cast<double*>(scratch);
         double* scal = part + kAdamBlocks;
-        sumsq_kernel<<<kAdamBlocks, NT, 0, st>>>(grads, n, part);
+        sumsq_kernel<<<kAdamBlocks, kAdamThreads, 0, st>>>(grads, n, part);
         clipcoef_kernel<<<1, 1, 0, st>>>(part, clip, scal, gnorm_out);
         const float bc1 = 1.0f - std::pow(b1, static_cast<float>(step));
         const float bc2 = 1.0f - std::pow(b2, static_cast<float>(step));

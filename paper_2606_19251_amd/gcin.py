@@ -16,43 +16,49 @@ HIDDEN = 64
 LAYERS = 4
 
 
-def param_shapes(degree: int = 2):
-    """(name, shape) of every tensor in the flat parameter vector, in storage order."""
+def param_shapes(degree: int = 2, hidden: int = HIDDEN):
+    """(name, shape) of every tensor in the flat parameter vector, in storage order (hidden
+    width 64, or 32 for the smaller variant)."""
     shapes = []
     for l in range(LAYERS):
-        shapes += [(f"conv{l}.W", (2 if l == 0 else HIDDEN, HIDDEN)), (f"conv{l}.b", (HIDDEN,)),
-                   (f"norm{l}.gamma", (HIDDEN,)), (f"norm{l}.beta", (HIDDEN,))]
+        shapes += [(f"conv{l}.W", (2 if l == 0 else hidden, hidden)), (f"conv{l}.b", (hidden,)),
+                   (f"norm{l}.gamma", (hidden,)), (f"norm{l}.beta", (hidden,))]
     for l in range(LAYERS):
-        shapes += [(f"readout{l}.W", (2 * HIDDEN, 32)), (f"readout{l}.b", (32,))]
+        shapes += [(f"readout{l}.W", (2 * hidden, 32)), (f"readout{l}.b", (32,))]
     shapes += [("ln.gamma", (128,)), ("ln.beta", (128,)), ("mlp0.W", (128, 128)), ("mlp0.b", (128,)),
                ("mlp1.W", (128, 64)), ("mlp1.b", (64,)), ("mlp2.W", (64, 2 * degree + 1)),
                ("mlp2.b", (2 * degree + 1,))]
     return shapes
 
 
+def hidden_of(params: dict) -> int:
+    return int(np.shape(params["conv0.W"])[1])
+
+
 def pack(params: dict, degree: int = 2) -> np.ndarray:
-    """Flat float32 vector from a {name: array} dict."""
-    flat = np.concatenate([np.asarray(params[k], np.float64).reshape(-1) for k, _ in param_shapes(degree)])
-    assert flat.size == capi.gcin_param_count(degree)
+    """Flat float32 vector from a {name: array} dict (the hidden width is read from conv0.W)."""
+    hidden = hidden_of(params)
+    flat = np.concatenate([np.asarray(params[k], np.float64).reshape(-1) for k, _ in param_shapes(degree, hidden)])
+    assert flat.size == capi.gcin_param_count(degree, hidden)
     return flat.astype(np.float32)
 
 
-def unpack(flat: np.ndarray, degree: int = 2) -> dict:
+def unpack(flat: np.ndarray, degree: int = 2, hidden: int = HIDDEN) -> dict:
     out, k = {}, 0
-    for name, shape in param_shapes(degree):
+    for name, shape in param_shapes(degree, hidden):
         sz = int(np.prod(shape))
         out[name] = np.asarray(flat[k:k + sz], np.float64).reshape(shape)
         k += sz
     return out
 
 
-def init_flat(degree: int = 2, seed: int = 0, omega: float = 2.0 / 3.0) -> np.ndarray:
+def init_flat(degree: int = 2, seed: int = 0, omega: float = 2.0 / 3.0, hidden: int = HIDDEN) -> np.ndarray:
     """Initial parameters: uniform(+-1/sqrt(fan_in)) weights, zero biases, unit norm gains; the
     last layer is scaled by 1e-2 and its bias set to (omega, 0, ...), so the untrained
     predictor starts next to omega-Jacobi."""
     rng = np.random.default_rng(seed)
     p = {}
-    for name, shape in param_shapes(degree):
+    for name, shape in param_shapes(degree, hidden):
         if name.endswith(".W"):
             b = 1.0 / np.sqrt(shape[0])
             p[name] = rng.uniform(-b, b, size=shape)
@@ -68,23 +74,24 @@ def init_flat(degree: int = 2, seed: int = 0, omega: float = 2.0 / 3.0) -> np.nd
 class GraphBatch:
     """A batch of level graphs on the GPU (gcin_batch_create); keeps its workspace alive."""
 
-    def __init__(self, graphs, device):
+    def __init__(self, graphs, device, hidden: int = HIDDEN):
         """graphs: list of (rowptr, col, val) CUDA tensors (int32, int32, float64) of level matrices."""
         import torch
 
         self.torch = torch
         self.device = device
+        self.hidden = hidden
         self.ngraphs = len(graphs)
         n = np.array([int(g[0].numel() - 1) for g in graphs], np.int32)
         nnz = np.array([int(g[1].numel()) for g in graphs], np.int32)
         self.n = n
-        self.ws_bytes = capi.gcin_batch_workspace_bytes(n, nnz)
+        self.ws_bytes = capi.gcin_batch_workspace_bytes(n, nnz, hidden)
         raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
         off = (-raw.data_ptr()) % 256
         self._raw = raw
         self.ws = raw[off:off + self.ws_bytes]
         views = [(int(n[i]), int(nnz[i]), g[0].data_ptr(), g[1].data_ptr(), g[2].data_ptr()) for i, g in enumerate(graphs)]
-        self.handle = capi.gcin_batch_create(views, self.ws.data_ptr(), self.ws_bytes, self.stream)
+        self.handle = capi.gcin_batch_create(views, self.ws.data_ptr(), self.ws_bytes, self.stream, hidden)
 
     @property
     def stream(self):
@@ -120,26 +127,31 @@ class GraphBatch:
 class Predictor:
     """GCIN parameters on the device; predicts per-level smoother coefficients of a solver."""
 
-    def __init__(self, flat: np.ndarray, device, degree: int = 2, precision: int = capi.GCIN_BF16):
+    def __init__(self, flat: np.ndarray, device, degree: int = 2, precision: int = capi.GCIN_BF16,
+                 hidden: int = HIDDEN):
         import torch
 
         self.torch = torch
         self.device = device
         self.degree = degree
         self.precision = precision
+        self.hidden = hidden
+        if np.size(flat) != capi.gcin_param_count(degree, hidden):
+            raise ValueError(f"{np.size(flat)} parameters do not fit degree {degree}, hidden width {hidden}")
         self.params = torch.from_numpy(np.ascontiguousarray(flat, np.float32)).to(device)
 
     @classmethod
     def load(cls, path, device, precision: int = capi.GCIN_BF16):
         z = np.load(path, allow_pickle=False)
-        return cls(z["params"], device, int(z["degree"]), precision)
+        hidden = int(z["hidden"]) if "hidden" in z.files else HIDDEN
+        return cls(z["params"], device, int(z["degree"]), precision, hidden)
 
     def save(self, path):
-        np.savez(path, params=self.params.cpu().numpy(), degree=np.int64(self.degree))
+        np.savez(path, params=self.params.cpu().numpy(), degree=np.int64(self.degree), hidden=np.int64(self.hidden))
 
     def predict(self, hier, ds):
         """Coefficients [nlevels, 2d+1] (float32 CUDA tensor) for a DeviceSolver's levels."""
-        batch = GraphBatch([ds.A[l] for l in range(ds.nlevels)], self.device)
+        batch = GraphBatch([ds.A[l] for l in range(ds.nlevels)], self.device, self.hidden)
         out = batch.forward(self.params, self.degree, self.precision)
         self._last_batch = batch
         return out
@@ -169,7 +181,7 @@ class Trainer:
         for ds in solvers:
             self.slices.append((len(graphs), len(graphs) + ds.nlevels))
             graphs += [ds.A[l] for l in range(ds.nlevels)]
-        self.batch = GraphBatch(graphs, dev)
+        self.batch = GraphBatch(graphs, dev, predictor.hidden)
         d = predictor.degree
         n = predictor.params.numel()
         self.m = torch.zeros(n, dtype=torch.float32, device=dev)

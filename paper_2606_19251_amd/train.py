@@ -5,7 +5,10 @@ Training problems (all levels of all meshes of a mini-batch in one GCIN launch),
   cmesh     finite-volume C-meshes around random NACA 4-digit sections, ~24k-41k cells, wall
             aspect ratios 1e3-1e4 (for the 4M-cell airfoil mesh, 128 times larger);
   tet       finite-volume Poisson on jittered Kuhn tetrahedral meshes, ~8k-55k cells;
-  mixed     the three families in turn (a union of 2D and 3D problems, as in the paper's
+  grid      5-point Laplacians on square structured grids, 2k-16k nodes, Dirichlet (the
+            structured case, for which the paper proposes the smaller 32-channel GCIN:
+            --hidden 32);
+  mixed     the three unstructured families in turn (a union of 2D and 3D problems, as in the paper's
             combined training set).
 Each step:
 batched GCIN forward, per-problem smoother assembly and nvc V(1,1) cycles from u = 0 with a
@@ -46,6 +49,8 @@ def make_matrix(family, rng, seed):
     if family == "tet":
         P, T = W.kuhn_tets(int(rng.integers(12, 23)), seed, float(rng.uniform(0.05, 0.15)))
         return W.tet_fv_mesh(P, T)
+    if family == "grid":
+        return W.grid5(int(rng.integers(45, 127)))
     raise ValueError(family)
 
 
@@ -82,7 +87,8 @@ def train_one(args, seed, train, val, dev):
         return [torch.from_numpy(W.rhs_uniform(ds.n, int(r.integers(1 << 30)), zero_mean=bool(ds.singular))).to(dev)
                 for ds in problems]
 
-    pred = G.Predictor(G.init_flat(args.degree, seed), dev, args.degree, capi.GCIN_BF16X3)
+    pred = G.Predictor(G.init_flat(args.degree, seed, hidden=args.hidden), dev, args.degree, capi.GCIN_BF16X3,
+                       args.hidden)
     nb = max(1, len(train) // args.batch)
     trainers = [G.Trainer(train[b * args.batch:(b + 1) * args.batch], rhs_for(train[b * args.batch:(b + 1) * args.batch], b),
                           pred, lr=args.lr, nu=nu, nvc=args.nvc) for b in range(nb)]
@@ -150,7 +156,8 @@ def main(argv=None):
     ap.add_argument("--min-lr", type=float, default=1e-5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--seeds", type=int, default=1, help="independent initialisations; the best is kept")
-    ap.add_argument("--family", choices=[*FAMILIES, "mixed"], default="delaunay")
+    ap.add_argument("--family", choices=[*FAMILIES, "grid", "mixed"], default="delaunay")
+    ap.add_argument("--hidden", type=int, choices=[64, 32], default=64, help="GCIN channels")
     args = ap.parse_args(argv)
 
     import torch
@@ -167,8 +174,8 @@ def main(argv=None):
         print(f"[train] seed {args.seed + k}: best validation {best:+.4f}", flush=True)
     vals = np.array([r[0] for r in runs])
     best, flat, history = runs[int(np.argmin(vals))]
-    np.savez(args.out, params=flat, degree=np.int64(args.degree), nvc=np.int64(args.nvc), nu=np.int64(args.nu),
-             family=args.family, history=json.dumps(history), ensemble_val=vals)
+    np.savez(args.out, params=flat, degree=np.int64(args.degree), hidden=np.int64(args.hidden), nvc=np.int64(args.nvc),
+             nu=np.int64(args.nu), family=args.family, history=json.dumps(history), ensemble_val=vals)
     print(f"[train] ensemble of {len(vals)}: validation mean {vals.mean():+.4f} std {vals.std():.4f} "
           f"best {best:+.4f}; saved {args.out}", flush=True)
 

@@ -1,8 +1,8 @@
 """What the trained GCIN gains over the method without it (the omega-Jacobi smoother, the
 paper's baseline and fallback), on meshes none of the training or validation sets contained.
 
-For each mesh family the shipped weights were trained on (Sec. 3.3-3.4, Alg. 1), held-out
-meshes are solved with FP32 V(1,1) cycles inside FP64 flexible CG, once with omega-Jacobi and
+For each mesh family the shipped weights were trained on (Sec. 3.3-3.4, Alg. 1; for structured
+grids also the 32-channel variant proposed for them), held-out meshes are solved with FP32 V(1,1) cycles inside FP64 flexible CG, once with omega-Jacobi and
 once with the GCIN-predicted coefficients; the learned smoother must not need more V-cycles in
 total, and its validation metric (Eq. 13: log10 of the residual after the trained number of
 cycles relative to omega-Jacobi's, averaged over the meshes as in validation) must be negative. The cycle counts of FP64
@@ -25,6 +25,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _meshes(family):
+    if family == "grid":  # structured grids larger than every training grid (45^2..126^2 nodes)
+        return [W.grid5(k) for k in (150, 200, 256)]
     if family == "delaunay":
         return [W.delaunay_p1(W.gmm_points(n, 70_000 + k)) for k, n in enumerate((9000, 12000, 15000))]
     if family == "tet":
@@ -36,7 +38,9 @@ def _meshes(family):
                                             ("cmesh", "gcin_cmesh_deg2.npz"),
                                             # one model trained on the union of the three families (on
                                             # the C-meshes it gains nothing: Eq. 13 metric +0.008)
-                                            ("delaunay", "gcin_mixed_deg2.npz"), ("tet", "gcin_mixed_deg2.npz")])
+                                            ("delaunay", "gcin_mixed_deg2.npz"), ("tet", "gcin_mixed_deg2.npz"),
+                                            # structured grids: the 32-channel GCIN and the full one
+                                            ("grid", "gcin_grid_h32_deg2.npz"), ("grid", "gcin_grid_deg2.npz")])
 def test_trained_gcin_beats_jacobi_on_held_out_meshes(family, weights):
     from paper_2606_19251_amd import capi
     from paper_2606_19251_amd import gcin as G
