@@ -31,7 +31,7 @@
  *
  * Hidden width: the functions without a width argument build the 64-channel network above.
  * The *_hidden variants also build the 32-channel variant that the paper proposes for
- * structured meshes, where the smaller network costs less setup time (Sec. 5): every 64
+ * structured meshes, where the smaller network costs less setup time (App. B.3): every 64
  * above that counts GCIN channels becomes 32 (conv_l.W [in_l x 32], readout_l.W [64 x 32]);
  * the readout width, the head and the coefficient count are unchanged. Its tile products
  * run in FP32 whatever the precision argument (the MFMA tiling is written for 64 channels).

@@ -6,7 +6,7 @@ Training problems (all levels of all meshes of a mini-batch in one GCIN launch),
             aspect ratios 1e3-1e4 (for the 4M-cell airfoil mesh, 128 times larger);
   tet       finite-volume Poisson on jittered Kuhn tetrahedral meshes, ~8k-55k cells;
   grid      5-point Laplacians on square structured grids, 2k-16k nodes, Dirichlet (the
-            structured case, for which the paper proposes the smaller 32-channel GCIN:
+            structured case, for which the paper proposes the smaller 32-channel GCIN, App. B.3:
             --hidden 32);
   mixed     the three unstructured families in turn (a union of 2D and 3D problems, as in the paper's
             combined training set).
