@@ -396,6 +396,8 @@ def main():
                     help="only launch the dominant kernel and a calibration copy (for counter runs)")
     ap.add_argument("--profile-gcin", action="store_true",
                     help="only run the GCIN inference (BF16 MFMA) on the workload's hierarchy, 5 times (for counter runs)")
+    ap.add_argument("--only-training", action="store_true",
+                    help="only time the training step on the 32-mesh batch and print its JSON (for profiling)")
     ap.add_argument("--nu", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -407,6 +409,9 @@ def main():
 
     from paper_2606_19251_amd import capi
 
+    if args.only_training:
+        print(json.dumps({"training": training_step(torch)}), flush=True)
+        return
     case = Case(torch, args.workload, with_host_setup=not (args.profile_gcin or args.profile_kernels))
     ds, hh = case.ds, case.hh
     if args.profile_gcin:

@@ -169,8 +169,9 @@ typedef struct {
     const double* q_val;     /* nnz, smoother values on A's pattern */
     const float* q_val32;    /* nnz */
     const double* diag;      /* n */
-    const double* scale;     /* 1 value: s_l */
-    const double* coarse_inv;/* n*n row-major on the coarsest level, else NULL */
+    const double* scale;     /* 1 value: s_l (of the whole level; block scales are internal) */
+    const double* coarse_inv;/* n*n row-major on the coarsest level, else NULL; on a
+                                block-diagonal level the blocks' n_b*n_b inverses in turn */
     int32_t fused_rows;      /* rows per block of the fused smoothing kernels, 0 = not fused */
 } amgg_level_view;
 int amgg_level_view_get(const amgg_ctx* ctx, int lvl, amgg_level_view* out);

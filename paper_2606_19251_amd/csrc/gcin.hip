@@ -331,8 +331,12 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
                                                    const float* __restrict__ W, const float* __restrict__ b,
                                                    float* __restrict__ Hout, float* __restrict__ Y,
                                                    double* __restrict__ tstat) {
+    // The product overwrites the aggregates in place: every wavefront reads only its own 16
+    // rows of Hs and writes the same rows, each output after all of its row's reads (the
+    // stores depend on them), so one tile buffer serves both and twice as many workgroups fit
+    // a CU's LDS.
     __shared__ float Hs[TILE][HD + 1];
-    __shared__ float Ds[TILE][HD + 1];
+    float (*Ds)[HD + 1] = Hs;
     __shared__ unsigned short Bt[HD][HD + 8];
     __shared__ unsigned short Btlo[X3 ? HD : 1][HD + 8];
     __shared__ double sh[4][HD];
@@ -776,7 +780,7 @@ __global__ __launch_bounds__(4 * HD) void bwd_b_kernel(int ntiles, const int32_t
                                                    float* __restrict__ wpart, double* __restrict__ bpart) {
     __shared__ float dYs[TILE][HD + 1];
     __shared__ float Hs[TILE][HD + 1];
-    __shared__ float Ds[TILE][HD + 1];
+    float (*Ds)[HD + 1] = Hs;  // the dH product is formed after dW no longer needs Hs
     __shared__ unsigned short Bt[HD][HD + 8];
     __shared__ double sh[4][HD];
     const int wv = threadIdx.x / HD, c = threadIdx.x % HD;
@@ -809,25 +813,6 @@ __global__ __launch_bounds__(4 * HD) void bwd_b_kernel(int ntiles, const int32_t
             accb += dy;
         }
         __syncthreads();
-        if (dH) {
-            if constexpr (!MFMA) {
-                for (int r = 0; r < 16; ++r) {
-                    const int lr = wv * 16 + r;
-                    float acc = 0.0f;
-#pragma unroll 8
-                    for (int q = 0; q < HD; ++q) acc += dYs[lr][q] * W[c * HD + q];
-                    Ds[lr][c] = acc;
-                }
-            } else {
-                tile_gemm<HD, true>(dYs, W, Bt, Ds);
-            }
-            __syncthreads();
-            for (int r = 0; r < 16; ++r) {
-                const int lr = wv * 16 + r;
-                const int32_t row = tile * TILE + lr;
-                dH[static_cast<int64_t>(row) * HD + c] = row < end ? Ds[lr][c] : 0.0f;
-            }
-        }
         // dW[k][c'] += sum_rows H[row][k] dY[row][c']
         if constexpr (!MFMA) {
             for (int q = 0; q < NW; ++q) {
@@ -879,6 +864,26 @@ __global__ __launch_bounds__(4 * HD) void bwd_b_kernel(int ntiles, const int32_t
                 }
             }
         }
+        if (dH) {  // dH = dY W^T into the rows of Hs
+            __syncthreads();
+            if constexpr (!MFMA) {
+                for (int r = 0; r < 16; ++r) {
+                    const int lr = wv * 16 + r;
+                    float acc = 0.0f;
+#pragma unroll 8
+                    for (int q = 0; q < HD; ++q) acc += dYs[lr][q] * W[c * HD + q];
+                    Ds[lr][c] = acc;
+                }
+            } else {
+                tile_gemm<HD, true>(dYs, W, Bt, Ds);
+            }
+            __syncthreads();
+            for (int r = 0; r < 16; ++r) {
+                const int lr = wv * 16 + r;
+                const int32_t row = tile * TILE + lr;
+                dH[static_cast<int64_t>(row) * HD + c] = row < end ? Ds[lr][c] : 0.0f;
+            }
+        }
         __syncthreads();
     }
     // write this workgroup's partials in plain [k][c] order
@@ -918,23 +923,23 @@ __global__ __launch_bounds__(256) void tile_gemm_check_kernel(const float* __res
     for (int e = threadIdx.x; e < TILE * HD; e += NT) D2[e] = Ds[e / HD][e % HD];
 }
 
-// grads[off + e] = sum over `parts` partial arrays (stride `stride`) in order.
-__global__ void reduce_parts_f32_kernel(const float* __restrict__ part, int parts, int64_t stride, int64_t count,
-                                        float* __restrict__ out) {
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= count) return;
+// out[e] = sum over the `parts` partial arrays (stride `stride`) of part[k][e], one wavefront
+// per output: lane l sums parts l, l + 64, ... in order, then a fixed shuffle tree (the same
+// order in every run).
+template <typename T>
+__global__ __launch_bounds__(64) void reduce_parts_kernel(const T* __restrict__ part, int parts, int64_t stride,
+                                                          float* __restrict__ out) {
+    const int64_t e = blockIdx.x;
     double s = 0.0;
-    for (int k = 0; k < parts; ++k) s += part[k * stride + e];
-    out[e] = static_cast<float>(s);
+    for (int k = threadIdx.x; k < parts; k += 64) s += static_cast<double>(part[k * stride + e]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (threadIdx.x == 0) out[e] = static_cast<float>(s);
 }
 
-__global__ void reduce_parts_f64_kernel(const double* __restrict__ part, int parts, int64_t stride, int64_t count,
-                                        float* __restrict__ out) {
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= count) return;
-    double s = 0.0;
-    for (int k = 0; k < parts; ++k) s += part[k * stride + e];
-    out[e] = static_cast<float>(s);
+template <typename T>
+void reduce_parts(const T* part, int parts, int64_t stride, int64_t count, float* out, hipStream_t st) {
+    if (count > 0) reduce_parts_kernel<T><<<static_cast<unsigned>(count), 64, 0, st>>>(part, parts, stride, out);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1290,7 +1295,7 @@ void backward_impl(gcin_batch* b, int degree, int precision, const float* P, con
     head_bwd_kernel<HD><<<G, 128, 0, st>>>(P, o, b->pooled, b->hs, dcoeffs, b->ghead, b->ghstride, b->dpooled);
     // head parameters: sum over graphs
     const int64_t nhead = o.total - o.head0;
-    reduce_parts_f32_kernel<<<grid_of(nhead, 256), 256, 0, st>>>(b->ghead, G, b->ghstride, nhead, grads + o.head0);
+    reduce_parts<float>(b->ghead, G, b->ghstride, nhead, grads + o.head0, st);
     float* dHn = nullptr;  // dH of the layer above (for the aggregation backward)
     float* bufs[2] = {b->dHa, b->dHb};
     for (int l = NL - 1; l >= 0; --l) {
@@ -1300,8 +1305,8 @@ void backward_impl(gcin_batch* b, int degree, int precision, const float* P, con
         chunk_sum_kernel<HD, 4><<<b->nchunks, NT, 0, st>>>(b->tb, b->d_cbound, b->cbuf);
         bwd_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->gmean, b->ggb);
         // gamma / beta of this layer
-        reduce_parts_f64_kernel<<<1, HD, 0, st>>>(b->ggb, G, 2 * HD, HD, grads + o.gam[l]);
-        reduce_parts_f64_kernel<<<1, HD, 0, st>>>(b->ggb + HD, G, 2 * HD, HD, grads + o.bet[l]);
+        reduce_parts<double>(b->ggb, G, 2 * HD, HD, grads + o.gam[l], st);
+        reduce_parts<double>(b->ggb + HD, G, 2 * HD, HD, grads + o.bet[l], st);
         float* dHout = l > 0 ? bufs[l & 1] : nullptr;
         const int in_dim = l == 0 ? 2 : HD;
         const float* Hin = l == 0 ? b->H0 : b->H[l];
@@ -1311,9 +1316,8 @@ void backward_impl(gcin_batch* b, int degree, int precision, const float* P, con
             if (precision != GCIN_FP32) kern = bwd_b_kernel<HD, true>;
         kern<<<grid, NT, 0, st>>>(T, b->d_tile_graph, b->d_gend, b->Y[l], b->mu[l], b->rstd[l], b->gmean, b->dxh, Hin,
                                   in_dim, P + o.convW[l], dHout, b->wpart, b->bpart);
-        reduce_parts_f32_kernel<<<grid_of(in_dim * HD, 256), 256, 0, st>>>(b->wpart, grid, HD * HD, in_dim * HD,
-                                                                          grads + o.convW[l]);
-        reduce_parts_f64_kernel<<<1, HD, 0, st>>>(b->bpart, grid, HD, HD, grads + o.convb[l]);
+        reduce_parts<float>(b->wpart, grid, HD * HD, in_dim * HD, grads + o.convW[l], st);
+        reduce_parts<double>(b->bpart, grid, HD, HD, grads + o.convb[l], st);
         dHn = dHout;
     }
 }
