@@ -90,42 +90,67 @@ __device__ __forceinline__ float normrelu(float y, float mu, float rs, float ga,
     return fmaxf((y - mu) * rs * ga + be, 0.0f);
 }
 
-// Aggregation over the stored entries of a wavefront's rows [r0, r1) of the batched graph (the
-// row index is uniform over the wavefront, lane = channel). Entries are visited in stored order,
+// Aggregation over the stored entries of a lane group's rows [r0, r1) of the batched graph (W
+// lanes, one per channel, share the row index; r1 - r0 < W). The group's row bounds are loaded
+// once, one per lane, and read across lanes at each row change, so that the walk over the rows
+// has no dependent global load. Entries are visited in stored order,
 // kAggBatch at a time: the batch's column indices and weights are loaded first, then all of its
 // gathers load(j), so that each wavefront keeps kAggBatch gathers in flight; use(w, v) is then
 // applied in entry order and done(row) is called once per row after its last entry (rows
 // without entries included).
 constexpr int kAggBatch = 16;
 
-template <typename V, class Load, class Use, class Done>
+template <int W, typename V, class Load, class Use, class Done>
 __device__ __forceinline__ void visit_rows(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                            const float* __restrict__ w, int32_t r0, int32_t r1, Load load, Use use,
                                            Done done) {
-    const int32_t kend = ptr[r1];
+    const int32_t rp = ptr[r0 + min(static_cast<int32_t>(threadIdx.x % W), r1 - r0)];
+    // ptr[r0 + i], i <= r1 - r0; with 64-lane groups the value is uniform over the wavefront and
+    // kept in a scalar register, so the entry indices and weights below are scalar loads
+    auto bound = [&](int32_t i) {
+        const int32_t v = __shfl(rp, i, W);
+        if constexpr (W == 64) return __builtin_amdgcn_readfirstlane(v);
+        return v;
+    };
+    const int32_t kend = bound(r1 - r0);
     int32_t r = r0;
-    int32_t rnext = ptr[r0 + 1];
-    for (int32_t k = ptr[r0]; k < kend; k += kAggBatch) {
-        int32_t cj[kAggBatch];
-        float wj[kAggBatch];
-        V vj[kAggBatch];
+    int32_t rnext = bound(1);
+    const int32_t kbeg = bound(0);
+    // the next batch's columns and weights are loaded while this batch's gathers are in flight
+    int32_t cj[kAggBatch];
+    float wj[kAggBatch];
+    if (kbeg < kend) {
 #pragma unroll
         for (int q = 0; q < kAggBatch; ++q) {
-            const int32_t kk = min(k + q, kend - 1);
+            const int32_t kk = min(kbeg + q, kend - 1);
             cj[q] = col[kk];
             wj[q] = w[kk];
         }
+    }
+    for (int32_t k = kbeg; k < kend; k += kAggBatch) {
+        V vj[kAggBatch];
 #pragma unroll
         for (int q = 0; q < kAggBatch; ++q) vj[q] = load(cj[q]);
+        float wcur[kAggBatch];
+#pragma unroll
+        for (int q = 0; q < kAggBatch; ++q) wcur[q] = wj[q];
+        if (k + kAggBatch < kend) {
+#pragma unroll
+            for (int q = 0; q < kAggBatch; ++q) {
+                const int32_t kk = min(k + kAggBatch + q, kend - 1);
+                cj[q] = col[kk];
+                wj[q] = w[kk];
+            }
+        }
 #pragma unroll
         for (int q = 0; q < kAggBatch; ++q) {
             if (k + q < kend) {
                 while (k + q >= rnext) {
                     done(r);
                     ++r;
-                    rnext = ptr[r + 1];
+                    rnext = bound(r + 1 - r0);
                 }
-                use(wj[q], vj[q]);
+                use(wcur[q], vj[q]);
             }
         }
     }
@@ -197,7 +222,7 @@ __global__ __launch_bounds__(4 * HD) void layer0_kernel(const int32_t* __restric
     double s1 = 0.0, s2 = 0.0;
     float h0 = 0.0f, h1 = 0.0f;
     const int32_t r0 = tile * TILE + wv * 16;
-    visit_rows<float2>(
+    visit_rows<HD, float2>(
         ptr, col, w, r0, r0 + 16,
         [&](int32_t j) { return make_float2(x0[2 * j], x0[2 * j + 1]); },
         [&](float wp, float2 v) {
@@ -350,7 +375,7 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
         stage_bf16<HD>(W, true, Bt);
     float h = 0.0f;
     const int32_t r0 = tile * TILE + wv * 16;
-    visit_rows<float>(
+    visit_rows<HD, float>(
         ptr, col, w, r0, r0 + 16, [&](int32_t j) { return Yp[static_cast<int64_t>(j) * HD + c]; },
         [&](float wp, float v) { h += wp * normrelu(v, mu, rs, ga, be); },
         [&](int32_t row) {
@@ -726,7 +751,7 @@ __global__ __launch_bounds__(4 * HD) void bwd_a_kernel(const int32_t* __restrict
     };
     const int32_t r0 = tile * TILE + wv * 16;
     if (dHn)
-        visit_rows<float>(
+        visit_rows<HD, float>(
             ptr, col, w, r0, r0 + 16, [&](int32_t j) { return dHn[static_cast<int64_t>(j) * HD + c]; },
             [&](float wp, float v) { acc += wp * v; }, row_done);
     else

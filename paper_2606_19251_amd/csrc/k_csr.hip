@@ -130,6 +130,56 @@ __device__ __forceinline__ void stream_products(int32_t ne, const T* __restrict_
 }
 static_assert(kStreamCap % (kChunk * kBlock) == 0, "product buffers hold whole rounds");
 
+// Two product streams in the same rounds (out1[k] = m1[k] x[c1[k]], k < n1, and likewise for
+// stream 2): a round issues the value/column loads of both, then the gathers of both, so the
+// two dependent load chains overlap instead of running one after the other. Same products and
+// storage as two stream_products calls.
+template <typename T>
+__device__ __forceinline__ void stream_products_pair(int32_t n1, const T* __restrict__ m1, const int32_t* __restrict__ c1,
+                                                     T* __restrict__ out1, int32_t n2, const T* __restrict__ m2,
+                                                     const int32_t* __restrict__ c2, T* __restrict__ out2,
+                                                     const T* __restrict__ x) {
+    const int32_t n = max(n1, n2);
+    for (int32_t base = 0; base < n; base += kChunk * kBlock) {
+        const bool a = base < n1, b = base < n2;
+        T v1[kChunk], v2[kChunk];
+        int32_t i1[kChunk], i2[kChunk];
+        if (a) {
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) {
+                const int32_t k = min(base + static_cast<int32_t>(threadIdx.x) + q * kBlock, n1 - 1);
+                v1[q] = m1[k];
+                i1[q] = c1[k];
+            }
+        }
+        if (b) {
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) {
+                const int32_t k = min(base + static_cast<int32_t>(threadIdx.x) + q * kBlock, n2 - 1);
+                v2[q] = m2[k];
+                i2[q] = c2[k];
+            }
+        }
+        T p1[kChunk], p2[kChunk];
+        if (a) {
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) p1[q] = v1[q] * x[i1[q]];
+        }
+        if (b) {
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) p2[q] = v2[q] * x[i2[q]];
+        }
+        if (a) {
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) out1[base + static_cast<int32_t>(threadIdx.x) + q * kBlock] = p1[q];
+        }
+        if (b) {
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) out2[base + static_cast<int32_t>(threadIdx.x) + q * kBlock] = p2[q];
+        }
+    }
+}
+
 // Sum of buf[pb..pe) from left to right (the order of the stored row); the LDS reads are
 // issued four at a time ahead of the dependent additions.
 template <typename T>
@@ -400,8 +450,7 @@ __global__ __launch_bounds__(kBlock) void csr_halo_kernel(int32_t nrows, const i
         }
     }
     // phase 1: z on the own rows and the halo rows
-    if (fits) stream_products<T>(ne, m1 + e0, col + e0, x, nullptr, prod);
-    stream_products<T>(nhe, hm1 + he0, h.hcol + he0, x, nullptr, hprod);
+    stream_products_pair<T>(fits ? ne : 0, m1 + e0, col + e0, prod, nhe, hm1 + he0, h.hcol + he0, hprod, x);
     __syncthreads();
     if (mine) {
         T s = T(0);
