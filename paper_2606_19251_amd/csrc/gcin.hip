@@ -482,10 +482,17 @@ __global__ __launch_bounds__(4 * HD) void pool_tile_kernel(const int32_t* __rest
     double s = 0.0;
     float mx = -INFINITY;
     int32_t am = INT32_MAX;
+    float yv[16];  // the 16 rows' loads are issued together
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int32_t row = tile * TILE + wv * 16 + r;
+        yv[r] = row < end ? Y[static_cast<int64_t>(row) * HD + c] : 0.0f;
+    }
+#pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int32_t row = tile * TILE + wv * 16 + r;
         if (row < end) {
-            const float x = normrelu(Y[static_cast<int64_t>(row) * HD + c], m, rs, ga, be);
+            const float x = normrelu(yv[r], m, rs, ga, be);
             s += x;
             if (x > mx) {
                 mx = x;
@@ -731,13 +738,33 @@ __global__ __launch_bounds__(4 * HD) void bwd_a_kernel(const int32_t* __restrict
     const float dmean = dpooled[(g * NL + layer) * 2 * HD + c] / gcnt[g];
     const float dmax = dpooled[(g * NL + layer) * 2 * HD + HD + c];
     const int32_t am = argmax[(g * NL + layer) * HD + c];
+    __shared__ float aggs[TILE][HD];  // per row: sum of w * dH of the layer above (A_hat^T = A_hat)
     double sa = 0.0, sb = 0.0, sg = 0.0, sbe = 0.0;
-    float acc = 0.0f;  // sum over the row of w * dH of the layer above (A_hat^T = A_hat)
-    auto row_done = [&](int32_t row) {
+    const int32_t r0 = tile * TILE + wv * 16;
+    float yv[16];  // this wavefront's rows of Y, loaded together while the aggregation runs
+#pragma unroll
+    for (int r = 0; r < 16; ++r) yv[r] = r0 + r < end ? Y[static_cast<int64_t>(r0 + r) * HD + c] : 0.0f;
+    float acc = 0.0f;
+    if (dHn) {
+        visit_rows<HD, float>(
+            ptr, col, w, r0, r0 + 16, [&](int32_t j) { return dHn[static_cast<int64_t>(j) * HD + c]; },
+            [&](float wp, float v) { acc += wp * v; },
+            [&](int32_t row) {
+                aggs[row - tile * TILE][c] = acc;
+                acc = 0.0f;
+            });
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) aggs[wv * 16 + r][c] = 0.0f;
+    }
+    // each lane reads back only what it wrote (same wavefront, same channel): no barrier needed
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int32_t row = r0 + r;
         float d = 0.0f;
         if (row < end) {
-            const float dx = dmean + (row == am ? dmax : 0.0f) + acc;
-            const float xh = (Y[static_cast<int64_t>(row) * HD + c] - m) * rs;
+            const float dx = dmean + (row == am ? dmax : 0.0f) + aggs[wv * 16 + r][c];
+            const float xh = (yv[r] - m) * rs;
             const float xn = xh * ga + be;
             const float dxn = xn > 0.0f ? dx : 0.0f;
             d = dxn * ga;
@@ -747,15 +774,7 @@ __global__ __launch_bounds__(4 * HD) void bwd_a_kernel(const int32_t* __restrict
             sbe += dxn;
         }
         dxh[static_cast<int64_t>(row) * HD + c] = d;
-        acc = 0.0f;
-    };
-    const int32_t r0 = tile * TILE + wv * 16;
-    if (dHn)
-        visit_rows<HD, float>(
-            ptr, col, w, r0, r0 + 16, [&](int32_t j) { return dHn[static_cast<int64_t>(j) * HD + c]; },
-            [&](float wp, float v) { acc += wp * v; }, row_done);
-    else
-        for (int32_t row = r0; row < r0 + 16; ++row) row_done(row);
+    }
     sa = wave4_sum(sa, sh);
     sb = wave4_sum(sb, sh);
     sg = wave4_sum(sg, sh);
@@ -823,19 +842,31 @@ __global__ __launch_bounds__(4 * HD) void bwd_b_kernel(int ntiles, const int32_t
         const int32_t end = gend[g];
         const float m = mu[g * HD + c], rs = rstd[g * HD + c];
         const float ma = gmean[g * 2 * HD + c], mb = gmean[g * 2 * HD + HD + c];
-        for (int r = 0; r < 16; ++r) {
-            const int lr = wv * 16 + r;
-            const int32_t row = tile * TILE + lr;
-            float dy = 0.0f, h = 0.0f;
-            if (row < end) {
+        // eight rows at a time, their loads issued together
+        for (int r8 = 0; r8 < 16; r8 += 8) {
+            float yv[8], dv[8], hv[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int32_t row = tile * TILE + wv * 16 + r8 + r;
                 const int64_t k = static_cast<int64_t>(row) * HD + c;
-                const float xh = (Y[k] - m) * rs;
-                dy = rs * (dxh[k] - ma - xh * mb);
-                if (c < in_dim) h = H[static_cast<int64_t>(row) * in_dim + c];
+                const bool ok = row < end;
+                yv[r] = ok ? Y[k] : 0.0f;
+                dv[r] = ok ? dxh[k] : 0.0f;
+                hv[r] = ok && c < in_dim ? H[static_cast<int64_t>(row) * in_dim + c] : 0.0f;
             }
-            dYs[lr][c] = dy;
-            Hs[lr][c] = h;
-            accb += dy;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int lr = wv * 16 + r8 + r;
+                const int32_t row = tile * TILE + lr;
+                float dy = 0.0f;
+                if (row < end) {
+                    const float xh = (yv[r] - m) * rs;
+                    dy = rs * (dv[r] - ma - xh * mb);
+                }
+                dYs[lr][c] = dy;
+                Hs[lr][c] = hv[r];
+                accb += dy;
+            }
         }
         __syncthreads();
         // dW[k][c'] += sum_rows H[row][k] dY[row][c']
