@@ -57,23 +57,47 @@ __device__ __forceinline__ void adj_smooth_row(int32_t i, const int32_t* __restr
                                                T* __restrict__ t, int deg, double* g) {
     const double ui = static_cast<double>(ubar[i]);
     const double aii = diag[i];
+    const int32_t pb = ptr[i], pe = ptr[i + 1];
     T acc = T(0);
-    for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p) {
-        const int32_t j = col[p];
-        acc += q[p] * ubar[j];
-        const double a = val[p];
-        const double x = a / s;
-        if (j == i) {
-            double w = ui * static_cast<double>(r[i]) / aii;
-            for (int m = 0; m <= deg; ++m) {
-                g[m] += w;
-                w *= x;
-            }
-        } else {
-            double w = ui * static_cast<double>(r[j]) / (aii + diag[j]) * x;
-            for (int m = 1; m <= deg; ++m) {
-                g[deg + m] += w;
-                w *= x;
+    // eight entries at a time: their columns and values, then the gathers at the neighbours, are
+    // loaded together; the sums still run over the entries in stored order (a past-the-end slot
+    // re-reads the row's last entry and is not used)
+    constexpr int kE = 8;
+    for (int32_t base = pb; base < pe; base += kE) {
+        int32_t jv[kE];
+        T qv[kE], uj[kE], rj[kE];
+        double av[kE], dj[kE];
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            const int32_t p = min(base + e, pe - 1);
+            jv[e] = col[p];
+            qv[e] = q[p];
+            av[e] = val[p];
+        }
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            uj[e] = ubar[jv[e]];
+            rj[e] = r[jv[e]];
+            dj[e] = diag[jv[e]];
+        }
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            if (base + e >= pe) break;
+            const int32_t j = jv[e];
+            acc += qv[e] * uj[e];
+            const double x = av[e] / s;
+            if (j == i) {
+                double w = ui * static_cast<double>(rj[e]) / aii;
+                for (int m = 0; m <= deg; ++m) {
+                    g[m] += w;
+                    w *= x;
+                }
+            } else {
+                double w = ui * static_cast<double>(rj[e]) / (aii + dj[e]) * x;
+                for (int m = 1; m <= deg; ++m) {
+                    g[deg + m] += w;
+                    w *= x;
+                }
             }
         }
     }

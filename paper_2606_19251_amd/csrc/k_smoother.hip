@@ -35,20 +35,38 @@ __device__ __forceinline__ void assemble_row(int32_t i, const int32_t* __restric
                                              double* __restrict__ qd64, float* __restrict__ qd32) {
 #pragma clang fp contract(off)
     const double aii = diag[i];
-    for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p) {
-        const int32_t j = col[p];
-        const double a = val[p];
-        const double x = a / s;
-        double q;
-        if (j == i) {
-            q = horner_diag(x, c, deg) / a;
-            qd64[i] = q;
-            qd32[i] = static_cast<float>(q);
-        } else {
-            q = horner_off(x, c + deg + 1, deg) / (aii + diag[j]);
+    const int32_t pb = ptr[i], pe = ptr[i + 1];
+    // eight entries at a time: their columns and values, then the neighbours' diagonals, are
+    // loaded together (a past-the-end slot re-reads the row's last entry and is not stored)
+    constexpr int kE = 8;
+    for (int32_t base = pb; base < pe; base += kE) {
+        int32_t j[kE];
+        double a[kE], dj[kE];
+#pragma unroll
+        for (int q = 0; q < kE; ++q) {
+            const int32_t p = min(base + q, pe - 1);
+            j[q] = col[p];
+            a[q] = val[p];
         }
-        q64[p] = q;
-        q32[p] = static_cast<float>(q);
+#pragma unroll
+        for (int q = 0; q < kE; ++q) dj[q] = diag[j[q]];
+#pragma unroll
+        for (int q = 0; q < kE; ++q) {
+            const int32_t p = base + q;
+            if (p < pe) {
+                const double x = a[q] / s;
+                double v;
+                if (j[q] == i) {
+                    v = horner_diag(x, c, deg) / a[q];
+                    qd64[i] = v;
+                    qd32[i] = static_cast<float>(v);
+                } else {
+                    v = horner_off(x, c + deg + 1, deg) / (aii + dj[q]);
+                }
+                q64[p] = v;
+                q32[p] = static_cast<float>(v);
+            }
+        }
     }
 }
 
