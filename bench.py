@@ -82,8 +82,8 @@ def outer_bytes_fcg(n: int, nnz: int) -> float:
 # as null once that source changes (summaries under profiles/).
 TRAFFIC_SOURCE = "paper_2606_19251_amd/csrc/k_csr.hip"
 TRAFFIC = {  # workload -> (sha256 prefix of TRAFFIC_SOURCE, bytes per launch)
-    "delaunay1m": ("0a5b7f02c26dffaa", 72729049),
-    "tet8m": ("0a5b7f02c26dffaa", 462842842),
+    "delaunay1m": ("dd7fe8afb557d84a", 72728662),
+    "tet8m": ("dd7fe8afb557d84a", 462812930),
 }
 
 
@@ -112,6 +112,24 @@ def time_kernel(torch, launch_timed, stream, reps=50):
     per = [s.elapsed_time(e) for s, e in pairs]
     interval = pairs[0][0].elapsed_time(pairs[-1][1]) / reps
     return sum(per) / reps, interval
+
+
+def copy_rate_gbs(torch, dev, mib=512, reps=20):
+    """Device-to-device copy rate of a plain `mib` MiB buffer (bytes read + written per second,
+    GB/s): the practical streaming ceiling of this GPU, reported beside the nominal HBM peak."""
+    a = torch.empty(mib * 2**20 // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del a, b
+    return 2 * mib * 2**20 / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(A, f, gpu_iters, budget_s=20.0):
@@ -288,11 +306,13 @@ class Case:
         rows = 256 if z0 / n0 * 256 * 1.25 <= 4096 else 128
         k_bytes = z0 * 8 + 4 * (n0 + 1) + 3 * n0 * 4
         achieved = k_bytes / (k_ms * 1e-3) / 1e9
+        copy = copy_rate_gbs(torch, self.dev)
         return {"kernel": f"csr_stream_kernel<float, Resid, {rows}, 0> (fine level r = f - A u, FP32, {self.name})",
                 "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(self.name),
                 "launch_ms": round(k_ms, 5), "launch_interval_ms": round(k_interval_ms, 5),
-                "algorithmic_bytes": int(k_bytes)}
+                "algorithmic_bytes": int(k_bytes), "copy_gbs": round(copy, 1),
+                "frac_of_copy": round(achieved / copy, 4)}
 
 
 def training_step(torch, steps=10, warmup=3):

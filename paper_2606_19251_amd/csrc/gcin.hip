@@ -222,27 +222,57 @@ __global__ __launch_bounds__(4 * HD) void layer0_kernel(const int32_t* __restric
     double s1 = 0.0, s2 = 0.0;
     float h0 = 0.0f, h1 = 0.0f;
     const int32_t r0 = tile * TILE + wv * 16;
-    visit_rows<HD, float2>(
-        ptr, col, w, r0, r0 + 16,
-        [&](int32_t j) { return make_float2(x0[2 * j], x0[2 * j + 1]); },
-        [&](float wp, float2 v) {
-            h0 += wp * v.x;
-            h1 += wp * v.y;
-        },
-        [&](int32_t row) {
-            float y = 0.0f;
-            if (row < end) {
-                y = bb + h0 * w0 + h1 * w1;
-                if (c == 0) {
-                    H0[2 * row] = h0;
-                    H0[2 * row + 1] = h1;
-                }
-                s1 += y;
-                s2 += static_cast<double>(y) * y;
+    auto done = [&](int32_t row) {
+        float y = 0.0f;
+        if (row < end) {
+            y = bb + h0 * w0 + h1 * w1;
+            if (c == 0) {
+                H0[2 * row] = h0;
+                H0[2 * row + 1] = h1;
             }
-            Y[static_cast<int64_t>(row) * HD + c] = y;
-            h0 = h1 = 0.0f;
-        });
+            s1 += y;
+            s2 += static_cast<double>(y) * y;
+        }
+        Y[static_cast<int64_t>(row) * HD + c] = y;
+        h0 = h1 = 0.0f;
+    };
+    if constexpr (HD == 64) {
+        // The input features are two numbers per node, the same for every channel: lane l loads
+        // entry k + l of a round of 64 (column, weight and the neighbour's two features) and
+        // the wavefront reads them lane by lane, in stored order.
+        const int32_t rp = ptr[r0 + min(c, 16)];
+        auto bound = [&](int32_t i) { return __builtin_amdgcn_readfirstlane(__shfl(rp, i, 64)); };
+        const int32_t kbeg = bound(0), kend = bound(16);
+        int32_t r = r0, rnext = bound(1);
+        for (int32_t k = kbeg; k < kend; k += 64) {
+            const int32_t kk = min(k + c, kend - 1);
+            const float wl = w[kk];
+            const int32_t j = col[kk];
+            const float2 xv = *reinterpret_cast<const float2*>(x0 + 2 * static_cast<int64_t>(j));
+            const int32_t cnt = min(64, kend - k);
+            for (int32_t q = 0; q < cnt; ++q) {
+                while (k + q >= rnext) {
+                    done(r);
+                    ++r;
+                    rnext = bound(r + 1 - r0);
+                }
+                const float wq = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wl), q));
+                const float xq = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, xv.x), q));
+                const float yq = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, xv.y), q));
+                h0 += wq * xq;
+                h1 += wq * yq;
+            }
+        }
+        for (; r < r0 + 16; ++r) done(r);
+    } else {
+        visit_rows<HD, float2>(
+            ptr, col, w, r0, r0 + 16, [&](int32_t j) { return make_float2(x0[2 * j], x0[2 * j + 1]); },
+            [&](float wp, float2 v) {
+                h0 += wp * v.x;
+                h1 += wp * v.y;
+            },
+            done);
+    }
     s1 = wave4_sum(s1, sh);
     s2 = wave4_sum(s2, sh);
     if (wv == 0) {
