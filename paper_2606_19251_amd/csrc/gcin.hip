@@ -93,21 +93,22 @@ __device__ __forceinline__ float normrelu(float y, float mu, float rs, float ga,
 // Aggregation over the stored entries of a lane group's rows [r0, r1) of the batched graph (W
 // lanes, one per channel, share the row index; r1 - r0 < W). The group's row bounds are loaded
 // once, one per lane, and read across lanes at each row change, so that the walk over the rows
-// has no dependent global load. Entries are visited in stored order,
-// kAggBatch at a time: the batch's column indices and weights are loaded first, then all of its
-// gathers load(j), so that each wavefront keeps kAggBatch gathers in flight; use(w, v) is then
-// applied in entry order and done(row) is called once per row after its last entry (rows
-// without entries included).
+// has no dependent global load. Entries are visited in stored order, kAggBatch at a time: the
+// batch's gathers load(j) are issued together (each wavefront keeps kAggBatch of them in flight)
+// while the next batch's column indices and weights load; use(w, v) is then applied in entry
+// order and done(row) is called once per row after its last entry (rows without entries
+// included). With 64-lane groups the indices are uniform over the wavefront and held in scalar
+// registers; a 32-lane group (two per wavefront, on different rows) spreads its batch over its
+// lanes, lane l holding entry l, and reads the entries across lanes.
 constexpr int kAggBatch = 16;
 
 template <int W, typename V, class Load, class Use, class Done>
 __device__ __forceinline__ void visit_rows(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                            const float* __restrict__ w, int32_t r0, int32_t r1, Load load, Use use,
                                            Done done) {
+    static_assert(W == 64 || W == 32, "lane groups of 64 or 32");
     const int32_t rp = ptr[r0 + min(static_cast<int32_t>(threadIdx.x % W), r1 - r0)];
-    // ptr[r0 + i], i <= r1 - r0; with 64-lane groups the value is uniform over the wavefront and
-    // kept in a scalar register, so the entry indices and weights below are scalar loads
-    auto bound = [&](int32_t i) {
+    auto bound = [&](int32_t i) {  // ptr[r0 + i], i <= r1 - r0
         const int32_t v = __shfl(rp, i, W);
         if constexpr (W == 64) return __builtin_amdgcn_readfirstlane(v);
         return v;
@@ -116,42 +117,66 @@ __device__ __forceinline__ void visit_rows(const int32_t* __restrict__ ptr, cons
     int32_t r = r0;
     int32_t rnext = bound(1);
     const int32_t kbeg = bound(0);
-    // the next batch's columns and weights are loaded while this batch's gathers are in flight
-    int32_t cj[kAggBatch];
-    float wj[kAggBatch];
-    if (kbeg < kend) {
-#pragma unroll
-        for (int q = 0; q < kAggBatch; ++q) {
-            const int32_t kk = min(kbeg + q, kend - 1);
-            cj[q] = col[kk];
-            wj[q] = w[kk];
+    auto walk = [&](int32_t k, int q, float wq, const V& v) {
+        if (k + q < kend) {
+            while (k + q >= rnext) {
+                done(r);
+                ++r;
+                rnext = bound(r + 1 - r0);
+            }
+            use(wq, v);
         }
-    }
-    for (int32_t k = kbeg; k < kend; k += kAggBatch) {
-        V vj[kAggBatch];
-#pragma unroll
-        for (int q = 0; q < kAggBatch; ++q) vj[q] = load(cj[q]);
-        float wcur[kAggBatch];
-#pragma unroll
-        for (int q = 0; q < kAggBatch; ++q) wcur[q] = wj[q];
-        if (k + kAggBatch < kend) {
+    };
+    if constexpr (W == 64) {
+        int32_t cj[kAggBatch];
+        float wj[kAggBatch];
+        if (kbeg < kend) {
 #pragma unroll
             for (int q = 0; q < kAggBatch; ++q) {
-                const int32_t kk = min(k + kAggBatch + q, kend - 1);
+                const int32_t kk = min(kbeg + q, kend - 1);
                 cj[q] = col[kk];
                 wj[q] = w[kk];
             }
         }
+        for (int32_t k = kbeg; k < kend; k += kAggBatch) {
+            V vj[kAggBatch];
 #pragma unroll
-        for (int q = 0; q < kAggBatch; ++q) {
-            if (k + q < kend) {
-                while (k + q >= rnext) {
-                    done(r);
-                    ++r;
-                    rnext = bound(r + 1 - r0);
+            for (int q = 0; q < kAggBatch; ++q) vj[q] = load(cj[q]);
+            float wcur[kAggBatch];
+#pragma unroll
+            for (int q = 0; q < kAggBatch; ++q) wcur[q] = wj[q];
+            if (k + kAggBatch < kend) {
+#pragma unroll
+                for (int q = 0; q < kAggBatch; ++q) {
+                    const int32_t kk = min(k + kAggBatch + q, kend - 1);
+                    cj[q] = col[kk];
+                    wj[q] = w[kk];
                 }
-                use(wcur[q], vj[q]);
             }
+#pragma unroll
+            for (int q = 0; q < kAggBatch; ++q) walk(k, q, wcur[q], vj[q]);
+        }
+    } else {
+        const int32_t l = static_cast<int32_t>(threadIdx.x % W) % kAggBatch;
+        int32_t cl = 0;
+        float wl = 0.0f;
+        if (kbeg < kend) {
+            const int32_t kk = min(kbeg + l, kend - 1);
+            cl = col[kk];
+            wl = w[kk];
+        }
+        for (int32_t k = kbeg; k < kend; k += kAggBatch) {
+            V vj[kAggBatch];
+#pragma unroll
+            for (int q = 0; q < kAggBatch; ++q) vj[q] = load(__shfl(cl, q, W));
+            const float wcur = wl;
+            if (k + kAggBatch < kend) {
+                const int32_t kk = min(k + kAggBatch + l, kend - 1);
+                cl = col[kk];
+                wl = w[kk];
+            }
+#pragma unroll
+            for (int q = 0; q < kAggBatch; ++q) walk(k, q, __shfl(wcur, q, W), vj[q]);
         }
     }
     for (; r < r1; ++r) done(r);
