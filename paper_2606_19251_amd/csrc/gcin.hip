@@ -480,7 +480,21 @@ __global__ __launch_bounds__(4 * HD) void chunk_sum_kernel(const double* __restr
     double s[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) s[j] = 0.0;
-    for (int32_t i = bounds[k] + wv; i < bounds[k + 1]; i += 4)
+    // items wv, wv + 4, ... in order; four items' loads are issued ahead of their additions
+    const int32_t i1 = bounds[k + 1];
+    int32_t i = bounds[k] + wv;
+    for (; i + 12 < i1; i += 16) {
+        double v[4][K];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int j = 0; j < K; ++j) v[u][j] = in[(static_cast<int64_t>(i + 4 * u) * K + j) * HD + c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int j = 0; j < K; ++j) s[j] += v[u][j];
+    }
+    for (; i < i1; i += 4)
 #pragma unroll
         for (int j = 0; j < K; ++j) s[j] += in[(static_cast<int64_t>(i) * K + j) * HD + c];
 #pragma unroll
@@ -591,7 +605,27 @@ __global__ __launch_bounds__(4 * HD) void pool_chunk_kernel(const double* __rest
     double s = 0.0;
     float mx = -INFINITY;
     int32_t am = INT32_MAX;
-    for (int32_t t = bounds[k] + wv; t < bounds[k + 1]; t += 4) {
+    // tiles wv, wv + 4, ... in order; four tiles' loads are issued ahead of their use
+    const int32_t t1 = bounds[k + 1];
+    int32_t t = bounds[k] + wv;
+    for (; t + 12 < t1; t += 16) {
+        double vs[4];
+        float vm[4];
+        int32_t va[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t e = static_cast<int64_t>(t + 4 * u) * HD + c;
+            vs[u] = tsum[e];
+            vm[u] = tmax[e];
+            va[u] = targ[e];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            s += vs[u];
+            max_merge(mx, am, vm[u], va[u]);
+        }
+    }
+    for (; t < t1; t += 4) {
         s += tsum[static_cast<int64_t>(t) * HD + c];
         max_merge(mx, am, tmax[static_cast<int64_t>(t) * HD + c], targ[static_cast<int64_t>(t) * HD + c]);
     }
