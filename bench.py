@@ -132,7 +132,37 @@ def copy_rate_gbs(torch, dev, mib=512, reps=20):
     return 2 * mib * 2**20 / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(A, f, gpu_iters, budget_s=20.0):
+_TP = {}  # hierarchy and sample size shared with the forked throughput workers
+
+
+def _throughput_worker(_):
+    from threadpoolctl import threadpool_limits
+
+    from oracle import amg
+
+    with threadpool_limits(limits=1):
+        t0 = time.time()
+        res = amg.solve_fcg(_TP["h"], _TP["Qs"], _TP["f"], tol=1e-8, maxit=_TP["iters"])
+        return time.time() - t0, res.iterations
+
+
+def cpu_throughput(h, Qs, fn, gpu_iters, iters, procs):
+    """`procs` single-threaded oracle solves of the same bounded sample at once (forked workers
+    sharing the hierarchy): host solves per second when every process solves its own system."""
+    import multiprocessing as mp
+
+    _TP.update(h=h, Qs=Qs, f=fn, iters=iters)
+    with mp.get_context("fork").Pool(procs) as pool:
+        out = pool.map(_throughput_worker, range(procs), chunksize=1)
+    _TP.clear()
+    wall = max(t for t, _ in out)
+    done = min(k for _, k in out)
+    per_solve = wall * gpu_iters / max(done, 1)
+    return {"solves_per_s": round(procs / per_solve, 3), "processes": procs, "threads_per_process": 1,
+            "sample": f"{done} iterations per process, slowest process {wall:.1f} s, scaled to {gpu_iters} iterations"}
+
+
+def cpu_baseline(A, f, gpu_iters, budget_s=20.0, throughput_procs=0):
     """The oracle's FP64 flexible-CG solve timed on the host for a bounded number of iterations
     (one thread; the smoother has A's pattern whatever its coefficients, so the cost per
     iteration is that of the GCIN-smoothed solve too)."""
@@ -155,7 +185,12 @@ def cpu_baseline(A, f, gpu_iters, budget_s=20.0):
         res = amg.solve_fcg(h, Qs, fn, tol=1e-8, maxit=iters)
         el = time.time() - t0
     per_iter = el / max(res.iterations, 1)
+    extra = {}
+    if throughput_procs > 0:
+        extra["throughput"] = cpu_throughput(h, Qs, fn, gpu_iters, res.iterations, throughput_procs)
+        log(f"oracle throughput: {extra['throughput']}")
     return {
+        **extra,
         "value": per_iter * gpu_iters * 1e3,
         "unit": "ms",
         "cores": 1,
@@ -270,13 +305,15 @@ class Case:
         for _ in range(warmup):
             self.ds.solve(self.b, self.x, **kw)
         torch.cuda.synchronize()
-        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        s.record()
-        for _ in range(steps):
+        pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for s, e in pairs:
+            s.record()
             _, rc, info, _ = self.ds.solve(self.b, self.x, **kw)
-        e.record()
+            e.record()
         torch.cuda.synchronize()
-        ms = s.elapsed_time(e) / steps
+        per = [s.elapsed_time(e) for s, e in pairs]
+        ms = sum(per) / steps
+        median = float(np.median(per))
         # residual recomputed in FP64 on the host from the returned x
         xh = self.x.cpu().numpy()
         fb = self.f - self.f.mean() if self.hh.singular else self.f
@@ -284,8 +321,8 @@ class Case:
         tag = "FCG" if outer == capi.AMGG_OUTER_FCG else "IR"
         log(f"{self.name} {smoother} {tag}: {ms:.3f} ms/solve, {info.vcycles} V-cycles, rc={rc}, "
             f"fell_back={info.fell_back}, rel={true_rel:.2e}")
-        return {"ms": round(ms, 4), "vcycles": info.vcycles, "iterations": info.iterations, "status": rc,
-                "fell_back": info.fell_back, "relres": true_rel}
+        return {"ms": round(ms, 4), "ms_median": round(median, 4), "vcycles": info.vcycles,
+                "iterations": info.iterations, "status": rc, "fell_back": info.fell_back, "relres": true_rel}
 
     def roofline(self):
         """Fine-level FP32 residual r = f - A u: algorithmic bytes / kernel time from HIP events
@@ -407,6 +444,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=list(WORKLOADS), default="delaunay1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-throughput", type=int, default=0, metavar="P",
+                    help="also time P single-threaded oracle solves at once (host solves/s)")
     ap.add_argument("--no-training", action="store_true", help="skip the training-step timing")
     ap.add_argument("--no-structured", action="store_true",
                     help="skip the structured-grid comparison (32-channel GCIN) that follows the default workload")
@@ -493,13 +532,20 @@ def main():
         "gnn": gnn,
         "gnn_over_jacobi_time": round(gnn["ms"] / jac["ms"], 4),
         "ir": ir_res,
+        # solves after which the GCIN setup (first prediction + smoother assembly) is paid back
+        # by faster solves; null where the GCIN-smoothed solve is not the faster one
+        "gnn_setup_break_even_solves": {
+            "fcg": round(gnn["setup_ms"] / (jac["ms"] - gnn["ms"]), 1) if jac["ms"] > gnn["ms"] else None,
+            "ir": (round(gnn["setup_ms"] / (ir_res["jacobi"]["ms"] - ir_res["gnn"]["ms"]), 1)
+                   if ir_res["jacobi"]["ms"] > ir_res["gnn"]["ms"] else None)},
         "vcycle_bytes": int(vbytes),
         "solve_gbs_algorithmic": round(solve_gbs, 1),
         "setup": case.setup,
         "roofline": roof,
     }
     if args.workload == "delaunay1m" and not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case.A, case.f, gnn["iterations"])
+        out["cpu_baseline"] = cpu_baseline(case.A, case.f, gnn["iterations"],
+                                           throughput_procs=args.cpu_throughput)
     ds.close()
     if args.workload == "delaunay1m" and not args.no_training:
         out["training"] = training_step(torch)
