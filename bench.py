@@ -288,7 +288,18 @@ class Case:
         self.coeffs = self.pred.predict(self.hh, self.ds)
         e.record()
         torch.cuda.synchronize()
-        self.gnn_setup_ms = s.elapsed_time(e)
+        # first prediction on a new hierarchy: graph batch construction (its workspace allocated
+        # the first time) and the GCIN forward
+        self.gnn_setup_first_ms = s.elapsed_time(e)
+        # setup of a further matrix in the same process: graph batch, GCIN forward and smoother
+        # assembly (the paper's GNN inference + pseudo-inverse construction)
+        s.record()
+        for _ in range(3):
+            self.coeffs = self.pred.predict(self.hh, self.ds)
+            self.ds.set_coeffs_device(self.coeffs, self.pred.degree)
+        e.record()
+        torch.cuda.synchronize()
+        self.gnn_setup_ms = s.elapsed_time(e) / 3
 
     def set(self, smoother):
         if smoother == "jacobi":
@@ -504,7 +515,8 @@ def main():
     jac = case.solves("jacobi", fcg, args.steps, args.warmup, args.nu)
     gnn = case.solves("gnn", fcg, args.steps, args.warmup, args.nu)
     gnn["setup_ms"] = round(case.gnn_setup_ms, 3)
-    ir_res = {"jacobi": case.solves("jacobi", ir, 2, 1, args.nu), "gnn": case.solves("gnn", ir, 2, 1, args.nu)}
+    gnn["setup_first_ms"] = round(case.gnn_setup_first_ms, 3)
+    ir_res = {"jacobi": case.solves("jacobi", ir, 5, 1, args.nu), "gnn": case.solves("gnn", ir, 5, 1, args.nu)}
 
     n0, z0 = hh.levels[0].n, hh.levels[0].nnz
     vbytes = level_bytes_vcycle(hh, smoother_sparse=True)
@@ -532,7 +544,7 @@ def main():
         "gnn": gnn,
         "gnn_over_jacobi_time": round(gnn["ms"] / jac["ms"], 4),
         "ir": ir_res,
-        # solves after which the GCIN setup (first prediction + smoother assembly) is paid back
+        # solves after which the GCIN setup (prediction + smoother assembly) is paid back
         # by faster solves; null where the GCIN-smoothed solve is not the faster one
         "gnn_setup_break_even_solves": {
             "fcg": round(gnn["setup_ms"] / (jac["ms"] - gnn["ms"]), 1) if jac["ms"] > gnn["ms"] else None,
