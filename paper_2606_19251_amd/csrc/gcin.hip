@@ -417,9 +417,11 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
     // a CU's LDS.
     __shared__ float Hs[TILE][HD + 1];
     float (*Ds)[HD + 1] = Hs;
-    __shared__ unsigned short Bt[HD][HD + 8];
+    // the statistics buffer reuses the weight tile, which is no longer read after the product
+    __shared__ __align__(16) unsigned short Bt[HD][HD + 8];
+    static_assert(sizeof(Bt) >= 4 * HD * sizeof(double), "statistics buffer fits the weight tile");
+    double (*sh)[HD] = reinterpret_cast<double (*)[HD]>(&Bt[0][0]);
     __shared__ unsigned short Btlo[X3 ? HD : 1][HD + 8];
-    __shared__ double sh[4][HD];
     const int tile = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
     const int g = tile_graph[tile];
     const int32_t end = gend[g];
