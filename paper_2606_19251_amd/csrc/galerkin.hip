@@ -508,7 +508,7 @@ extern "C" int amgg_galerkin_device(int device, int32_t n, int32_t nc, const int
             *ac_nnz = Ac.nnz;
             return AMGG_OK;
         } catch (const Failure& f) {
-            hipStreamSynchronize(st);
+            (void)hipStreamSynchronize(st);  // the failure is what is reported
             return fail(f.code, f.msg);
         }
     });
