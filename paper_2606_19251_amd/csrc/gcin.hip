@@ -93,13 +93,13 @@ __device__ __forceinline__ float normrelu(float y, float mu, float rs, float ga,
 // Aggregation over the stored entries of a lane group's rows [r0, r1) of the batched graph (W
 // lanes, one per channel, share the row index; r1 - r0 < W). The group's row bounds are loaded
 // once, one per lane, and read across lanes at each row change, so that the walk over the rows
-// has no dependent global load. Entries are visited in stored order, kAggBatch at a time: the
-// batch's gathers load(j) are issued together (each wavefront keeps kAggBatch of them in flight)
-// while the next batch's column indices and weights load; use(w, v) is then applied in entry
-// order and done(row) is called once per row after its last entry (rows without entries
-// included). With 64-lane groups the indices are uniform over the wavefront and held in scalar
-// registers; a 32-lane group (two per wavefront, on different rows) spreads its batch over its
-// lanes, lane l holding entry l, and reads the entries across lanes.
+// has no dependent global load. Entries are visited in stored order, a batch at a time: the
+// batch's column indices and weights are spread over the group's lanes (lane l holds entry l),
+// its gathers load(j) are issued together while the next batch's indices load, and use(w, v)
+// is then applied in entry order, each entry's index and weight read across lanes; done(row) is
+// called once per row after its last entry (rows without entries included). A 64-lane group
+// owns its wavefront, so the indices it reads are uniform (scalar registers) and it takes 32
+// entries per batch; a 32-lane group (two per wavefront, on different rows) takes kAggBatch.
 constexpr int kAggBatch = 16;
 
 template <int W, typename V, class Load, class Use, class Done>
@@ -128,33 +128,28 @@ __device__ __forceinline__ void visit_rows(const int32_t* __restrict__ ptr, cons
         }
     };
     if constexpr (W == 64) {
-        int32_t cj[kAggBatch];
-        float wj[kAggBatch];
+        constexpr int B = 2 * kAggBatch;  // 32 gathers in flight per wavefront
+        const int32_t l = static_cast<int32_t>(threadIdx.x % 64) % B;
+        int32_t cl = 0;
+        float wl = 0.0f;
         if (kbeg < kend) {
-#pragma unroll
-            for (int q = 0; q < kAggBatch; ++q) {
-                const int32_t kk = min(kbeg + q, kend - 1);
-                cj[q] = col[kk];
-                wj[q] = w[kk];
-            }
+            const int32_t kk = min(kbeg + l, kend - 1);
+            cl = col[kk];
+            wl = w[kk];
         }
-        for (int32_t k = kbeg; k < kend; k += kAggBatch) {
-            V vj[kAggBatch];
+        for (int32_t k = kbeg; k < kend; k += B) {
+            V vj[B];
 #pragma unroll
-            for (int q = 0; q < kAggBatch; ++q) vj[q] = load(cj[q]);
-            float wcur[kAggBatch];
-#pragma unroll
-            for (int q = 0; q < kAggBatch; ++q) wcur[q] = wj[q];
-            if (k + kAggBatch < kend) {
-#pragma unroll
-                for (int q = 0; q < kAggBatch; ++q) {
-                    const int32_t kk = min(k + kAggBatch + q, kend - 1);
-                    cj[q] = col[kk];
-                    wj[q] = w[kk];
-                }
+            for (int q = 0; q < B; ++q) vj[q] = load(__builtin_amdgcn_readlane(cl, q));
+            const float wcur = wl;
+            if (k + B < kend) {
+                const int32_t kk = min(k + B + l, kend - 1);
+                cl = col[kk];
+                wl = w[kk];
             }
 #pragma unroll
-            for (int q = 0; q < kAggBatch; ++q) walk(k, q, wcur[q], vj[q]);
+            for (int q = 0; q < B; ++q)
+                walk(k, q, __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wcur), q)), vj[q]);
         }
     } else {
         const int32_t l = static_cast<int32_t>(threadIdx.x % W) % kAggBatch;
