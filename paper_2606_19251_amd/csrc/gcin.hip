@@ -191,27 +191,59 @@ __device__ __forceinline__ double wave4_sum(double v, double (*sh)[HD]) {
 // ------------------------------------------------------------------------------------------
 // batch construction
 // ------------------------------------------------------------------------------------------
-__global__ void fill_graph_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ cl,
-                                  const double* __restrict__ va, int32_t row0, int32_t e0, int32_t* __restrict__ ptr,
-                                  int32_t* __restrict__ col, float* __restrict__ w, float* __restrict__ x0) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int32_t b = rp[i], e = rp[i + 1];
-    ptr[row0 + i] = e0 + b;
-    double aii = 0.0;
-    for (int32_t p = b; p < e; ++p) {
+// A workgroup owns 256 consecutive rows of the level graph. Each thread writes its row's
+// pointer and degree feature and marks the row's entries in an LDS map; the entries are then
+// copied with unit stride (columns shifted to the graph's first batch row, weights a_ij, 1 for
+// the self-loop of A_hat, whose entry also writes the a_ii feature). A block whose entries do
+// not fit the map is copied row by row.
+constexpr int kFillCap = 4096;
+
+__global__ __launch_bounds__(256) void fill_graph_kernel(int32_t n, const int32_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ cl,
+                                                        const double* __restrict__ va, int32_t row0, int32_t e0,
+                                                        int32_t* __restrict__ ptr, int32_t* __restrict__ col,
+                                                        float* __restrict__ w, float* __restrict__ x0) {
+    __shared__ uint8_t rowof[kFillCap];
+    const int t = static_cast<int>(threadIdx.x);
+    const int32_t r0 = static_cast<int32_t>(blockIdx.x) * 256;
+    const int32_t r1 = min(r0 + 256, n);
+    const int32_t b0 = rp[r0];
+    const int32_t ne = rp[r1] - b0;
+    const bool fits = ne <= kFillCap;
+    const int32_t i = r0 + t;
+    int32_t b = 0, e = 0;
+    if (i < r1) {
+        b = rp[i];
+        e = rp[i + 1];
+        ptr[row0 + i] = e0 + b;
+        x0[2 * (row0 + i)] = 0.0f;  // a_ii; the diagonal entry writes it below
+        x0[2 * (row0 + i) + 1] = static_cast<float>(e - b - 1);
+        if (fits)
+            for (int32_t k = b - b0; k < e - b0; ++k) rowof[k] = static_cast<uint8_t>(t);
+    }
+    __syncthreads();
+    if (!fits) {
+        if (i < r1)
+            for (int32_t p = b; p < e; ++p) {
+                const int32_t j = cl[p];
+                col[e0 + p] = row0 + j;
+                w[e0 + p] = j == i ? 1.0f : static_cast<float>(va[p]);
+                if (j == i) x0[2 * (row0 + i)] = static_cast<float>(va[p]);
+            }
+        return;
+    }
+    for (int32_t k = t; k < ne; k += 256) {
+        const int32_t p = b0 + k;
         const int32_t j = cl[p];
-        if (j == i) {
-            col[e0 + p] = row0 + i;
+        const int32_t row = r0 + rowof[k];
+        col[e0 + p] = row0 + j;
+        if (j == row) {
             w[e0 + p] = 1.0f;  // self-loop of A_hat
-            aii = va[p];
+            x0[2 * (row0 + row)] = static_cast<float>(va[p]);
         } else {
-            col[e0 + p] = row0 + j;
             w[e0 + p] = static_cast<float>(va[p]);
         }
     }
-    x0[2 * (row0 + i)] = static_cast<float>(aii);
-    x0[2 * (row0 + i) + 1] = static_cast<float>(e - b - 1);
 }
 
 __global__ void set_int_kernel(int32_t* __restrict__ p, int32_t v) { p[0] = v; }
