@@ -377,12 +377,18 @@ def jacobi_coeffs(omega: float = 2.0 / 3.0, degree: int = 2) -> np.ndarray:
 
 
 def offdiag_scale(A: sp.csr_matrix) -> float:
-    """s = max |a_ij| over stored off-diagonal entries, one number per level; 1 if there are none."""
+    """s = max |a_ij| over stored off-diagonal entries, one number per level (Sec. 3.1, Eq. 5).
+
+    Reading: Eq. 5 divides by s, which is undefined for a level without a nonzero
+    off-diagonal (no stored off-diagonal, or only stored zeros); s = 1 is taken then.
+    The off-diagonal part of Q is zero either way, since f_o(0) = 0.
+    """
     rowid = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
     off = A.indices != rowid
     if not off.any():
         return 1.0
-    return float(np.max(np.abs(A.data[off])))
+    s = float(np.max(np.abs(A.data[off])))
+    return s if s > 0.0 else 1.0
 
 
 def poly_diag(x, d):

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kBlock) void absmax_final_kernel(const double* __re
         if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) scale[0] = red[0] < 0.0 ? 1.0 : red[0];
+    if (threadIdx.x == 0) scale[0] = red[0] <= 0.0 ? 1.0 : red[0];  // no nonzero off-diagonal: s = 1
 }
 
 // --- transpose -----------------------------------------------------------------------
