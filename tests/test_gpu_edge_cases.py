@@ -182,3 +182,42 @@ def test_fp32_cycle_fcg_reaches_tolerance(kind):
     fb = f - f.mean() if ho.singular else f
     rel = np.linalg.norm(fb - ho.levels[0].A @ x.cpu().numpy()) / np.linalg.norm(fb)
     assert rel <= 1.01e-8, (kind, rel)
+
+
+def test_level_with_stored_zero_offdiagonals_gets_unit_scale():
+    """A level whose stored off-diagonal entries are all exact zeros has no nonzero off-diagonal,
+    so the s of Eq. 5 is taken as 1 (the oracle's reading): the smoother values are finite and
+    bitwise the oracle's, on the unbatched level and on the same level inside a batch."""
+    from paper_2606_19251_amd.solver import BatchSolver, DeviceSolver, HostHierarchy, HostLevel
+
+    n = 8
+    diag = np.arange(2.0, 2.0 + n)
+    A0 = sp.csr_matrix(np.diag(diag))
+    for i in range(0, n, 2):  # stored zeros on a 2 x 2 block pattern
+        A0[i, i + 1] = 0.0
+        A0[i + 1, i] = 0.0
+    A0 = sp.csr_matrix(A0)
+    A0.sort_indices()
+    A0.data[A0.indices != np.repeat(np.arange(n), np.diff(A0.indptr))] = 0.0
+    assert A0.nnz == 2 * n  # the zeros stay stored
+    P0 = sp.csr_matrix(np.kron(np.eye(n // 2), np.ones((2, 1))))
+    A1 = sp.csr_matrix(P0.T @ A0 @ P0)
+    A1.sort_indices()
+    L0 = HostLevel(n, A0.indptr.astype(np.int32), A0.indices.astype(np.int32), A0.data.copy(), n // 2,
+                   P0.indptr.astype(np.int32), P0.indices.astype(np.int32), P0.data.copy())
+    L1 = HostLevel(n // 2, A1.indptr.astype(np.int32), A1.indices.astype(np.int32), A1.data.copy())
+    h = HostHierarchy([L0, L1], False)
+    c = np.array([0.5, 0.25, -0.01, 0.3, 0.1])
+    ref = amg.assemble_smoother(A0, c, 2)
+    assert amg.offdiag_scale(A0) == 1.0 and np.all(np.isfinite(ref.data))
+    ds = DeviceSolver(h, 0)
+    ds.set_coeffs(c, 2)
+    v = ds.level_view(0)
+    torch.cuda.synchronize()
+    assert float(v["scale"].cpu().numpy()[0]) == 1.0
+    assert np.array_equal(_bits(v["q_val"].cpu().numpy()), _bits(ref.data))
+    bs = BatchSolver([h, h], 0)
+    bs.set_coeffs_device(torch.from_numpy(np.tile(c.astype(np.float32), (4, 1))).cuda(), 2)
+    q = bs.ds.level_view(0)["q_val"].cpu().numpy()
+    ref32 = amg.assemble_smoother(A0, c.astype(np.float32).astype(np.float64), 2).data
+    assert np.array_equal(_bits(q), _bits(np.concatenate([ref32, ref32])))

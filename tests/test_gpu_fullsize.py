@@ -72,3 +72,22 @@ def test_full_solve_residual(full, smoother):
     rel = np.linalg.norm(fb - ho.levels[0].A @ x.cpu().numpy()) / np.linalg.norm(fb)
     print(f"[gpu] {smoother}: {info.vcycles} cycles, oracle residual {rel:.2e}", flush=True)
     assert rel <= 1e-8 * 1.01
+
+
+def test_full_fp32_level_operators_elementwise(full):
+    """The FP32 operators of the timed cycle on the fine and first coarse level, row by row within
+    the FP32 rounding bound of each row's sum (tests/fp32_operators.py)."""
+    import scipy.sparse as sp
+
+    from fp32_operators import check_level
+    from paper_2606_19251_amd import capi
+
+    A, f, ho, hp, ds = full
+    c = np.array([0.6, 0.01, -0.001, 0.12, 0.01])
+    ds.set_coeffs(c, 2)
+    for l in (0, 1):
+        L = hp.levels[l]
+        Al = sp.csr_matrix((L.val, L.col, L.rowptr), shape=(L.n, L.n))
+        P = sp.csr_matrix((L.p_val, L.p_col, L.p_rowptr), shape=(L.n, L.p_ncols))
+        worst = check_level(torch, capi, ds, Al, P, amg.assemble_smoother(Al, c, 2), l, 10 + l)
+        print(f"[gpu] 1M level {l}: largest FP32 error / bound {worst:.3f}", flush=True)
