@@ -108,6 +108,20 @@ size_t adam_scratch_bytes(void);
 int adam_step(float* params, const float* grads, float* m, float* v, int64_t n, float lr, float b1, float b2,
               float eps, int step, float clip, float* gnorm_out, void* scratch, void* stream);
 
+/* adam_step without any allocation, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight training loops, harnesses that forbid hipMalloc): the same kernels and
+ * results, with the step's scratch (the per-workgroup partial sums of ||g||^2 and the clipping
+ * scalars, adam_scratch_bytes() = 2,112 bytes) in a static device array of exactly that size that
+ * the library holds on each GPU it runs on until the process ends. That scratch does not grow
+ * with n, so no n >= 1 is beyond its capacity. Allocates nothing (no hipMalloc, no library
+ * allocation). The stream's device (the current device for stream NULL) is the GPU used. Every
+ * call on one GPU shares that GPU's scratch: calls that overlap in time on one GPU (on different
+ * streams, or from several threads) race and must be serialised by the caller. Each call writes
+ * every scratch value it reads before reading it, so no clearing is needed between calls.
+ * Errors: AMGG_EINVAL (null pointer, n < 1, step < 1), AMGG_EHIP. */
+int adam_step_noalloc(float* params, const float* grads, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                      float eps, int step, float clip, float* gnorm_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

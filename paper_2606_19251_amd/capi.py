@@ -112,6 +112,8 @@ SIGNATURES = {
     "adam_scratch_bytes": (C.c_size_t, []),
     "adam_step": (_I, [_VP, _VP, _VP, _VP, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, _I, C.c_float,
                        _VP, _VP, _VP]),
+    "adam_step_noalloc": (_I, [_VP, _VP, _VP, _VP, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, _I,
+                               C.c_float, _VP, _VP]),
 }
 
 _lib = None
@@ -412,6 +414,11 @@ def adam_scratch_bytes() -> int:
 def adam_step(params, grads, m, v, n, lr, b1, b2, eps, step, clip, gnorm_out, scratch, stream):
     return _check(lib().adam_step(params, grads, m, v, n, lr, b1, b2, eps, step, clip, gnorm_out, scratch, stream),
                   "adam_step")
+
+
+def adam_step_noalloc(params, grads, m, v, n, lr, b1, b2, eps, step, clip, gnorm_out, stream):
+    return _check(lib().adam_step_noalloc(params, grads, m, v, n, lr, b1, b2, eps, step, clip, gnorm_out, stream),
+                  "adam_step_noalloc")
 
 
 def gcin_tile_gemm_check(A, B, D_fp32, D_bf16, stream):

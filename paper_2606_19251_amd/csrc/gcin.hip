@@ -17,6 +17,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1540,23 +1541,92 @@ extern "C" int gcin_tile_gemm_check(const float* A, const float* B, float* D_fp3
     return AMGG_OK;
 }
 
-extern "C" size_t adam_scratch_bytes(void) { return sizeof(double) * (kAdamBlocks + 8); }
+constexpr size_t kAdamScratchDoubles = kAdamBlocks + 8;  // partial sums of ||g||^2, then the clip scalars
+
+extern "C" size_t adam_scratch_bytes(void) { return sizeof(double) * kAdamScratchDoubles; }
+
+namespace {
+// The three launches of one Adam step; `work` holds kAdamScratchDoubles doubles of device memory.
+// Every entry of `work` that is read was written earlier in the same step (each partial by its
+// workgroup, the scalars by the one-thread kernel), so it needs no clearing between calls.
+hipError_t adam_launch(float* params, const float* grads, float* m, float* v, int64_t n, float lr, float b1,
+                       float b2, float eps, int step, float clip, float* gnorm_out, double* work, hipStream_t st) {
+    double* part = work;
+    double* scal = part + kAdamBlocks;
+    sumsq_kernel<<<kAdamBlocks, kAdamThreads, 0, st>>>(grads, n, part);
+    clipcoef_kernel<<<1, 1, 0, st>>>(part, clip, scal, gnorm_out);
+    const float bc1 = 1.0f - std::pow(b1, static_cast<float>(step));
+    const float bc2 = 1.0f - std::pow(b2, static_cast<float>(step));
+    adam_kernel<<<grid_of(n, 256), 256, 0, st>>>(params, grads, m, v, n, lr, b1, b2, eps, bc1, bc2, scal);
+    return hipGetLastError();
+}
+
+bool adam_args_ok(const float* params, const float* grads, const float* m, const float* v, int64_t n, int step) {
+    return params && grads && m && v && n > 0 && step >= 1;
+}
+}  // namespace
 
 extern "C" int adam_step(float* params, const float* grads, float* m, float* v, int64_t n, float lr, float b1, float b2,
-                         float eps, int step, float clip, float* gnorm_out, void* scratch, void* stream) {
+                         float eps, int step, float clip, float* gnorm_out, void* workspace, void* stream) {
     return amgg::guarded([&]() -> int {
-        if (!params || !grads || !m || !v || !scratch || n <= 0 || step < 1)
+        if (!adam_args_ok(params, grads, m, v, n, step) || !workspace)
             return amgg::fail(AMGG_EINVAL, "adam_step: bad argument");
-        hipStream_t st = static_cast<hipStream_t>(stream);
-        double* part = static_cast<double*>(scratch);
-        double* scal = part + kAdamBlocks;
-        sumsq_kernel<<<kAdamBlocks, kAdamThreads, 0, st>>>(grads, n, part);
-        clipcoef_kernel<<<1, 1, 0, st>>>(part, clip, scal, gnorm_out);
-        const float bc1 = 1.0f - std::pow(b1, static_cast<float>(step));
-        const float bc2 = 1.0f - std::pow(b2, static_cast<float>(step));
-        adam_kernel<<<grid_of(n, 256), 256, 0, st>>>(params, grads, m, v, n, lr, b1, b2, eps, bc1, bc2, scal);
-        const hipError_t e = hipGetLastError();
+        const hipError_t e = adam_launch(params, grads, m, v, n, lr, b1, b2, eps, step, clip, gnorm_out,
+                                         static_cast<double*>(workspace), static_cast<hipStream_t>(stream));
         if (e != hipSuccess) return hip_err(e, "adam_step");
+        return AMGG_OK;
+    });
+}
+
+// ------------------------------------------------------------------------------------------
+// Adam step without any allocation: the step's scratch (kAdamScratchDoubles doubles) is this
+// file-scope device array, one copy per GPU, held until the process ends. Host code never
+// passes `scratch` itself to a kernel (on the host it names a stand-in, not device memory):
+// it uses the address hipGetSymbolAddress returns on each device, looked up once per device.
+// ------------------------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kAdamScratchDoubles];
+static_assert(sizeof(scratch) == sizeof(double) * kAdamScratchDoubles, "one Adam step's scratch, whatever n");
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[64] = {};  // per device ordinal: the address of `scratch` on that device
+
+// Address of `scratch` on `device`, looked up on the first call for that device with the device
+// current (the caller's current device is restored afterwards).
+hipError_t scratch_on(int device, double** out) {
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int prev = -1;
+        hipError_t e = hipGetDevice(&prev);
+        if (e == hipSuccess && prev != device) e = hipSetDevice(device);
+        void* p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev >= 0 && prev != device) {
+            const hipError_t e2 = hipSetDevice(prev);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+}  // namespace
+
+extern "C" int adam_step_noalloc(float* params, const float* grads, float* m, float* v, int64_t n, float lr,
+                                 float b1, float b2, float eps, int step, float clip, float* gnorm_out,
+                                 void* stream) {
+    return amgg::guarded([&]() -> int {
+        if (!adam_args_ok(params, grads, m, v, n, step)) return amgg::fail(AMGG_EINVAL, "adam_step_noalloc: bad argument");
+        const hipStream_t st = static_cast<hipStream_t>(stream);
+        int device = -1;
+        hipError_t e = st ? hipStreamGetDevice(st, &device) : hipGetDevice(&device);
+        double* work = nullptr;
+        if (e == hipSuccess) e = scratch_on(device, &work);
+        if (e == hipSuccess) e = adam_launch(params, grads, m, v, n, lr, b1, b2, eps, step, clip, gnorm_out, work, st);
+        if (e != hipSuccess) return hip_err(e, "adam_step_noalloc");
         return AMGG_OK;
     });
 }
