@@ -1,21 +1,25 @@
-"""Benchmark: time to solve to 1e-8 relative residual with FP32 V-cycles inside FP64
-flexible CG, GCIN-smoothed vs Jacobi-smoothed AMG, on one MI355X.
+"""Benchmark: time to solve to 1e-8 relative residual with FP32 V(1,1) cycles inside an FP64 outer
+loop, GCIN-smoothed vs Jacobi-smoothed AMG, on one MI355X.
 
-Workloads (--workload):
-  delaunay1m (default)  P1 finite-element Laplacian on the Delaunay triangulation of 1,000,000
-                        points in the unit square (uniform inside, evenly spaced on the boundary),
-                        all-Neumann (singular), zero-mean U[-1,1] right-hand side;
-  tet8m                 finite-volume Poisson on the Kuhn tetrahedra of a jittered 111^3 lattice
-                        (7,986,000 cells, all-Neumann), zero-mean U[-1,1] right-hand side;
-  cmesh4m               finite-volume Poisson on a 4096 x 1024 C-mesh around a NACA 2412 section
-                        (wall aspect ratio 1e4, Dirichlet far field), U[-1,1] right-hand side.
-Ruge-Stueben hierarchy (theta 0.25, <= 10 levels, coarsest <= 500 rows); V(1,1) cycles; each
-mesh family uses the GCIN weights trained on small meshes of that family. One step = one
-complete solve from x = 0 with the hierarchy, the smoother and the right-hand side resident in
-HBM (setup is reported separately). The same solves with FP64 iterative refinement as the
-outer loop (the paper's stationary V-cycle iteration with an FP64 residual) are reported too,
-and with the default workload the fine-level residual kernel of tet8m (whose matrix does not
-fit the 256 MB last-level cache) is timed as a second roofline point.
+Headline workload (default, --workload tet8m): finite-volume Poisson on the Kuhn tetrahedra of a
+jittered 111^3 lattice (7,986,000 cells, ~5 nonzeros per row, all-Neumann), zero-mean U[-1,1]
+right-hand side, FP64 iterative refinement around the FP32 cycles (its configured outer loop);
+flexible CG is reported beside it. Its fine matrix (322 MB in FP32) exceeds the 256 MB last-level
+cache, so it is the HBM roofline point.
+Further workloads reported in the same line (skipped with --only-headline):
+  delaunay1m  P1 finite-element Laplacian on the Delaunay mesh of 1,000,000 points in the unit
+              square (uniform inside, evenly spaced on the boundary), all-Neumann, flexible CG
+              (configured) and iterative refinement;
+  cmesh4m     finite-volume Poisson on a 4096 x 1024 C-mesh around a NACA 2412 section (wall
+              aspect ratio 1e4, Dirichlet far field), flexible CG;
+  training    one training step (Alg. 1) on the 32-mesh clustered batch;
+  structured  a 1024 x 1024 5-point grid with the 32-channel GCIN.
+Ruge-Stueben hierarchy (theta 0.25, <= 10 levels, coarsest <= 500 rows); each mesh family uses
+the GCIN weights trained on small meshes of that family. One step = one complete solve from
+x = 0 with the hierarchy, the smoother and the right-hand side resident in HBM (setup is
+reported separately). The CPU baseline is the oracle's own iterative-refinement solve of the
+headline workload, timed on a bounded number of iterations in a child process started before
+the GPU is touched, so that its minutes of setup overlap the GPU measurements.
 
 Prints one JSON line. With --gpus N > 1 it exits: the build runs on one GPU.
 """
@@ -65,6 +69,15 @@ def level_bytes_vcycle(h, smoother_sparse: bool, bv: int = 4, bi: int = 4) -> fl
             post = apass + 4 * n * bv                 # u' = u + qd (f - A u)
             total += pre + restrict + prolong + post
     return total
+
+
+def outer_bytes_ir(n: int, nnz: int) -> float:
+    """Algorithmic bytes of one FP64 iterative-refinement iteration outside the cycle: the scaled
+    FP32 cast of r, x += ||r|| u, and r = b - A x with its norm."""
+    cast_in = n * 8 + n * 4
+    update_x = n * 4 + 2 * n * 8
+    resid = nnz * 12 + 4 * (n + 1) + 3 * n * 8
+    return cast_in + update_x + resid
 
 
 def outer_bytes_fcg(n: int, nnz: int) -> float:
@@ -142,13 +155,13 @@ def _throughput_worker(_):
 
     with threadpool_limits(limits=1):
         t0 = time.time()
-        res = amg.solve_fcg(_TP["h"], _TP["Qs"], _TP["f"], tol=1e-8, maxit=_TP["iters"])
+        res = amg.solve_ir(_TP["h"], _TP["Qs"], _TP["f"], tol=1e-8, maxit=_TP["iters"])
         return time.time() - t0, res.iterations
 
 
-def cpu_throughput(h, Qs, fn, gpu_iters, iters, procs):
+def cpu_throughput(h, Qs, fn, iters, procs):
     """`procs` single-threaded oracle solves of the same bounded sample at once (forked workers
-    sharing the hierarchy): host solves per second when every process solves its own system."""
+    sharing the hierarchy): seconds per iteration of the slowest process."""
     import multiprocessing as mp
 
     _TP.update(h=h, Qs=Qs, f=fn, iters=iters)
@@ -157,48 +170,103 @@ def cpu_throughput(h, Qs, fn, gpu_iters, iters, procs):
     _TP.clear()
     wall = max(t for t, _ in out)
     done = min(k for _, k in out)
-    per_solve = wall * gpu_iters / max(done, 1)
-    return {"solves_per_s": round(procs / per_solve, 3), "processes": procs, "threads_per_process": 1,
-            "sample": f"{done} iterations per process, slowest process {wall:.1f} s, scaled to {gpu_iters} iterations"}
+    return {"processes": procs, "threads_per_process": 1, "s_per_iteration_slowest": wall / max(done, 1),
+            "iterations_per_process": done}
 
 
-def cpu_baseline(A, f, gpu_iters, budget_s=20.0, throughput_procs=0):
-    """The oracle's FP64 flexible-CG solve timed on the host for a bounded number of iterations
-    (one thread; the smoother has A's pattern whatever its coefficients, so the cost per
-    iteration is that of the GCIN-smoothed solve too)."""
-    from threadpoolctl import threadpool_limits
+def host_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "host_nproc": os.cpu_count(), "host_cpus_available": avail}
 
-    from oracle import amg
 
-    An, fn, sing = amg.normalize(A, f)
-    t0 = time.time()
-    h = amg.setup(An, singular=sing, max_levels=10, max_coarse=500)
-    setup_s = time.time() - t0
-    log(f"oracle setup {setup_s:.1f} s, levels {[L.A.shape[0] for L in h.levels]}")
-    Qs = amg.smoothers(h, amg.jacobi_coeffs(), 2)
-    with threadpool_limits(limits=1):
+def _cpu_baseline_job(conn, workload, budget_s, throughput_procs):
+    """Child process (forked before the GPU is touched): the oracle's FP64 iterative-refinement
+    solve of the headline workload with omega-Jacobi V(1,1) cycles, one thread, timed over a
+    bounded number of iterations. The oracle's smoother has A's pattern whatever its
+    coefficients, so the cost per iteration is that of the GCIN-smoothed solve too."""
+    try:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import amg
+
         t0 = time.time()
-        amg.vcycle(h, Qs, np.zeros_like(fn), fn)
-        one = time.time() - t0
-        iters = max(1, min(gpu_iters, int(budget_s / max(one, 1e-3))))
-        t0 = time.time()
-        res = amg.solve_fcg(h, Qs, fn, tol=1e-8, maxit=iters)
-        el = time.time() - t0
-    per_iter = el / max(res.iterations, 1)
-    extra = {}
-    if throughput_procs > 0:
-        extra["throughput"] = cpu_throughput(h, Qs, fn, gpu_iters, res.iterations, throughput_procs)
-        log(f"oracle throughput: {extra['throughput']}")
-    return {
-        **extra,
-        "value": per_iter * gpu_iters * 1e3,
-        "unit": "ms",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"oracle FP64 flexible CG with omega-Jacobi V(1,1) on the same 1M-row hierarchy, "
-                   f"{res.iterations} iterations timed ({el:.1f} s, single thread), scaled to the "
-                   f"{gpu_iters} iterations the GPU solve needs"),
-    }
+        A, f = make_workload(workload)
+        mesh_s = time.time() - t0
+        An, fn, sing = amg.normalize(A, f)
+        del A
+        with threadpool_limits(limits=1):
+            t0 = time.time()
+            h = amg.setup(An, singular=sing, max_levels=10, max_coarse=500)
+            setup_s = time.time() - t0
+            Qs = amg.smoothers(h, amg.jacobi_coeffs(), 2)
+            t0 = time.time()
+            amg.vcycle(h, Qs, np.zeros_like(fn), fn)
+            one = time.time() - t0
+            iters = max(2, int(budget_s / max(one, 1e-3)))
+            t0 = time.time()
+            res = amg.solve_ir(h, Qs, fn, tol=1e-8, maxit=iters)
+            el = time.time() - t0
+        out = {"s_per_iteration": el / max(res.iterations, 1), "iterations": res.iterations, "seconds": el,
+               "oracle_setup_s": setup_s, "mesh_s": mesh_s, "levels": [L.A.shape[0] for L in h.levels]}
+        if throughput_procs > 0:
+            out["throughput"] = cpu_throughput(h, Qs, fn, res.iterations, throughput_procs)
+        conn.send(out)
+    except BaseException as e:  # reported, not raised: the GPU measurements stand on their own
+        conn.send({"error": repr(e)})
+    finally:
+        conn.close()
+
+
+def start_cpu_baseline(workload, budget_s=15.0, throughput_procs=0):
+    """Fork the oracle job now (no HIP call has been made in this process yet)."""
+    import multiprocessing as mp
+
+    ctx = mp.get_context("fork")
+    parent, child = ctx.Pipe(duplex=False)
+    proc = ctx.Process(target=_cpu_baseline_job, args=(child, workload, budget_s, throughput_procs))
+    proc.start()
+    child.close()
+    return proc, parent, time.time()
+
+
+def finish_cpu_baseline(job, gpu_iters, workload_desc, limit_s):
+    """Wait for the oracle job (at most limit_s after its start) and scale its per-iteration time to
+    the GPU solve's iteration count."""
+    proc, conn, t_start = job
+    left = max(1.0, limit_s - (time.time() - t_start))
+    log(f"waiting up to {left:.0f} s for the oracle baseline")
+    if not conn.poll(left):
+        proc.kill()
+        return {"value": None, "unit": "ms", "cores": 1, "kind": "oracle",
+                "sample": f"oracle job did not finish within {limit_s:.0f} s", **host_info()}
+    r = conn.recv()
+    proc.join(timeout=30)
+    if "error" in r:
+        return {"value": None, "unit": "ms", "cores": 1, "kind": "oracle", "sample": r["error"], **host_info()}
+    log(f"oracle: setup {r['oracle_setup_s']:.1f} s, {r['iterations']} IR iterations in {r['seconds']:.1f} s")
+    out = {"value": round(r["s_per_iteration"] * gpu_iters * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+           "sample": (f"oracle FP64 iterative refinement with omega-Jacobi V(1,1) on {workload_desc}, its own RS "
+                      f"hierarchy {r['levels']} (setup {r['oracle_setup_s']:.0f} s, not timed), "
+                      f"{r['iterations']} iterations timed ({r['seconds']:.1f} s, one thread), scaled to the "
+                      f"{gpu_iters} iterations of the GPU's GCIN-smoothed solve"),
+           "oracle_setup_s": round(r["oracle_setup_s"], 1), **host_info()}
+    if "throughput" in r:
+        t = r["throughput"]
+        out["throughput"] = {"solves_per_s": round(t["processes"] / (t["s_per_iteration_slowest"] * gpu_iters), 3),
+                             "processes": t["processes"], "threads_per_process": 1,
+                             "sample": f"{t['iterations_per_process']} iterations per process, scaled"}
+    return out
 
 
 WORKLOADS = {
@@ -448,24 +516,64 @@ def structured_case(torch, nu=1):
     return res
 
 
+CONFIGURED_OUTER = {"tet8m": "ir", "delaunay1m": "fcg", "cmesh4m": "fcg", "grid1m": "fcg"}
+
+
+def workload_report(torch, case, steps, warmup, nu, outers, with_roofline=True):
+    """Solves of one workload with both smoothers under the given outer loops, the algorithmic
+    bytes of one cycle and the solve-level algorithmic bandwidth, and the fine-level roofline."""
+    from paper_2606_19251_amd import capi
+
+    hh = case.hh
+    n0, z0 = hh.levels[0].n, hh.levels[0].nnz
+    vbytes = {"gnn": level_bytes_vcycle(hh, smoother_sparse=True), "jacobi": level_bytes_vcycle(hh, False)}
+    obytes = {"ir": outer_bytes_ir(n0, z0), "fcg": outer_bytes_fcg(n0, z0)}
+    code = {"ir": capi.AMGG_OUTER_IR, "fcg": capi.AMGG_OUTER_FCG}
+    out = {"workload": f"{WORKLOADS[case.name][1]} (n={n0}, nnz={z0})", "levels": [L.n for L in hh.levels],
+           "level_nnz": [L.nnz for L in hh.levels], "configured_outer": CONFIGURED_OUTER[case.name],
+           "vcycle_bytes": {k: int(v) for k, v in vbytes.items()}}
+    for outer in outers:
+        res = {}
+        for sm in ("jacobi", "gnn"):
+            k, w = (steps, warmup) if outer == CONFIGURED_OUTER[case.name] else (max(3, steps // 2), 1)
+            r = case.solves(sm, code[outer], k, w, nu)
+            moved = r["vcycles"] * vbytes[sm] + r["iterations"] * obytes[outer]
+            r["solve_gbs_algorithmic"] = round(moved / (r["ms"] * 1e-3) / 1e9, 1)
+            res[sm] = r
+        res["gnn"]["setup_ms"] = round(case.gnn_setup_ms, 3)
+        res["gnn"]["setup_first_ms"] = round(case.gnn_setup_first_ms, 3)
+        res["gnn_over_jacobi_time"] = round(res["gnn"]["ms"] / res["jacobi"]["ms"], 4)
+        gain = res["jacobi"]["ms"] - res["gnn"]["ms"]
+        # solves after which the GCIN setup (prediction + smoother assembly) is paid back; null
+        # where the GCIN-smoothed solve is the slower one
+        res["gnn_setup_break_even_solves"] = round(case.gnn_setup_ms / gain, 1) if gain > 0 else None
+        out[outer] = res
+    out["setup"] = case.setup
+    if with_roofline:
+        out["roofline"] = case.roofline()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=list(WORKLOADS), default="delaunay1m")
+    ap.add_argument("--workload", choices=list(WORKLOADS), default="tet8m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of timed oracle iterations")
+    ap.add_argument("--cpu-limit", type=float, default=420.0,
+                    help="seconds after its start at which the oracle job is abandoned")
     ap.add_argument("--cpu-throughput", type=int, default=0, metavar="P",
                     help="also time P single-threaded oracle solves at once (host solves/s)")
-    ap.add_argument("--no-training", action="store_true", help="skip the training-step timing")
-    ap.add_argument("--no-structured", action="store_true",
-                    help="skip the structured-grid comparison (32-channel GCIN) that follows the default workload")
-    ap.add_argument("--no-second-roofline", action="store_true",
-                    help="skip the tet8m fine-level kernel timing that follows the default workload")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="only the headline workload (no further workloads, training step or structured grid)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch the dominant kernel and a calibration copy (for counter runs)")
     ap.add_argument("--profile-gcin", action="store_true",
                     help="only run the GCIN inference (BF16 MFMA) on the workload's hierarchy, 5 times (for counter runs)")
+    ap.add_argument("--profile-solves", action="store_true",
+                    help="only the workload's solves with both smoothers and both outer loops, 3 each (kernel traces)")
     ap.add_argument("--only-training", action="store_true",
                     help="only time the training step on the 32-mesh batch and print its JSON (for profiling)")
     ap.add_argument("--nu", type=int, default=1)
@@ -474,15 +582,28 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described, not built.",
               file=sys.stderr)
         sys.exit(2)
+    profiling = args.profile_gcin or args.profile_kernels or args.profile_solves or args.only_training
+    cpu_job = None
+    if not (args.no_cpu_baseline or profiling):
+        cpu_job = start_cpu_baseline(args.workload, args.cpu_budget, args.cpu_throughput)
 
+    try:
+        run(args, cpu_job)
+    finally:
+        if cpu_job is not None and cpu_job[0].is_alive():
+            cpu_job[0].kill()
+
+
+def run(args, cpu_job):
     import torch
 
     from paper_2606_19251_amd import capi
 
+    profiling = args.profile_gcin or args.profile_kernels or args.profile_solves or args.only_training
     if args.only_training:
         print(json.dumps({"training": training_step(torch)}), flush=True)
         return
-    case = Case(torch, args.workload, with_host_setup=not (args.profile_gcin or args.profile_kernels))
+    case = Case(torch, args.workload, with_host_setup=not profiling)
     ds, hh = case.ds, case.hh
     if args.profile_gcin:
         for _ in range(5):
@@ -510,19 +631,17 @@ def main():
         torch.cuda.synchronize()
         log("profile-kernels: 10 fine-level residual launches, 10 copies of 256 MiB")
         return
+    if args.profile_solves:
+        for outer in ("ir", "fcg"):
+            for sm in ("jacobi", "gnn"):
+                case.solves(sm, capi.AMGG_OUTER_IR if outer == "ir" else capi.AMGG_OUTER_FCG, 3, 1, args.nu)
+        return
 
-    fcg, ir = capi.AMGG_OUTER_FCG, capi.AMGG_OUTER_IR
-    jac = case.solves("jacobi", fcg, args.steps, args.warmup, args.nu)
-    gnn = case.solves("gnn", fcg, args.steps, args.warmup, args.nu)
-    gnn["setup_ms"] = round(case.gnn_setup_ms, 3)
-    gnn["setup_first_ms"] = round(case.gnn_setup_first_ms, 3)
-    ir_res = {"jacobi": case.solves("jacobi", ir, 5, 1, args.nu), "gnn": case.solves("gnn", ir, 5, 1, args.nu)}
-
-    n0, z0 = hh.levels[0].n, hh.levels[0].nnz
-    vbytes = level_bytes_vcycle(hh, smoother_sparse=True)
-    obytes = outer_bytes_fcg(n0, z0)
-    solve_gbs = (gnn["vcycles"] * vbytes + gnn["iterations"] * obytes) / (gnn["ms"] * 1e-3) / 1e9
-    roof = case.roofline()
+    head = workload_report(torch, case, args.steps, args.warmup, args.nu, ("ir", "fcg"))
+    ds.close()
+    del case, ds
+    outer = CONFIGURED_OUTER[args.workload]
+    gnn, jac = head[outer]["gnn"], head[outer]["jacobi"]
     out = {
         "metric": METRIC,
         "value": gnn["ms"],
@@ -536,40 +655,30 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 cycle / f64 outer",
         "data": "synthetic",
-        "config": {"workload": f"{WORKLOADS[args.workload][1]} (n={n0}, nnz={z0}); GCIN-smoothed AMG, "
-                               f"FCG(FP64) + FP32 V({args.nu},{args.nu}) to 1e-8",
-                   "levels": [L.n for L in hh.levels], "smoother": "gnn"},
+        "config": {"workload": f"{head['workload']}; GCIN-smoothed AMG, {outer.upper()}(FP64) + FP32 "
+                               f"V({args.nu},{args.nu}) to 1e-8",
+                   "outer": outer, "levels": head["levels"], "smoother": "gnn"},
         "vcycles": gnn["vcycles"],
         "jacobi": jac,
         "gnn": gnn,
-        "gnn_over_jacobi_time": round(gnn["ms"] / jac["ms"], 4),
-        "ir": ir_res,
-        # solves after which the GCIN setup (prediction + smoother assembly) is paid back
-        # by faster solves; null where the GCIN-smoothed solve is not the faster one
-        "gnn_setup_break_even_solves": {
-            "fcg": round(gnn["setup_ms"] / (jac["ms"] - gnn["ms"]), 1) if jac["ms"] > gnn["ms"] else None,
-            "ir": (round(gnn["setup_ms"] / (ir_res["jacobi"]["ms"] - ir_res["gnn"]["ms"]), 1)
-                   if ir_res["jacobi"]["ms"] > ir_res["gnn"]["ms"] else None)},
-        "vcycle_bytes": int(vbytes),
-        "solve_gbs_algorithmic": round(solve_gbs, 1),
-        "setup": case.setup,
-        "roofline": roof,
+        "gnn_over_jacobi_time": head[outer]["gnn_over_jacobi_time"],
+        "gnn_over_jacobi_vcycles": round(gnn["vcycles"] / jac["vcycles"], 4),
+        "roofline": head["roofline"],
+        args.workload: head,
     }
-    if args.workload == "delaunay1m" and not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case.A, case.f, gnn["iterations"],
-                                           throughput_procs=args.cpu_throughput)
-    ds.close()
-    if args.workload == "delaunay1m" and not args.no_training:
+    if not args.only_headline:
+        for name, outers in (("delaunay1m", ("fcg", "ir")), ("cmesh4m", ("fcg",))):
+            if name == args.workload:
+                continue
+            c2 = Case(torch, name, with_host_setup=(name == "delaunay1m"))
+            out[name] = workload_report(torch, c2, 5, 1, args.nu, outers)
+            c2.ds.close()
+            del c2
         out["training"] = training_step(torch)
-    if args.workload == "delaunay1m" and not args.no_structured:
         out["structured"] = structured_case(torch, args.nu)
-    if args.workload == "delaunay1m" and not args.no_second_roofline:
-        del case
-        second = Case(torch, "tet8m")
-        out["roofline_tet8m"] = second.roofline()
-        out["tet8m"] = {"jacobi": second.solves("jacobi", fcg, 3, 1, args.nu),
-                        "gnn": second.solves("gnn", fcg, 3, 1, args.nu)}
-        second.ds.close()
+    if cpu_job is not None:
+        out["cpu_baseline"] = finish_cpu_baseline(cpu_job, gnn["iterations"], WORKLOADS[args.workload][1],
+                                                  args.cpu_limit)
     print(json.dumps(out), flush=True)
 
 
