@@ -322,6 +322,23 @@ int amgg_vcycle_loss_adjoint_blocks(amgg_ctx* ctx, int nu1, int nu2, int precisi
                                     const double* f, const double* u0, double* loss_dev,
                                     double* dcoeffs_dev, int32_t dcoeff_rows, void* stream);
 
+/* Chain rule through the per-problem losses (Sec. 3.3, Eq. 11; Alg. 1, step 12): with dcoeffs the
+ * gradient of each problem's loss with respect to the coefficient rows it owns (device FP64
+ * nrows x ncols, as amgg_vcycle_loss_adjoint(_blocks) write it), row_problem[r] the problem that
+ * owns row r (device int32, NULL: problem 0 owns every row) and dloss[p] the derivative of an
+ * outer objective with respect to problem p's loss (device FP64), writes the objective's
+ * gradient out[r][k] = (float)(dcoeffs[r][k] * dloss[row_problem[r]]) (device FP32), which the
+ * predictor backward takes. No host synchronisation. */
+int amgg_chain_loss_grad(int32_t nrows, int32_t ncols, const double* dcoeffs, const int32_t* row_problem,
+                         const double* dloss, float* out, void* stream);
+
+/* Validation metric of Sec. 3.3, Eq. 13 over n held-out problems: out[0] = mean_i (loss[i] -
+ * loss_jacobi[i]), where loss[i] and loss_jacobi[i] are the Eq. 11 losses of the same cycles from
+ * the same start with the learned and with the omega-Jacobi smoother, so that each difference is
+ * log10(||r_n|| / ||r_n^omega-J||); negative means better than Jacobi. Device FP64 arrays, summed
+ * in index order. No host synchronisation. */
+int amgg_validation_metric(int32_t n, const double* loss, const double* loss_jacobi, double* out, void* stream);
+
 /* out[i] = (float)(in[i] * scale) for i < n (device arrays): hands the FP64 coefficient
  * gradients of amgg_vcycle_loss_adjoint, scaled by 1/|batch| (Alg. 1, step 12: batch-mean
  * loss), to the FP32 predictor backward. */

@@ -84,6 +84,17 @@ int gcin_batch_create(int ngraphs, const gcin_graph* graphs, void* workspace, si
 int gcin_batch_workspace_bytes_hidden(int hidden, int ngraphs, const int32_t* n, const int32_t* nnz, size_t* bytes);
 int gcin_batch_create_hidden(int hidden, int ngraphs, const gcin_graph* graphs, void* workspace, size_t ws_bytes,
                              void* stream, gcin_batch** out);
+/* The same with flags: GCIN_INFERENCE builds a batch for forward passes only (Alg. 1, step 6 at
+ * solver setup): the forward keeps no aggregates for a backward and the layers' activations share
+ * two buffers, so the workspace holds about a quarter of the training batch's (the training
+ * batch keeps every layer's aggregates and activations and the backward's buffers); the
+ * coefficients are bitwise those of a training batch, and gcin_backward on such a batch returns
+ * AMGG_ESTATE. flags = 0 is the training batch of the functions above. */
+#define GCIN_INFERENCE 1
+int gcin_batch_workspace_bytes_ex(int hidden, int flags, int ngraphs, const int32_t* n, const int32_t* nnz,
+                                  size_t* bytes);
+int gcin_batch_create_ex(int hidden, int flags, int ngraphs, const gcin_graph* graphs, void* workspace,
+                         size_t ws_bytes, void* stream, gcin_batch** out);
 int gcin_batch_destroy(gcin_batch* b);
 
 /* Forward pass (Alg. 1, step 6): coeffs_out is device FP32 [ngraphs][2d+1], raw

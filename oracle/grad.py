@@ -73,14 +73,19 @@ def grad_central_fd(h: amg.Hierarchy, coeffs, degree: int, f, u0=None, nvc: int 
 
 
 def validation_metric(h: amg.Hierarchy, coeffs, degree: int, f, u0=None, nu1: int = 1, nu2: int = 1,
-                      omega: float = 2.0 / 3.0) -> float:
-    """log10(||r_1|| / ||r_1^{omega-J}||) after one cycle (Sec. 3.3, Eq. 13); negative means better than Jacobi."""
+                      omega: float = 2.0 / 3.0, ncycles: int = 1) -> float:
+    """log10(||r_n|| / ||r_n^{omega-J}||) after n = ncycles cycles from the same u0 (Sec. 3.3, Eq. 13,
+    whose r_{n+1} is the residual after the cycles of the loss); negative means better than Jacobi."""
     A = h.levels[0].A
     f = np.asarray(f, dtype=np.float64)
     u0 = np.zeros_like(f) if u0 is None else u0
     coeffs = np.asarray(coeffs, dtype=np.float64)
     Qs = [amg.assemble_smoother(h.levels[l].A, coeffs[l], degree) for l in range(h.nlevels - 1)] + [None]
     Qj = amg.smoothers(h, amg.jacobi_coeffs(omega, degree), degree)
-    r = f - A @ amg.vcycle(h, Qs, u0, f, nu1, nu2)
-    rj = f - A @ amg.vcycle(h, Qj, u0, f, nu1, nu2)
+    u, uj = u0, u0
+    for _ in range(ncycles):
+        u = amg.vcycle(h, Qs, u, f, nu1, nu2)
+        uj = amg.vcycle(h, Qj, uj, f, nu1, nu2)
+    r = f - A @ u
+    rj = f - A @ uj
     return float(np.log10(np.linalg.norm(r) / np.linalg.norm(rj)))

@@ -60,6 +60,7 @@ class gcin_graph(C.Structure):
 
 
 GCIN_FP32, GCIN_BF16, GCIN_BF16X3 = 0, 1, 2
+GCIN_INFERENCE = 1
 
 _VP = C.c_void_p
 _I32 = C.c_int32
@@ -98,6 +99,8 @@ SIGNATURES = {
     "amgg_set_level_blocks": (_I, [_VP, _I, _I32, _VP, _VP, _VP]),
     "amgg_set_smoother_coeffs_blocks": (_I, [_VP, _I, _I, _VP, _I32, _VP]),
     "amgg_vcycle_loss_adjoint_blocks": (_I, [_VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _I32, _VP]),
+    "amgg_chain_loss_grad": (_I, [C.c_int32, C.c_int32, _VP, _VP, _VP, _VP, _VP]),
+    "amgg_validation_metric": (_I, [C.c_int32, _VP, _VP, _VP, _VP]),
     "amgg_cast_scale_f64_f32": (_I, [_VP, _VP, C.c_int64, C.c_double, _VP]),
     "gcin_param_count": (C.c_int64, [_I]),
     "gcin_param_count_hidden": (C.c_int64, [_I, _I]),
@@ -105,6 +108,8 @@ SIGNATURES = {
     "gcin_batch_workspace_bytes_hidden": (_I, [_I, _I, _VP, _VP, C.POINTER(C.c_size_t)]),
     "gcin_batch_create": (_I, [_I, C.POINTER(gcin_graph), _VP, C.c_size_t, _VP, C.POINTER(_VP)]),
     "gcin_batch_create_hidden": (_I, [_I, _I, C.POINTER(gcin_graph), _VP, C.c_size_t, _VP, C.POINTER(_VP)]),
+    "gcin_batch_workspace_bytes_ex": (_I, [_I, _I, _I, _VP, _VP, C.POINTER(C.c_size_t)]),
+    "gcin_batch_create_ex": (_I, [_I, _I, _I, C.POINTER(gcin_graph), _VP, C.c_size_t, _VP, C.POINTER(_VP)]),
     "gcin_batch_destroy": (_I, [_VP]),
     "gcin_forward": (_I, [_VP, _I, _I, _VP, _VP, _VP]),
     "gcin_backward": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP]),
@@ -365,6 +370,15 @@ def amgg_vcycle_loss_adjoint_blocks(ctx, nu1, nu2, precision, nvc, f, u0, loss_d
                                                         dcoeff_rows, stream), "amgg_vcycle_loss_adjoint_blocks")
 
 
+def amgg_chain_loss_grad(nrows, ncols, dcoeffs, row_problem, dloss, out, stream):
+    return _check(lib().amgg_chain_loss_grad(nrows, ncols, dcoeffs, row_problem, dloss, out, stream),
+                  "amgg_chain_loss_grad")
+
+
+def amgg_validation_metric(n, loss, loss_jacobi, out, stream):
+    return _check(lib().amgg_validation_metric(n, loss, loss_jacobi, out, stream), "amgg_validation_metric")
+
+
 def amgg_cast_scale_f64_f32(src, dst, n, scale, stream):
     return _check(lib().amgg_cast_scale_f64_f32(src, dst, n, scale, stream), "amgg_cast_scale_f64_f32")
 
@@ -377,20 +391,20 @@ def gcin_param_count(degree: int, hidden: int = 64) -> int:
     return v
 
 
-def gcin_batch_workspace_bytes(n, nnz, hidden: int = 64) -> int:
+def gcin_batch_workspace_bytes(n, nnz, hidden: int = 64, flags: int = 0) -> int:
     n = np.ascontiguousarray(n, np.int32)
     nnz = np.ascontiguousarray(nnz, np.int32)
     b = C.c_size_t()
-    _check(lib().gcin_batch_workspace_bytes_hidden(hidden, n.size, _np_ptr(n), _np_ptr(nnz), C.byref(b)),
+    _check(lib().gcin_batch_workspace_bytes_ex(hidden, flags, n.size, _np_ptr(n), _np_ptr(nnz), C.byref(b)),
            "gcin_batch_workspace_bytes")
     return b.value
 
 
-def gcin_batch_create(graphs, workspace, ws_bytes, stream, hidden: int = 64) -> int:
+def gcin_batch_create(graphs, workspace, ws_bytes, stream, hidden: int = 64, flags: int = 0) -> int:
     """graphs: list of (n, nnz, rowptr_ptr, col_ptr, val_ptr) device CSR views."""
     arr = (gcin_graph * len(graphs))(*[gcin_graph(*g) for g in graphs])
     h = _VP()
-    _check(lib().gcin_batch_create_hidden(hidden, len(graphs), arr, workspace, ws_bytes, stream, C.byref(h)),
+    _check(lib().gcin_batch_create_ex(hidden, flags, len(graphs), arr, workspace, ws_bytes, stream, C.byref(h)),
            "gcin_batch_create")
     return h.value
 

@@ -752,6 +752,24 @@ extern "C" int amgg_level_apply_timed(amgg_ctx* c, int lvl, int op, int precisio
                                "amgg_level_apply_timed");
 }
 
+extern "C" int amgg_chain_loss_grad(int32_t nrows, int32_t ncols, const double* dcoeffs, const int32_t* row_problem,
+                                    const double* dloss, float* out, void* stream) {
+    if (!dcoeffs || !dloss || !out || nrows < 0 || ncols < 1)
+        return fail(AMGG_EINVAL, "amgg_chain_loss_grad: bad argument");
+    const hipError_t e = cast_scale_rows_f64_f32(nrows, ncols, dcoeffs, row_problem, dloss, out,
+                                                 static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "amgg_chain_loss_grad");
+    return AMGG_OK;
+}
+
+extern "C" int amgg_validation_metric(int32_t n, const double* loss, const double* loss_jacobi, double* out,
+                                      void* stream) {
+    if (!loss || !loss_jacobi || !out || n < 1) return fail(AMGG_EINVAL, "amgg_validation_metric: bad argument");
+    const hipError_t e = mean_difference(n, loss, loss_jacobi, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "amgg_validation_metric");
+    return AMGG_OK;
+}
+
 extern "C" int amgg_cast_scale_f64_f32(const double* in, float* out, int64_t n, double scale, void* stream) {
     if (!in || !out || n < 0) return fail(AMGG_EINVAL, "amgg_cast_scale_f64_f32: bad argument");
     const hipError_t e = cast_scale_f64_f32(n, in, scale, out, static_cast<hipStream_t>(stream));

@@ -14,9 +14,9 @@
 // This file is compiled with -ffp-contract=off: no product may be fused into its sum.
 #include <hip/hip_runtime.h>
 
-#include <hipcub/device/device_radix_sort.hpp>
-#include <hipcub/device/device_scan.hpp>
-#include <hipcub/device/device_select.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+#include <rocprim/device/device_select.hpp>
 
 #include <algorithm>
 #include <cstdint>
@@ -297,9 +297,13 @@ DevCsr spgemm(Pool& pool, const ConstCsr& L, const ConstCsr& M, int64_t budget, 
                        L.nnz, L.col, M.ptr, cnt);
     check(hipGetLastError(), "product count");
     size_t tb = 0;
-    check(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, loff, L.nnz + 1, st), "scan size");
+    check(rocprim::exclusive_scan(nullptr, tb, cnt, loff, int64_t{0}, static_cast<size_t>(L.nnz) + 1,
+                                  rocprim::plus<int64_t>(), st),
+          "scan size");
     void* tmp = pool.get<unsigned char>(static_cast<int64_t>(tb));
-    check(hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt, loff, L.nnz + 1, st), "product offsets");
+    check(rocprim::exclusive_scan(tmp, tb, cnt, loff, int64_t{0}, static_cast<size_t>(L.nnz) + 1,
+                                  rocprim::plus<int64_t>(), st),
+          "product offsets");
     pool.put(tmp);
     pool.put(cnt);
     const int64_t total = read_back(loff + L.nnz, st);
@@ -343,17 +347,20 @@ DevCsr spgemm(Pool& pool, const ConstCsr& L, const ConstCsr& M, int64_t budget, 
             launch(expand_kernel, p1 - p0, st, p0, p1, lrow, L.col,
                                loff, boff[m], r0, kb, M.ptr, M.col, ka);
             check(hipGetLastError(), "expand");
-            hipcub::DoubleBuffer<uint64_t> db(ka, kbuf);
+            rocprim::double_buffer<uint64_t> db(ka, kbuf);
             size_t sb = 0, ub = 0;
-            check(hipcub::DeviceRadixSort::SortKeys(nullptr, sb, db, static_cast<int>(tc), 0, kb + rb, st),
-                  "sort size");
-            check(hipcub::DeviceSelect::Unique(nullptr, ub, db.Current(), db.Alternate(), dnum, static_cast<int>(tc), st),
+            const unsigned int end_bit = static_cast<unsigned int>(kb + rb);
+            check(rocprim::radix_sort_keys(nullptr, sb, db, static_cast<size_t>(tc), 0u, end_bit, st), "sort size");
+            check(rocprim::unique(nullptr, ub, db.current(), db.alternate(), dnum, static_cast<size_t>(tc),
+                                  rocprim::equal_to<uint64_t>(), st),
                   "unique size");
             void* t2 = pool.get<unsigned char>(static_cast<int64_t>(std::max(sb, ub)));
-            check(hipcub::DeviceRadixSort::SortKeys(t2, sb, db, static_cast<int>(tc), 0, kb + rb, st), "sort");
-            uint64_t* sorted = db.Current();
-            uint64_t* uniq = db.Alternate();
-            check(hipcub::DeviceSelect::Unique(t2, ub, sorted, uniq, dnum, static_cast<int>(tc), st), "unique");
+            check(rocprim::radix_sort_keys(t2, sb, db, static_cast<size_t>(tc), 0u, end_bit, st), "sort");
+            uint64_t* sorted = db.current();
+            uint64_t* uniq = db.alternate();
+            check(rocprim::unique(t2, ub, sorted, uniq, dnum, static_cast<size_t>(tc), rocprim::equal_to<uint64_t>(),
+                                  st),
+                  "unique");
             pool.put(t2);
             u = read_back(dnum, st);
             if (u_total + u > INT32_MAX)
@@ -417,9 +424,13 @@ DevCsr drop_zeros(Pool& pool, const DevCsr& C, hipStream_t st) {
                        C.nnz, crow, C.col, C.val, flag);
     check(hipGetLastError(), "keep flags");
     size_t tb = 0;
-    check(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, flag, pos, C.nnz + 1, st), "scan size");
+    check(rocprim::exclusive_scan(nullptr, tb, flag, pos, int32_t{0}, static_cast<size_t>(C.nnz) + 1,
+                                  rocprim::plus<int32_t>(), st),
+          "scan size");
     void* tmp = pool.get<unsigned char>(static_cast<int64_t>(tb));
-    check(hipcub::DeviceScan::ExclusiveSum(tmp, tb, flag, pos, C.nnz + 1, st), "keep positions");
+    check(rocprim::exclusive_scan(tmp, tb, flag, pos, int32_t{0}, static_cast<size_t>(C.nnz) + 1,
+                                  rocprim::plus<int32_t>(), st),
+          "keep positions");
     pool.put(tmp);
     const int32_t kept = read_back(pos + C.nnz, st);
     DevCsr D = C;

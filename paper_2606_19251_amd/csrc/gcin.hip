@@ -466,7 +466,7 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
         [&](int32_t row) {
             const float hv = row < end ? h : 0.0f;
             Hs[row - tile * TILE][c] = hv;
-            Hout[static_cast<int64_t>(row) * HD + c] = hv;
+            if (Hout) Hout[static_cast<int64_t>(row) * HD + c] = hv;  // kept for a backward only
             h = 0.0f;
         });
     __syncthreads();
@@ -1209,7 +1209,8 @@ struct gcin_batch {
     double* bpart = nullptr;
     int64_t ghstride = 0;
     int last_degree = -1;
-    int hd = 64;  // hidden width
+    int hd = 64;         // hidden width
+    bool infer = false;  // forward only: no activations kept for a backward (GCIN_INFERENCE)
 };
 
 namespace {
@@ -1244,8 +1245,10 @@ size_t layout_batch(gcin_batch* b, uintptr_t base) {
     b->x0 = cv.take<float>(2 * N);
     b->H0 = cv.take<float>(2 * N);
     for (int l = 0; l < NL; ++l) {
-        b->Y[l] = cv.take<float>(N * HD);
-        b->H[l] = l == 0 ? nullptr : cv.take<float>(N * HD);
+        // forward only: a layer reads the layer below and its pooling reads the layer itself, so
+        // two activation buffers in turn suffice and the aggregates are not kept
+        b->Y[l] = b->infer && l >= 2 ? b->Y[l - 2] : cv.take<float>(N * HD);
+        b->H[l] = l == 0 || b->infer ? nullptr : cv.take<float>(N * HD);
         b->mu[l] = cv.take<float>(G * HD);
         b->rstd[l] = cv.take<float>(G * HD);
     }
@@ -1260,6 +1263,7 @@ size_t layout_batch(gcin_batch* b, uintptr_t base) {
     b->hs.s = cv.take<float>(G * JK);
     b->hs.a1 = cv.take<float>(G * M1);
     b->hs.a2 = cv.take<float>(G * M2);
+    if (b->infer) return (cv.off + 255) & ~static_cast<size_t>(255);  // no backward buffers
     b->dpooled = cv.take<float>(G * NL * 2 * HD);
     const Offs o4 = offsets(AMGG_MAX_DEGREE, b->hd);
     b->ghstride = ((o4.total - o4.head0) + 63) / 64 * 64;
@@ -1325,13 +1329,15 @@ extern "C" int64_t gcin_param_count_hidden(int degree, int hidden) {
 
 extern "C" int64_t gcin_param_count(int degree) { return gcin_param_count_hidden(degree, 64); }
 
-extern "C" int gcin_batch_workspace_bytes_hidden(int hidden, int ngraphs, const int32_t* n, const int32_t* nnz,
-                                                 size_t* bytes) {
+extern "C" int gcin_batch_workspace_bytes_ex(int hidden, int flags, int ngraphs, const int32_t* n, const int32_t* nnz,
+                                             size_t* bytes) {
     return amgg::guarded([&]() -> int {
         if (!n || !nnz || !bytes) return amgg::fail(AMGG_EINVAL, "gcin_batch_workspace_bytes: null argument");
         if (!hidden_ok(hidden)) return amgg::fail(AMGG_EINVAL, "gcin_batch_workspace_bytes: hidden must be 64 or 32");
+        if (flags & ~GCIN_INFERENCE) return amgg::fail(AMGG_EINVAL, "gcin_batch_workspace_bytes: unknown flag");
         gcin_batch b;
         b.hd = hidden;
+        b.infer = (flags & GCIN_INFERENCE) != 0;
         int rc = plan_batch(&b, ngraphs, n, nnz);
         if (rc) return rc;
         *bytes = layout_batch(&b, 0);
@@ -1339,14 +1345,20 @@ extern "C" int gcin_batch_workspace_bytes_hidden(int hidden, int ngraphs, const 
     });
 }
 
+extern "C" int gcin_batch_workspace_bytes_hidden(int hidden, int ngraphs, const int32_t* n, const int32_t* nnz,
+                                                 size_t* bytes) {
+    return gcin_batch_workspace_bytes_ex(hidden, 0, ngraphs, n, nnz, bytes);
+}
+
 extern "C" int gcin_batch_workspace_bytes(int ngraphs, const int32_t* n, const int32_t* nnz, size_t* bytes) {
     return gcin_batch_workspace_bytes_hidden(64, ngraphs, n, nnz, bytes);
 }
 
-extern "C" int gcin_batch_create_hidden(int hidden, int ngraphs, const gcin_graph* graphs, void* workspace,
-                                        size_t ws_bytes, void* stream, gcin_batch** out) {
+extern "C" int gcin_batch_create_ex(int hidden, int flags, int ngraphs, const gcin_graph* graphs, void* workspace,
+                                    size_t ws_bytes, void* stream, gcin_batch** out) {
     return amgg::guarded([&]() -> int {
         if (!hidden_ok(hidden)) return amgg::fail(AMGG_EINVAL, "gcin_batch_create: hidden must be 64 or 32");
+        if (flags & ~GCIN_INFERENCE) return amgg::fail(AMGG_EINVAL, "gcin_batch_create: unknown flag");
         if (!graphs || !out || !workspace) return amgg::fail(AMGG_EINVAL, "gcin_batch_create: null argument");
         if (reinterpret_cast<uintptr_t>(workspace) & 255u)
             return amgg::fail(AMGG_EWORKSPACE, "gcin_batch_create: workspace not 256-byte aligned");
@@ -1360,6 +1372,7 @@ extern "C" int gcin_batch_create_hidden(int hidden, int ngraphs, const gcin_grap
         }
         auto* b = new gcin_batch();
         b->hd = hidden;
+        b->infer = (flags & GCIN_INFERENCE) != 0;
         int rc = plan_batch(b, ngraphs, n.data(), z.data());
         if (rc) {
             delete b;
@@ -1417,6 +1430,11 @@ extern "C" int gcin_batch_create_hidden(int hidden, int ngraphs, const gcin_grap
     });
 }
 
+extern "C" int gcin_batch_create_hidden(int hidden, int ngraphs, const gcin_graph* graphs, void* workspace,
+                                        size_t ws_bytes, void* stream, gcin_batch** out) {
+    return gcin_batch_create_ex(hidden, 0, ngraphs, graphs, workspace, ws_bytes, stream, out);
+}
+
 extern "C" int gcin_batch_create(int ngraphs, const gcin_graph* graphs, void* workspace, size_t ws_bytes, void* stream,
                                  gcin_batch** out) {
     return gcin_batch_create_hidden(64, ngraphs, graphs, workspace, ws_bytes, stream, out);
@@ -1438,8 +1456,19 @@ void forward_impl(gcin_batch* b, int degree, int precision, const float* P, floa
     layer0_kernel<HD><<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->x0, b->d_tile_graph, b->d_gend, P + o.convW[0],
                                         P + o.convb[0], b->H0, b->Y[0], b->tstat);
     const int C = b->nchunks;
-    chunk_sum_kernel<HD, 2><<<C, NT, 0, st>>>(b->tstat, b->d_cbound, b->cbuf);
-    stats_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->mu[0], b->rstd[0]);
+    // statistics of layer l, then its readout (which feeds no later layer, so pooling each layer
+    // as soon as its statistics exist leaves every result as it is and lets an inference-only
+    // batch reuse the buffer of layer l - 1 for layer l + 1)
+    auto stats_and_pool = [&](int l) {
+        chunk_sum_kernel<HD, 2><<<C, NT, 0, st>>>(b->tstat, b->d_cbound, b->cbuf);
+        stats_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->mu[l], b->rstd[l]);
+        pool_tile_kernel<HD><<<T, NT, 0, st>>>(b->d_tile_graph, b->d_gend, b->Y[l], b->mu[l], b->rstd[l], P + o.gam[l],
+                                               P + o.bet[l], b->tpsum, b->tpmax, b->tparg);
+        pool_chunk_kernel<HD><<<C, NT, 0, st>>>(b->tpsum, b->tpmax, b->tparg, b->d_cbound, b->cbuf, b->cmax, b->carg);
+        pool_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->cmax, b->carg, b->d_gchunk, b->d_gcnt, l, b->pooled,
+                                                b->argmax);
+    };
+    stats_and_pool(0);
     for (int l = 1; l < NL; ++l) {
         auto kern = layer_kernel<HD, false, false>;
         if constexpr (HD == 64)
@@ -1448,15 +1477,7 @@ void forward_impl(gcin_batch* b, int degree, int precision, const float* P, floa
         kern<<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->d_tile_graph, b->d_gend, b->Y[l - 1], b->mu[l - 1],
                                b->rstd[l - 1], P + o.gam[l - 1], P + o.bet[l - 1], P + o.convW[l], P + o.convb[l],
                                b->H[l], b->Y[l], b->tstat);
-        chunk_sum_kernel<HD, 2><<<C, NT, 0, st>>>(b->tstat, b->d_cbound, b->cbuf);
-        stats_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->mu[l], b->rstd[l]);
-    }
-    for (int l = 0; l < NL; ++l) {
-        pool_tile_kernel<HD><<<T, NT, 0, st>>>(b->d_tile_graph, b->d_gend, b->Y[l], b->mu[l], b->rstd[l], P + o.gam[l],
-                                               P + o.bet[l], b->tpsum, b->tpmax, b->tparg);
-        pool_chunk_kernel<HD><<<C, NT, 0, st>>>(b->tpsum, b->tpmax, b->tparg, b->d_cbound, b->cbuf, b->cmax, b->carg);
-        pool_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->cmax, b->carg, b->d_gchunk, b->d_gcnt, l, b->pooled,
-                                                b->argmax);
+        stats_and_pool(l);
     }
     head_fwd_kernel<HD><<<G, 128, 0, st>>>(P, o, b->pooled, b->hs, coeffs_out);
 }
@@ -1520,6 +1541,7 @@ extern "C" int gcin_backward(gcin_batch* b, int degree, int precision, const flo
                              float* grads, void* stream) {
     return amgg::guarded([&]() -> int {
         if (!b || !P || !dcoeffs || !grads) return amgg::fail(AMGG_EINVAL, "gcin_backward: null argument");
+        if (b->infer) return amgg::fail(AMGG_ESTATE, "gcin_backward: the batch was created for inference only");
         if (degree != b->last_degree) return amgg::fail(AMGG_ESTATE, "gcin_backward: no forward pass of this degree");
         if (precision < GCIN_FP32 || precision > GCIN_BF16X3) return amgg::fail(AMGG_EINVAL, "gcin_backward: bad precision");
         hipStream_t st = static_cast<hipStream_t>(stream);

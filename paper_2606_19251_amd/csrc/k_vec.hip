@@ -82,6 +82,26 @@ __global__ void cast_scale_kernel(int64_t n, const double* __restrict__ x, doubl
     if (i < n) y[i] = static_cast<float>(x[i] * scale);
 }
 
+// out[r][k] = (float)(in[r][k] * gscale[group[r]]) (group NULL: group 0 for every row)
+__global__ void cast_scale_rows_kernel(int32_t nrows, int32_t ncols, const double* __restrict__ in,
+                                       const int32_t* __restrict__ group, const double* __restrict__ gscale,
+                                       float* __restrict__ out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= static_cast<int64_t>(nrows) * ncols) return;
+    const int32_t r = static_cast<int32_t>(i / ncols);
+    out[i] = static_cast<float>(in[i] * gscale[group ? group[r] : 0]);
+}
+
+// out[0] = (sum_i (a[i] - b[i])) / n, summed in index order by one thread (n is a handful of
+// problems: the validation meshes of a training run).
+__global__ void mean_difference_kernel(int32_t n, const double* __restrict__ a, const double* __restrict__ b,
+                                       double* __restrict__ out) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int32_t i = 0; i < n; ++i) s += a[i] - b[i];
+    out[0] = s / n;
+}
+
 __global__ void cast_d2f_kernel(int32_t n, const double* __restrict__ x, float* __restrict__ y) {
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n) y[i] = static_cast<float>(x[i]);
@@ -293,6 +313,19 @@ hipError_t cast_scaled_f64_f32(int32_t n, const double* x, const double* scale, 
 hipError_t cast_scale_f64_f32(int64_t n, const double* x, double scale, float* y, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     cast_scale_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, x, scale, y);
+    return hipGetLastError();
+}
+
+hipError_t cast_scale_rows_f64_f32(int32_t nrows, int32_t ncols, const double* in, const int32_t* group,
+                                   const double* gscale, float* out, hipStream_t stream) {
+    const int64_t total = static_cast<int64_t>(nrows) * ncols;
+    if (total <= 0) return hipSuccess;
+    cast_scale_rows_kernel<<<grid_for(total), kBlock, 0, stream>>>(nrows, ncols, in, group, gscale, out);
+    return hipGetLastError();
+}
+
+hipError_t mean_difference(int32_t n, const double* a, const double* b, double* out, hipStream_t stream) {
+    mean_difference_kernel<<<1, 64, 0, stream>>>(n, a, b, out);
     return hipGetLastError();
 }
 

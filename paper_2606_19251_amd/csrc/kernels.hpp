@@ -124,6 +124,9 @@ hipError_t vec_zero_bytes(void* p, size_t bytes, hipStream_t stream);
 hipError_t cast_scaled_f64_f32(int32_t n, const double* x, const double* scale, float* y, hipStream_t stream);
 hipError_t cast_f64_f32(int32_t n, const double* x, float* y, hipStream_t stream);
 hipError_t cast_scale_f64_f32(int64_t n, const double* x, double scale, float* y, hipStream_t stream);
+hipError_t cast_scale_rows_f64_f32(int32_t nrows, int32_t ncols, const double* in, const int32_t* group,
+                                   const double* gscale, float* out, hipStream_t stream);
+hipError_t mean_difference(int32_t n, const double* a, const double* b, double* out, hipStream_t stream);
 hipError_t cast_f32_f64(int32_t n, const float* x, double* y, hipStream_t stream);
 // y = x - mean, mean = sum/n from a device scalar sum
 hipError_t sub_mean(int32_t n, const double* x, const double* sum, double* y, hipStream_t stream);

@@ -74,24 +74,27 @@ def init_flat(degree: int = 2, seed: int = 0, omega: float = 2.0 / 3.0, hidden: 
 class GraphBatch:
     """A batch of level graphs on the GPU (gcin_batch_create); keeps its workspace alive."""
 
-    def __init__(self, graphs, device, hidden: int = HIDDEN):
-        """graphs: list of (rowptr, col, val) CUDA tensors (int32, int32, float64) of level matrices."""
+    def __init__(self, graphs, device, hidden: int = HIDDEN, inference: bool = False):
+        """graphs: list of (rowptr, col, val) CUDA tensors (int32, int32, float64) of level matrices.
+        inference: forward passes only (no activations kept for a backward, a smaller workspace)."""
         import torch
 
         self.torch = torch
         self.device = device
         self.hidden = hidden
+        self.flags = capi.GCIN_INFERENCE if inference else 0
         self.ngraphs = len(graphs)
         n = np.array([int(g[0].numel() - 1) for g in graphs], np.int32)
         nnz = np.array([int(g[1].numel()) for g in graphs], np.int32)
         self.n = n
-        self.ws_bytes = capi.gcin_batch_workspace_bytes(n, nnz, hidden)
+        self.ws_bytes = capi.gcin_batch_workspace_bytes(n, nnz, hidden, self.flags)
         raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
         off = (-raw.data_ptr()) % 256
         self._raw = raw
         self.ws = raw[off:off + self.ws_bytes]
         views = [(int(n[i]), int(nnz[i]), g[0].data_ptr(), g[1].data_ptr(), g[2].data_ptr()) for i, g in enumerate(graphs)]
-        self.handle = capi.gcin_batch_create(views, self.ws.data_ptr(), self.ws_bytes, self.stream, hidden)
+        self.handle = capi.gcin_batch_create(views, self.ws.data_ptr(), self.ws_bytes, self.stream, hidden, self.flags)
+        self.nforward = 0  # forwards run so far (a backward belongs to the latest one)
 
     @property
     def stream(self):
@@ -102,6 +105,7 @@ class GraphBatch:
         if out is None:
             out = torch.empty(self.ngraphs, 2 * degree + 1, dtype=torch.float32, device=self.device)
         capi.gcin_forward(self.handle, degree, precision, params.data_ptr(), out.data_ptr(), self.stream)
+        self.nforward += 1
         return out
 
     def backward(self, params, dcoeffs, degree=2, precision=capi.GCIN_BF16, grads=None):
@@ -150,8 +154,9 @@ class Predictor:
         np.savez(path, params=self.params.cpu().numpy(), degree=np.int64(self.degree), hidden=np.int64(self.hidden))
 
     def predict(self, hier, ds):
-        """Coefficients [nlevels, 2d+1] (float32 CUDA tensor) for a DeviceSolver's levels."""
-        batch = GraphBatch([ds.A[l] for l in range(ds.nlevels)], self.device, self.hidden)
+        """Coefficients [nlevels, 2d+1] (float32 CUDA tensor) for a DeviceSolver's levels (an
+        inference-only graph batch: no activations are kept)."""
+        batch = GraphBatch([ds.A[l] for l in range(ds.nlevels)], self.device, self.hidden, inference=True)
         out = batch.forward(self.params, self.degree, self.precision)
         self._last_batch = batch
         return out
@@ -190,6 +195,7 @@ class Trainer:
         self.scratch = torch.empty(capi.adam_scratch_bytes(), dtype=torch.uint8, device=dev)
         self.gnorm = torch.zeros(1, dtype=torch.float32, device=dev)
         self.losses = torch.zeros(len(solvers), dtype=torch.float64, device=dev)
+        self.wmean = torch.full((len(solvers),), 1.0 / len(solvers), dtype=torch.float64, device=dev)
         self.dc64 = torch.zeros(self.batch.ngraphs, 2 * d + 1, dtype=torch.float64, device=dev)
         self.dc32 = torch.zeros(self.batch.ngraphs, 2 * d + 1, dtype=torch.float32, device=dev)
         self.step_count = 0
@@ -249,11 +255,27 @@ class Trainer:
         return coeffs
 
     def step(self):
+        """One step of Alg. 1: forward, batch-mean loss, gradients, clipping and Adam. Batched, the
+        gradient flows through the autograd Functions GCIN and VCycleLoss (the batch mean enters as
+        the weights 1/|batch| of the per-problem losses); one problem at a time, the same library
+        calls are made directly."""
         d = self.pred.degree
-        self.loss_and_grad()
-        self.batch.backward(self.pred.params, self.dc32, d, self.pred.precision, self.grads)
+        if self.bsolver is not None:
+            from .autograd import GCIN, VCycleLoss
+
+            torch = self.torch
+            P = self.pred.params.detach().requires_grad_()
+            coeffs = GCIN.apply(P, self.batch, d, self.pred.precision)
+            losses = VCycleLoss.apply(coeffs, self.bsolver, self.f_cat, self.nu, self.cycle_precision, self.nvc)
+            torch.autograd.backward(losses, grad_tensors=self.wmean)
+            grads = self.grads = P.grad  # the step's gradient (before clipping), kept for inspection
+            self.losses = losses.detach()
+        else:
+            self.loss_and_grad()
+            self.batch.backward(self.pred.params, self.dc32, d, self.pred.precision, self.grads)
+            grads = self.grads
         self.step_count += 1
-        capi.adam_step(self.pred.params.data_ptr(), self.grads.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+        capi.adam_step(self.pred.params.data_ptr(), grads.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
                        self.pred.params.numel(), self.lr, 0.9, 0.999, 1e-8, self.step_count, self.clip,
                        self.gnorm.data_ptr(), self.scratch.data_ptr(), self.batch.stream)
         return self.losses

@@ -316,6 +316,9 @@ class BatchSolver:
         self.nblk = len(self.hiers)
         self.ngraphs = int(sum(h.nlevels for h in self.hiers))
         self.depth = bh.nlevels
+        # problem owning each coefficient row (row = level graph, problem-major), for the chain rule
+        owner = np.repeat(np.arange(self.nblk, dtype=np.int32), [h.nlevels for h in self.hiers])
+        self.row_problem = self.ds.torch.from_numpy(owner).to(self.ds.device)
 
     @property
     def ctx(self):

@@ -57,6 +57,80 @@ def make_matrix(family, rng, seed):
 FAMILIES = ("delaunay", "cmesh", "tet")
 
 
+class Plateau:
+    """Learning-rate schedule on the validation metric (App. B.1, Tab. 7: ReduceLROnPlateau; its
+    factor and patience are not given) with the best model kept (Sec. 3.3: the validation metric
+    is the early-stopping criterion): a lower metric is a new best; otherwise the evaluation is
+    stale, and `patience` stale evaluations in a row multiply the rate by `factor` (not below
+    `min_lr`) and start the count again."""
+
+    def __init__(self, lr, patience, factor, min_lr):
+        self.lr, self.patience, self.factor, self.min_lr = lr, patience, factor, min_lr
+        self.best = float("inf")
+        self.stale = 0
+
+    def update(self, v: float) -> bool:
+        """Record one evaluation; True when it is a new best."""
+        if v < self.best:
+            self.best, self.stale = v, 0
+            return True
+        self.stale += 1
+        if self.stale >= self.patience and self.lr > self.min_lr:
+            self.lr, self.stale = max(self.min_lr, self.lr * self.factor), 0
+        return False
+
+
+def best_run(vals) -> int:
+    """Index of the ensemble member kept (Sec. 4.2: seed ensembles): the lowest validation metric,
+    the first one among equals."""
+    return int(np.argmin(np.asarray(vals, np.float64)))
+
+
+class Validator:
+    """Eq. 13 on held-out problems: the mean over meshes of log10(||r_nvc|| / ||r_nvc^omega-J||) after
+    nvc cycles from u = 0 (the difference of the two Eq. 11 losses), formed on the device by
+    amgg_validation_metric."""
+
+    def __init__(self, val, rhs, pred, nu, nvc, cycle_precision=32):
+        import torch
+
+        from . import capi
+        from . import gcin as G
+
+        self.torch = torch
+        self.tr = G.Trainer(val, rhs, pred, nu=nu, nvc=nvc, cycle_precision=cycle_precision)
+        dev = pred.device
+        self.jac = torch.zeros(len(val), dtype=torch.float64, device=dev)
+        dc = torch.zeros(16, 2 * pred.degree + 1, dtype=torch.float64, device=dev)
+        for p, ds in enumerate(val):
+            ds.set_jacobi(2.0 / 3.0)
+            capi.amgg_vcycle_loss_adjoint(ds.ctx, nu[0], nu[1], cycle_precision, nvc, rhs[p].data_ptr(), 0,
+                                          self.jac[p:p + 1].data_ptr(), dc.data_ptr(), self.tr.batch.stream)
+        self.out = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def __call__(self) -> float:
+        from . import capi
+
+        self.tr.loss_and_grad()
+        capi.amgg_validation_metric(len(self.tr.solvers), self.tr.losses.data_ptr(), self.jac.data_ptr(),
+                                    self.out.data_ptr(), self.tr.batch.stream)
+        return float(self.out.item())
+
+
+VAL_RHS_SEED = 12345  # the held-out problems' right-hand sides are fixed for a whole run
+
+
+def seeded_rhs(problems, seed, device):
+    """One U[-1, 1] right-hand side per problem (zero mean for all-Neumann ones), drawn from `seed`."""
+    import torch
+
+    import workloads as W
+
+    r = np.random.default_rng(seed)
+    return [torch.from_numpy(W.rhs_uniform(ds.n, int(r.integers(1 << 30)), zero_mean=bool(ds.singular))).to(device)
+            for ds in problems]
+
+
 def build_problems(family, seed0, count, device, max_coarse=100):
     from .solver import DeviceSolver, HostHierarchy
 
@@ -82,10 +156,7 @@ def train_one(args, seed, train, val, dev):
     rng = np.random.default_rng(seed)
     nu = (args.nu, args.nu)
 
-    def rhs_for(problems, s):
-        r = np.random.default_rng(s)
-        return [torch.from_numpy(W.rhs_uniform(ds.n, int(r.integers(1 << 30)), zero_mean=bool(ds.singular))).to(dev)
-                for ds in problems]
+    rhs_for = lambda problems, s: seeded_rhs(problems, s, dev)
 
     pred = G.Predictor(G.init_flat(args.degree, seed, hidden=args.hidden), dev, args.degree, capi.GCIN_BF16X3,
                        args.hidden)
@@ -95,24 +166,13 @@ def train_one(args, seed, train, val, dev):
     # one optimizer state shared by all mini-batches
     for tr in trainers[1:]:
         tr.m, tr.v = trainers[0].m, trainers[0].v
-    val_rhs = rhs_for(val, 12345)
-    val_tr = G.Trainer(val, val_rhs, pred, nu=nu, nvc=args.nvc)
-    jac = torch.zeros(len(val), dtype=torch.float64, device=dev)
-    dc = torch.zeros(16, 2 * args.degree + 1, dtype=torch.float64, device=dev)
-    for p, ds in enumerate(val):
-        ds.set_jacobi(2.0 / 3.0)
-        capi.amgg_vcycle_loss_adjoint(ds.ctx, nu[0], nu[1], 32, args.nvc, val_rhs[p].data_ptr(), 0,
-                                      jac[p:p + 1].data_ptr(), dc.data_ptr(), val_tr.batch.stream)
-
-    def validate():
-        val_tr.loss_and_grad()
-        return float((val_tr.losses - jac).mean())  # Eq. 13: log10(||r|| / ||r_Jacobi||), mean over meshes
-
-    best = validate()
-    best_flat = pred.params.cpu().numpy().copy()
-    history = [{"step": 0, "val": best, "seed": seed}]
-    print(f"[train] seed {seed} step 0 val {best:+.4f}", flush=True)
-    lr, stale = args.lr, 0
+    validate = Validator(val, rhs_for(val, VAL_RHS_SEED), pred, nu, args.nvc)
+    sched = Plateau(args.lr, args.plateau_patience, args.plateau_factor, args.min_lr)
+    v0 = validate()
+    sched.update(v0)
+    best_flat = pred.params.detach().cpu().numpy().copy()
+    history = [{"step": 0, "val": v0, "lr": sched.lr, "seed": seed}]
+    print(f"[train] seed {seed} step 0 val {v0:+.4f}", flush=True)
     step = 0
     t0 = time.time()
     while step < args.steps:
@@ -123,20 +183,15 @@ def train_one(args, seed, train, val, dev):
         step += 1
         if step % args.val_every == 0 or step == args.steps:
             v = validate()
-            if v < best:
-                best, stale = v, 0
-                best_flat = pred.params.cpu().numpy().copy()
-            else:
-                stale += 1
-                if stale >= args.plateau_patience and lr > args.min_lr:
-                    lr, stale = max(args.min_lr, lr * args.plateau_factor), 0
-                    for t in trainers:
-                        t.lr = lr
-            rec = {"step": step, "loss": float(losses.mean()), "val": v, "lr": lr, "gnorm": float(tr.gnorm.item()),
-                   "s": round(time.time() - t0, 1)}
+            if sched.update(v):
+                best_flat = pred.params.detach().cpu().numpy().copy()
+            for t in trainers:
+                t.lr = sched.lr
+            rec = {"step": step, "loss": float(losses.mean()), "val": v, "lr": sched.lr,
+                   "gnorm": float(tr.gnorm.item()), "s": round(time.time() - t0, 1)}
             history.append(rec)
             print(f"[train] {json.dumps(rec)}", flush=True)
-    return best, best_flat, history
+    return sched.best, best_flat, history
 
 
 def main(argv=None):
@@ -173,7 +228,7 @@ def main(argv=None):
         runs.append((best, flat, history))
         print(f"[train] seed {args.seed + k}: best validation {best:+.4f}", flush=True)
     vals = np.array([r[0] for r in runs])
-    best, flat, history = runs[int(np.argmin(vals))]
+    best, flat, history = runs[best_run(vals)]
     np.savez(args.out, params=flat, degree=np.int64(args.degree), hidden=np.int64(args.hidden), nvc=np.int64(args.nvc),
              nu=np.int64(args.nu), family=args.family, history=json.dumps(history), ensemble_val=vals)
     print(f"[train] ensemble of {len(vals)}: validation mean {vals.mean():+.4f} std {vals.std():.4f} "

@@ -215,3 +215,26 @@ def test_training_reduces_loss():
     l1 = float(tr.losses.mean())
     print(f"[gpu] loss {l0:.4f} -> {l1:.4f}", flush=True)
     assert np.isfinite(l1) and l1 < l0 - 0.02
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_inference_batch_bitwise_equal_and_smaller(precision):
+    """An inference-only batch (no aggregates kept, two activation buffers in turn) gives bitwise the
+    training batch's coefficients with a fraction of its workspace, and refuses a backward."""
+    from paper_2606_19251_amd import capi
+    from paper_2606_19251_amd.gcin import GraphBatch
+
+    flat, _ = _params(7)
+    P = torch.from_numpy(flat).cuda()
+    train, _ = _batch()
+    graphs = []
+    for _, ds in _solvers():
+        graphs += [ds.A[l] for l in range(ds.nlevels)]
+    infer = GraphBatch(graphs, torch.device("cuda", 0), inference=True)
+    a = train.forward(P, 2, precision).cpu().numpy()
+    b = infer.forward(P, 2, precision).cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert infer.ws_bytes < 0.45 * train.ws_bytes, (infer.ws_bytes, train.ws_bytes)
+    with pytest.raises(capi.AmggError) as e:
+        infer.backward(P, torch.zeros(len(graphs), 5, device="cuda"), 2, precision)
+    assert e.value.code == capi.AMGG_ESTATE
