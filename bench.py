@@ -44,9 +44,21 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def level_bytes_vcycle(h, smoother_sparse: bool, bv: int = 4, bi: int = 4) -> float:
+def col_bytes(view, which: int, nz: int, nrows: int) -> int:
+    """Bytes of the column indices a CSR-stream pass reads for matrix `which` (0: A and Q, 1: P,
+    2: R) of a level: 2-byte packed offsets, 6 bytes per far entry (slot and column) and 8 per row
+    block (base column, far-list offset), or the plain 4-byte columns."""
+    rows = view["pack_rows"][which]
+    if rows <= 0:
+        return 4 * nz
+    return 2 * nz + 6 * view["pack_far"][which] + 8 * ((nrows + rows - 1) // rows)
+
+
+def level_bytes_vcycle(h, views, smoother_sparse: bool, bv: int = 4) -> float:
     """Algorithmic HBM bytes of one V(1,1) preconditioner cycle (u = 0 on entry) on the hierarchy:
-    every matrix entry read once per pass, every vector once per pass (gathers counted once)."""
+    every matrix entry read once per pass (value plus column index, packed where the level has
+    packed columns; levels served by the fused halo kernels read plain columns), every vector
+    once per pass (gathers counted once)."""
     total = 0.0
     L = h.nlevels
     for l, lev in enumerate(h.levels):
@@ -54,12 +66,14 @@ def level_bytes_vcycle(h, smoother_sparse: bool, bv: int = 4, bi: int = 4) -> fl
         if l == L - 1:
             total += n * n * 8 + 2 * n * bv
             continue
+        v = views[l]
         p = int(lev.p_col.size)
         nc = lev.p_ncols
-        apass = z * (bv + bi) + 4 * (n + 1)
+        ia = 4 * z if v["fused_rows"] > 0 else col_bytes(v, 0, z, n)
+        apass = z * bv + ia + 4 * (n + 1)
         resid = apass + 3 * n * bv
-        restrict = p * (bv + bi) + 4 * (nc + 1) + n * bv + nc * bv
-        prolong = p * (bv + bi) + 4 * (n + 1) + nc * bv + 2 * n * bv
+        restrict = p * bv + col_bytes(v, 2, p, nc) + 4 * (nc + 1) + n * bv + nc * bv
+        prolong = p * bv + col_bytes(v, 1, p, n) + 4 * (n + 1) + nc * bv + 2 * n * bv
         if smoother_sparse:
             pre = apass + 2 * n * bv                 # u = Q f
             post = resid + apass + 3 * n * bv         # r = f - A u ; u += Q r
@@ -71,18 +85,19 @@ def level_bytes_vcycle(h, smoother_sparse: bool, bv: int = 4, bi: int = 4) -> fl
     return total
 
 
-def outer_bytes_ir(n: int, nnz: int) -> float:
+def outer_bytes_ir(n: int, nnz: int, idx: int) -> float:
     """Algorithmic bytes of one FP64 iterative-refinement iteration outside the cycle: the scaled
-    FP32 cast of r, x += ||r|| u, and r = b - A x with its norm."""
+    FP32 cast of r, x += ||r|| u, and r = b - A x with its norm (idx: bytes of A's column indices)."""
     cast_in = n * 8 + n * 4
     update_x = n * 4 + 2 * n * 8
-    resid = nnz * 12 + 4 * (n + 1) + 3 * n * 8
+    resid = nnz * 8 + idx + 4 * (n + 1) + 3 * n * 8
     return cast_in + update_x + resid
 
 
-def outer_bytes_fcg(n: int, nnz: int) -> float:
-    """Algorithmic bytes of one FP64 flexible-CG iteration outside the cycle."""
-    spmv_dot = nnz * 12 + 4 * (n + 1) + 2 * n * 8
+def outer_bytes_fcg(n: int, nnz: int, idx: int) -> float:
+    """Algorithmic bytes of one FP64 flexible-CG iteration outside the cycle (idx: bytes of A's
+    column indices)."""
+    spmv_dot = nnz * 8 + idx + 4 * (n + 1) + 2 * n * 8
     update_xr = 6 * n * 8
     cast_in = n * 8 + n * 4
     castback = n * 4 + 2 * n * 8 + n * 8
@@ -420,10 +435,13 @@ class Case:
                                                               ys.data_ptr(), fs.data_ptr(), s0, s1, st),
             torch.cuda.current_stream(self.dev))
         rows = 256 if z0 / n0 * 256 * 1.25 <= 4096 else 128
-        k_bytes = z0 * 8 + 4 * (n0 + 1) + 3 * n0 * 4
+        v0 = self.ds.level_view(0)
+        k_bytes = z0 * 4 + col_bytes(v0, 0, z0, n0) + 4 * (n0 + 1) + 3 * n0 * 4
         achieved = k_bytes / (k_ms * 1e-3) / 1e9
         copy = copy_rate_gbs(torch, self.dev)
-        return {"kernel": f"csr_stream_kernel<float, Resid, {rows}, 0> (fine level r = f - A u, FP32, {self.name})",
+        packed = v0["pack_rows"][0] > 0
+        return {"kernel": (f"csr_stream_kernel<float, Resid, {rows}, 0, {'true' if packed else 'false'}> (fine level "
+                           f"r = f - A u, FP32, {'packed' if packed else 'plain'} columns, {self.name})"),
                 "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(self.name),
                 "launch_ms": round(k_ms, 5), "launch_interval_ms": round(k_interval_ms, 5),
@@ -526,12 +544,16 @@ def workload_report(torch, case, steps, warmup, nu, outers, with_roofline=True):
 
     hh = case.hh
     n0, z0 = hh.levels[0].n, hh.levels[0].nnz
-    vbytes = {"gnn": level_bytes_vcycle(hh, smoother_sparse=True), "jacobi": level_bytes_vcycle(hh, False)}
-    obytes = {"ir": outer_bytes_ir(n0, z0), "fcg": outer_bytes_fcg(n0, z0)}
+    views = [case.ds.level_view(l) for l in range(hh.nlevels)]
+    vbytes = {"gnn": level_bytes_vcycle(hh, views, smoother_sparse=True),
+              "jacobi": level_bytes_vcycle(hh, views, False)}
+    idx0 = col_bytes(views[0], 0, z0, n0)
+    obytes = {"ir": outer_bytes_ir(n0, z0, idx0), "fcg": outer_bytes_fcg(n0, z0, idx0)}
     code = {"ir": capi.AMGG_OUTER_IR, "fcg": capi.AMGG_OUTER_FCG}
     out = {"workload": f"{WORKLOADS[case.name][1]} (n={n0}, nnz={z0})", "levels": [L.n for L in hh.levels],
            "level_nnz": [L.nnz for L in hh.levels], "configured_outer": CONFIGURED_OUTER[case.name],
-           "vcycle_bytes": {k: int(v) for k, v in vbytes.items()}}
+           "vcycle_bytes": {k: int(v) for k, v in vbytes.items()},
+           "packed_columns": [{"rows": v["pack_rows"], "far": v["pack_far"]} for v in views]}
     for outer in outers:
         res = {}
         for sm in ("jacobi", "gnn"):

@@ -173,6 +173,11 @@ typedef struct {
     const double* coarse_inv;/* n*n row-major on the coarsest level, else NULL; on a
                                 block-diagonal level the blocks' n_b*n_b inverses in turn */
     int32_t fused_rows;      /* rows per block of the fused smoothing kernels, 0 = not fused */
+    /* Packed columns of A_l (shared by Q_l), P_l and R_l, in this order: rows per block of the
+     * packing (0: the kernels read the 4-byte columns) and its far entries (columns outside the
+     * 16-bit window of their block, listed separately). */
+    int32_t pack_rows[3];
+    int64_t pack_far[3];
 } amgg_level_view;
 int amgg_level_view_get(const amgg_ctx* ctx, int lvl, amgg_level_view* out);
 
@@ -230,6 +235,14 @@ int amgg_level_apply(amgg_ctx* ctx, int lvl, int op, int precision, const void* 
  * keeps its order, so the results are bitwise the same as with enable = 0, where each
  * operator is its own pass. Drops the captured solve graphs. */
 int amgg_set_fusion(amgg_ctx* ctx, int enable);
+
+/* Column-packing switch (diagnostics and tests). With enable = 1 (the default) the CSR-stream
+ * kernels of every matrix whose packing fits read 2-byte column offsets from a per-block base
+ * column, with the few columns outside a block's 16-bit window read from a per-block list
+ * (built at amgg_finalize; a matrix with more than 1/8 of its entries outside keeps the plain
+ * columns). The products and their order are those of the plain CSR walk, so results are
+ * bitwise the same as with enable = 0. Drops the captured solve graphs. */
+int amgg_set_packed_columns(amgg_ctx* ctx, int enable);
 
 /* The same operator, launched so that the kernel itself records start_event when it begins
  * and stop_event when it ends (both hipEvent_t created by the caller with timing enabled;

@@ -40,7 +40,8 @@ class amgg_level_view(C.Structure):
                 ("r_rowptr", C.c_void_p), ("r_col", C.c_void_p), ("r_val", C.c_void_p),
                 ("a_val32", C.c_void_p), ("p_val32", C.c_void_p), ("r_val32", C.c_void_p),
                 ("q_val", C.c_void_p), ("q_val32", C.c_void_p), ("diag", C.c_void_p),
-                ("scale", C.c_void_p), ("coarse_inv", C.c_void_p), ("fused_rows", C.c_int32)]
+                ("scale", C.c_void_p), ("coarse_inv", C.c_void_p), ("fused_rows", C.c_int32),
+                ("pack_rows", C.c_int32 * 3), ("pack_far", C.c_int64 * 3)]
 
 
 class amgg_solve_opts(C.Structure):
@@ -93,6 +94,7 @@ SIGNATURES = {
     "amgg_vcycle": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP]),
     "amgg_level_apply": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _VP]),
     "amgg_set_fusion": (_I, [_VP, _I]),
+    "amgg_set_packed_columns": (_I, [_VP, _I]),
     "amgg_level_apply_timed": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP]),
     "amgg_solve": (_I, [_VP, C.POINTER(amgg_solve_opts), _VP, _VP, C.POINTER(amgg_solve_info), _VP, _I, _VP]),
     "amgg_vcycle_loss_adjoint": (_I, [_VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _VP]),
@@ -327,6 +329,10 @@ def amgg_vcycle(ctx, nu1, nu2, precision, f, u, stream):
 
 def amgg_level_apply(ctx, lvl, op, precision, x, y, f, stream):
     return _check(lib().amgg_level_apply(ctx, lvl, op, precision, x, y, f, stream), "amgg_level_apply")
+
+
+def amgg_set_packed_columns(ctx, enable):
+    return _check(lib().amgg_set_packed_columns(ctx, int(enable)), "amgg_set_packed_columns")
 
 
 def amgg_set_fusion(ctx, enable):

@@ -65,8 +65,27 @@ size_t layout(amgg_ctx* c, uintptr_t base) {
         L.f32 = b.take<float>(n);
         L.r32 = b.take<float>(n);
         L.t32 = b.take<float>(n);
+        // packed columns of A (Q shares them), and of P and R below
+        auto take_pack = [&](Level::Pack& pk, int32_t rows_m, int32_t nz) {
+            pk.rows = stream_rows_for(rows_m, nz);
+            pk.nfar = -1;
+            if (pk.rows <= 0 || nz <= 0) {
+                pk.rows = 0;
+                return;
+            }
+            const size_t nb = (static_cast<size_t>(rows_m) + pk.rows - 1) / pk.rows;
+            pk.cap = static_cast<int64_t>(nz) / 8 + 64;  // beyond 1/8 of the entries far, plain columns
+            pk.off = b.take<uint16_t>(nz);
+            pk.base = b.take<int32_t>(nb);
+            pk.foff = b.take<int32_t>(nb + 1);
+            pk.fslot = b.take<uint16_t>(pk.cap);
+            pk.fcol = b.take<int32_t>(pk.cap);
+        };
+        take_pack(L.pa, L.n, L.nnz);
         if (l + 1 < c->nlevels) {
             const size_t pz = L.pnnz;
+            take_pack(L.pp, L.n, L.pnnz);
+            take_pack(L.pr, L.nc, L.pnnz);
             L.pval32 = b.take<float>(pz);
             L.rptr = b.take<int32_t>(L.nc + 1);
             L.rcol = b.take<int32_t>(pz);
@@ -121,6 +140,7 @@ size_t layout(amgg_ctx* c, uintptr_t base) {
     c->partial2 = b.take<double>(2 * kReduceBlocks);
     c->flags = b.take<int32_t>(8);
     c->cursor = b.take<int32_t>(max_nc + 1);
+    c->pack_parts = b.take<int32_t>(kScanPartsMax + 1);
     c->ra = b.take<double>(n0);
     c->rb = b.take<double>(n0);
     c->z = b.take<double>(n0);
@@ -477,6 +497,21 @@ extern "C" int amgg_finalize(amgg_ctx* c, int singular, void* workspace, size_t 
             ok(dense_lu_inverse(Lc.n, Lc.dense, Lc.piv, Lc.inv, c->flags + 1, st));
         }
         if (e != hipSuccess) return hip_fail(e, "amgg_finalize (launch)");
+        // packed columns of every CSR-stream matrix (each call synchronises to read its far count)
+        for (int l = 0; l < c->nlevels && e == hipSuccess; ++l) {
+            Level& L = c->lv[l];
+            auto pack = [&](Level::Pack& pk, int32_t rows_m, int32_t nz, const int32_t* ptr, const int32_t* col) {
+                if (pk.rows > 0 && e == hipSuccess)
+                    ok(pack_columns(rows_m, nz, ptr, col, pk.rows, pk.off, pk.base, pk.foff, pk.fslot, pk.fcol, pk.cap,
+                                    c->pack_parts, &pk.nfar, st));
+            };
+            pack(L.pa, L.n, L.nnz, L.ptr, L.col);
+            if (l + 1 < c->nlevels) {
+                pack(L.pp, L.n, L.pnnz, L.pptr, L.pcol);
+                pack(L.pr, L.nc, L.pnnz, L.rptr, L.rcol);
+            }
+        }
+        if (e != hipSuccess) return hip_fail(e, "amgg_finalize (column packing)");
         if ((e = build_halos(c, st)) != hipSuccess) return hip_fail(e, "amgg_finalize (halo lists)");
         int32_t flags[3] = {0, 0, 0};
         if ((e = hipMemcpyAsync(flags, c->flags, sizeof(flags), hipMemcpyDeviceToHost, st)) != hipSuccess ||
@@ -493,6 +528,13 @@ extern "C" int amgg_finalize(amgg_ctx* c, int singular, void* workspace, size_t 
 extern "C" int amgg_set_fusion(amgg_ctx* c, int enable) {
     if (!c) return fail(AMGG_EINVAL, "amgg_set_fusion: null context");
     for (int l = 0; l < c->nlevels; ++l) c->lv[l].fuse = enable != 0;
+    drop_graphs(c);
+    return AMGG_OK;
+}
+
+extern "C" int amgg_set_packed_columns(amgg_ctx* c, int enable) {
+    if (!c) return fail(AMGG_EINVAL, "amgg_set_packed_columns: null context");
+    for (int l = 0; l < c->nlevels; ++l) c->lv[l].pack = enable != 0;
     drop_graphs(c);
     return AMGG_OK;
 }
@@ -519,6 +561,12 @@ extern "C" int amgg_level_view_get(const amgg_ctx* c, int lvl, amgg_level_view* 
     v->scale = L.scale;
     v->coarse_inv = coarse ? L.inv : nullptr;
     v->fused_rows = L.hrows;
+    const Level::Pack* packs[3] = {&L.pa, &L.pp, &L.pr};
+    for (int k = 0; k < 3; ++k) {
+        const bool use = packs[k]->usable() && (k == 0 || !coarse);
+        v->pack_rows[k] = use ? packs[k]->rows : 0;
+        v->pack_far[k] = use ? packs[k]->nfar : 0;
+    }
     return AMGG_OK;
 }
 

@@ -63,6 +63,24 @@ struct Level {
     float* hq32 = nullptr;
     uint16_t* hloc = nullptr;
     bool fuse = true;  // use the fused kernels where available
+    // packed columns (ColPack) of A_l (which Q_l shares), P_l and R_l for the CSR-stream kernels
+    struct Pack {
+        uint16_t* off = nullptr;
+        int32_t* base = nullptr;
+        int32_t* foff = nullptr;
+        uint16_t* fslot = nullptr;
+        int32_t* fcol = nullptr;
+        int rows = 0;       // rows per block the packing is for (0: none)
+        int64_t cap = 0;    // far-entry capacity
+        int64_t nfar = -1;  // far entries found at finalize (-1: not built)
+        bool usable() const { return rows > 0 && nfar >= 0 && nfar <= cap; }
+        ColPack view(bool on) const {
+            if (!on || !usable()) return ColPack{};
+            return ColPack{off, base, foff, fslot, fcol, rows};
+        }
+    };
+    Pack pa, pp, pr;
+    bool pack = true;  // read packed columns where available
     // adjoint scratch, kAdjVecs vectors of n per precision (see AdjVec)
     double* adj64[8] = {};
     float* adj32[8] = {};
@@ -85,9 +103,9 @@ struct Level {
     int degree = 0;
     bool baseline = false;  // exactly the omega = 2/3 Jacobi smoother (the fallback target)
 
-    CsrView A() const { return {n, nnz, ptr, col, lanes_for(n, nnz)}; }
-    CsrView P() const { return {n, pnnz, pptr, pcol, lanes_for(n, pnnz)}; }
-    CsrView R() const { return {nc, pnnz, rptr, rcol, lanes_for(nc, pnnz)}; }
+    CsrView A() const { return {n, nnz, ptr, col, lanes_for(n, nnz), pa.view(pack)}; }
+    CsrView P() const { return {n, pnnz, pptr, pcol, lanes_for(n, pnnz), pp.view(pack)}; }
+    CsrView R() const { return {nc, pnnz, rptr, rcol, lanes_for(nc, pnnz), pr.view(pack)}; }
     HaloView H() const { return {hrows, hoff, halo, hend, heoff, hcol, hloc}; }
     template <typename T> const T* hav() const { if constexpr (std::is_same_v<T, double>) return ha64; else return ha32; }
     template <typename T> const T* hqv() const { if constexpr (std::is_same_v<T, double>) return hq64; else return hq32; }
@@ -140,6 +158,7 @@ struct amgg_ctx {
     double* partial2 = nullptr;
     int32_t* flags = nullptr;
     int32_t* cursor = nullptr;
+    int32_t* pack_parts = nullptr;  // scan scratch of the column packing
     double *ra = nullptr, *rb = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *bproj = nullptr;
     double* adj_partial = nullptr;
     double* adj_scal = nullptr;

@@ -33,7 +33,6 @@ int lanes_for(int32_t nrows, int32_t nnz) {
 
 namespace {
 
-constexpr int kStreamCap = 4096;  // products held in LDS per workgroup
 
 // Rows per stream workgroup for a mean row length, or 0 for the lane kernel.
 int stream_rows(int32_t nrows, int32_t nnz) {
@@ -119,6 +118,55 @@ __device__ __forceinline__ void stream_products_g(int32_t ne, const T* __restric
     }
 }
 
+// The same products from packed columns (ColPack): a round loads 2-byte offsets instead of
+// 4-byte columns; a far entry (offset kFarCol) is neither gathered nor stored here, and
+// far_products then writes its product into its own slot from the block's far list, so every
+// slot ends up holding exactly the product of the plain walk.
+template <typename T, class Gather>
+__device__ __forceinline__ void stream_products_packed(int32_t ne, const T* __restrict__ m,
+                                                       const uint16_t* __restrict__ off, int32_t cbase, Gather gather,
+                                                       T* __restrict__ out) {
+    for (int32_t base = 0; base < ne; base += kChunk * kBlock) {
+        T v[kChunk];
+        uint32_t o[kChunk];
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) {
+            const int32_t k = min(base + static_cast<int32_t>(threadIdx.x) + q * kBlock, ne - 1);
+            v[q] = m[k];
+            o[q] = off[k];
+        }
+        T p[kChunk];
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) p[q] = o[q] != kFarCol ? v[q] * gather(cbase + static_cast<int32_t>(o[q])) : T(0);
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q)
+            if (o[q] != kFarCol) out[base + static_cast<int32_t>(threadIdx.x) + q * kBlock] = p[q];
+    }
+}
+
+template <typename T, class Gather>
+__device__ __forceinline__ void far_products(int32_t f0, int32_t f1, const T* __restrict__ m,
+                                             const uint16_t* __restrict__ fslot, const int32_t* __restrict__ fcol,
+                                             Gather gather, T* __restrict__ out) {
+    for (int32_t j = f0 + static_cast<int32_t>(threadIdx.x); j < f1; j += kBlock) {
+        const int32_t s = fslot[j];
+        out[s] = m[s] * gather(fcol[j]);
+    }
+}
+
+// Products of block b's entries (ne <= kStreamCap) into out, from packed or plain columns.
+template <typename T, bool PACKED, class Gather>
+__device__ __forceinline__ void block_products(int32_t b, int32_t e0, int32_t ne, const T* __restrict__ val,
+                                               const int32_t* __restrict__ col, const ColPack& cp, Gather gather,
+                                               T* __restrict__ out) {
+    if constexpr (PACKED) {
+        stream_products_packed<T>(ne, val + e0, cp.off + e0, cp.base[b], gather, out);
+        far_products<T>(cp.foff[b], cp.foff[b + 1], val + e0, cp.fslot, cp.fcol, gather, out);
+    } else {
+        stream_products_g<T>(ne, val + e0, col + e0, gather, out);
+    }
+}
+
 template <typename T, bool SCALED = false>
 __device__ __forceinline__ void stream_products(int32_t ne, const T* __restrict__ m, const int32_t* __restrict__ col,
                                                 const T* __restrict__ x, const T* __restrict__ d,
@@ -198,15 +246,17 @@ __device__ __forceinline__ T row_sum(const T* buf, int32_t pb, int32_t pe) {
 }
 
 // DOT: 0 none; 1 partial of x_i y_i (q = A p, p^T q); 2 partial of y_i^2 (r = b - A x, r^T r).
-template <typename T, Epi E, int ROWS, int DOT>
+// PACKED: columns from cp (packed for blocks of ROWS rows), else from col.
+template <typename T, Epi E, int ROWS, int DOT, bool PACKED>
 __global__ __launch_bounds__(kBlock) void csr_stream_kernel(int32_t nrows, const int32_t* __restrict__ ptr,
-                                                           const int32_t* __restrict__ col,
+                                                           const int32_t* __restrict__ col, ColPack cp,
                                                            const T* __restrict__ val, const T* __restrict__ x,
                                                            T* __restrict__ y, const T* __restrict__ f,
                                                            const T* __restrict__ qd, const T* __restrict__ u,
                                                            double* __restrict__ partial) {
     __shared__ T prod[kStreamCap];
-    const int32_t r0 = xcd_block() * ROWS;
+    const int32_t blk = xcd_block();
+    const int32_t r0 = blk * ROWS;
     const int32_t r1 = min(r0 + ROWS, nrows);
     const int32_t e0 = ptr[r0];
     const int32_t ne = ptr[r1] - e0;
@@ -228,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void csr_stream_kernel(int32_t nrows, const
     }
     T s = T(0);
     if (ne <= kStreamCap) {
-        stream_products<T>(ne, val + e0, col + e0, x, nullptr, prod);
+        block_products<T, PACKED>(blk, e0, ne, val, col, cp, [&](int32_t j) { return x[j]; }, prod);
         __syncthreads();
         if (mine) s = row_sum(prod, pb - e0, pe - e0);
     } else if (mine) {
@@ -303,19 +353,19 @@ template <typename T, Epi E, int DOT>
 hipError_t launch_stream(int rows, const CsrView& m, const T* val, const T* x, T* y, const T* f, const T* qd,
                          const T* u, double* partial, hipStream_t stream) {
     const dim3 grid(static_cast<unsigned>((m.nrows + rows - 1) / rows));
+    const bool packed = m.cp.rows == rows && m.cp.off != nullptr;
     switch (rows) {
-        case 256:
-            return launch_kernel(csr_stream_kernel<T, E, 256, DOT>, grid, dim3(kBlock), stream, m.nrows, m.ptr, m.col,
-                                 val, x, y, f, qd, u, partial);
-        case 128:
-            return launch_kernel(csr_stream_kernel<T, E, 128, DOT>, grid, dim3(kBlock), stream, m.nrows, m.ptr, m.col,
-                                 val, x, y, f, qd, u, partial);
-        case 64:
-            return launch_kernel(csr_stream_kernel<T, E, 64, DOT>, grid, dim3(kBlock), stream, m.nrows, m.ptr, m.col,
-                                 val, x, y, f, qd, u, partial);
-        case 32:
-            return launch_kernel(csr_stream_kernel<T, E, 32, DOT>, grid, dim3(kBlock), stream, m.nrows, m.ptr, m.col,
-                                 val, x, y, f, qd, u, partial);
+#define AMGG_CASE(R)                                                                                              \
+    case R:                                                                                                       \
+        return packed ? launch_kernel(csr_stream_kernel<T, E, R, DOT, true>, grid, dim3(kBlock), stream, m.nrows, \
+                                      m.ptr, m.col, m.cp, val, x, y, f, qd, u, partial)                           \
+                      : launch_kernel(csr_stream_kernel<T, E, R, DOT, false>, grid, dim3(kBlock), stream, m.nrows, \
+                                      m.ptr, m.col, ColPack{}, val, x, y, f, qd, u, partial);
+        AMGG_CASE(256)
+        AMGG_CASE(128)
+        AMGG_CASE(64)
+        AMGG_CASE(32)
+#undef AMGG_CASE
         default:
             return hipErrorInvalidValue;
     }
@@ -512,14 +562,15 @@ __global__ __launch_bounds__(kBlock) void csr_halo_kernel(int32_t nrows, const i
 // products gather d_j f_j, rounded exactly as the separate u = d f pass rounds them.
 //   NEXT_RESID: u_i = d_i f_i, y_i = f_i - (A u)_i
 //   otherwise:  y_i = d_i f_i + d_i (f_i - (A u)_i)
-template <typename T, int ROWS, bool NEXT_RESID>
+template <typename T, int ROWS, bool NEXT_RESID, bool PACKED>
 __global__ __launch_bounds__(kBlock) void csr_jpre_kernel(int32_t nrows, const int32_t* __restrict__ ptr,
-                                                         const int32_t* __restrict__ col,
+                                                         const int32_t* __restrict__ col, ColPack cp,
                                                          const T* __restrict__ val, const T* __restrict__ d,
                                                          const T* __restrict__ f, T* __restrict__ y,
                                                          T* __restrict__ uout) {
     __shared__ T prod[kStreamCap];
-    const int32_t r0 = xcd_block() * ROWS;
+    const int32_t blk = xcd_block();
+    const int32_t r0 = blk * ROWS;
     const int32_t r1 = min(r0 + ROWS, nrows);
     const int32_t e0 = ptr[r0];
     const int32_t ne = ptr[r1] - e0;
@@ -535,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void csr_jpre_kernel(int32_t nrows, const i
     }
     T s = T(0);
     if (ne <= kStreamCap) {
-        stream_products<T, true>(ne, val + e0, col + e0, f, d, prod);
+        block_products<T, PACKED>(blk, e0, ne, val, col, cp, [&](int32_t j) { return d[j] * f[j]; }, prod);
         __syncthreads();
         if (mine) s = row_sum(prod, pb - e0, pe - e0);
     } else if (mine) {
@@ -595,11 +646,14 @@ hipError_t launch_jpre(const CsrView& m, const T* a, const T* d, const T* f, T* 
         return csr_apply<T>(m, a, u, y, f, nullptr, nullptr, Epi::Resid, stream);
     }
     const dim3 grid(static_cast<unsigned>((m.nrows + rows - 1) / rows));
+    const bool packed = m.cp.rows == rows && m.cp.off != nullptr;
     switch (rows) {
-#define AMGG_CASE(R)                                                                                               \
-    case R:                                                                                                        \
-        return launch_kernel(csr_jpre_kernel<T, R, NEXT_RESID>, grid, dim3(kBlock), stream, m.nrows, m.ptr, m.col, \
-                             a, d, f, y, u);
+#define AMGG_CASE(R)                                                                                             \
+    case R:                                                                                                      \
+        return packed ? launch_kernel(csr_jpre_kernel<T, R, NEXT_RESID, true>, grid, dim3(kBlock), stream, m.nrows, \
+                                      m.ptr, m.col, m.cp, a, d, f, y, u)                                         \
+                      : launch_kernel(csr_jpre_kernel<T, R, NEXT_RESID, false>, grid, dim3(kBlock), stream,      \
+                                      m.nrows, m.ptr, m.col, ColPack{}, a, d, f, y, u);
         AMGG_CASE(256)
         AMGG_CASE(128)
         AMGG_CASE(64)

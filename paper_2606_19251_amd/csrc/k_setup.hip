@@ -74,6 +74,7 @@ __global__ void count_cols_kernel(int32_t nnz, const int32_t* __restrict__ col, 
 // scans each piece from its offset. Integer sums: the result does not depend on the order.
 constexpr int kScanBlock = 1024;  // 16 wavefronts
 constexpr int64_t kScanParts = 1024;  // at most ceil(m / kScanBlock) <= m pieces
+static_assert(kScanParts <= kScanPartsMax, "pack_columns scratch holds the piece sums");
 
 __device__ int32_t block_inclusive_scan(int32_t v, int32_t* lds, int32_t* total) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -394,6 +395,90 @@ hipError_t offdiag_absmax(int32_t n, const int32_t* ptr, const int32_t* col, con
                           double* scale, hipStream_t stream) {
     absmax_partial_kernel<<<kReduceBlocks, kBlock, 0, stream>>>(n, ptr, col, val, partial);
     absmax_final_kernel<<<1, kBlock, 0, stream>>>(partial, scale);
+    return hipGetLastError();
+}
+
+// --- packed columns --------------------------------------------------------------------
+// One workgroup per row block: the base column (the middle entry of the block's middle row,
+// less 32767, at least 0: with sorted columns that entry sits among the row's near neighbours,
+// the diagonal for a level matrix, so the 16-bit window is centred on the block's own
+// neighbourhood), every entry's offset from it, and the count of far entries into cnt[b + 1]
+// (none for a block beyond the product buffer, whose rows read the plain columns).
+__global__ __launch_bounds__(kBlock) void pack_count_kernel(int32_t nrows, int rows, const int32_t* __restrict__ ptr,
+                                                           const int32_t* __restrict__ col, uint16_t* __restrict__ off,
+                                                           int32_t* __restrict__ base, int32_t* __restrict__ cnt) {
+    __shared__ int32_t nfar;
+    const int32_t b = blockIdx.x;
+    const int32_t r0 = b * rows, r1 = min(r0 + rows, nrows);
+    const int32_t e0 = ptr[r0], ne = ptr[r1] - e0;
+    const int32_t rm = r0 + (r1 - r0) / 2;
+    const int32_t mb = ptr[rm], me = ptr[rm + 1];
+    const int32_t anchor = me > mb ? col[mb + (me - mb) / 2] : (ne > 0 ? col[e0 + ne / 2] : 0);
+    const int32_t bs = max(0, anchor - 32767);
+    if (threadIdx.x == 0) nfar = 0;
+    __syncthreads();
+    int32_t mine = 0;
+    for (int32_t k = threadIdx.x; k < ne; k += kBlock) {
+        const int64_t o = static_cast<int64_t>(col[e0 + k]) - bs;
+        const bool near = o >= 0 && o < kFarCol;
+        off[e0 + k] = near ? static_cast<uint16_t>(o) : kFarCol;
+        mine += near ? 0 : 1;
+    }
+    if (mine) atomicAdd(&nfar, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        base[b] = bs;
+        cnt[b + 1] = ne <= kStreamCap ? nfar : 0;
+    }
+}
+
+// Far entries of each block at foff[b]..: entry index within the block and full column. Their
+// order within a block is immaterial (each one is written to its own product slot).
+__global__ __launch_bounds__(kBlock) void pack_far_kernel(int32_t nrows, int rows, const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ col,
+                                                         const uint16_t* __restrict__ off,
+                                                         const int32_t* __restrict__ foff,
+                                                         uint16_t* __restrict__ fslot, int32_t* __restrict__ fcol) {
+    __shared__ int32_t pos;
+    const int32_t b = blockIdx.x;
+    const int32_t r0 = b * rows, r1 = min(r0 + rows, nrows);
+    const int32_t e0 = ptr[r0], ne = ptr[r1] - e0;
+    if (ne > kStreamCap || foff[b + 1] == foff[b]) return;  // uniform over the workgroup
+    const int32_t f0 = foff[b];
+    if (threadIdx.x == 0) pos = 0;
+    __syncthreads();
+    for (int32_t k = threadIdx.x; k < ne; k += kBlock)
+        if (off[e0 + k] == kFarCol) {
+            const int32_t j = f0 + atomicAdd(&pos, 1);
+            fslot[j] = static_cast<uint16_t>(k);
+            fcol[j] = col[e0 + k];
+        }
+}
+
+hipError_t pack_columns(int32_t nrows, int32_t nnz, const int32_t* ptr, const int32_t* col, int rows, uint16_t* off,
+                        int32_t* base, int32_t* foff, uint16_t* fslot, int32_t* fcol, int64_t cap, int32_t* parts,
+                        int64_t* nfar, hipStream_t stream) {
+    *nfar = -1;
+    if (nrows <= 0 || nnz <= 0 || rows <= 0) return hipSuccess;
+    const int32_t nb = (nrows + rows - 1) / rows;
+    hipError_t e = vec_zero_bytes(foff, sizeof(int32_t), stream);
+    if (e != hipSuccess) return e;
+    pack_count_kernel<<<nb, kBlock, 0, stream>>>(nrows, rows, ptr, col, off, base, foff);
+    // in-place inclusive scan of the counts foff[1..nb]: foff[b] = far entries before block b
+    const int32_t nparts = static_cast<int32_t>(
+        std::min<int64_t>(kScanParts, (static_cast<int64_t>(nb) + kScanBlock - 1) / kScanBlock));
+    const int32_t piece = static_cast<int32_t>((static_cast<int64_t>(nb) + nparts - 1) / nparts);
+    scan_reduce_kernel<<<nparts, kScanBlock, 0, stream>>>(nb, piece, foff, parts);
+    scan_parts_kernel<<<1, kScanBlock, 0, stream>>>(nparts, parts);
+    scan_apply_kernel<<<nparts, kScanBlock, 0, stream>>>(nb, piece, foff, parts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int32_t total = 0;
+    if ((e = hipMemcpyAsync(&total, foff + nb, sizeof(int32_t), hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess)
+        return e;
+    *nfar = total;
+    if (total > cap || total == 0) return hipSuccess;  // over capacity: the plain columns stay in use
+    pack_far_kernel<<<nb, kBlock, 0, stream>>>(nrows, rows, ptr, col, off, foff, fslot, fcol);
     return hipGetLastError();
 }
 

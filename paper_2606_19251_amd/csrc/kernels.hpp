@@ -35,6 +35,7 @@ inline hipError_t launch_kernel(void (*kernel)(KArgs...), dim3 grid, dim3 block,
 }
 
 constexpr int kBlock = 256;         // threads per workgroup (4 wavefronts of 64)
+constexpr int kStreamCap = 4096;    // products a CSR-stream workgroup holds in LDS
 constexpr int kReduceBlocks = 1024; // fixed partial count: reductions are deterministic
 
 // ---------------------------------------------------------------------------------------
@@ -48,13 +49,41 @@ enum class Epi : int {
     Sub = 4,     // y_i -= s
 };
 
+// Column indices of a CSR matrix packed for the CSR-stream kernels: rows are grouped in blocks
+// of `rows` consecutive rows (the kernels' row blocks), every entry stores its column as a 16-bit
+// offset from its block's base column, and the few entries whose column lies outside
+// [base, base + 65534] ("far" entries, offset kFarCol) are listed per block with their entry
+// index within the block and their full column. The kernels form exactly the products of the
+// plain CSR walk (only the loads of the columns change), so results are bitwise the same.
+constexpr uint16_t kFarCol = 0xFFFF;
+struct ColPack {
+    const uint16_t* off = nullptr;    // [nnz]
+    const int32_t* base = nullptr;    // [blocks]
+    const int32_t* foff = nullptr;    // [blocks + 1] far entries of each block
+    const uint16_t* fslot = nullptr;  // entry index within the block of each far entry
+    const int32_t* fcol = nullptr;    // column of each far entry
+    int rows = 0;                     // rows per block of the encoding (0: none, plain columns)
+};
+
 struct CsrView {
     int32_t nrows;
     int32_t nnz;
     const int32_t* ptr;
     const int32_t* col;
-    int lanes;  // 1, 2, 4, ..., 64
+    int lanes;        // 1, 2, 4, ..., 64
+    ColPack cp = {};  // packed columns (cp.rows == the stream kernel's rows per block), if any
 };
+
+// Pack the columns of an nrows-row CSR matrix for row blocks of `rows` rows (a value of
+// stream_rows_for): off [nnz], base [blocks], foff [blocks + 1], and at most `cap` far entries
+// in fslot / fcol. `parts` is scratch of at least kScanParts + 1 ints. Synchronises the stream;
+// *nfar receives the number of far entries (the packing is unusable when it exceeds cap).
+// Blocks whose entries exceed the stream kernels' product buffer record no far entries (their
+// rows are summed from the plain columns).
+hipError_t pack_columns(int32_t nrows, int32_t nnz, const int32_t* ptr, const int32_t* col, int rows, uint16_t* off,
+                        int32_t* base, int32_t* foff, uint16_t* fslot, int32_t* fcol, int64_t cap, int32_t* parts,
+                        int64_t* nfar, hipStream_t stream);
+constexpr int64_t kScanPartsMax = 1024;  // scratch of pack_columns: kScanPartsMax + 1 ints
 
 int lanes_for(int32_t nrows, int32_t nnz);
 

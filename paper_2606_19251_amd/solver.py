@@ -179,6 +179,9 @@ class DeviceSolver:
     def set_fusion(self, enable: bool):
         capi.amgg_set_fusion(self.ctx, enable)
 
+    def set_packed_columns(self, enable: bool):
+        capi.amgg_set_packed_columns(self.ctx, enable)
+
     def close(self):
         if self.ctx:
             capi.amgg_destroy(self.ctx)
@@ -251,6 +254,8 @@ class DeviceSolver:
             "scale": s(v.scale, 1, torch.float64),
             "coarse_inv": s(v.coarse_inv, v.n * v.n, torch.float64),
             "fused_rows": int(v.fused_rows),
+            "pack_rows": [int(x) for x in v.pack_rows],  # A (and Q), P, R; 0 = plain columns
+            "pack_far": [int(x) for x in v.pack_far],
         }
 
 

@@ -1,0 +1,152 @@
+"""Packed column indices of the CSR-stream kernels against the plain 4-byte columns.
+
+Each matrix served by the stream kernels carries its columns as 2-byte offsets from a base
+column per row block, with the entries outside a block's 16-bit window ("far" entries) listed
+per block; beyond 1/8 of the entries far, the matrix keeps its plain columns. The products
+and their summation order do not change, so every result must be bitwise the one of the plain
+columns. Cases:
+- Kuhn tetrahedra of a jittered 30^3 lattice (146,334 cells, Morton order: a few per cent of
+  the fine entries far, as on the 8M-cell mesh);
+- a 300 x 300 grid with 2 % of its unknowns swapped at random (far entries well inside the
+  capacity, clustered in few blocks, many far entries per block);
+- the same grid randomly permuted (nearly every entry far: over capacity, plain columns).
+Checked with packing on and off: every level operator in FP32 and FP64, one V-cycle in both
+precisions, and an FP32-cycle / FP64 flexible-CG solve (same iterations, bitwise the same x);
+and, packed, the FP64 fine-level residual bitwise against the oracle's sparse product.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import amg
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+_cache = {}
+
+
+def _permuted_grid(N, frac, seed):
+    A = W.grid5(N).to_scipy()
+    n = A.shape[0]
+    rng = np.random.default_rng(seed)
+    perm = np.arange(n)
+    if frac >= 1.0:
+        perm = rng.permutation(n)
+    else:
+        k = int(frac * n) // 2 * 2
+        pick = rng.choice(n, size=k, replace=False)
+        perm[pick[0::2]], perm[pick[1::2]] = pick[1::2], pick[0::2]
+    P = sp.csr_matrix((np.ones(n), (np.arange(n), perm)), shape=(n, n))
+    B = sp.csr_matrix(P @ A @ P.T)
+    B.sort_indices()
+    return W.CSRMatrix(B.indptr.astype(np.int32), B.indices.astype(np.int32), B.data.astype(np.float64), n, n)
+
+
+def _case(kind):
+    if kind not in _cache:
+        from paper_2606_19251_amd.solver import DeviceSolver, HostHierarchy
+
+        if kind == "tet146k":
+            A, f = W.tet_kuhn_problem(30, 1)
+        elif kind == "grid_swap":
+            A = _permuted_grid(300, 0.02, 3)
+            f = W.rhs_uniform(A.nrows, 4)
+        else:
+            A = _permuted_grid(300, 1.0, 5)
+            f = W.rhs_uniform(A.nrows, 6)
+        hp = HostHierarchy.build(A.rowptr, A.col, A.val, max_levels=10, max_coarse=500)
+        ds = DeviceSolver(hp, 0)
+        views = [ds.level_view(l) for l in range(ds.nlevels)]
+        print(f"[gpu] packed {kind}: levels {[L.n for L in hp.levels]}, packing rows (A,P,R) "
+              f"{[v['pack_rows'] for v in views]}, far {[v['pack_far'] for v in views]}", flush=True)
+        _cache[kind] = (A, f, hp, ds, views)
+    return _cache[kind]
+
+
+def _bits(a):
+    a = np.ascontiguousarray(a)
+    return a.view(np.uint64 if a.dtype == np.float64 else np.uint32)
+
+
+def test_packing_is_built_where_expected():
+    _, _, hp, _, v = _case("tet146k")
+    assert v[0]["pack_rows"][0] > 0 and v[0]["pack_far"][0] > 0  # Morton 3D: some far entries
+    assert 0 < v[0]["pack_far"][0] <= hp.levels[0].nnz // 8
+    _, _, hp, _, v = _case("grid_swap")
+    assert v[0]["pack_rows"][0] > 0 and v[0]["pack_far"][0] > 1000
+    _, _, hp, _, v = _case("grid_perm")
+    assert v[0]["pack_rows"][0] == 0 and v[0]["pack_far"][0] == 0  # over capacity: plain columns
+
+
+@pytest.mark.parametrize("kind", ["tet146k", "grid_swap", "grid_perm"])
+@pytest.mark.parametrize("precision", [32, 64])
+def test_level_operators_bitwise_packed_vs_plain(kind, precision):
+    from paper_2606_19251_amd import capi
+
+    A, f, hp, ds, views = _case(kind)
+    ds.set_coeffs(np.array([0.6, 0.01, -0.001, 0.12, 0.01]), 2)
+    dt = torch.float64 if precision == 64 else torch.float32
+    rng = np.random.default_rng(7)
+    for l in range(ds.nlevels):
+        n = hp.levels[l].n
+        ops = [capi.AMGG_OP_SPMV, capi.AMGG_OP_RESIDUAL, capi.AMGG_OP_SMOOTH, capi.AMGG_OP_JACOBI]
+        if l + 1 < ds.nlevels:
+            ops += [capi.AMGG_OP_RESTRICT, capi.AMGG_OP_PROLONG]
+        for op in ops:
+            nin = hp.levels[l].p_ncols if op == capi.AMGG_OP_PROLONG else n
+            nout = hp.levels[l].p_ncols if op == capi.AMGG_OP_RESTRICT else n
+            x = torch.from_numpy(rng.standard_normal(nin)).to(dt).cuda()
+            fv = torch.from_numpy(rng.standard_normal(n)).to(dt).cuda()
+            y0 = torch.from_numpy(rng.standard_normal(nout)).to(dt).cuda()
+            out = []
+            for packed in (True, False):
+                ds.set_packed_columns(packed)
+                y = y0.clone()
+                capi.amgg_level_apply(ds.ctx, l, op, precision, x.data_ptr(), y.data_ptr(), fv.data_ptr(), ds.stream)
+                torch.cuda.synchronize()
+                out.append(y.cpu().numpy())
+            assert np.array_equal(_bits(out[0]), _bits(out[1])), (kind, precision, l, op)
+    ds.set_packed_columns(True)
+
+
+@pytest.mark.parametrize("kind", ["tet146k", "grid_swap"])
+def test_cycles_and_solve_bitwise_packed_vs_plain(kind):
+    from paper_2606_19251_amd import capi
+
+    A, f, hp, ds, _ = _case(kind)
+    ds.set_coeffs(np.array([0.6, 0.01, -0.001, 0.12, 0.01]), 2)
+    u0 = np.random.default_rng(8).standard_normal(A.nrows)
+    res = {}
+    for packed in (True, False):
+        ds.set_packed_columns(packed)
+        out = []
+        for precision in (64, 32):
+            u = torch.from_numpy(u0).cuda()
+            ds.vcycle(torch.from_numpy(f).cuda(), u, 1, 1, precision)
+            out.append(u.cpu().numpy())
+        x, rc, info, _ = ds.solve(torch.from_numpy(f).cuda(), outer=capi.AMGG_OUTER_FCG, precision=32, tol=1e-8)
+        assert rc == 0
+        res[packed] = (out, x.cpu().numpy(), info.iterations)
+    ds.set_packed_columns(True)
+    (o1, x1, k1), (o0, x0, k0) = res[True], res[False]
+    assert k1 == k0
+    assert np.array_equal(_bits(x1), _bits(x0))
+    for a, b in zip(o1, o0):
+        assert np.array_equal(_bits(a), _bits(b))
+
+
+@pytest.mark.parametrize("kind", ["tet146k", "grid_swap"])
+def test_packed_fp64_residual_bitwise_oracle(kind):
+    from paper_2606_19251_amd import capi
+
+    A, f, hp, ds, _ = _case(kind)
+    Al = A.to_scipy()
+    x = np.random.default_rng(9).standard_normal(A.nrows)
+    y = torch.zeros(A.nrows, dtype=torch.float64, device="cuda")
+    xd, fd = torch.from_numpy(x).cuda(), torch.from_numpy(f).cuda()
+    capi.amgg_level_apply(ds.ctx, 0, capi.AMGG_OP_RESIDUAL, 64, xd.data_ptr(), y.data_ptr(), fd.data_ptr(), ds.stream)
+    torch.cuda.synchronize()
+    ref = f - amg.to_scipy(A) @ x
+    assert np.array_equal(_bits(y.cpu().numpy()), _bits(ref))
