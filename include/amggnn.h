@@ -236,13 +236,16 @@ int amgg_level_apply(amgg_ctx* ctx, int lvl, int op, int precision, const void* 
  * operator is its own pass. Drops the captured solve graphs. */
 int amgg_set_fusion(amgg_ctx* ctx, int enable);
 
-/* Column-packing switch (diagnostics and tests). With enable = 1 (the default) the CSR-stream
- * kernels of every matrix whose packing fits read 2-byte column offsets from a per-block base
- * column, with the few columns outside a block's 16-bit window read from a per-block list
- * (built at amgg_finalize; a matrix with more than 1/8 of its entries outside keeps the plain
- * columns). The products and their order are those of the plain CSR walk, so results are
- * bitwise the same as with enable = 0. Drops the captured solve graphs. */
-int amgg_set_packed_columns(amgg_ctx* ctx, int enable);
+/* Column packing of the CSR-stream kernels. amgg_finalize packs the columns of every level
+ * matrix, prolongation and restriction as 2-byte offsets from a base column per row block, the
+ * few columns outside a block's 16-bit window kept in a per-block list (a matrix with more
+ * than 1/8 of its entries outside keeps its plain 4-byte columns). mode 1 (the default) reads
+ * the packed columns of matrices with at least 2^24 entries, which stream from HBM (smaller
+ * ones stay in the last-level cache, where the packing does not pay); mode 2 reads them for
+ * every matrix whose packing fits; mode 0 never. The products and their order are those of
+ * the plain CSR walk, so results are bitwise the same in every mode. Drops the captured
+ * solve graphs. */
+int amgg_set_packed_columns(amgg_ctx* ctx, int mode);
 
 /* The same operator, launched so that the kernel itself records start_event when it begins
  * and stop_event when it ends (both hipEvent_t created by the caller with timing enabled;

@@ -331,8 +331,8 @@ def amgg_level_apply(ctx, lvl, op, precision, x, y, f, stream):
     return _check(lib().amgg_level_apply(ctx, lvl, op, precision, x, y, f, stream), "amgg_level_apply")
 
 
-def amgg_set_packed_columns(ctx, enable):
-    return _check(lib().amgg_set_packed_columns(ctx, int(enable)), "amgg_set_packed_columns")
+def amgg_set_packed_columns(ctx, mode):
+    return _check(lib().amgg_set_packed_columns(ctx, int(mode)), "amgg_set_packed_columns")
 
 
 def amgg_set_fusion(ctx, enable):

@@ -532,9 +532,9 @@ extern "C" int amgg_set_fusion(amgg_ctx* c, int enable) {
     return AMGG_OK;
 }
 
-extern "C" int amgg_set_packed_columns(amgg_ctx* c, int enable) {
-    if (!c) return fail(AMGG_EINVAL, "amgg_set_packed_columns: null context");
-    for (int l = 0; l < c->nlevels; ++l) c->lv[l].pack = enable != 0;
+extern "C" int amgg_set_packed_columns(amgg_ctx* c, int mode) {
+    if (!c || mode < 0 || mode > 2) return fail(AMGG_EINVAL, "amgg_set_packed_columns: null context or bad mode");
+    for (int l = 0; l < c->nlevels; ++l) c->lv[l].pack = mode;
     drop_graphs(c);
     return AMGG_OK;
 }
@@ -563,7 +563,7 @@ extern "C" int amgg_level_view_get(const amgg_ctx* c, int lvl, amgg_level_view* 
     v->fused_rows = L.hrows;
     const Level::Pack* packs[3] = {&L.pa, &L.pp, &L.pr};
     for (int k = 0; k < 3; ++k) {
-        const bool use = packs[k]->usable() && (k == 0 || !coarse);
+        const bool use = packs[k]->view(L.pack, k == 0 ? L.nnz : L.pnnz).off != nullptr && (k == 0 || !coarse);
         v->pack_rows[k] = use ? packs[k]->rows : 0;
         v->pack_far[k] = use ? packs[k]->nfar : 0;
     }

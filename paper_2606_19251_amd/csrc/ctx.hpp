@@ -74,13 +74,15 @@ struct Level {
         int64_t cap = 0;    // far-entry capacity
         int64_t nfar = -1;  // far entries found at finalize (-1: not built)
         bool usable() const { return rows > 0 && nfar >= 0 && nfar <= cap; }
-        ColPack view(bool on) const {
-            if (!on || !usable()) return ColPack{};
+        // mode 0: plain columns; 1: packed for matrices of at least kPackMinEntries entries;
+        // 2: packed wherever the packing fits
+        ColPack view(int mode, int32_t nz) const {
+            if (mode == 0 || !usable() || (mode == 1 && nz < kPackMinEntries)) return ColPack{};
             return ColPack{off, base, foff, fslot, fcol, rows};
         }
     };
     Pack pa, pp, pr;
-    bool pack = true;  // read packed columns where available
+    int pack = 1;  // packing mode of the CSR-stream kernels (see Pack::view)
     // adjoint scratch, kAdjVecs vectors of n per precision (see AdjVec)
     double* adj64[8] = {};
     float* adj32[8] = {};
@@ -103,9 +105,9 @@ struct Level {
     int degree = 0;
     bool baseline = false;  // exactly the omega = 2/3 Jacobi smoother (the fallback target)
 
-    CsrView A() const { return {n, nnz, ptr, col, lanes_for(n, nnz), pa.view(pack)}; }
-    CsrView P() const { return {n, pnnz, pptr, pcol, lanes_for(n, pnnz), pp.view(pack)}; }
-    CsrView R() const { return {nc, pnnz, rptr, rcol, lanes_for(nc, pnnz), pr.view(pack)}; }
+    CsrView A() const { return {n, nnz, ptr, col, lanes_for(n, nnz), pa.view(pack, nnz)}; }
+    CsrView P() const { return {n, pnnz, pptr, pcol, lanes_for(n, pnnz), pp.view(pack, pnnz)}; }
+    CsrView R() const { return {nc, pnnz, rptr, rcol, lanes_for(nc, pnnz), pr.view(pack, pnnz)}; }
     HaloView H() const { return {hrows, hoff, halo, hend, heoff, hcol, hloc}; }
     template <typename T> const T* hav() const { if constexpr (std::is_same_v<T, double>) return ha64; else return ha32; }
     template <typename T> const T* hqv() const { if constexpr (std::is_same_v<T, double>) return hq64; else return hq32; }

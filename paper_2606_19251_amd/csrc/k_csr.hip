@@ -119,28 +119,29 @@ __device__ __forceinline__ void stream_products_g(int32_t ne, const T* __restric
 }
 
 // The same products from packed columns (ColPack): a round loads 2-byte offsets instead of
-// 4-byte columns; a far entry (offset kFarCol) is neither gathered nor stored here, and
-// far_products then writes its product into its own slot from the block's far list, so every
-// slot ends up holding exactly the product of the plain walk.
+// 4-byte columns. A far entry (offset kFarCol) gathers the block's base column instead (in
+// range, and branch-free, so that all gathers of a round stay in flight together); after a
+// barrier far_products overwrites its slot from the block's far list, so every slot ends up
+// holding exactly the product of the plain walk.
 template <typename T, class Gather>
 __device__ __forceinline__ void stream_products_packed(int32_t ne, const T* __restrict__ m,
                                                        const uint16_t* __restrict__ off, int32_t cbase, Gather gather,
                                                        T* __restrict__ out) {
     for (int32_t base = 0; base < ne; base += kChunk * kBlock) {
         T v[kChunk];
-        uint32_t o[kChunk];
+        int32_t c[kChunk];
 #pragma unroll
         for (int q = 0; q < kChunk; ++q) {
             const int32_t k = min(base + static_cast<int32_t>(threadIdx.x) + q * kBlock, ne - 1);
             v[q] = m[k];
-            o[q] = off[k];
+            const uint32_t o = off[k];
+            c[q] = cbase + static_cast<int32_t>(o == kFarCol ? 0u : o);
         }
         T p[kChunk];
 #pragma unroll
-        for (int q = 0; q < kChunk; ++q) p[q] = o[q] != kFarCol ? v[q] * gather(cbase + static_cast<int32_t>(o[q])) : T(0);
+        for (int q = 0; q < kChunk; ++q) p[q] = v[q] * gather(c[q]);
 #pragma unroll
-        for (int q = 0; q < kChunk; ++q)
-            if (o[q] != kFarCol) out[base + static_cast<int32_t>(threadIdx.x) + q * kBlock] = p[q];
+        for (int q = 0; q < kChunk; ++q) out[base + static_cast<int32_t>(threadIdx.x) + q * kBlock] = p[q];
     }
 }
 
@@ -160,8 +161,12 @@ __device__ __forceinline__ void block_products(int32_t b, int32_t e0, int32_t ne
                                                const int32_t* __restrict__ col, const ColPack& cp, Gather gather,
                                                T* __restrict__ out) {
     if constexpr (PACKED) {
+        const int32_t f0 = cp.foff[b], f1 = cp.foff[b + 1];
         stream_products_packed<T>(ne, val + e0, cp.off + e0, cp.base[b], gather, out);
-        far_products<T>(cp.foff[b], cp.foff[b + 1], val + e0, cp.fslot, cp.fcol, gather, out);
+        if (f1 > f0) {  // uniform over the workgroup
+            __syncthreads();  // the stand-in products of the far slots are stored
+            far_products<T>(f0, f1, val + e0, cp.fslot, cp.fcol, gather, out);
+        }
     } else {
         stream_products_g<T>(ne, val + e0, col + e0, gather, out);
     }

@@ -84,6 +84,12 @@ hipError_t pack_columns(int32_t nrows, int32_t nnz, const int32_t* ptr, const in
                         int32_t* base, int32_t* foff, uint16_t* fslot, int32_t* fcol, int64_t cap, int32_t* parts,
                         int64_t* nfar, hipStream_t stream);
 constexpr int64_t kScanPartsMax = 1024;  // scratch of pack_columns: kScanPartsMax + 1 ints
+// Matrices with fewer entries keep their plain columns: measured on one MI355X, packing pays only
+// where a pass streams its matrix from HBM (8M-cell mesh: fine-level residual 91 -> 84 us,
+// solves 1-3 % faster); a matrix that stays in the 256 MB last-level cache is latency-bound,
+// and there the far-entry pass costs more than the saved bytes (1M P1 mesh: solves 2-5 %
+// slower with every matrix packed). 2^24 entries = 128 MB of FP32 values and plain columns.
+constexpr int32_t kPackMinEntries = 1 << 24;
 
 int lanes_for(int32_t nrows, int32_t nnz);
 

@@ -179,8 +179,9 @@ class DeviceSolver:
     def set_fusion(self, enable: bool):
         capi.amgg_set_fusion(self.ctx, enable)
 
-    def set_packed_columns(self, enable: bool):
-        capi.amgg_set_packed_columns(self.ctx, enable)
+    def set_packed_columns(self, mode: int):
+        """0: plain columns; 1: packed for matrices of >= 2^24 entries (default); 2: packed wherever built."""
+        capi.amgg_set_packed_columns(self.ctx, mode)
 
     def close(self):
         if self.ctx:

@@ -10,7 +10,8 @@ columns. Cases:
 - a 300 x 300 grid with 2 % of its unknowns swapped at random (far entries well inside the
   capacity, clustered in few blocks, many far entries per block);
 - the same grid randomly permuted (nearly every entry far: over capacity, plain columns).
-Checked with packing on and off: every level operator in FP32 and FP64, one V-cycle in both
+Packing is forced on every matrix here (mode 2: these matrices are below the size from which
+the default mode packs). Checked with packing on and off: every level operator in FP32 and FP64, one V-cycle in both
 precisions, and an FP32-cycle / FP64 flexible-CG solve (same iterations, bitwise the same x);
 and, packed, the FP64 fine-level residual bitwise against the oracle's sparse product.
 """
@@ -58,6 +59,7 @@ def _case(kind):
             f = W.rhs_uniform(A.nrows, 6)
         hp = HostHierarchy.build(A.rowptr, A.col, A.val, max_levels=10, max_coarse=500)
         ds = DeviceSolver(hp, 0)
+        ds.set_packed_columns(2)  # these matrices are below the default size threshold
         views = [ds.level_view(l) for l in range(ds.nlevels)]
         print(f"[gpu] packed {kind}: levels {[L.n for L in hp.levels]}, packing rows (A,P,R) "
               f"{[v['pack_rows'] for v in views]}, far {[v['pack_far'] for v in views]}", flush=True)
@@ -101,14 +103,14 @@ def test_level_operators_bitwise_packed_vs_plain(kind, precision):
             fv = torch.from_numpy(rng.standard_normal(n)).to(dt).cuda()
             y0 = torch.from_numpy(rng.standard_normal(nout)).to(dt).cuda()
             out = []
-            for packed in (True, False):
+            for packed in (2, 0):
                 ds.set_packed_columns(packed)
                 y = y0.clone()
                 capi.amgg_level_apply(ds.ctx, l, op, precision, x.data_ptr(), y.data_ptr(), fv.data_ptr(), ds.stream)
                 torch.cuda.synchronize()
                 out.append(y.cpu().numpy())
             assert np.array_equal(_bits(out[0]), _bits(out[1])), (kind, precision, l, op)
-    ds.set_packed_columns(True)
+    ds.set_packed_columns(2)
 
 
 @pytest.mark.parametrize("kind", ["tet146k", "grid_swap"])
@@ -119,7 +121,7 @@ def test_cycles_and_solve_bitwise_packed_vs_plain(kind):
     ds.set_coeffs(np.array([0.6, 0.01, -0.001, 0.12, 0.01]), 2)
     u0 = np.random.default_rng(8).standard_normal(A.nrows)
     res = {}
-    for packed in (True, False):
+    for packed in (2, 0):
         ds.set_packed_columns(packed)
         out = []
         for precision in (64, 32):
@@ -129,8 +131,8 @@ def test_cycles_and_solve_bitwise_packed_vs_plain(kind):
         x, rc, info, _ = ds.solve(torch.from_numpy(f).cuda(), outer=capi.AMGG_OUTER_FCG, precision=32, tol=1e-8)
         assert rc == 0
         res[packed] = (out, x.cpu().numpy(), info.iterations)
-    ds.set_packed_columns(True)
-    (o1, x1, k1), (o0, x0, k0) = res[True], res[False]
+    ds.set_packed_columns(2)
+    (o1, x1, k1), (o0, x0, k0) = res[2], res[0]
     assert k1 == k0
     assert np.array_equal(_bits(x1), _bits(x0))
     for a, b in zip(o1, o0):
@@ -150,3 +152,13 @@ def test_packed_fp64_residual_bitwise_oracle(kind):
     torch.cuda.synchronize()
     ref = f - amg.to_scipy(A) @ x
     assert np.array_equal(_bits(y.cpu().numpy()), _bits(ref))
+
+
+def test_default_mode_packs_only_large_matrices():
+    """Mode 1 (the default) reads packed columns only for matrices of at least 2^24 entries."""
+    _, _, hp, ds, _ = _case("tet146k")
+    ds.set_packed_columns(1)
+    v = ds.level_view(0)
+    assert v["pack_rows"] == [0, 0, 0]
+    ds.set_packed_columns(2)
+    assert ds.level_view(0)["pack_rows"][0] > 0
