@@ -54,11 +54,12 @@ def col_bytes(view, which: int, nz: int, nrows: int) -> int:
     return 2 * nz + 6 * view["pack_far"][which] + 8 * ((nrows + rows - 1) // rows)
 
 
-def level_bytes_vcycle(h, views, smoother_sparse: bool, bv: int = 4) -> float:
+def level_bytes_vcycle(h, views, smoother_sparse: bool, bv: int = 4, diag_levels: int = 0) -> float:
     """Algorithmic HBM bytes of one V(1,1) preconditioner cycle (u = 0 on entry) on the hierarchy:
     every matrix entry read once per pass (value plus column index, packed where the level has
     packed columns; levels served by the fused halo kernels read plain columns), every vector
-    once per pass (gathers counted once)."""
+    once per pass (gathers counted once). With the sparse smoother, the `diag_levels` finest
+    levels take the one-pass diagonal step (the diagonal form of Eq. 5)."""
     total = 0.0
     L = h.nlevels
     for l, lev in enumerate(h.levels):
@@ -74,7 +75,7 @@ def level_bytes_vcycle(h, views, smoother_sparse: bool, bv: int = 4) -> float:
         resid = apass + 3 * n * bv
         restrict = p * bv + col_bytes(v, 2, p, nc) + 4 * (nc + 1) + n * bv + nc * bv
         prolong = p * bv + col_bytes(v, 1, p, n) + 4 * (n + 1) + nc * bv + 2 * n * bv
-        if smoother_sparse:
+        if smoother_sparse and l >= diag_levels:
             pre = apass + 2 * n * bv                 # u = Q f
             post = resid + apass + 3 * n * bv         # r = f - A u ; u += Q r
             total += pre + resid + restrict + prolong + post
@@ -284,15 +285,23 @@ def finish_cpu_baseline(job, gpu_iters, workload_desc, limit_s):
     return out
 
 
+# Each mesh family's GCIN weights. The first is the network the GCIN rows of the JSON line use: on
+# the 1M P1 and 8M tetrahedral meshes the cost-aware one, trained with the diagonal form of Eq. 5
+# (f_o = 0) on the 3 / 2 finest levels, where the sparse smoother's second matrix pass costs the
+# most; the second (where given) is the network with the sparse form on every level, reported as
+# `gnn_sparse_all_levels`.
 WORKLOADS = {
-    "delaunay1m": ("gcin_deg2.npz", "P1 Laplacian on the Delaunay mesh of 1,000,000 points in the unit square, "
-                                    "all-Neumann"),
-    "tet8m": ("gcin_tet_deg2.npz", "FV Poisson on the Kuhn tetrahedra of a jittered 111^3 lattice "
-                                   "(7,986,000 cells), all-Neumann"),
+    "delaunay1m": ("gcin_deg2_d3.npz", "P1 Laplacian on the Delaunay mesh of 1,000,000 points in the unit square, "
+                                       "all-Neumann"),
+    "tet8m": ("gcin_tet_deg2_d2.npz", "FV Poisson on the Kuhn tetrahedra of a jittered 111^3 lattice "
+                                      "(7,986,000 cells), all-Neumann"),
     "cmesh4m": ("gcin_cmesh_deg2.npz", "FV Poisson on a 4096 x 1024 C-mesh around NACA 2412, wall aspect 1e4"),
     "grid1m": ("gcin_grid_h32_deg2.npz", "5-point Laplacian on a 1024 x 1024 structured grid, Dirichlet "
                                          "(32-channel GCIN)"),
 }
+
+
+SPARSE_ALL_LEVELS = {"delaunay1m": "gcin_deg2.npz", "tet8m": "gcin_tet_deg2.npz"}
 
 
 def make_workload(name):
@@ -379,16 +388,23 @@ class Case:
         s.record()
         for _ in range(3):
             self.coeffs = self.pred.predict(self.hh, self.ds)
-            self.ds.set_coeffs_device(self.coeffs, self.pred.degree)
+            self.ds.set_coeffs_device(self.coeffs, self.pred.degree, diag_levels=self.pred.diag_levels)
         e.record()
         torch.cuda.synchronize()
         self.gnn_setup_ms = s.elapsed_time(e) / 3
+        self.pred_sparse = self.coeffs_sparse = None
+        if name in SPARSE_ALL_LEVELS:  # the network with the sparse form of Eq. 5 on every level
+            self.pred_sparse = G.Predictor.load(os.path.join(ROOT, "paper_2606_19251_amd", "weights",
+                                                             SPARSE_ALL_LEVELS[name]), self.dev)
+            self.coeffs_sparse = self.pred_sparse.predict(self.hh, self.ds)
 
     def set(self, smoother):
         if smoother == "jacobi":
             self.ds.set_jacobi(2.0 / 3.0)
+        elif smoother == "gnn_sparse_all_levels":
+            self.ds.set_coeffs_device(self.coeffs_sparse, self.pred_sparse.degree, diag_levels=0)
         else:
-            self.ds.set_coeffs_device(self.coeffs, self.pred.degree)
+            self.ds.set_coeffs_device(self.coeffs, self.pred.degree, diag_levels=self.pred.diag_levels)
 
     def solves(self, smoother, outer, steps, warmup, nu=1):
         from paper_2606_19251_amd import capi
@@ -554,14 +570,22 @@ def workload_report(torch, case, steps, warmup, nu, outers, with_roofline=True):
            "level_nnz": [L.nnz for L in hh.levels], "configured_outer": CONFIGURED_OUTER[case.name],
            "vcycle_bytes": {k: int(v) for k, v in vbytes.items()},
            "packed_columns": [{"rows": v["pack_rows"], "far": v["pack_far"]} for v in views]}
+    vbytes["gnn_sparse_all_levels"] = vbytes["gnn"]
+    if case.pred.diag_levels > 0:  # the cost-aware network: one-pass diagonal steps on its finest levels
+        vbytes["gnn"] = level_bytes_vcycle(hh, views, smoother_sparse=True, diag_levels=case.pred.diag_levels)
+    out["gnn_diag_levels"] = case.pred.diag_levels
     for outer in outers:
         res = {}
-        for sm in ("jacobi", "gnn"):
+        smoothers = ("jacobi", "gnn") + (("gnn_sparse_all_levels",) if case.pred_sparse is not None else ())
+        for sm in smoothers:
             k, w = (steps, warmup) if outer == CONFIGURED_OUTER[case.name] else (max(3, steps // 2), 1)
             r = case.solves(sm, code[outer], k, w, nu)
             moved = r["vcycles"] * vbytes[sm] + r["iterations"] * obytes[outer]
             r["solve_gbs_algorithmic"] = round(moved / (r["ms"] * 1e-3) / 1e9, 1)
             res[sm] = r
+        if "gnn_sparse_all_levels" in res:
+            res["gnn_sparse_all_levels_over_jacobi_time"] = round(res["gnn_sparse_all_levels"]["ms"] /
+                                                                  res["jacobi"]["ms"], 4)
         res["gnn"]["setup_ms"] = round(case.gnn_setup_ms, 3)
         res["gnn"]["setup_first_ms"] = round(case.gnn_setup_first_ms, 3)
         res["gnn_over_jacobi_time"] = round(res["gnn"]["ms"] / res["jacobi"]["ms"], 4)
@@ -685,6 +709,8 @@ def run(args, cpu_job):
         "gnn": gnn,
         "gnn_over_jacobi_time": head[outer]["gnn_over_jacobi_time"],
         "gnn_over_jacobi_vcycles": round(gnn["vcycles"] / jac["vcycles"], 4),
+        "gnn_diag_levels": head["gnn_diag_levels"],
+        "gnn_sparse_all_levels": head[outer].get("gnn_sparse_all_levels"),
         "roofline": head["roofline"],
         args.workload: head,
     }

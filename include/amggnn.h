@@ -194,6 +194,15 @@ int amgg_set_smoother_coeffs(amgg_ctx* ctx, int lvl, int degree, const double* c
 /* Device coefficients (FP32, 2*degree+1 values, e.g. straight from the GCIN output):
  * always assembled as a general sparse smoother; no host synchronisation. */
 int amgg_set_smoother_coeffs_device(amgg_ctx* ctx, int lvl, int degree, const float* coeffs_dev, void* stream);
+/* The diagonal form of Eq. 5 from device coefficients (diagonal != 0): f_o is taken as 0 whatever
+ * the off-diagonal coefficients hold, so Q^{-1} is the diagonal q_ii = f_d(a_ii/s)/a_ii, the cycle
+ * uses the one-pass diagonal step on the level, and the coefficient gradients of
+ * amgg_vcycle_loss_adjoint(_blocks) for o1..o_deg are 0 there (they are no parameters of the
+ * level). A member of the Eq. 5 family chosen for cost: on the large levels the sparse Q^{-1}
+ * adds a second pass over the level's matrix to every smoothing step. diagonal == 0 is
+ * amgg_set_smoother_coeffs_device. */
+int amgg_set_smoother_coeffs_device_form(amgg_ctx* ctx, int lvl, int degree, const float* coeffs_dev, int diagonal,
+                                         void* stream);
 /* omega-Jacobi, the paper's baseline (Sec. 2.3, Eq. 4; Sec. 4: omega = 2/3) = coeffs (omega, 0, ..). */
 int amgg_set_smoother_jacobi(amgg_ctx* ctx, int lvl, double omega, void* stream);
 
@@ -328,6 +337,9 @@ int amgg_set_level_blocks(amgg_ctx* ctx, int lvl, int32_t nblk, const int32_t* o
  * all problems, one row per level graph; stride >= 2*degree+1). */
 int amgg_set_smoother_coeffs_blocks(amgg_ctx* ctx, int lvl, int degree, const float* coeffs_dev,
                                     int32_t stride, void* stream);
+/* The same with the form of amgg_set_smoother_coeffs_device_form for every block of the level. */
+int amgg_set_smoother_coeffs_blocks_form(amgg_ctx* ctx, int lvl, int degree, const float* coeffs_dev,
+                                         int32_t stride, int diagonal, void* stream);
 /* amgg_vcycle_loss_adjoint of every block at once: loss_dev[b] (device FP64, nblk) is block
  * b's loss, and the gradient of block b's loss with respect to the coefficients of level l
  * is added to row coeff_rows_l[b] of dcoeffs_dev (device FP64, dcoeff_rows x (2*degree+1),

@@ -90,6 +90,7 @@ SIGNATURES = {
     "amgg_level_view_get": (_I, [_VP, _I, C.POINTER(amgg_level_view)]),
     "amgg_set_smoother_coeffs": (_I, [_VP, _I, _I, _VP, _VP]),
     "amgg_set_smoother_coeffs_device": (_I, [_VP, _I, _I, _VP, _VP]),
+    "amgg_set_smoother_coeffs_device_form": (_I, [_VP, _I, _I, _VP, _I, _VP]),
     "amgg_set_smoother_jacobi": (_I, [_VP, _I, C.c_double, _VP]),
     "amgg_vcycle": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP]),
     "amgg_level_apply": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _VP]),
@@ -100,6 +101,7 @@ SIGNATURES = {
     "amgg_vcycle_loss_adjoint": (_I, [_VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _VP]),
     "amgg_set_level_blocks": (_I, [_VP, _I, _I32, _VP, _VP, _VP]),
     "amgg_set_smoother_coeffs_blocks": (_I, [_VP, _I, _I, _VP, _I32, _VP]),
+    "amgg_set_smoother_coeffs_blocks_form": (_I, [_VP, _I, _I, _VP, _I32, _I, _VP]),
     "amgg_vcycle_loss_adjoint_blocks": (_I, [_VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _I32, _VP]),
     "amgg_chain_loss_grad": (_I, [C.c_int32, C.c_int32, _VP, _VP, _VP, _VP, _VP]),
     "amgg_validation_metric": (_I, [C.c_int32, _VP, _VP, _VP, _VP]),
@@ -319,6 +321,11 @@ def amgg_set_smoother_coeffs_device(ctx, lvl, degree, coeffs_dev, stream):
                   "amgg_set_smoother_coeffs_device")
 
 
+def amgg_set_smoother_coeffs_device_form(ctx, lvl, degree, coeffs_dev, diagonal, stream):
+    return _check(lib().amgg_set_smoother_coeffs_device_form(ctx, lvl, degree, coeffs_dev, int(diagonal), stream),
+                  "amgg_set_smoother_coeffs_device_form")
+
+
 def amgg_set_smoother_jacobi(ctx, lvl, omega, stream):
     return _check(lib().amgg_set_smoother_jacobi(ctx, lvl, omega, stream), "amgg_set_smoother_jacobi")
 
@@ -368,6 +375,12 @@ def amgg_set_level_blocks(ctx, lvl, offsets, coeff_rows=None, singular=None):
 def amgg_set_smoother_coeffs_blocks(ctx, lvl, degree, coeffs_dev, stride, stream):
     return _check(lib().amgg_set_smoother_coeffs_blocks(ctx, lvl, degree, coeffs_dev, stride, stream),
                   "amgg_set_smoother_coeffs_blocks")
+
+
+def amgg_set_smoother_coeffs_blocks_form(ctx, lvl, degree, coeffs_dev, stride, diagonal, stream):
+    return _check(lib().amgg_set_smoother_coeffs_blocks_form(ctx, lvl, degree, coeffs_dev, stride, int(diagonal),
+                                                             stream),
+                  "amgg_set_smoother_coeffs_blocks_form")
 
 
 def amgg_vcycle_loss_adjoint_blocks(ctx, nu1, nu2, precision, nvc, f, u0, loss_dev, dcoeffs_dev, dcoeff_rows,

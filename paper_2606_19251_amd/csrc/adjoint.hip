@@ -158,8 +158,10 @@ __global__ __launch_bounds__(kBlock) void adj_smooth_blocks_kernel(
 }
 
 // cbar[crow[b]][m] += sum of block b's chunk partials (in chunk order), one workgroup per block.
+// The first nkeep of each row's ncoef gradients are accumulated (the diagonal form of Eq. 5 keeps
+// d0..d_deg only: its off-diagonal coefficients are no parameters and keep a zero gradient).
 __global__ __launch_bounds__(kBlock) void adj_coeff_reduce_blocks_kernel(const double* __restrict__ partial,
-                                                                        int32_t nchunk, int ncoef,
+                                                                        int32_t nchunk, int ncoef, int nkeep,
                                                                         const int32_t* __restrict__ blk_chunk,
                                                                         const int32_t* __restrict__ crow,
                                                                         double* __restrict__ cbar) {
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void adj_coeff_reduce_blocks_kernel(const d
     const int32_t row = crow[b];
     if (row < 0) return;  // uniform over the workgroup
     const int32_t c0 = blk_chunk[b], c1 = blk_chunk[b + 1];
-    for (int m = 0; m < ncoef; ++m) {
+    for (int m = 0; m < nkeep; ++m) {
         double v = 0.0;
         for (int32_t k = c0 + threadIdx.x; k < c1; k += kBlock) v += partial[m * nchunk + k];
         v = block_sum(v);
@@ -214,10 +216,10 @@ __global__ void scale_blocks_kernel(int32_t n, T* __restrict__ y, int32_t nblk, 
     if (i < n) y[i] = static_cast<T>(static_cast<double>(y[i]) * s[block_of_row(i, nblk, off)]);
 }
 
-__global__ __launch_bounds__(kBlock) void adj_coeff_reduce_kernel(const double* __restrict__ partial, int ncoef,
+__global__ __launch_bounds__(kBlock) void adj_coeff_reduce_kernel(const double* __restrict__ partial, int nkeep,
                                                                  double* __restrict__ cbar) {
     __shared__ double red[kBlock];
-    for (int m = 0; m < ncoef; ++m) {
+    for (int m = 0; m < nkeep; ++m) {
         double v = 0.0;
         for (int k = threadIdx.x; k < kReduceBlocks; k += kBlock) v += partial[m * kReduceBlocks + k];
         red[threadIdx.x] = v;
@@ -324,13 +326,15 @@ struct Adj {
                                                                 L.col, L.val, L.diag, L.qval<T>(), ub, r, tq, deg,
                                                                 c->blk_partial);
             ok(hipGetLastError());
-            adj_coeff_reduce_blocks_kernel<<<L.nblk, kBlock, 0, st>>>(c->blk_partial, nch, 2 * deg + 1, L.blk_chunk,
-                                                                      L.blk_crow, cbar);
+            adj_coeff_reduce_blocks_kernel<<<L.nblk, kBlock, 0, st>>>(c->blk_partial, nch, 2 * deg + 1,
+                                                                      L.diag_form ? deg + 1 : 2 * deg + 1,
+                                                                      L.blk_chunk, L.blk_crow, cbar);
         } else {
             adj_smooth_kernel<T><<<kReduceBlocks, kBlock, 0, st>>>(L.n, L.ptr, L.col, L.val, L.diag, L.scale,
                                                                     L.qval<T>(), ub, r, tq, deg, c->adj_partial);
             ok(hipGetLastError());
-            adj_coeff_reduce_kernel<<<1, kBlock, 0, st>>>(c->adj_partial, 2 * deg + 1, cbar + l * (2 * deg + 1));
+            adj_coeff_reduce_kernel<<<1, kBlock, 0, st>>>(c->adj_partial, L.diag_form ? deg + 1 : 2 * deg + 1,
+                                                          cbar + l * (2 * deg + 1));
         }
         ok(hipGetLastError());
         axpy<T>(L.n, tq, L.adj<T>(kAdjFbar));

@@ -573,14 +573,16 @@ extern "C" int amgg_level_view_get(const amgg_ctx* c, int lvl, amgg_level_view* 
 // ------------------------------------------------------------------------------------
 // Smoother
 // ------------------------------------------------------------------------------------
-static int set_coeffs_impl(amgg_ctx* c, int lvl, int degree, const double* coeffs, const float* dev, void* stream) {
+static int set_coeffs_impl(amgg_ctx* c, int lvl, int degree, const double* coeffs, const float* dev, void* stream,
+                           int diag_only = 0) {
     if (!c || lvl < 0 || lvl >= c->nlevels) return fail(AMGG_EINVAL, "amgg_set_smoother: bad context or level");
     if (!c->finalized) return fail(AMGG_ESTATE, "amgg_set_smoother: hierarchy not finalized");
     if (degree < 1 || degree > AMGG_MAX_DEGREE) return fail(AMGG_EINVAL, "amgg_set_smoother: degree out of range");
     if (!coeffs && !dev) return fail(AMGG_EINVAL, "amgg_set_smoother: null coefficients");
     PolyCoeffs pc{};
     pc.degree = degree;
-    bool diagonal = false, baseline = false;
+    pc.diag_only = diag_only ? 1 : 0;
+    bool diagonal = diag_only != 0, baseline = false;
     if (coeffs) {
         diagonal = true;
         baseline = coeffs[0] == 2.0 / 3.0;
@@ -606,6 +608,7 @@ static int set_coeffs_impl(amgg_ctx* c, int lvl, int degree, const double* coeff
     L.smoother = diagonal ? kSmootherDiagonal : kSmootherSparse;
     L.degree = degree;
     L.baseline = baseline;
+    L.diag_form = diag_only != 0;
     return AMGG_OK;
 }
 
@@ -618,13 +621,18 @@ extern "C" int amgg_set_smoother_coeffs_device(amgg_ctx* c, int lvl, int degree,
     return guarded([&] { return set_coeffs_impl(c, lvl, degree, nullptr, coeffs_dev, stream); });
 }
 
+extern "C" int amgg_set_smoother_coeffs_device_form(amgg_ctx* c, int lvl, int degree, const float* coeffs_dev,
+                                                    int diagonal, void* stream) {
+    return guarded([&] { return set_coeffs_impl(c, lvl, degree, nullptr, coeffs_dev, stream, diagonal ? 1 : 0); });
+}
+
 extern "C" int amgg_set_smoother_jacobi(amgg_ctx* c, int lvl, double omega, void* stream) {
     double cf[3] = {omega, 0.0, 0.0};
     return guarded([&] { return set_coeffs_impl(c, lvl, 1, cf, nullptr, stream); });
 }
 
-extern "C" int amgg_set_smoother_coeffs_blocks(amgg_ctx* c, int lvl, int degree, const float* coeffs_dev,
-                                               int32_t stride, void* stream) {
+static int set_coeffs_blocks_impl(amgg_ctx* c, int lvl, int degree, const float* coeffs_dev, int32_t stride,
+                                  int diag_only, void* stream) {
     return guarded([&]() -> int {
         if (!c || lvl < 0 || lvl >= c->nlevels) return fail(AMGG_EINVAL, "amgg_set_smoother_coeffs_blocks: bad level");
         if (!c->finalized) return fail(AMGG_ESTATE, "amgg_set_smoother_coeffs_blocks: hierarchy not finalized");
@@ -634,6 +642,7 @@ extern "C" int amgg_set_smoother_coeffs_blocks(amgg_ctx* c, int lvl, int degree,
             return fail(AMGG_EINVAL, "amgg_set_smoother_coeffs_blocks: bad degree, stride or null coefficients");
         PolyCoeffs pc{};
         pc.degree = degree;
+        pc.diag_only = diag_only ? 1 : 0;
         const hipStream_t st = static_cast<hipStream_t>(stream);
         hipError_t e = hipSetDevice(c->device);
         if (e == hipSuccess)
@@ -641,11 +650,22 @@ extern "C" int amgg_set_smoother_coeffs_blocks(amgg_ctx* c, int lvl, int degree,
                                          pc, coeffs_dev, stride, L.q64, L.q32, L.qd64, L.qd32, st);
         if (e == hipSuccess && L.hrows > 0) e = gather_values(L.nhent, L.hent, L.q64, L.q32, L.hq64, L.hq32, st);
         if (e != hipSuccess) return hip_fail(e, "amgg_set_smoother_coeffs_blocks");
-        L.smoother = kSmootherSparse;
+        L.smoother = diag_only ? kSmootherDiagonal : kSmootherSparse;
         L.degree = degree;
         L.baseline = false;
+        L.diag_form = diag_only != 0;
         return AMGG_OK;
     });
+}
+
+extern "C" int amgg_set_smoother_coeffs_blocks(amgg_ctx* c, int lvl, int degree, const float* coeffs_dev,
+                                               int32_t stride, void* stream) {
+    return set_coeffs_blocks_impl(c, lvl, degree, coeffs_dev, stride, 0, stream);
+}
+
+extern "C" int amgg_set_smoother_coeffs_blocks_form(amgg_ctx* c, int lvl, int degree, const float* coeffs_dev,
+                                                    int32_t stride, int diagonal, void* stream) {
+    return set_coeffs_blocks_impl(c, lvl, degree, coeffs_dev, stride, diagonal ? 1 : 0, stream);
 }
 
 extern "C" int amgg_set_level_blocks(amgg_ctx* c, int lvl, int32_t nblk, const int32_t* offsets,

@@ -104,6 +104,8 @@ struct Level {
     int smoother = kSmootherNone;
     int degree = 0;
     bool baseline = false;  // exactly the omega = 2/3 Jacobi smoother (the fallback target)
+    bool diag_form = false; // diagonal form of Eq. 5 (f_o = 0): the off-diagonal coefficients are no
+                            // parameters of the level, their gradient is zero
 
     CsrView A() const { return {n, nnz, ptr, col, lanes_for(n, nnz), pa.view(pack, nnz)}; }
     CsrView P() const { return {n, pnnz, pptr, pcol, lanes_for(n, pnnz), pp.view(pack, pnnz)}; }

@@ -115,6 +115,10 @@ __global__ __launch_bounds__(kBlock) void assemble_stream_kernel(
             r = crow[b];
         }
         for (int k = 0; k < 2 * deg + 1; ++k) {
+            if (pc.diag_only && k > deg) {
+                cs[t][k] = 0.0;
+                continue;
+            }
             if constexpr (BLOCKS)
                 cs[t][k] = r < 0 ? 0.0
                            : coeffs_dev ? static_cast<double>(coeffs_dev[static_cast<int64_t>(r) * stride + k])

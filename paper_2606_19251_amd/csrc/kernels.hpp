@@ -233,6 +233,7 @@ hipError_t transpose_csr(int32_t nf, int32_t nc, int32_t nnz, const int32_t* p_p
 struct PolyCoeffs {
     double c[2 * 4 + 1];
     int degree;
+    int diag_only = 0;  // the diagonal form of Eq. 5: f_o taken as 0 whatever the coefficients say
 };
 // Eq. (5) smoother values on A's pattern; also the diagonal of Q^{-1} in both precisions.
 hipError_t assemble_smoother(int32_t n, const int32_t* ptr, const int32_t* col, const double* val,

@@ -132,7 +132,9 @@ class Predictor:
     """GCIN parameters on the device; predicts per-level smoother coefficients of a solver."""
 
     def __init__(self, flat: np.ndarray, device, degree: int = 2, precision: int = capi.GCIN_BF16,
-                 hidden: int = HIDDEN):
+                 hidden: int = HIDDEN, diag_levels: int = 0):
+        """diag_levels: the number of finest levels whose smoother takes the diagonal form of
+        Eq. 5 (f_o = 0), as the network was trained."""
         import torch
 
         self.torch = torch
@@ -140,6 +142,7 @@ class Predictor:
         self.degree = degree
         self.precision = precision
         self.hidden = hidden
+        self.diag_levels = int(diag_levels)
         if np.size(flat) != capi.gcin_param_count(degree, hidden):
             raise ValueError(f"{np.size(flat)} parameters do not fit degree {degree}, hidden width {hidden}")
         self.params = torch.from_numpy(np.ascontiguousarray(flat, np.float32)).to(device)
@@ -148,14 +151,18 @@ class Predictor:
     def load(cls, path, device, precision: int = capi.GCIN_BF16):
         z = np.load(path, allow_pickle=False)
         hidden = int(z["hidden"]) if "hidden" in z.files else HIDDEN
-        return cls(z["params"], device, int(z["degree"]), precision, hidden)
+        diag = int(z["diag_levels"]) if "diag_levels" in z.files else 0
+        return cls(z["params"], device, int(z["degree"]), precision, hidden, diag)
 
     def save(self, path):
-        np.savez(path, params=self.params.cpu().numpy(), degree=np.int64(self.degree), hidden=np.int64(self.hidden))
+        np.savez(path, params=self.params.detach().cpu().numpy(), degree=np.int64(self.degree),
+                 hidden=np.int64(self.hidden), diag_levels=np.int64(self.diag_levels))
 
     def predict(self, hier, ds):
         """Coefficients [nlevels, 2d+1] (float32 CUDA tensor) for a DeviceSolver's levels (an
-        inference-only graph batch: no activations are kept)."""
+        inference-only graph batch: no activations are kept). Also records on the solver the
+        number of finest levels that take the diagonal form (used by its set_coeffs_device)."""
+        ds.diag_levels = self.diag_levels
         batch = GraphBatch([ds.A[l] for l in range(ds.nlevels)], self.device, self.hidden, inference=True)
         out = batch.forward(self.params, self.degree, self.precision)
         self._last_batch = batch
@@ -171,7 +178,8 @@ class Trainer:
                  cycle_precision=32, streams=1, batched=True):
         """batched: cycle every problem in one block-diagonal context (one launch per level
         operation for the whole mini-batch); otherwise problem by problem, spread over
-        `streams` streams."""
+        `streams` streams. The predictor's diag_levels finest levels of every problem take the
+        diagonal form of Eq. 5 (their off-diagonal coefficients get a zero gradient)."""
         import torch
 
         self.torch = torch
@@ -203,10 +211,13 @@ class Trainer:
         # over that many streams (default priority) between two event joins
         self.side = [torch.cuda.Stream(device=dev) for _ in range(streams)] if streams > 1 and not batched else []
         self.bsolver = None
+        for ds in solvers:
+            ds.diag_levels = predictor.diag_levels
         if batched:
             from .solver import BatchSolver
 
             self.bsolver = BatchSolver([ds.hier for ds in solvers], dev.index or 0)
+            self.bsolver.diag_levels = predictor.diag_levels
             assert self.bsolver.ngraphs == self.batch.ngraphs
         # fork / join events live as long as the trainer: an event must outlive the waits
         # queued on it

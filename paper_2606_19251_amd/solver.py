@@ -141,6 +141,7 @@ class DeviceSolver:
         self.nlevels = hier.nlevels
         self.n = hier.levels[0].n
         self.singular = bool(hier.singular)
+        self.diag_levels = 0  # finest levels set in the diagonal form of Eq. 5 by set_coeffs_device
         self._keep = []
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(self.device)
         self.ctx = capi.amgg_create(device, self.nlevels)
@@ -202,14 +203,16 @@ class DeviceSolver:
         for l in (range(self.nlevels) if levels is None else levels):
             capi.amgg_set_smoother_coeffs(self.ctx, l, degree, coeffs[l], self.stream)
 
-    def set_coeffs_device(self, coeffs_dev, degree, stream=None):
+    def set_coeffs_device(self, coeffs_dev, degree, stream=None, diag_levels=None):
         """coeffs_dev: float32 CUDA tensor [nlevels, 2*degree+1]; queued on `stream` (a raw
-        hipStream_t, default: the solver's stream)."""
+        hipStream_t, default: the solver's stream). The `diag_levels` finest levels (default: the
+        solver's diag_levels attribute, 0) take the diagonal form of Eq. 5 (f_o = 0)."""
         assert coeffs_dev.dtype == self.torch.float32 and coeffs_dev.is_contiguous()
         stride = coeffs_dev.shape[1] * 4
         st = self.stream if stream is None else stream
+        k = self.diag_levels if diag_levels is None else diag_levels
         for l in range(self.nlevels):
-            capi.amgg_set_smoother_coeffs_device(self.ctx, l, degree, coeffs_dev.data_ptr() + l * stride, st)
+            capi.amgg_set_smoother_coeffs_device_form(self.ctx, l, degree, coeffs_dev.data_ptr() + l * stride, l < k, st)
 
     def set_jacobi(self, omega=2.0 / 3.0):
         for l in range(self.nlevels):
@@ -322,6 +325,7 @@ class BatchSolver:
         self.nblk = len(self.hiers)
         self.ngraphs = int(sum(h.nlevels for h in self.hiers))
         self.depth = bh.nlevels
+        self.diag_levels = 0  # finest super levels set in the diagonal form of Eq. 5
         # problem owning each coefficient row (row = level graph, problem-major), for the chain rule
         owner = np.repeat(np.arange(self.nblk, dtype=np.int32), [h.nlevels for h in self.hiers])
         self.row_problem = self.ds.torch.from_numpy(owner).to(self.ds.device)
@@ -330,14 +334,18 @@ class BatchSolver:
     def ctx(self):
         return self.ds.ctx
 
-    def set_coeffs_device(self, coeffs_dev, degree, stream=None):
+    def set_coeffs_device(self, coeffs_dev, degree, stream=None, diag_levels=None):
         """coeffs_dev: float32 CUDA tensor [ngraphs, 2*degree+1], one row per level graph of
-        every problem (problem-major), as the batched GCIN forward returns them."""
+        every problem (problem-major), as the batched GCIN forward returns them. Super level l
+        holds level l of every problem deep enough, so the `diag_levels` finest super levels
+        are each problem's finest levels (diagonal form of Eq. 5 there)."""
         assert coeffs_dev.dtype == self.ds.torch.float32 and coeffs_dev.is_contiguous()
         assert coeffs_dev.shape[0] == self.ngraphs
         st = self.ds.stream if stream is None else stream
+        k = self.diag_levels if diag_levels is None else diag_levels
         for l in range(self.depth - 1):
-            capi.amgg_set_smoother_coeffs_blocks(self.ctx, l, degree, coeffs_dev.data_ptr(), coeffs_dev.shape[1], st)
+            capi.amgg_set_smoother_coeffs_blocks_form(self.ctx, l, degree, coeffs_dev.data_ptr(), coeffs_dev.shape[1],
+                                                      l < k, st)
 
     def loss_adjoint(self, f_cat, losses, dcoeffs, nu=(1, 1), precision=32, nvc=1, stream=None):
         """Per-problem losses [nblk] and coefficient gradients [ngraphs, 2*degree+1] (FP64)."""

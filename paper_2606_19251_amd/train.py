@@ -159,7 +159,7 @@ def train_one(args, seed, train, val, dev):
     rhs_for = lambda problems, s: seeded_rhs(problems, s, dev)
 
     pred = G.Predictor(G.init_flat(args.degree, seed, hidden=args.hidden), dev, args.degree, capi.GCIN_BF16X3,
-                       args.hidden)
+                       args.hidden, getattr(args, "diag_levels", 0))
     nb = max(1, len(train) // args.batch)
     trainers = [G.Trainer(train[b * args.batch:(b + 1) * args.batch], rhs_for(train[b * args.batch:(b + 1) * args.batch], b),
                           pred, lr=args.lr, nu=nu, nvc=args.nvc) for b in range(nb)]
@@ -213,6 +213,8 @@ def main(argv=None):
     ap.add_argument("--seeds", type=int, default=1, help="independent initialisations; the best is kept")
     ap.add_argument("--family", choices=[*FAMILIES, "grid", "mixed"], default="delaunay")
     ap.add_argument("--hidden", type=int, choices=[64, 32], default=64, help="GCIN channels")
+    ap.add_argument("--diag-levels", type=int, default=0,
+                    help="finest levels whose smoother takes the diagonal form of Eq. 5 (f_o = 0)")
     args = ap.parse_args(argv)
 
     import torch
@@ -229,7 +231,8 @@ def main(argv=None):
         print(f"[train] seed {args.seed + k}: best validation {best:+.4f}", flush=True)
     vals = np.array([r[0] for r in runs])
     best, flat, history = runs[best_run(vals)]
-    np.savez(args.out, params=flat, degree=np.int64(args.degree), hidden=np.int64(args.hidden), nvc=np.int64(args.nvc),
+    np.savez(args.out, params=flat, degree=np.int64(args.degree), hidden=np.int64(args.hidden),
+             diag_levels=np.int64(args.diag_levels), nvc=np.int64(args.nvc),
              nu=np.int64(args.nu), family=args.family, history=json.dumps(history), ensemble_val=vals)
     print(f"[train] ensemble of {len(vals)}: validation mean {vals.mean():+.4f} std {vals.std():.4f} "
           f"best {best:+.4f}; saved {args.out}", flush=True)

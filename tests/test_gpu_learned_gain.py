@@ -35,6 +35,9 @@ def _meshes(family):
 
 
 @pytest.mark.parametrize("family,weights", [("delaunay", "gcin_deg2.npz"), ("tet", "gcin_tet_deg2.npz"),
+                                            # cost-aware networks: the diagonal form of Eq. 5 on the 3
+                                            # (P1) or 2 (tetrahedra) finest levels
+                                            ("delaunay", "gcin_deg2_d3.npz"), ("tet", "gcin_tet_deg2_d2.npz"),
                                             ("cmesh", "gcin_cmesh_deg2.npz"),
                                             # one model trained on the union of the three families (on
                                             # the C-meshes it gains nothing: Eq. 13 metric +0.008)
