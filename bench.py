@@ -654,9 +654,14 @@ def run(args, cpu_job):
     if args.profile_gcin:
         for _ in range(5):
             case.pred.predict(hh, ds)
+        # a plain copy of known size to calibrate byte counters (256 MiB read + 256 MiB written)
+        src = torch.ones(64 << 20, dtype=torch.float32, device=case.dev)
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
         torch.cuda.synchronize()
         log(f"profile-gcin: 5 GCIN forward passes over {hh.nlevels} levels "
-            f"({sum(L.n for L in hh.levels)} nodes, {sum(L.nnz for L in hh.levels)} entries)")
+            f"({sum(L.n for L in hh.levels)} nodes, {sum(L.nnz for L in hh.levels)} entries), 10 copies of 256 MiB")
         return
     if args.profile_kernels:
         # counter runs: the dominant kernel alone, and a plain copy of known size to calibrate
