@@ -178,6 +178,9 @@ typedef struct {
      * 16-bit window of their block, listed separately). */
     int32_t pack_rows[3];
     int64_t pack_far[3];
+    /* Products the CSR-stream kernels hold in LDS per workgroup for A_l (and Q_l), P_l and R_l:
+     * the largest row block rounded up to whole rounds of 2048, at most 4096. */
+    int32_t stream_cap[3];
 } amgg_level_view;
 int amgg_level_view_get(const amgg_ctx* ctx, int lvl, amgg_level_view* out);
 

@@ -41,7 +41,8 @@ class amgg_level_view(C.Structure):
                 ("a_val32", C.c_void_p), ("p_val32", C.c_void_p), ("r_val32", C.c_void_p),
                 ("q_val", C.c_void_p), ("q_val32", C.c_void_p), ("diag", C.c_void_p),
                 ("scale", C.c_void_p), ("coarse_inv", C.c_void_p), ("fused_rows", C.c_int32),
-                ("pack_rows", C.c_int32 * 3), ("pack_far", C.c_int64 * 3)]
+                ("pack_rows", C.c_int32 * 3), ("pack_far", C.c_int64 * 3),
+                ("stream_cap", C.c_int32 * 3)]
 
 
 class amgg_solve_opts(C.Structure):

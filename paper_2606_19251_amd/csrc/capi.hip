@@ -141,6 +141,7 @@ size_t layout(amgg_ctx* c, uintptr_t base) {
     c->flags = b.take<int32_t>(8);
     c->cursor = b.take<int32_t>(max_nc + 1);
     c->pack_parts = b.take<int32_t>(kScanPartsMax + 1);
+    c->blkmax = b.take<int32_t>(3 * AMGG_MAX_LEVELS);
     c->ra = b.take<double>(n0);
     c->rb = b.take<double>(n0);
     c->z = b.take<double>(n0);
@@ -190,15 +191,26 @@ hipError_t smooth_step(Level& L, const T* f, T*& cur, T*& oth, T* r, bool from_z
 template hipError_t smooth_step<float>(Level&, const float*, float*&, float*&, float*, bool, hipStream_t);
 template hipError_t smooth_step<double>(Level&, const double*, double*&, double*&, double*, bool, hipStream_t);
 
+bool takes_ready_u(const amgg_ctx* c, int l, int nu1) {
+    if (l >= c->nlevels - 1 || nu1 < 1) return false;
+    const Level& L = c->lv[l];
+    return L.fuse && L.smoother == kSmootherDiagonal;
+}
+
+// u_ready (only with zero): u already holds qd f, the first diagonal smoothing step from zero,
+// formed by the pass that produced f (the restriction or the outer loop's cast). The step after
+// it then reads u like any other iterate: the same products and roundings as the fused kernel
+// that forms d_j f_j per gathered entry, with one gathered vector instead of two.
 template <typename T>
 hipError_t vcycle_level(amgg_ctx* c, int l, const T* f, T* u, T* t, bool zero, int nu1, int nu2, hipStream_t st,
-                        T** result, bool store) {
+                        T** result, bool store, bool u_ready) {
     Level& L = c->lv[l];
     hipError_t e;
     if (l == c->nlevels - 1) {
         *result = u;
         return coarse_solve<T>(L, f, u, st);
     }
+    if (u_ready && !(zero && takes_ready_u(c, l, nu1))) return hipErrorInvalidValue;
     T* cur = u;
     T* oth = t;
     T* r = L.r<T>();
@@ -207,7 +219,18 @@ hipError_t vcycle_level(amgg_ctx* c, int l, const T* f, T* u, T* t, bool zero, i
     // with the second step), sparse smoother u = Q f with the residual.
     int k0 = 0;
     bool have_r = false;
-    if (zero && nu1 >= 1 && L.fuse) {
+    if (u_ready) {
+        if (nu1 == 1) {
+            if ((e = csr_apply<T>(L.A(), L.aval<T>(), cur, r, f, nullptr, nullptr, Epi::Resid, st)) != hipSuccess)
+                return e;
+            have_r = true;
+        } else {
+            if ((e = csr_apply<T>(L.A(), L.aval<T>(), cur, oth, f, L.qd<T>(), cur, Epi::Jacobi, st)) != hipSuccess)
+                return e;
+            std::swap(cur, oth);
+        }
+        k0 = nu1 == 1 ? 1 : 2;
+    } else if (zero && nu1 >= 1 && L.fuse) {
         if (L.smoother == kSmootherDiagonal) {
             if (nu1 == 1) {
                 if ((e = jacobi_pre_resid<T>(L.A(), L.aval<T>(), L.qd<T>(), f, cur, r, st)) != hipSuccess) return e;
@@ -237,10 +260,14 @@ hipError_t vcycle_level(amgg_ctx* c, int l, const T* f, T* u, T* t, bool zero, i
         res = r;
     }
     Level& C = c->lv[l + 1];
-    if ((e = csr_apply<T>(L.R(), L.rv<T>(), res, C.f<T>(), nullptr, nullptr, nullptr, Epi::Store, st)) != hipSuccess)
+    // the restriction also forms the coarse level's first smoothing step where that is diagonal
+    const bool ready = takes_ready_u(c, l + 1, nu1);
+    if ((e = csr_apply<T>(L.R(), L.rv<T>(), res, C.f<T>(), nullptr, ready ? C.qd<T>() : nullptr, nullptr,
+                          ready ? Epi::StoreScaled : Epi::Store, st, ready ? C.u<T>() : nullptr)) != hipSuccess)
         return e;
     T* ec = nullptr;
-    if ((e = vcycle_level<T>(c, l + 1, C.f<T>(), C.u<T>(), C.t<T>(), true, nu1, nu2, st, &ec, store)) != hipSuccess)
+    if ((e = vcycle_level<T>(c, l + 1, C.f<T>(), C.u<T>(), C.t<T>(), true, nu1, nu2, st, &ec, store, ready)) !=
+        hipSuccess)
         return e;
     if ((e = csr_apply<T>(L.P(), L.pv<T>(), ec, cur, nullptr, nullptr, nullptr, still_zero ? Epi::Store : Epi::Add,
                           st)) != hipSuccess)
@@ -254,9 +281,9 @@ hipError_t vcycle_level(amgg_ctx* c, int l, const T* f, T* u, T* t, bool zero, i
 }
 
 template hipError_t vcycle_level<float>(amgg_ctx*, int, const float*, float*, float*, bool, int, int, hipStream_t,
-                                        float**, bool);
+                                        float**, bool, bool);
 template hipError_t vcycle_level<double>(amgg_ctx*, int, const double*, double*, double*, bool, int, int,
-                                         hipStream_t, double**, bool);
+                                         hipStream_t, double**, bool, bool);
 
 int check_ready(const amgg_ctx* c, const char* where) {
     if (!c) return fail(AMGG_EINVAL, std::string(where) + ": null context");
@@ -512,11 +539,31 @@ extern "C" int amgg_finalize(amgg_ctx* c, int singular, void* workspace, size_t 
             }
         }
         if (e != hipSuccess) return hip_fail(e, "amgg_finalize (column packing)");
+        // largest row block of every CSR-stream matrix: sizes the kernels' LDS product buffers
+        ok(vec_zero_bytes(c->blkmax, sizeof(int32_t) * 3 * AMGG_MAX_LEVELS, st));
+        for (int l = 0; l < c->nlevels && e == hipSuccess; ++l) {
+            Level& L = c->lv[l];
+            int32_t* m = c->blkmax + 3 * l;
+            ok(block_max_entries(L.n, L.ptr, stream_rows_for(L.n, L.nnz), m, st));
+            if (l + 1 < c->nlevels) {
+                ok(block_max_entries(L.n, L.pptr, stream_rows_for(L.n, L.pnnz), m + 1, st));
+                ok(block_max_entries(L.nc, L.rptr, stream_rows_for(L.nc, L.pnnz), m + 2, st));
+            }
+        }
+        if (e != hipSuccess) return hip_fail(e, "amgg_finalize (row blocks)");
         if ((e = build_halos(c, st)) != hipSuccess) return hip_fail(e, "amgg_finalize (halo lists)");
         int32_t flags[3] = {0, 0, 0};
+        std::vector<int32_t> bmax(3 * AMGG_MAX_LEVELS, 0);
         if ((e = hipMemcpyAsync(flags, c->flags, sizeof(flags), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(bmax.data(), c->blkmax, sizeof(int32_t) * bmax.size(), hipMemcpyDeviceToHost, st)) !=
+                hipSuccess ||
             (e = hipStreamSynchronize(st)) != hipSuccess)
             return hip_fail(e, "amgg_finalize (sync)");
+        for (int l = 0; l < c->nlevels; ++l) {
+            c->lv[l].acap = stream_cap_for(bmax[3 * l]);
+            c->lv[l].pcap = stream_cap_for(bmax[3 * l + 1]);
+            c->lv[l].rcap = stream_cap_for(bmax[3 * l + 2]);
+        }
         if (flags[0]) return fail(AMGG_EINVAL, "amgg_finalize: a level matrix has a missing or non-positive diagonal");
         if (flags[1]) return fail(AMGG_EINVAL, "amgg_finalize: coarsest matrix is singular (zero pivot)");
         if (flags[2]) return fail(AMGG_EINVAL, "amgg_finalize: a prolongation couples different blocks");
@@ -567,6 +614,9 @@ extern "C" int amgg_level_view_get(const amgg_ctx* c, int lvl, amgg_level_view* 
         v->pack_rows[k] = use ? packs[k]->rows : 0;
         v->pack_far[k] = use ? packs[k]->nfar : 0;
     }
+    v->stream_cap[0] = L.acap;
+    v->stream_cap[1] = coarse ? 0 : L.pcap;
+    v->stream_cap[2] = coarse ? 0 : L.rcap;
     return AMGG_OK;
 }
 

@@ -107,9 +107,12 @@ struct Level {
     bool diag_form = false; // diagonal form of Eq. 5 (f_o = 0): the off-diagonal coefficients are no
                             // parameters of the level, their gradient is zero
 
-    CsrView A() const { return {n, nnz, ptr, col, lanes_for(n, nnz), pa.view(pack, nnz)}; }
-    CsrView P() const { return {n, pnnz, pptr, pcol, lanes_for(n, pnnz), pp.view(pack, pnnz)}; }
-    CsrView R() const { return {nc, pnnz, rptr, rcol, lanes_for(nc, pnnz), pr.view(pack, pnnz)}; }
+    // LDS product capacity of the CSR-stream kernels for A (and Q), P and R (set at finalize)
+    int32_t acap = kStreamCap, pcap = kStreamCap, rcap = kStreamCap;
+
+    CsrView A() const { return {n, nnz, ptr, col, lanes_for(n, nnz), pa.view(pack, nnz), acap}; }
+    CsrView P() const { return {n, pnnz, pptr, pcol, lanes_for(n, pnnz), pp.view(pack, pnnz), pcap}; }
+    CsrView R() const { return {nc, pnnz, rptr, rcol, lanes_for(nc, pnnz), pr.view(pack, pnnz), rcap}; }
     HaloView H() const { return {hrows, hoff, halo, hend, heoff, hcol, hloc}; }
     template <typename T> const T* hav() const { if constexpr (std::is_same_v<T, double>) return ha64; else return ha32; }
     template <typename T> const T* hqv() const { if constexpr (std::is_same_v<T, double>) return hq64; else return hq32; }
@@ -163,6 +166,7 @@ struct amgg_ctx {
     int32_t* flags = nullptr;
     int32_t* cursor = nullptr;
     int32_t* pack_parts = nullptr;  // scan scratch of the column packing
+    int32_t* blkmax = nullptr;      // largest row block of A, P and R per level (3 x AMGG_MAX_LEVELS)
     double *ra = nullptr, *rb = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *bproj = nullptr;
     double* adj_partial = nullptr;
     double* adj_scal = nullptr;
@@ -180,7 +184,10 @@ int hip_fail(hipError_t e, const char* where);
 int check_ready(const amgg_ctx* c, const char* where);
 template <typename T>
 hipError_t vcycle_level(amgg_ctx* c, int l, const T* f, T* u, T* t, bool zero, int nu1, int nu2, hipStream_t st,
-                        T** result, bool store = false);
+                        T** result, bool store = false, bool u_ready = false);
+// True when a cycle from u = 0 on level l starts with a diagonal smoothing step u = qd f that
+// the producer of f may form in the same pass (vcycle_level's u_ready).
+bool takes_ready_u(const amgg_ctx* c, int l, int nu1);
 template <typename T>
 hipError_t smooth_step(Level& L, const T* f, T*& cur, T*& oth, T* r, bool from_zero, hipStream_t st);
 // Coarsest-level solve: the dense inverse, or the block inverses of a block-diagonal level.

@@ -62,9 +62,12 @@ __device__ __forceinline__ T group_sum(T s) {
 
 template <typename T, Epi E>
 __device__ __forceinline__ void epilogue(int32_t row, T s, T* __restrict__ y, const T* __restrict__ f,
-                                         const T* __restrict__ qd, const T* __restrict__ u) {
+                                         const T* __restrict__ qd, const T* __restrict__ u, T* __restrict__ y2) {
     if constexpr (E == Epi::Store) {
         y[row] = s;
+    } else if constexpr (E == Epi::StoreScaled) {
+        y[row] = s;
+        y2[row] = qd[row] * s;
     } else if constexpr (E == Epi::Resid) {
         y[row] = f[row] - s;
     } else if constexpr (E == Epi::Add) {
@@ -182,6 +185,7 @@ __device__ __forceinline__ void stream_products(int32_t ne, const T* __restrict_
         stream_products_g<T>(ne, m, col, [&](int32_t j) { return x[j]; }, out);
 }
 static_assert(kStreamCap % (kChunk * kBlock) == 0, "product buffers hold whole rounds");
+static_assert(kStreamRound == kChunk * kBlock, "a product round");
 
 // Two product streams in the same rounds (out1[k] = m1[k] x[c1[k]], k < n1, and likewise for
 // stream 2): a round issues the value/column loads of both, then the gathers of both, so the
@@ -258,8 +262,10 @@ __global__ __launch_bounds__(kBlock) void csr_stream_kernel(int32_t nrows, const
                                                            const T* __restrict__ val, const T* __restrict__ x,
                                                            T* __restrict__ y, const T* __restrict__ f,
                                                            const T* __restrict__ qd, const T* __restrict__ u,
-                                                           double* __restrict__ partial) {
-    __shared__ T prod[kStreamCap];
+                                                           T* __restrict__ y2, double* __restrict__ partial,
+                                                           int32_t cap) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* prod = reinterpret_cast<T*>(lds_raw);  // cap products (dynamic LDS)
     const int32_t blk = xcd_block();
     const int32_t r0 = blk * ROWS;
     const int32_t r1 = min(r0 + ROWS, nrows);
@@ -278,11 +284,12 @@ __global__ __launch_bounds__(kBlock) void csr_stream_kernel(int32_t nrows, const
             qr = qd[row];
             ur = u[row];
         }
+        if constexpr (E == Epi::StoreScaled) qr = qd[row];
         if constexpr (E == Epi::Add || E == Epi::Sub) yr = y[row];
         if constexpr (DOT == 1) xr = x[row];
     }
     T s = T(0);
-    if (ne <= kStreamCap) {
+    if (ne <= cap) {
         block_products<T, PACKED>(blk, e0, ne, val, col, cp, [&](int32_t j) { return x[j]; }, prod);
         __syncthreads();
         if (mine) s = row_sum(prod, pb - e0, pe - e0);
@@ -292,7 +299,8 @@ __global__ __launch_bounds__(kBlock) void csr_stream_kernel(int32_t nrows, const
     double d = 0.0;
     if (mine) {
         T out;
-        if constexpr (E == Epi::Store) out = s;
+        if constexpr (E == Epi::Store || E == Epi::StoreScaled) out = s;
+        if constexpr (E == Epi::StoreScaled) y2[row] = qr * s;
         if constexpr (E == Epi::Resid) out = fr - s;
         if constexpr (E == Epi::Add) out = yr + s;
         if constexpr (E == Epi::Sub) out = yr - s;
@@ -309,7 +317,8 @@ __global__ __launch_bounds__(kBlock) void csr_rows_kernel(int32_t nrows, const i
                                                          const int32_t* __restrict__ col,
                                                          const T* __restrict__ val, const T* __restrict__ x,
                                                          T* __restrict__ y, const T* __restrict__ f,
-                                                         const T* __restrict__ qd, const T* __restrict__ u) {
+                                                         const T* __restrict__ qd, const T* __restrict__ u,
+                                                         T* __restrict__ y2) {
     const int32_t t = blockIdx.x * kBlock + threadIdx.x;
     const int32_t row = t / LANES;
     const int lane = t % LANES;
@@ -319,7 +328,7 @@ __global__ __launch_bounds__(kBlock) void csr_rows_kernel(int32_t nrows, const i
         for (int32_t p = ptr[row] + lane; p < end; p += LANES) s += val[p] * x[col[p]];
     }
     s = group_sum<T, LANES>(s);
-    if (row < nrows && lane == 0) epilogue<T, E>(row, s, y, f, qd, u);
+    if (row < nrows && lane == 0) epilogue<T, E>(row, s, y, f, qd, u, y2);
 }
 
 // Lane kernel with a fixed grid and per-workgroup partial sums (long rows in the outer loop).
@@ -356,16 +365,18 @@ __global__ __launch_bounds__(kBlock) void rows_dot_kernel(int32_t nrows, const i
 
 template <typename T, Epi E, int DOT>
 hipError_t launch_stream(int rows, const CsrView& m, const T* val, const T* x, T* y, const T* f, const T* qd,
-                         const T* u, double* partial, hipStream_t stream) {
+                         const T* u, T* y2, double* partial, hipStream_t stream) {
     const dim3 grid(static_cast<unsigned>((m.nrows + rows - 1) / rows));
     const bool packed = m.cp.rows == rows && m.cp.off != nullptr;
+    if (m.cap < kStreamRound || m.cap > kStreamCap || m.cap % kStreamRound) return hipErrorInvalidValue;
+    const size_t lds = static_cast<size_t>(m.cap) * sizeof(T);
     switch (rows) {
 #define AMGG_CASE(R)                                                                                              \
     case R:                                                                                                       \
-        return packed ? launch_kernel(csr_stream_kernel<T, E, R, DOT, true>, grid, dim3(kBlock), stream, m.nrows, \
-                                      m.ptr, m.col, m.cp, val, x, y, f, qd, u, partial)                           \
-                      : launch_kernel(csr_stream_kernel<T, E, R, DOT, false>, grid, dim3(kBlock), stream, m.nrows, \
-                                      m.ptr, m.col, ColPack{}, val, x, y, f, qd, u, partial);
+        return packed ? launch_kernel_lds(csr_stream_kernel<T, E, R, DOT, true>, grid, dim3(kBlock), lds, stream, \
+                                          m.nrows, m.ptr, m.col, m.cp, val, x, y, f, qd, u, y2, partial, m.cap)   \
+                      : launch_kernel_lds(csr_stream_kernel<T, E, R, DOT, false>, grid, dim3(kBlock), lds, stream, \
+                                          m.nrows, m.ptr, m.col, ColPack{}, val, x, y, f, qd, u, y2, partial, m.cap);
         AMGG_CASE(256)
         AMGG_CASE(128)
         AMGG_CASE(64)
@@ -378,17 +389,17 @@ hipError_t launch_stream(int rows, const CsrView& m, const T* val, const T* x, T
 
 template <typename T, Epi E>
 hipError_t launch_rows(const CsrView& m, const T* val, const T* x, T* y, const T* f, const T* qd, const T* u,
-                       hipStream_t stream) {
+                       T* y2, hipStream_t stream) {
     if (m.nrows <= 0) return hipSuccess;
     const int rows = stream_rows(m.nrows, m.nnz);
-    if (rows > 0) return launch_stream<T, E, 0>(rows, m, val, x, y, f, qd, u, nullptr, stream);
+    if (rows > 0) return launch_stream<T, E, 0>(rows, m, val, x, y, f, qd, u, y2, nullptr, stream);
     const int64_t threads = static_cast<int64_t>(m.nrows) * m.lanes;
     const dim3 grid(static_cast<unsigned>((threads + kBlock - 1) / kBlock));
     switch (m.lanes) {
 #define AMGG_CASE(L)                                                                                        \
     case L:                                                                                                 \
         return launch_kernel(csr_rows_kernel<T, L, E>, grid, dim3(kBlock), stream, m.nrows, m.ptr, m.col, val, x, y, \
-                             f, qd, u);
+                             f, qd, u, y2);
         AMGG_CASE(1)
         AMGG_CASE(2)
         AMGG_CASE(4)
@@ -408,9 +419,11 @@ int launch_outer(const CsrView& m, const double* val, const double* x, const dou
     const int rows = stream_rows(m.nrows, m.nnz);
     if (rows > 0) {
         if constexpr (DOT == 1)
-            *err = launch_stream<double, Epi::Store, 1>(rows, m, val, x, y, nullptr, nullptr, nullptr, partial, stream);
+            *err = launch_stream<double, Epi::Store, 1>(rows, m, val, x, y, nullptr, nullptr, nullptr, nullptr, partial,
+                                                        stream);
         else
-            *err = launch_stream<double, Epi::Resid, 2>(rows, m, val, x, y, b, nullptr, nullptr, partial, stream);
+            *err = launch_stream<double, Epi::Resid, 2>(rows, m, val, x, y, b, nullptr, nullptr, nullptr, partial,
+                                                        stream);
         return (m.nrows + rows - 1) / rows;
     }
     switch (m.lanes) {
@@ -572,8 +585,9 @@ __global__ __launch_bounds__(kBlock) void csr_jpre_kernel(int32_t nrows, const i
                                                          const int32_t* __restrict__ col, ColPack cp,
                                                          const T* __restrict__ val, const T* __restrict__ d,
                                                          const T* __restrict__ f, T* __restrict__ y,
-                                                         T* __restrict__ uout) {
-    __shared__ T prod[kStreamCap];
+                                                         T* __restrict__ uout, int32_t cap) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* prod = reinterpret_cast<T*>(lds_raw);  // cap products (dynamic LDS)
     const int32_t blk = xcd_block();
     const int32_t r0 = blk * ROWS;
     const int32_t r1 = min(r0 + ROWS, nrows);
@@ -590,7 +604,7 @@ __global__ __launch_bounds__(kBlock) void csr_jpre_kernel(int32_t nrows, const i
         dr = d[row];
     }
     T s = T(0);
-    if (ne <= kStreamCap) {
+    if (ne <= cap) {
         block_products<T, PACKED>(blk, e0, ne, val, col, cp, [&](int32_t j) { return d[j] * f[j]; }, prod);
         __syncthreads();
         if (mine) s = row_sum(prod, pb - e0, pe - e0);
@@ -652,13 +666,15 @@ hipError_t launch_jpre(const CsrView& m, const T* a, const T* d, const T* f, T* 
     }
     const dim3 grid(static_cast<unsigned>((m.nrows + rows - 1) / rows));
     const bool packed = m.cp.rows == rows && m.cp.off != nullptr;
+    if (m.cap < kStreamRound || m.cap > kStreamCap || m.cap % kStreamRound) return hipErrorInvalidValue;
+    const size_t lds = static_cast<size_t>(m.cap) * sizeof(T);
     switch (rows) {
 #define AMGG_CASE(R)                                                                                             \
     case R:                                                                                                      \
-        return packed ? launch_kernel(csr_jpre_kernel<T, R, NEXT_RESID, true>, grid, dim3(kBlock), stream, m.nrows, \
-                                      m.ptr, m.col, m.cp, a, d, f, y, u)                                         \
-                      : launch_kernel(csr_jpre_kernel<T, R, NEXT_RESID, false>, grid, dim3(kBlock), stream,      \
-                                      m.nrows, m.ptr, m.col, ColPack{}, a, d, f, y, u);
+        return packed ? launch_kernel_lds(csr_jpre_kernel<T, R, NEXT_RESID, true>, grid, dim3(kBlock), lds, stream, \
+                                          m.nrows, m.ptr, m.col, m.cp, a, d, f, y, u, m.cap)                     \
+                      : launch_kernel_lds(csr_jpre_kernel<T, R, NEXT_RESID, false>, grid, dim3(kBlock), lds,     \
+                                          stream, m.nrows, m.ptr, m.col, ColPack{}, a, d, f, y, u, m.cap);
         AMGG_CASE(256)
         AMGG_CASE(128)
         AMGG_CASE(64)
@@ -669,7 +685,31 @@ hipError_t launch_jpre(const CsrView& m, const T* a, const T* d, const T* f, T* 
     }
 }
 
+__global__ __launch_bounds__(kBlock) void block_max_kernel(int32_t nrows, const int32_t* __restrict__ ptr, int rows,
+                                                          int32_t* __restrict__ out) {
+    __shared__ int32_t red[kBlock / 64];
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t r0 = b * rows;
+    int32_t m = 0;
+    if (r0 < nrows) m = ptr[min(r0 + rows, static_cast<int64_t>(nrows))] - ptr[r0];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kBlock / 64; ++k) m = max(m, red[k]);
+        atomicMax(out, m);
+    }
+}
+
 }  // namespace
+
+hipError_t block_max_entries(int32_t nrows, const int32_t* ptr, int rows, int32_t* out, hipStream_t stream) {
+    if (nrows <= 0 || rows <= 0) return hipSuccess;
+    const int64_t nb = (static_cast<int64_t>(nrows) + rows - 1) / rows;
+    block_max_kernel<<<static_cast<unsigned>((nb + kBlock - 1) / kBlock), kBlock, 0, stream>>>(nrows, ptr, rows, out);
+    return hipGetLastError();
+}
 
 int stream_rows_for(int32_t nrows, int32_t nnz) { return stream_rows(nrows, nnz); }
 
@@ -680,26 +720,29 @@ int outer_partials(int32_t nrows, int32_t nnz) {
 
 template <typename T>
 hipError_t csr_apply(const CsrView& m, const T* val, const T* x, T* y, const T* f, const T* qd, const T* u,
-                     Epi epi, hipStream_t stream) {
+                     Epi epi, hipStream_t stream, T* y2) {
     switch (epi) {
         case Epi::Store:
-            return launch_rows<T, Epi::Store>(m, val, x, y, f, qd, u, stream);
+            return launch_rows<T, Epi::Store>(m, val, x, y, f, qd, u, nullptr, stream);
         case Epi::Resid:
-            return launch_rows<T, Epi::Resid>(m, val, x, y, f, qd, u, stream);
+            return launch_rows<T, Epi::Resid>(m, val, x, y, f, qd, u, nullptr, stream);
         case Epi::Add:
-            return launch_rows<T, Epi::Add>(m, val, x, y, f, qd, u, stream);
+            return launch_rows<T, Epi::Add>(m, val, x, y, f, qd, u, nullptr, stream);
         case Epi::Jacobi:
-            return launch_rows<T, Epi::Jacobi>(m, val, x, y, f, qd, u, stream);
+            return launch_rows<T, Epi::Jacobi>(m, val, x, y, f, qd, u, nullptr, stream);
         case Epi::Sub:
-            return launch_rows<T, Epi::Sub>(m, val, x, y, f, qd, u, stream);
+            return launch_rows<T, Epi::Sub>(m, val, x, y, f, qd, u, nullptr, stream);
+        case Epi::StoreScaled:
+            if (!qd || !y2) return hipErrorInvalidValue;
+            return launch_rows<T, Epi::StoreScaled>(m, val, x, y, f, qd, u, y2, stream);
     }
     return hipErrorInvalidValue;
 }
 
 template hipError_t csr_apply<float>(const CsrView&, const float*, const float*, float*, const float*,
-                                     const float*, const float*, Epi, hipStream_t);
+                                     const float*, const float*, Epi, hipStream_t, float*);
 template hipError_t csr_apply<double>(const CsrView&, const double*, const double*, double*, const double*,
-                                      const double*, const double*, Epi, hipStream_t);
+                                      const double*, const double*, Epi, hipStream_t, double*);
 
 hipError_t csr_spmv_dot(const CsrView& m, const double* val, const double* p, double* q, double* partial, int* count,
                         hipStream_t stream) {

@@ -71,10 +71,14 @@ __global__ void zero_kernel(uint32_t* __restrict__ p, int64_t words) {
     if (i < words) p[i] = 0u;
 }
 
+template <bool DIAG>
 __global__ void cast_scaled_kernel(int32_t n, const double* __restrict__ x, const double* __restrict__ scale,
-                                   float* __restrict__ y) {
+                                   float* __restrict__ y, const float* __restrict__ d, float* __restrict__ u) {
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) y[i] = static_cast<float>(x[i] * scale[0]);
+    if (i >= n) return;
+    const float yi = static_cast<float>(x[i] * scale[0]);
+    y[i] = yi;
+    if constexpr (DIAG) u[i] = d[i] * yi;
 }
 
 __global__ void cast_scale_kernel(int64_t n, const double* __restrict__ x, double scale, float* __restrict__ y) {
@@ -304,9 +308,14 @@ hipError_t vec_zero_bytes(void* p, size_t bytes, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t cast_scaled_f64_f32(int32_t n, const double* x, const double* scale, float* y, hipStream_t stream) {
+hipError_t cast_scaled_f64_f32(int32_t n, const double* x, const double* scale, float* y, hipStream_t stream,
+                               const float* d, float* u) {
     if (n <= 0) return hipSuccess;
-    cast_scaled_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, x, scale, y);
+    if ((d == nullptr) != (u == nullptr)) return hipErrorInvalidValue;
+    if (d)
+        cast_scaled_kernel<true><<<grid_for(n), kBlock, 0, stream>>>(n, x, scale, y, d, u);
+    else
+        cast_scaled_kernel<false><<<grid_for(n), kBlock, 0, stream>>>(n, x, scale, y, nullptr, nullptr);
     return hipGetLastError();
 }
 

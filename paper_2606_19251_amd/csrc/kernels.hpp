@@ -34,6 +34,21 @@ inline hipError_t launch_kernel(void (*kernel)(KArgs...), dim3 grid, dim3 block,
     return hipGetLastError();
 }
 
+// The same with `lds` bytes of dynamic LDS.
+template <typename... KArgs, typename... Args>
+inline hipError_t launch_kernel_lds(void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t lds, hipStream_t stream,
+                                    Args... args) {
+    LaunchEvents& ev = armed_events();
+    if (ev.start != nullptr) {
+        const hipEvent_t s = ev.start, e = ev.stop;
+        ev = LaunchEvents{};
+        hipExtLaunchKernelGGL(kernel, grid, block, lds, stream, s, e, 0, static_cast<KArgs>(args)...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, lds, stream, static_cast<KArgs>(args)...);
+    }
+    return hipGetLastError();
+}
+
 constexpr int kBlock = 256;         // threads per workgroup (4 wavefronts of 64)
 constexpr int kStreamCap = 4096;    // products a CSR-stream workgroup holds in LDS
 constexpr int kReduceBlocks = 1024; // fixed partial count: reductions are deterministic
@@ -47,6 +62,8 @@ enum class Epi : int {
     Add = 2,     // y_i += s
     Jacobi = 3,  // y_i = u_i + qd_i (f_i - s)      (one-pass diagonal smoothing step)
     Sub = 4,     // y_i -= s
+    StoreScaled = 5,  // y_i = s and y2_i = qd_i s (a restriction that also forms the coarse
+                      // level's first diagonal smoothing step from zero, u = qd f)
 };
 
 // Column indices of a CSR matrix packed for the CSR-stream kernels: rows are grouped in blocks
@@ -72,7 +89,21 @@ struct CsrView {
     const int32_t* col;
     int lanes;        // 1, 2, 4, ..., 64
     ColPack cp = {};  // packed columns (cp.rows == the stream kernel's rows per block), if any
+    // products the CSR-stream kernel keeps in LDS per workgroup: a whole number of product
+    // rounds covering the matrix's largest row block, at most kStreamCap (blocks beyond it sum
+    // their rows from global memory). Smaller buffers let more workgroups share a compute unit.
+    int32_t cap = kStreamCap;
 };
+
+// LDS product capacity for a matrix whose largest row block (of the stream kernel's rows) holds
+// `maxblk` entries.
+constexpr int32_t kStreamRound = 2048;  // entries of one product round (8 per thread)
+inline int32_t stream_cap_for(int32_t maxblk) {
+    const int32_t c = (maxblk + kStreamRound - 1) / kStreamRound * kStreamRound;
+    return c < kStreamRound ? kStreamRound : (c > kStreamCap ? kStreamCap : c);
+}
+// out[0] = max over row blocks of `rows` rows of the block's entries (out[0] must start at 0).
+hipError_t block_max_entries(int32_t nrows, const int32_t* ptr, int rows, int32_t* out, hipStream_t stream);
 
 // Pack the columns of an nrows-row CSR matrix for row blocks of `rows` rows (a value of
 // stream_rows_for): off [nnz], base [blocks], foff [blocks + 1], and at most `cap` far entries
@@ -95,7 +126,7 @@ int lanes_for(int32_t nrows, int32_t nnz);
 
 template <typename T>
 hipError_t csr_apply(const CsrView& m, const T* val, const T* x, T* y, const T* f, const T* qd, const T* u,
-                     Epi epi, hipStream_t stream);
+                     Epi epi, hipStream_t stream, T* y2 = nullptr);
 
 // Rows per workgroup of the CSR-stream kernels for a matrix of this shape (0: lane kernel).
 int stream_rows_for(int32_t nrows, int32_t nnz);
@@ -155,8 +186,10 @@ hipError_t vec_mul(int32_t n, const T* a, const T* b, T* y, hipStream_t stream);
 template <typename T>
 hipError_t vec_copy(int32_t n, const T* a, T* y, hipStream_t stream);
 hipError_t vec_zero_bytes(void* p, size_t bytes, hipStream_t stream);
-// y32 = (float)(x * scale[0]) ; scale on device
-hipError_t cast_scaled_f64_f32(int32_t n, const double* x, const double* scale, float* y, hipStream_t stream);
+// y32 = (float)(x * scale[0]) ; scale on device. With d and u: also u = d y32 (FP32 product),
+// the first diagonal smoothing step from zero of the cycle that receives y32.
+hipError_t cast_scaled_f64_f32(int32_t n, const double* x, const double* scale, float* y, hipStream_t stream,
+                               const float* d = nullptr, float* u = nullptr);
 hipError_t cast_f64_f32(int32_t n, const double* x, float* y, hipStream_t stream);
 hipError_t cast_scale_f64_f32(int64_t n, const double* x, double scale, float* y, hipStream_t stream);
 hipError_t cast_scale_rows_f64_f32(int32_t nrows, int32_t ncols, const double* in, const int32_t* group,

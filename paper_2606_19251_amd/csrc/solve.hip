@@ -50,8 +50,11 @@ struct Runner {
             return res;
         }
         float* res = nullptr;
-        ok(cast_scaled_f64_f32(L0.n, r, c->scal + kInvNorm, L0.f32, st));
-        ok(vcycle_level<float>(c, 0, L0.f32, L0.u32, L0.t32, true, nu1, nu2, st, &res));
+        // a diagonal first smoothing step u = qd f is formed by the cast itself
+        const bool ready = takes_ready_u(c, 0, nu1);
+        ok(cast_scaled_f64_f32(L0.n, r, c->scal + kInvNorm, L0.f32, st, ready ? L0.qd32 : nullptr,
+                               ready ? L0.u32 : nullptr));
+        ok(vcycle_level<float>(c, 0, L0.f32, L0.u32, L0.t32, true, nu1, nu2, st, &res, false, ready));
         last32 = res;
         return nullptr;
     }

@@ -260,6 +260,7 @@ class DeviceSolver:
             "fused_rows": int(v.fused_rows),
             "pack_rows": [int(x) for x in v.pack_rows],  # A (and Q), P, R; 0 = plain columns
             "pack_far": [int(x) for x in v.pack_far],
+            "stream_cap": [int(x) for x in v.stream_cap],  # LDS products per workgroup: A, P, R
         }
 
 

@@ -370,3 +370,76 @@ def test_timed_level_operator_records_kernel_time():
     with pytest.raises(capi.AmggError):
         capi.amgg_level_apply_timed(ds.ctx, 0, capi.AMGG_OP_RESIDUAL, 64, x.data_ptr(), y2.data_ptr(),
                                     fd.data_ptr(), 0, 0, ds.stream)
+
+
+@pytest.mark.parametrize("kind", ["grid64", "delaunay20k", "tet30k"])
+@pytest.mark.parametrize("smoother", ["jacobi", "diag2"])
+def test_ready_first_step_solves_equal_separate_passes(kind, smoother):
+    """Where a level's cycle from zero starts with a diagonal step, the pass that produces its
+    right-hand side (the outer loop's FP32 cast on the fine level, the restriction below it) also
+    forms u = qd f; the FP32-cycle solves (iterative refinement and flexible CG, V(1,1) and
+    V(2,2)) are bitwise those of the separate passes."""
+    from paper_2606_19251_amd import capi
+
+    A, f, ho, hp, ds = _setup(kind)
+    if smoother == "jacobi":
+        ds.set_jacobi()
+    else:  # Eq. 5 with f_o = 0 on the two finest levels, the sparse form below
+        c = np.tile(COEFFS["poly2"][0], (ds.nlevels, 1)).astype(np.float32)
+        ds.set_coeffs_device(torch.from_numpy(c).cuda(), 2, diag_levels=2)
+    fd = _dev(f)
+    try:
+        for outer in (capi.AMGG_OUTER_IR, capi.AMGG_OUTER_FCG):
+            for nu in ((1, 1), (2, 2)):
+                res = []
+                for fuse in (True, False):
+                    ds.set_fusion(fuse)
+                    x, rc, info, _ = ds.solve(fd, outer=outer, precision=32, nu1=nu[0], nu2=nu[1], tol=1e-8)
+                    torch.cuda.synchronize()
+                    res.append((x.clone(), info.iterations, rc, info.fell_back))
+                print(f"[gpu] {kind} {smoother} outer={outer} nu={nu}: rc={res[0][2]} it={res[0][1]} "
+                      f"fell_back={res[0][3]}", flush=True)
+                assert res[0][2] == 0 or smoother != "jacobi"
+                assert res[0][1:] == res[1][1:], (outer, nu)
+                assert torch.equal(res[0][0], res[1][0]), (outer, nu)
+    finally:
+        ds.set_fusion(True)
+
+
+def _stream_rows(n, nnz):
+    avg = nnz / n if n > 0 else 0.0
+    for r in (256, 128, 64, 32):
+        if r * avg * 1.25 <= 4096:
+            return r
+    return 0
+
+
+def _expected_cap(rowptr, n, nnz):
+    rows = _stream_rows(n, nnz)
+    if rows == 0:
+        return 4096  # lane kernel: the capacity is not used
+    starts = rowptr[np.minimum(np.arange(0, n, rows), n)]
+    ends = rowptr[np.minimum(np.arange(0, n, rows) + rows, n)]
+    big = int((ends - starts).max()) if n > 0 else 0
+    return min(4096, max(2048, -(-big // 2048) * 2048))
+
+
+@pytest.mark.parametrize("kind", ["grid64", "delaunay20k", "cmesh32k", "tet30k", "tiny"])
+def test_stream_lds_capacity_covers_largest_block(kind):
+    """The CSR-stream kernels' LDS product buffer of every matrix is the largest row block rounded
+    up to whole rounds of 2048 products (at most 4096), recomputed here from the host matrices."""
+    import scipy.sparse as sp
+
+    A, f, ho, hp, ds = _setup(kind)
+    caps = set()
+    for l, L in enumerate(hp.levels):
+        v = ds.level_view(l)
+        assert v["stream_cap"][0] == _expected_cap(L.rowptr, L.n, L.nnz), (l, "A")
+        caps.add(v["stream_cap"][0])
+        if l + 1 < hp.nlevels:
+            pz = int(L.p_col.size)
+            assert v["stream_cap"][1] == _expected_cap(L.p_rowptr, L.n, pz), (l, "P")
+            R = sp.csr_matrix((np.ones(pz), L.p_col, L.p_rowptr), shape=(L.n, L.p_ncols)).T.tocsr()
+            assert v["stream_cap"][2] == _expected_cap(R.indptr, L.p_ncols, pz), (l, "R")
+    print(f"[gpu] {kind}: stream caps {sorted(caps)}", flush=True)
+    assert 2048 in caps
