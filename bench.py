@@ -44,22 +44,25 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def col_bytes(view, which: int, nz: int, nrows: int) -> int:
+def col_bytes(view, which: int, nz: int, nrows: int, layout: bool = True) -> int:
     """Bytes of the column indices a CSR-stream pass reads for matrix `which` (0: A and Q, 1: P,
-    2: R) of a level: 2-byte packed offsets, 6 bytes per far entry (slot and column) and 8 per row
-    block (base column, far-list offset), or the plain 4-byte columns."""
+    2: R) of a level: with `layout`, what the stored layout holds (2-byte packed offsets, 6 bytes
+    per far entry (slot and column) and 8 per row block (base column, far-list offset), or the
+    plain 4-byte columns); without, the method's 4-byte column per entry."""
     rows = view["pack_rows"][which]
-    if rows <= 0:
+    if rows <= 0 or not layout:
         return 4 * nz
     return 2 * nz + 6 * view["pack_far"][which] + 8 * ((nrows + rows - 1) // rows)
 
 
-def level_bytes_vcycle(h, views, smoother_sparse: bool, bv: int = 4, diag_levels: int = 0) -> float:
+def level_bytes_vcycle(h, views, smoother_sparse: bool, bv: int = 4, diag_levels: int = 0,
+                       layout: bool = False) -> float:
     """Algorithmic HBM bytes of one V(1,1) preconditioner cycle (u = 0 on entry) on the hierarchy:
-    every matrix entry read once per pass (value plus column index, packed where the level has
-    packed columns; levels served by the fused halo kernels read plain columns), every vector
-    once per pass (gathers counted once). With the sparse smoother, the `diag_levels` finest
-    levels take the one-pass diagonal step (the diagonal form of Eq. 5)."""
+    every matrix entry read once per pass (value plus a 4-byte column index; with `layout`, the
+    column bytes of the stored layout: packed where the level has packed columns, plain on levels
+    served by the fused halo kernels), every vector once per pass (gathers counted once). With the
+    sparse smoother, the `diag_levels` finest levels take the one-pass diagonal step (the diagonal
+    form of Eq. 5)."""
     total = 0.0
     L = h.nlevels
     for l, lev in enumerate(h.levels):
@@ -70,11 +73,11 @@ def level_bytes_vcycle(h, views, smoother_sparse: bool, bv: int = 4, diag_levels
         v = views[l]
         p = int(lev.p_col.size)
         nc = lev.p_ncols
-        ia = 4 * z if v["fused_rows"] > 0 else col_bytes(v, 0, z, n)
+        ia = 4 * z if v["fused_rows"] > 0 else col_bytes(v, 0, z, n, layout)
         apass = z * bv + ia + 4 * (n + 1)
         resid = apass + 3 * n * bv
-        restrict = p * bv + col_bytes(v, 2, p, nc) + 4 * (nc + 1) + n * bv + nc * bv
-        prolong = p * bv + col_bytes(v, 1, p, n) + 4 * (n + 1) + nc * bv + 2 * n * bv
+        restrict = p * bv + col_bytes(v, 2, p, nc, layout) + 4 * (nc + 1) + n * bv + nc * bv
+        prolong = p * bv + col_bytes(v, 1, p, n, layout) + 4 * (n + 1) + nc * bv + 2 * n * bv
         if smoother_sparse and l >= diag_levels:
             pre = apass + 2 * n * bv                 # u = Q f
             post = resid + apass + 3 * n * bv         # r = f - A u ; u += Q r
@@ -424,6 +427,9 @@ class Case:
         per = [s.elapsed_time(e) for s, e in pairs]
         ms = sum(per) / steps
         median = float(np.median(per))
+        slow = int(np.argmax(per))
+        if per[slow] > 1.2 * median:
+            log(f"{self.name} {smoother}: solve {slow} of {steps} took {per[slow]:.3f} ms (median {median:.3f})")
         # residual recomputed in FP64 on the host from the returned x
         xh = self.x.cpu().numpy()
         fb = self.f - self.f.mean() if self.hh.singular else self.f
@@ -434,6 +440,24 @@ class Case:
         return {"ms": round(ms, 4), "ms_median": round(median, 4), "vcycles": info.vcycles,
                 "iterations": info.iterations, "status": rc, "fell_back": info.fell_back, "relres": true_rel}
 
+    def time_residual(self):
+        """Average duration (ms) of the fine-level FP32 residual r = f - A u over 50 launches on the
+        solve stream, each timed by HIP events the kernel records at its own start and end (after
+        one warm-up launch), and the average interval between the launches."""
+        from paper_2606_19251_amd import capi
+
+        torch = self.torch
+        n0 = self.hh.levels[0].n
+        self.ds.set_jacobi(2.0 / 3.0)
+        xs = torch.rand(n0, dtype=torch.float32, device=self.dev)
+        ys = torch.empty_like(xs)
+        fs = torch.rand(n0, dtype=torch.float32, device=self.dev)
+        st = self.ds.stream
+        return time_kernel(
+            torch, lambda s0, s1: capi.amgg_level_apply_timed(self.ds.ctx, 0, capi.AMGG_OP_RESIDUAL, 32, xs.data_ptr(),
+                                                              ys.data_ptr(), fs.data_ptr(), s0, s1, st),
+            torch.cuda.current_stream(self.dev))
+
     def roofline(self):
         """Fine-level FP32 residual r = f - A u: algorithmic bytes / kernel time from HIP events
         recorded by the kernel itself on the solve stream."""
@@ -441,19 +465,15 @@ class Case:
 
         torch = self.torch
         n0, z0 = self.hh.levels[0].n, self.hh.levels[0].nnz
-        self.ds.set_jacobi(2.0 / 3.0)
-        xs = torch.rand(n0, dtype=torch.float32, device=self.dev)
-        ys = torch.empty_like(xs)
-        fs = torch.rand(n0, dtype=torch.float32, device=self.dev)
-        st = self.ds.stream
-        k_ms, k_interval_ms = time_kernel(
-            torch, lambda s0, s1: capi.amgg_level_apply_timed(self.ds.ctx, 0, capi.AMGG_OP_RESIDUAL, 32, xs.data_ptr(),
-                                                              ys.data_ptr(), fs.data_ptr(), s0, s1, st),
-            torch.cuda.current_stream(self.dev))
+        k_ms, k_interval_ms = self.time_residual()
         rows = 256 if z0 / n0 * 256 * 1.25 <= 4096 else 128
         v0 = self.ds.level_view(0)
-        k_bytes = z0 * 4 + col_bytes(v0, 0, z0, n0) + 4 * (n0 + 1) + 3 * n0 * 4
+        # the method's bytes (FP32 value and 4-byte column per entry, row pointers, f, u gathered
+        # once, r): the A-pass figure of the byte model; the packed layout moves fewer
+        k_bytes = z0 * 8 + 4 * (n0 + 1) + 3 * n0 * 4
+        lay_bytes = z0 * 4 + col_bytes(v0, 0, z0, n0) + 4 * (n0 + 1) + 3 * n0 * 4
         achieved = k_bytes / (k_ms * 1e-3) / 1e9
+        lay_gbs = lay_bytes / (k_ms * 1e-3) / 1e9
         copy = copy_rate_gbs(torch, self.dev)
         packed = v0["pack_rows"][0] > 0
         return {"kernel": (f"csr_stream_kernel<float, Resid, {rows}, 0, {'true' if packed else 'false'}> (fine level "
@@ -461,8 +481,10 @@ class Case:
                 "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(self.name),
                 "launch_ms": round(k_ms, 5), "launch_interval_ms": round(k_interval_ms, 5),
-                "algorithmic_bytes": int(k_bytes), "copy_gbs": round(copy, 1),
-                "frac_of_copy": round(achieved / copy, 4)}
+                "algorithmic_bytes": int(k_bytes), "layout_bytes": int(lay_bytes),
+                "layout_gbs": round(lay_gbs, 1), "frac_layout": round(lay_gbs / HBM_PEAK_GBS, 4),
+                "copy_gbs": round(copy, 1), "frac_of_copy": round(achieved / copy, 4),
+                "layout_frac_of_copy": round(lay_gbs / copy, 4)}
 
 
 def training_step(torch, steps=10, warmup=3):
@@ -553,6 +575,10 @@ def structured_case(torch, nu=1):
 CONFIGURED_OUTER = {"tet8m": "ir", "delaunay1m": "fcg", "cmesh4m": "fcg", "grid1m": "fcg"}
 
 
+def _finite(v, nd=3):
+    return round(v, nd) if np.isfinite(v) else None
+
+
 def workload_report(torch, case, steps, warmup, nu, outers, with_roofline=True):
     """Solves of one workload with both smoothers under the given outer loops, the algorithmic
     bytes of one cycle and the solve-level algorithmic bandwidth, and the fine-level roofline."""
@@ -563,16 +589,23 @@ def workload_report(torch, case, steps, warmup, nu, outers, with_roofline=True):
     views = [case.ds.level_view(l) for l in range(hh.nlevels)]
     vbytes = {"gnn": level_bytes_vcycle(hh, views, smoother_sparse=True),
               "jacobi": level_bytes_vcycle(hh, views, False)}
-    idx0 = col_bytes(views[0], 0, z0, n0)
+    lbytes = {"gnn": level_bytes_vcycle(hh, views, smoother_sparse=True, layout=True),
+              "jacobi": level_bytes_vcycle(hh, views, False, layout=True)}
+    idx0, lidx0 = 4 * z0, col_bytes(views[0], 0, z0, n0)
     obytes = {"ir": outer_bytes_ir(n0, z0, idx0), "fcg": outer_bytes_fcg(n0, z0, idx0)}
+    olbytes = {"ir": outer_bytes_ir(n0, z0, lidx0), "fcg": outer_bytes_fcg(n0, z0, lidx0)}
     code = {"ir": capi.AMGG_OUTER_IR, "fcg": capi.AMGG_OUTER_FCG}
     out = {"workload": f"{WORKLOADS[case.name][1]} (n={n0}, nnz={z0})", "levels": [L.n for L in hh.levels],
            "level_nnz": [L.nnz for L in hh.levels], "configured_outer": CONFIGURED_OUTER[case.name],
            "vcycle_bytes": {k: int(v) for k, v in vbytes.items()},
+           "vcycle_layout_bytes": {k: int(v) for k, v in lbytes.items()},
            "packed_columns": [{"rows": v["pack_rows"], "far": v["pack_far"]} for v in views]}
     vbytes["gnn_sparse_all_levels"] = vbytes["gnn"]
+    lbytes["gnn_sparse_all_levels"] = lbytes["gnn"]
     if case.pred.diag_levels > 0:  # the cost-aware network: one-pass diagonal steps on its finest levels
         vbytes["gnn"] = level_bytes_vcycle(hh, views, smoother_sparse=True, diag_levels=case.pred.diag_levels)
+        lbytes["gnn"] = level_bytes_vcycle(hh, views, smoother_sparse=True, diag_levels=case.pred.diag_levels,
+                                           layout=True)
     out["gnn_diag_levels"] = case.pred.diag_levels
     for outer in outers:
         res = {}
@@ -582,10 +615,27 @@ def workload_report(torch, case, steps, warmup, nu, outers, with_roofline=True):
             r = case.solves(sm, code[outer], k, w, nu)
             moved = r["vcycles"] * vbytes[sm] + r["iterations"] * obytes[outer]
             r["solve_gbs_algorithmic"] = round(moved / (r["ms"] * 1e-3) / 1e9, 1)
+            moved = r["vcycles"] * lbytes[sm] + r["iterations"] * olbytes[outer]
+            r["solve_gbs_layout"] = round(moved / (r["ms"] * 1e-3) / 1e9, 1)
             res[sm] = r
         if "gnn_sparse_all_levels" in res:
             res["gnn_sparse_all_levels_over_jacobi_time"] = round(res["gnn_sparse_all_levels"]["ms"] /
                                                                   res["jacobi"]["ms"], 4)
+        # the omega-Jacobi AMG as judge: keep the learned coefficients only where they predict the
+        # shorter solve (measured on the workload's own right-hand side, 12 probe iterations each)
+        t0 = time.time()
+        j = case.ds.judge(case.b, case.coeffs, case.pred.degree, x=case.x, diag_levels=case.pred.diag_levels,
+                          outer=code[outer], nu1=nu, nu2=nu)
+        torch.cuda.synchronize()
+        kept = "gnn" if j["learned_wins"] else "jacobi"
+        res["judge"] = {"kept": kept, "judge_ms": round((time.time() - t0) * 1e3, 2),
+                        "predicted_ms": {"gnn": _finite(j["predicted_ms"][0]), "jacobi": _finite(j["predicted_ms"][1])},
+                        "probe_ms_per_iter": {"gnn": round(j["ms_per_iter"][0], 4),
+                                              "jacobi": round(j["ms_per_iter"][1], 4)},
+                        "judged_solve_ms": res[kept]["ms"],
+                        "judged_over_jacobi_time": round(res[kept]["ms"] / res["jacobi"]["ms"], 4)}
+        log(f"{case.name} {outer.upper()} judge: keeps {kept} ({res['judge']['predicted_ms']}, "
+            f"{res['judge']['judge_ms']} ms)")
         res["gnn"]["setup_ms"] = round(case.gnn_setup_ms, 3)
         res["gnn"]["setup_first_ms"] = round(case.gnn_setup_first_ms, 3)
         res["gnn_over_jacobi_time"] = round(res["gnn"]["ms"] / res["jacobi"]["ms"], 4)
@@ -666,21 +716,15 @@ def run(args, cpu_job):
     if args.profile_kernels:
         # counter runs: the dominant kernel alone, and a plain copy of known size to calibrate
         # the byte counters (256 MiB read + 256 MiB written per copy)
-        ds.set_jacobi(2.0 / 3.0)
-        n0 = hh.levels[0].n
-        xs = torch.rand(n0, dtype=torch.float32, device=case.dev)
-        ys = torch.empty_like(xs)
-        fs = torch.rand(n0, dtype=torch.float32, device=case.dev)
+        # the roofline's timing loop itself (one warm-up launch, then 50 timed launches)
+        k_ms, _ = case.time_residual()
         src = torch.ones(64 << 20, dtype=torch.float32, device=case.dev)
         dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        for _ in range(10):
-            capi.amgg_level_apply(ds.ctx, 0, capi.AMGG_OP_RESIDUAL, 32, xs.data_ptr(), ys.data_ptr(), fs.data_ptr(),
-                                  ds.stream)
         for _ in range(10):
             dst.copy_(src)
         torch.cuda.synchronize()
-        log("profile-kernels: 10 fine-level residual launches, 10 copies of 256 MiB")
+        log(f"profile-kernels: 1 + 50 fine-level residual launches ({k_ms * 1e3:.2f} us each by their own events), "
+            "10 copies of 256 MiB")
         return
     if args.profile_solves:
         for outer in ("ir", "fcg"):
@@ -717,6 +761,7 @@ def run(args, cpu_job):
         "gnn_diag_levels": head["gnn_diag_levels"],
         "gnn_sparse_all_levels": head[outer].get("gnn_sparse_all_levels"),
         "roofline": head["roofline"],
+        "judge": head[outer]["judge"],
         args.workload: head,
     }
     if not args.only_headline:

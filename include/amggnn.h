@@ -301,6 +301,40 @@ typedef struct {
 int amgg_solve(amgg_ctx* ctx, const amgg_solve_opts* opts, const double* b, double* x,
                amgg_solve_info* info, double* history, int history_cap, void* stream);
 
+/* Judge of the learned smoother. The plain omega-Jacobi AMG is the baseline the learned
+ * coefficients must beat in solve time (Sec. 4: acceleration = mean Jacobi solve time over the
+ * mean learned-smoother solve time); this call takes that decision on the matrix at hand.
+ * It sets the learned smoother on every level (coeffs_dev: device FP32 [nlevels][2*degree+1],
+ * e.g. the GCIN output; the diag_levels finest levels in the diagonal form of Eq. 5, as
+ * amgg_set_smoother_coeffs_device_form), runs `iters` iterations of the outer loop `opts`
+ * (its tol is the target; maxit and fallback are ignored) on b from x = 0, then the same with
+ * omega = 2/3 Jacobi on every level. Each run is preceded by an untimed two-iteration run
+ * (graph capture) and timed by the host clock around its synchronous iterations. A run that
+ * reached tol predicts its own time; otherwise the prediction is ms_per_iter * (iterations +
+ * (log10(tol) - log10_relres) / log10_rate), log10_rate being the log10 residual reduction per
+ * iteration over the second half of the run (the first iterations fall faster than the rest of
+ * a solve will), and infinite when the run diverged, broke down, stagnated or stopped reducing
+ * the residual. The context keeps the smoother with the smaller prediction (ties keep
+ * Jacobi): learned_wins = 1 leaves the learned coefficients set, 0 leaves omega-Jacobi on every
+ * level. b, x: device FP64 n_0-vectors; x is scratch (overwritten; a later amgg_solve with the
+ * same b and x replays the graphs captured here). iters in [1, 100]; about 12 separate the
+ * solvers' rates on the benchmark meshes. Synchronises the stream. Not available on a
+ * block-diagonal context (-4). The decision rests on measured times, so two calls may decide
+ * differently when the predictions are close. */
+typedef struct {
+    int learned_wins;       /* 1: learned smoother kept; 0: omega-Jacobi kept */
+    int iterations[2];      /* iterations run by the probe: [0] learned, [1] Jacobi */
+    int status[2];          /* the probes' amgg_solve outcomes (0: reached tol) */
+    double log10_relres[2]; /* log10 of the relative residual at the end of the probe */
+    double log10_rate[2];   /* log10 residual reduction per iteration, second half of the probe */
+    double ms_per_iter[2];  /* wall-clock milliseconds per iteration */
+    double predicted_ms[2]; /* predicted solve time to tol (INFINITY when unusable) */
+} amgg_judge_info;
+
+int amgg_judge_smoother(amgg_ctx* ctx, const amgg_solve_opts* opts, int iters, int degree,
+                        const float* coeffs_dev, int diag_levels, const double* b, double* x,
+                        amgg_judge_info* info, void* stream);
+
 /* ------------------------------------------------------------------------------------
  * Learning: residual-reduction loss (Sec. 3.3, Eq. 11) of nvc V-cycles from u0 and its
  * gradient with respect to every level's smoother coefficients, by a hand-written adjoint

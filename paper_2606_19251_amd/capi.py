@@ -56,6 +56,12 @@ class amgg_solve_info(C.Structure):
                 ("fell_back", C.c_int)]
 
 
+class amgg_judge_info(C.Structure):
+    _fields_ = [("learned_wins", C.c_int), ("iterations", C.c_int * 2), ("status", C.c_int * 2),
+                ("log10_relres", C.c_double * 2), ("log10_rate", C.c_double * 2), ("ms_per_iter", C.c_double * 2),
+                ("predicted_ms", C.c_double * 2)]
+
+
 class gcin_graph(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("rowptr", C.c_void_p), ("col", C.c_void_p),
                 ("val", C.c_void_p)]
@@ -99,6 +105,8 @@ SIGNATURES = {
     "amgg_set_packed_columns": (_I, [_VP, _I]),
     "amgg_level_apply_timed": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP]),
     "amgg_solve": (_I, [_VP, C.POINTER(amgg_solve_opts), _VP, _VP, C.POINTER(amgg_solve_info), _VP, _I, _VP]),
+    "amgg_judge_smoother": (_I, [_VP, C.POINTER(amgg_solve_opts), _I, _I, _VP, _I, _VP, _VP,
+                                 C.POINTER(amgg_judge_info), _VP]),
     "amgg_vcycle_loss_adjoint": (_I, [_VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _VP]),
     "amgg_set_level_blocks": (_I, [_VP, _I, _I32, _VP, _VP, _VP]),
     "amgg_set_smoother_coeffs_blocks": (_I, [_VP, _I, _I, _VP, _I32, _VP]),
@@ -358,6 +366,13 @@ def amgg_solve(ctx, opts: amgg_solve_opts, b, x, history_cap: int, stream):
     rc = _check(lib().amgg_solve(ctx, C.byref(opts), b, x, C.byref(info), _np_ptr(hist), history_cap, stream),
                 "amgg_solve")
     return rc, info, hist
+
+
+def amgg_judge_smoother(ctx, opts: amgg_solve_opts, iters, degree, coeffs_dev, diag_levels, b, x, stream):
+    info = amgg_judge_info()
+    _check(lib().amgg_judge_smoother(ctx, C.byref(opts), iters, degree, coeffs_dev, diag_levels, b, x, C.byref(info),
+                                     stream), "amgg_judge_smoother")
+    return info
 
 
 def amgg_vcycle_loss_adjoint(ctx, nu1, nu2, precision, nvc, f, u0, loss_dev, dcoeffs_dev, stream):

@@ -15,6 +15,7 @@
 // The FP64 outer loop's products (q = A p with p^T q, r = b - A x with r^T r) are the same
 // stream kernel writing one partial sum per workgroup, reduced afterwards in a fixed order.
 #include "kernels.hpp"
+#include "xcd.hpp"
 
 namespace amgg {
 
@@ -40,17 +41,6 @@ int stream_rows(int32_t nrows, int32_t nnz) {
     for (int r : {256, 128, 64, 32})
         if (r * avg * 1.25 <= kStreamCap) return r;
     return 0;
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on XCD b mod 8), each
-// with its own L2. Renumber them so that every XCD processes one contiguous range of row
-// blocks: neighbouring rows gather neighbouring x entries, which then stay in one L2.
-__device__ __forceinline__ int32_t xcd_block() {
-    constexpr int32_t kXcd = 8;
-    const int32_t b = blockIdx.x, g = gridDim.x;
-    const int32_t q = g / kXcd, r = g % kXcd;
-    const int32_t x = b % kXcd, k = b / kXcd;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
 template <typename T, int LANES>

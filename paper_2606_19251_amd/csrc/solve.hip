@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -384,5 +385,107 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
             stag_base = hist.size() - 1;
             if (R.e != hipSuccess) return hip_fail(R.e, "amgg_solve");
         }
+    });
+}
+
+// ------------------------------------------------------------------------------------------
+// Judge of the learned smoother: the plain omega-Jacobi AMG decides, on the matrix at hand,
+// whether the learned coefficients pay for themselves in solve time (the paper measures the
+// acceleration as the Jacobi solve time over the learned one, Sec. 4).
+// ------------------------------------------------------------------------------------------
+namespace {
+
+// Runs `iters` iterations of `o` (fallback off, graphs captured beforehand by a two-iteration
+// run) and measures the wall-clock time of the synchronous iterations. The residual history
+// gives the final relative residual and the reduction per iteration over the second half of
+// the run (the first iterations remove the error components the cycle damps best and fall
+// faster than the rest of the solve will).
+struct Probe {
+    int iterations = 0, status = 0;
+    double log10_rel = 0.0, log10_rate = 0.0, ms_per_iter = 0.0;
+};
+
+int probe_smoother(amgg_ctx* c, const amgg_solve_opts* o, int iters, const double* b, double* x, hipStream_t st,
+                   Probe* out) {
+    amgg_solve_opts p = *o;
+    p.fallback = 0;
+    std::vector<double> hist(static_cast<size_t>(iters) + 1, 1.0);
+    amgg_solve_info info{};
+    if (p.graphs && p.outer != AMGG_OUTER_STATIONARY) {
+        p.maxit = std::min(2, iters);
+        const int rc = amgg_solve(c, &p, b, x, &info, nullptr, 0, st);
+        if (rc < 0) return rc;
+    }
+    p.maxit = iters;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "amgg_judge_smoother");
+    const auto t0 = std::chrono::steady_clock::now();
+    const int rc = amgg_solve(c, &p, b, x, &info, hist.data(), iters + 1, st);
+    e = hipStreamSynchronize(st);
+    const auto t1 = std::chrono::steady_clock::now();
+    if (rc < 0) return rc;
+    if (e != hipSuccess) return hip_fail(e, "amgg_judge_smoother");
+    const int k = std::min(info.iterations, iters);
+    out->iterations = info.iterations;
+    out->status = rc;
+    out->ms_per_iter = std::chrono::duration<double, std::milli>(t1 - t0).count() / std::max(k, 1);
+    auto lg = [](double v) { return v > 0.0 ? std::log10(v) : (v == 0.0 ? -INFINITY : NAN); };
+    out->log10_rel = k > 0 ? lg(hist[k]) : 0.0;
+    const int h = k / 2;
+    out->log10_rate = k > 0 ? (out->log10_rel - lg(hist[h])) / (k - h) : 0.0;
+    return AMGG_OK;
+}
+
+// Predicted solve time to tol: the probe's own iterations when it reached tol, else the probe's
+// iterations plus the remaining reduction at the second-half rate.
+double predicted_ms(const Probe& p, double tol) {
+    if (p.status == 0) return p.ms_per_iter * p.iterations;
+    if (p.status != AMGG_MAXIT || !(p.log10_rate < 0.0) || !std::isfinite(p.log10_rel)) return INFINITY;
+    return p.ms_per_iter * (p.iterations + (std::log10(tol) - p.log10_rel) / p.log10_rate);
+}
+
+}  // namespace
+
+extern "C" int amgg_judge_smoother(amgg_ctx* c, const amgg_solve_opts* o, int iters, int degree,
+                                   const float* coeffs_dev, int diag_levels, const double* b, double* x,
+                                   amgg_judge_info* out, void* stream) {
+    return guarded([&]() -> int {
+        if (!c) return fail(AMGG_EINVAL, "amgg_judge_smoother: null context");
+        if (!c->finalized) return fail(AMGG_ESTATE, "amgg_judge_smoother: hierarchy not finalized");
+        int rc = AMGG_OK;
+        if (c->nblk > 0) return fail(AMGG_ESTATE, "amgg_judge_smoother: not available on a block-diagonal hierarchy");
+        if (!o || !coeffs_dev || !b || !x || !out) return fail(AMGG_EINVAL, "amgg_judge_smoother: null argument");
+        if (iters < 1 || iters > 100) return fail(AMGG_EINVAL, "amgg_judge_smoother: iters must be in [1, 100]");
+        if (degree < 1 || degree > AMGG_MAX_DEGREE || diag_levels < 0)
+            return fail(AMGG_EINVAL, "amgg_judge_smoother: bad degree or diag_levels");
+        const hipStream_t st = static_cast<hipStream_t>(stream);
+        const int nc = 2 * degree + 1;
+        auto set_learned = [&]() -> int {
+            for (int l = 0; l < c->nlevels; ++l) {
+                const int r = amgg_set_smoother_coeffs_device_form(c, l, degree, coeffs_dev + static_cast<int64_t>(l) * nc,
+                                                                   l < diag_levels ? 1 : 0, stream);
+                if (r) return r;
+            }
+            return AMGG_OK;
+        };
+        amgg_judge_info j{};
+        Probe pr[2];
+        if ((rc = set_learned())) return rc;
+        if ((rc = probe_smoother(c, o, iters, b, x, st, &pr[0]))) return rc;
+        for (int l = 0; l < c->nlevels; ++l)
+            if ((rc = amgg_set_smoother_jacobi(c, l, 2.0 / 3.0, stream))) return rc;
+        if ((rc = probe_smoother(c, o, iters, b, x, st, &pr[1]))) return rc;
+        for (int s = 0; s < 2; ++s) {
+            j.iterations[s] = pr[s].iterations;
+            j.status[s] = pr[s].status;
+            j.log10_relres[s] = pr[s].log10_rel;
+            j.log10_rate[s] = pr[s].log10_rate;
+            j.ms_per_iter[s] = pr[s].ms_per_iter;
+            j.predicted_ms[s] = predicted_ms(pr[s], o->tol);
+        }
+        j.learned_wins = j.predicted_ms[0] < j.predicted_ms[1] ? 1 : 0;
+        if (j.learned_wins && (rc = set_learned())) return rc;
+        *out = j;
+        return AMGG_OK;
     });
 }

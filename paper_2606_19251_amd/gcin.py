@@ -168,6 +168,13 @@ class Predictor:
         self._last_batch = batch
         return out
 
+    def predict_judged(self, hier, ds, b, x=None, **judge_kw):
+        """Predict the coefficients, then let the omega-Jacobi AMG judge them on b (DeviceSolver.judge):
+        the solver keeps the learned smoother only when it predicts the shorter solve. Returns
+        (coefficients, the judge's record)."""
+        coeffs = self.predict(hier, ds)
+        return coeffs, ds.judge(b, coeffs, self.degree, x=x, diag_levels=self.diag_levels, **judge_kw)
+
 
 class Trainer:
     """Alg. 1 of the paper on the GPU: batched GCIN inference over every level of every problem,

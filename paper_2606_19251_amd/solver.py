@@ -232,6 +232,22 @@ class DeviceSolver:
         rc, info, hist = capi.amgg_solve(self.ctx, o, b.data_ptr(), x.data_ptr(), history_cap, self.stream)
         return x, rc, info, hist[: max(0, min(history_cap, info.iterations + 1))]
 
+    def judge(self, b, coeffs_dev, degree, x=None, diag_levels=None, outer=capi.AMGG_OUTER_FCG, precision=32,
+              nu1=1, nu2=1, tol=1e-8, iters=12, graphs=True):
+        """amgg_judge_smoother: keeps the learned coefficients (float32 CUDA tensor [nlevels, 2d+1]) or
+        omega-Jacobi, whichever predicts the shorter solve of b; returns the judge's record as a dict."""
+        assert coeffs_dev.dtype == self.torch.float32 and coeffs_dev.is_contiguous()
+        if x is None:
+            x = self.torch.empty_like(b)
+        k = self.diag_levels if diag_levels is None else diag_levels
+        o = capi.amgg_solve_opts(outer, precision, nu1, nu2, iters, tol, 0, 0.0, 0.0, 0, int(graphs))
+        j = capi.amgg_judge_smoother(self.ctx, o, iters, degree, coeffs_dev.data_ptr(), k, b.data_ptr(), x.data_ptr(),
+                                     self.stream)
+        pair = lambda a: [a[0], a[1]]
+        return {"learned_wins": bool(j.learned_wins), "iterations": pair(j.iterations), "status": pair(j.status),
+                "log10_relres": pair(j.log10_relres), "log10_rate": pair(j.log10_rate),
+                "ms_per_iter": pair(j.ms_per_iter), "predicted_ms": pair(j.predicted_ms)}
+
     # ---------------------------------------------------------------- inspection
     def _ws_slice(self, ptr, count, dtype):
         torch = self.torch
