@@ -289,14 +289,15 @@ def finish_cpu_baseline(job, gpu_iters, workload_desc, limit_s):
 
 
 # Each mesh family's GCIN weights. The first is the network the GCIN rows of the JSON line use: on
-# the 1M P1 and 8M tetrahedral meshes the cost-aware one, trained with the diagonal form of Eq. 5
-# (f_o = 0) on the 3 / 2 finest levels, where the sparse smoother's second matrix pass costs the
-# most; the second (where given) is the network with the sparse form on every level, reported as
-# `gnn_sparse_all_levels`.
+# the 1M P1 and 8M tetrahedral meshes a cost-aware one, trained with the diagonal form of Eq. 5
+# (f_o = 0) on every level (P1; the fastest under flexible CG, the mesh's configured outer loop)
+# or on the 4 finest levels (tetrahedra; the fastest under both outer loops), where the sparse
+# smoother's second matrix pass costs the most; the second (where given) is the network with the
+# sparse form on every level, reported as `gnn_sparse_all_levels`.
 WORKLOADS = {
-    "delaunay1m": ("gcin_deg2_d3.npz", "P1 Laplacian on the Delaunay mesh of 1,000,000 points in the unit square, "
+    "delaunay1m": ("gcin_deg2_d8.npz", "P1 Laplacian on the Delaunay mesh of 1,000,000 points in the unit square, "
                                        "all-Neumann"),
-    "tet8m": ("gcin_tet_deg2_d2.npz", "FV Poisson on the Kuhn tetrahedra of a jittered 111^3 lattice "
+    "tet8m": ("gcin_tet_deg2_d4.npz", "FV Poisson on the Kuhn tetrahedra of a jittered 111^3 lattice "
                                       "(7,986,000 cells), all-Neumann"),
     "cmesh4m": ("gcin_cmesh_deg2.npz", "FV Poisson on a 4096 x 1024 C-mesh around NACA 2412, wall aspect 1e4"),
     "grid1m": ("gcin_grid_h32_deg2.npz", "5-point Laplacian on a 1024 x 1024 structured grid, Dirichlet "

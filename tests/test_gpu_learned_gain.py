@@ -36,8 +36,10 @@ def _meshes(family):
 
 @pytest.mark.parametrize("family,weights", [("delaunay", "gcin_deg2.npz"), ("tet", "gcin_tet_deg2.npz"),
                                             # cost-aware networks: the diagonal form of Eq. 5 on the 3
-                                            # (P1) or 2 (tetrahedra) finest levels
+                                            # (P1) or 2 or 4 (tetrahedra) finest levels, or on all
+                                            # levels (P1)
                                             ("delaunay", "gcin_deg2_d3.npz"), ("tet", "gcin_tet_deg2_d2.npz"),
+                                            ("tet", "gcin_tet_deg2_d4.npz"), ("delaunay", "gcin_deg2_d8.npz"),
                                             ("cmesh", "gcin_cmesh_deg2.npz"),
                                             # one model trained on the union of the three families (on
                                             # the C-meshes it gains nothing: Eq. 13 metric +0.008)
