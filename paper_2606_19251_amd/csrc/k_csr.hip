@@ -244,7 +244,8 @@ __device__ __forceinline__ T row_sum(const T* buf, int32_t pb, int32_t pe) {
     return s;
 }
 
-// DOT: 0 none; 1 partial of x_i y_i (q = A p, p^T q); 2 partial of y_i^2 (r = b - A x, r^T r).
+// DOT: 0 none; 1 partial of x_i y_i (q = A p, p^T q); 2 partial of y_i^2 (r = b - A x, r^T r);
+// 3 as 2, with the scaled FP32 copy of y written through cs instead of y itself.
 // PACKED: columns from cp (packed for blocks of ROWS rows), else from col.
 template <typename T, Epi E, int ROWS, int DOT, bool PACKED>
 __global__ __launch_bounds__(kBlock) void csr_stream_kernel(int32_t nrows, const int32_t* __restrict__ ptr,
@@ -253,7 +254,8 @@ __global__ __launch_bounds__(kBlock) void csr_stream_kernel(int32_t nrows, const
                                                            T* __restrict__ y, const T* __restrict__ f,
                                                            const T* __restrict__ qd, const T* __restrict__ u,
                                                            T* __restrict__ y2, double* __restrict__ partial,
-                                                           int32_t cap) {
+                                                           int32_t cap, Cast32 cs) {
+    static_assert(DOT != 3 || (E == Epi::Resid && sizeof(T) == 8), "the FP32 copy is of an FP64 residual");
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* prod = reinterpret_cast<T*>(lds_raw);  // cap products (dynamic LDS)
     const int32_t blk = xcd_block();
@@ -295,9 +297,15 @@ __global__ __launch_bounds__(kBlock) void csr_stream_kernel(int32_t nrows, const
         if constexpr (E == Epi::Add) out = yr + s;
         if constexpr (E == Epi::Sub) out = yr - s;
         if constexpr (E == Epi::Jacobi) out = ur + qr * (fr - s);
-        y[row] = out;
+        if constexpr (DOT == 3) {
+            const float fy = static_cast<float>(out * cs.scale[0]);
+            cs.f[row] = fy;
+            if (cs.qd) cs.u[row] = cs.qd[row] * fy;
+        } else {
+            y[row] = out;
+        }
         if constexpr (DOT == 1) d = static_cast<double>(xr) * static_cast<double>(s);
-        if constexpr (DOT == 2) d = static_cast<double>(out) * static_cast<double>(out);
+        if constexpr (DOT >= 2) d = static_cast<double>(out) * static_cast<double>(out);
     }
     if constexpr (DOT != 0) block_partial(d, partial);
 }
@@ -355,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void rows_dot_kernel(int32_t nrows, const i
 
 template <typename T, Epi E, int DOT>
 hipError_t launch_stream(int rows, const CsrView& m, const T* val, const T* x, T* y, const T* f, const T* qd,
-                         const T* u, T* y2, double* partial, hipStream_t stream) {
+                         const T* u, T* y2, double* partial, hipStream_t stream, const Cast32& cs = Cast32{}) {
     const dim3 grid(static_cast<unsigned>((m.nrows + rows - 1) / rows));
     const bool packed = m.cp.rows == rows && m.cp.off != nullptr;
     if (m.cap < kStreamRound || m.cap > kStreamCap || m.cap % kStreamRound) return hipErrorInvalidValue;
@@ -363,10 +371,11 @@ hipError_t launch_stream(int rows, const CsrView& m, const T* val, const T* x, T
     switch (rows) {
 #define AMGG_CASE(R)                                                                                              \
     case R:                                                                                                       \
-        return packed ? launch_kernel_lds(csr_stream_kernel<T, E, R, DOT, true>, grid, dim3(kBlock), lds, stream, \
-                                          m.nrows, m.ptr, m.col, m.cp, val, x, y, f, qd, u, y2, partial, m.cap)   \
-                      : launch_kernel_lds(csr_stream_kernel<T, E, R, DOT, false>, grid, dim3(kBlock), lds, stream, \
-                                          m.nrows, m.ptr, m.col, ColPack{}, val, x, y, f, qd, u, y2, partial, m.cap);
+        return packed ? launch_kernel_lds(csr_stream_kernel<T, E, R, DOT, true>, grid, dim3(kBlock), lds, stream,    \
+                                          m.nrows, m.ptr, m.col, m.cp, val, x, y, f, qd, u, y2, partial, m.cap, cs)  \
+                      : launch_kernel_lds(csr_stream_kernel<T, E, R, DOT, false>, grid, dim3(kBlock), lds, stream,   \
+                                          m.nrows, m.ptr, m.col, ColPack{}, val, x, y, f, qd, u, y2, partial, m.cap, \
+                                          cs);
         AMGG_CASE(256)
         AMGG_CASE(128)
         AMGG_CASE(64)
@@ -746,6 +755,15 @@ hipError_t csr_resid_norm(const CsrView& m, const double* val, const double* x, 
     hipError_t e = hipSuccess;
     *count = launch_outer<2>(m, val, x, b, r, partial, stream, &e);
     return e;
+}
+
+hipError_t csr_resid_cast(const CsrView& m, const double* val, const double* x, const double* b, const Cast32& cast,
+                          double* partial, int* count, hipStream_t stream) {
+    const int rows = stream_rows(m.nrows, m.nnz);
+    if (rows <= 0 || !cast.f || !cast.scale || (cast.qd == nullptr) != (cast.u == nullptr)) return hipErrorInvalidValue;
+    *count = (m.nrows + rows - 1) / rows;
+    return launch_stream<double, Epi::Resid, 3>(rows, m, val, x, nullptr, b, nullptr, nullptr, nullptr, partial, stream,
+                                                cast);
 }
 
 template <typename T>

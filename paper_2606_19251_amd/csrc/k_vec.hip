@@ -240,7 +240,25 @@ __global__ void ir_update_f32_kernel(int32_t n, double* __restrict__ x, const fl
                                      const double* __restrict__ s) {
     if (s[kHalt] != 0.0) return;
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) x[i] += static_cast<double>(u32[i]) * s[kNorm];
+    if (i < n) x[i] += static_cast<double>(u32[i]) * s[kUnscale];
+}
+
+// 2^-e with e the binary exponent of v (v in [2^e, 2^(e+1))); 1 for v = 0 or non-finite v
+__device__ __forceinline__ double pow2_scale(double v) {
+    return v > 0.0 && v <= 1.7976931348623157e308 ? ldexp(1.0, -ilogb(v)) : 1.0;
+}
+
+__device__ __forceinline__ void set_scales(double* s, double next, double cast) {
+    s[kScaleNext] = next;
+    s[kScaleCast] = cast;
+    s[kUnscale] = 1.0 / cast;  // exact: cast is a power of two
+}
+
+__global__ void ir_set_scales_kernel(double* __restrict__ s) {
+    if (threadIdx.x == 0) {
+        const double sc = pow2_scale(s[kNorm]);
+        set_scales(s, sc, sc);
+    }
 }
 
 __global__ void ir_update_f64_kernel(int32_t n, double* __restrict__ x, const double* __restrict__ e,
@@ -256,6 +274,8 @@ __global__ void fcg_set_limits_kernel(double* __restrict__ s, double tol2, doubl
         s[kDivRR] = div2 * s[kRR];
         s[kHalt] = 0.0;
         s[kFlag] = 0.0;
+        const double sc = pow2_scale(sqrt(s[kRR]));
+        set_scales(s, sc, sc);
     }
 }
 
@@ -276,6 +296,7 @@ __global__ __launch_bounds__(kFinish) void fcg_finish_rr_guarded_kernel(const do
         s[kNorm] = nrm;
         s[kInvNorm] = nrm > 0.0 ? 1.0 / nrm : 0.0;
         if (rr <= s[kTolRR] || !(rr <= s[kDivRR])) s[kHalt] = 1.0;
+        set_scales(s, pow2_scale(nrm), s[kScaleNext]);
     }
 }
 
@@ -423,6 +444,11 @@ hipError_t fcg_set_limits(double* s, double tol, double div, hipStream_t stream)
 
 hipError_t fcg_clear_halt(double* s, hipStream_t stream) {
     fcg_clear_halt_kernel<<<1, 64, 0, stream>>>(s);
+    return hipGetLastError();
+}
+
+hipError_t ir_set_scales(double* s, hipStream_t stream) {
+    ir_set_scales_kernel<<<1, 64, 0, stream>>>(s);
     return hipGetLastError();
 }
 

@@ -82,6 +82,16 @@ struct ColPack {
     int rows = 0;                     // rows per block of the encoding (0: none, plain columns)
 };
 
+// The FP32 right-hand side of the next cycle, written by the outer loop's residual kernel instead
+// of the FP64 residual: f[i] = (float)(r_i * scale[0]) and, with qd, u[i] = qd[i] * f[i] (the first
+// diagonal smoothing step from zero of the cycle that receives f).
+struct Cast32 {
+    float* f = nullptr;
+    const float* qd = nullptr;
+    float* u = nullptr;
+    const double* scale = nullptr;
+};
+
 struct CsrView {
     int32_t nrows;
     int32_t nnz;
@@ -175,7 +185,12 @@ hipError_t csr_spmv_dot(const CsrView& m, const double* val, const double* p, do
 // r = b - A x and per-workgroup partial sums of r_i^2; *count = partials written.
 hipError_t csr_resid_norm(const CsrView& m, const double* val, const double* x, const double* b, double* r,
                           double* partial, int* count, hipStream_t stream);
-// Number of partial sums the two calls above write for a matrix of this shape.
+// r = b - A x with the partials of r_i^2 as csr_resid_norm, but r itself is not stored: the kernel
+// writes its scaled FP32 copy (Cast32). Only for matrices the CSR-stream kernels serve
+// (stream_rows_for > 0); hipErrorInvalidValue otherwise.
+hipError_t csr_resid_cast(const CsrView& m, const double* val, const double* x, const double* b, const Cast32& cast,
+                          double* partial, int* count, hipStream_t stream);
+// Number of partial sums the calls above write for a matrix of this shape.
 int outer_partials(int32_t nrows, int32_t nnz);
 
 // ---------------------------------------------------------------------------------------
@@ -222,15 +237,25 @@ enum FcgSlot : int {
     kTolRR = 12,  // tol^2 ||b||^2: the guarded steps halt below it
     kDivRR = 13,  // div^2 ||b||^2: ... and above it (or on a non-finite norm)
     kHalt = 14,   // 1.0 once a guarded step has halted the iteration
-    kSlots = 16
+    // Iterative refinement with FP32 cycles scales each residual by a power of two (exact in
+    // both directions) fixed before the residual is formed, so that the residual kernel can
+    // write the cycle's FP32 right-hand side itself: r_k is scaled by 2^-e, e the exponent of
+    // ||r_{k-1}|| (r_k is at most about ||r_{k-1}||, so the FP32 values stay near 1).
+    kScaleNext = 15,  // scale for the residual about to be formed
+    kScaleCast = 16,  // scale of the residual held in FP32 (or to be cast next)
+    kUnscale = 17,    // 1 / kScaleCast, applied to the cycle's output
+    kSlots = 18
 };
 // Halting. An outer iteration may be enqueued before the host has read the previous one's
 // residual; the guarded steps below then leave x and the residual norm unchanged once the
 // iteration has converged, diverged or broken down (kHalt or kFlag set).
 // s[kTolRR] = tol^2 s[kRR], s[kDivRR] = div^2 s[kRR], s[kHalt] = s[kFlag] = 0 (from the initial residual)
 hipError_t fcg_set_limits(double* s, double tol, double div, hipStream_t stream);
+// the three scale slots from s[kNorm] (at the start of a solve and after a restart)
+hipError_t ir_set_scales(double* s, hipStream_t stream);
 hipError_t fcg_clear_halt(double* s, hipStream_t stream);  // s[kHalt] = s[kFlag] = 0
-// guarded fcg_finish_rr: skipped when halted; sets kHalt when rr <= s[kTolRR] or !(rr <= s[kDivRR])
+// guarded fcg_finish_rr: skipped when halted; sets kHalt when rr <= s[kTolRR] or !(rr <= s[kDivRR]);
+// moves kScaleNext to kScaleCast (and its inverse to kUnscale) and sets kScaleNext from the new norm
 hipError_t fcg_finish_rr_guarded(const double* partial, int count, double* s, hipStream_t stream);
 hipError_t fcg_finish_pq(const double* partial, int count, double* s, hipStream_t stream);  // pq, alpha = gamma/pq
 // x += a p ; rnew = r - a q (skipped, partials included, when halted)

@@ -36,6 +36,11 @@ struct Runner {
     amgg_ctx* c;
     int nu1, nu2, prec;
     hipError_t e = hipSuccess;
+    // Iterative refinement with FP32 cycles: the residual kernel writes the next cycle's FP32
+    // right-hand side itself (csr_resid_cast) instead of the FP64 residual and a cast pass; off
+    // with the fused kernels (amgg_set_fusion) and for matrices the CSR-stream kernels do not
+    // serve. Both forms give bitwise the same iterates.
+    bool ir_cast = false;
 
     void ok(hipError_t r) {
         if (r != hipSuccess && e == hipSuccess) e = r;
@@ -43,7 +48,18 @@ struct Runner {
 
     // z = V(0, r) on the fine level. FP64: returns the pointer holding z. FP32: the cycle's
     // FP32 result pointer is left in `last32` (the caller casts it back, scaled by ||r||).
-    const double* precondition(const double* r, hipStream_t st) {
+    // r scaled by s[slot] into the fine level's FP32 right-hand side; a diagonal first smoothing
+    // step u = qd f is formed by the cast itself
+    void cast_rhs(const double* r, int slot, hipStream_t st) {
+        Level& L0 = c->lv[0];
+        const bool ready = takes_ready_u(c, 0, nu1);
+        ok(cast_scaled_f64_f32(L0.n, r, c->scal + slot, L0.f32, st, ready ? L0.qd32 : nullptr,
+                               ready ? L0.u32 : nullptr));
+    }
+
+    // z = V(0, r). FP32: r is cast scaled by s[slot], unless r is null (the FP32 right-hand side
+    // is already in place).
+    const double* precondition(const double* r, hipStream_t st, int slot = kInvNorm) {
         Level& L0 = c->lv[0];
         if (prec == 64) {
             double* res = nullptr;
@@ -51,10 +67,8 @@ struct Runner {
             return res;
         }
         float* res = nullptr;
-        // a diagonal first smoothing step u = qd f is formed by the cast itself
         const bool ready = takes_ready_u(c, 0, nu1);
-        ok(cast_scaled_f64_f32(L0.n, r, c->scal + kInvNorm, L0.f32, st, ready ? L0.qd32 : nullptr,
-                               ready ? L0.u32 : nullptr));
+        if (r) cast_rhs(r, slot, st);
         ok(vcycle_level<float>(c, 0, L0.f32, L0.u32, L0.t32, true, nu1, nu2, st, &res, false, ready));
         last32 = res;
         return nullptr;
@@ -85,17 +99,28 @@ struct Runner {
         ok(fcg_finish_rr_guarded(c->partial, kReduceBlocks, s, st));
     }
 
-    // Iterative refinement: x += V(0, r); r = b - A x.
+    // Iterative refinement: x += V(0, r); r = b - A x. FP32 cycles take r scaled by a power of two
+    // (kScaleCast) and their output is scaled back exactly (kUnscale).
     void ir_iteration(double* x, const double* bb, double* r, hipStream_t st) {
         Level& L0 = c->lv[0];
         const int32_t n = L0.n;
-        const double* e64 = precondition(r, st);
+        const double* e64 = precondition(ir_cast ? nullptr : r, st, kScaleCast);
         if (prec == 64)
             ok(ir_update_f64(n, x, e64, c->scal, st));
         else
             ok(ir_update_f32(n, x, last32, c->scal, st));
         int cnt = 0;
-        ok(csr_resid_norm(L0.A(), L0.val, x, bb, r, c->partial, &cnt, st));
+        if (ir_cast) {
+            const bool ready = takes_ready_u(c, 0, nu1);
+            Cast32 cs;
+            cs.f = L0.f32;
+            cs.qd = ready ? L0.qd32 : nullptr;
+            cs.u = ready ? L0.u32 : nullptr;
+            cs.scale = c->scal + kScaleNext;
+            ok(csr_resid_cast(L0.A(), L0.val, x, bb, cs, c->partial, &cnt, st));
+        } else {
+            ok(csr_resid_norm(L0.A(), L0.val, x, bb, r, c->partial, &cnt, st));
+        }
         ok(fcg_finish_rr_guarded(c->partial, cnt, c->scal, st));
     }
 
@@ -177,6 +202,7 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
         Level& L0 = c->lv[0];
         const int32_t n = L0.n;
         const CsrView A = L0.A();
+        R.ir_cast = o->outer == AMGG_OUTER_IR && o->inner_precision == 32 && L0.fuse && stream_rows_for(n, L0.nnz) > 0;
         double* s = c->scal;
         double* hs = c->host_scal;
         int vcycles = 0;
@@ -259,6 +285,7 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
         // asynchronous copy of the scalar block into one of two pinned slots; the host keeps
         // one iteration in flight while it inspects the previous one.
         R.ok(fcg_set_limits(s, o->tol, div_factor, st));
+        if (R.ir_cast) R.cast_rhs(c->ra, kScaleCast, st);  // the first cycle's right-hand side: b
         struct InFlight {
             double* cu;
             double* pv;
@@ -378,6 +405,8 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
             int cnt = 0;
             R.ok(csr_resid_norm(A, L0.val, x, bb, c->ra, c->partial, &cnt, st));
             R.ok(fcg_finish_rr(c->partial, cnt, s, st));
+            R.ok(ir_set_scales(s, st));
+            if (R.ir_cast) R.cast_rhs(c->ra, kScaleCast, st);
             cur = c->ra;
             prev = c->rb;
             first = true;

@@ -377,8 +377,10 @@ def test_timed_level_operator_records_kernel_time():
 def test_ready_first_step_solves_equal_separate_passes(kind, smoother):
     """Where a level's cycle from zero starts with a diagonal step, the pass that produces its
     right-hand side (the outer loop's FP32 cast on the fine level, the restriction below it) also
-    forms u = qd f; the FP32-cycle solves (iterative refinement and flexible CG, V(1,1) and
-    V(2,2)) are bitwise those of the separate passes."""
+    forms u = qd f; under iterative refinement the FP64 residual kernel itself writes the next
+    cycle's FP32 right-hand side (scaled by a power of two) instead of the FP64 residual. The
+    FP32-cycle solves (iterative refinement and flexible CG, V(1,1) and V(2,2)) are bitwise those
+    of the separate passes."""
     from paper_2606_19251_amd import capi
 
     A, f, ho, hp, ds = _setup(kind)
