@@ -261,70 +261,64 @@ __global__ void pad_rows_kernel(int32_t from, int32_t to, int32_t eptr, int32_t*
 // ------------------------------------------------------------------------------------------
 // forward
 // ------------------------------------------------------------------------------------------
+// Output of layer 0 at a node from its two aggregated input features h = (A_hat x0)_i:
+// y_c = b0_c + h0 W0[0][c] + h1 W0[1][c]. The input features span two dimensions, so y is never
+// stored: every consumer (the layer's statistics and pooling, layer 1's aggregation, the
+// backward) forms it from h with this one expression, 8 bytes per node instead of 4 HD.
+__device__ __forceinline__ float y0_of(float2 h, float w0, float w1, float bb) {
+    return __builtin_fmaf(h.y, w1, __builtin_fmaf(h.x, w0, bb));
+}
+
+// Layer 0 of a tile: H0 = A_hat x0 (two features per node; 4 HD / 64 lanes per row, each summing
+// every such entry of the row, combined in a fixed butterfly) and the per-tile sums of y and
+// y^2 for the InstanceNorm statistics.
 template <int HD>
 __global__ __launch_bounds__(4 * HD) void layer0_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                                     const float* __restrict__ w, const float* __restrict__ x0,
                                                     const int32_t* __restrict__ tile_graph,
                                                     const int32_t* __restrict__ gend, const float* __restrict__ W0,
                                                     const float* __restrict__ b0, float* __restrict__ H0,
-                                                    float* __restrict__ Y, double* __restrict__ tstat) {
+                                                    double* __restrict__ tstat) {
+    constexpr int LPR = 4 * HD / TILE;
     __shared__ double sh[4][HD];
+    __shared__ float2 hs[TILE];
     const int tile = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
     const int32_t end = gend[tile_graph[tile]];
+    {
+        const int lr = threadIdx.x / LPR, q = threadIdx.x % LPR;
+        const int32_t row = tile * TILE + lr;
+        float h0 = 0.0f, h1 = 0.0f;
+        if (row < end) {
+            const int32_t pe = ptr[row + 1];
+            for (int32_t k = ptr[row] + q; k < pe; k += LPR) {
+                const float wk = w[k];
+                const float2 xv = *reinterpret_cast<const float2*>(x0 + 2 * static_cast<int64_t>(col[k]));
+                h0 = __builtin_fmaf(wk, xv.x, h0);
+                h1 = __builtin_fmaf(wk, xv.y, h1);
+            }
+        }
+#pragma unroll
+        for (int off = 1; off < LPR; off <<= 1) {
+            h0 += __shfl_xor(h0, off, LPR);
+            h1 += __shfl_xor(h1, off, LPR);
+        }
+        if (q == 0) {
+            const float2 hv = make_float2(h0, h1);
+            hs[lr] = hv;
+            reinterpret_cast<float2*>(H0)[row] = hv;
+        }
+    }
+    __syncthreads();
     const float w0 = W0[c], w1 = W0[HD + c], bb = b0[c];
     double s1 = 0.0, s2 = 0.0;
-    float h0 = 0.0f, h1 = 0.0f;
-    const int32_t r0 = tile * TILE + wv * 16;
-    auto done = [&](int32_t row) {
-        float y = 0.0f;
-        if (row < end) {
-            y = bb + h0 * w0 + h1 * w1;
-            if (c == 0) {
-                H0[2 * row] = h0;
-                H0[2 * row + 1] = h1;
-            }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int lr = wv * 16 + r;
+        if (tile * TILE + lr < end) {
+            const float y = y0_of(hs[lr], w0, w1, bb);
             s1 += y;
             s2 += static_cast<double>(y) * y;
         }
-        Y[static_cast<int64_t>(row) * HD + c] = y;
-        h0 = h1 = 0.0f;
-    };
-    if constexpr (HD == 64) {
-        // The input features are two numbers per node, the same for every channel: lane l loads
-        // entry k + l of a round of 64 (column, weight and the neighbour's two features) and
-        // the wavefront reads them lane by lane, in stored order.
-        const int32_t rp = ptr[r0 + min(c, 16)];
-        auto bound = [&](int32_t i) { return __builtin_amdgcn_readfirstlane(__shfl(rp, i, 64)); };
-        const int32_t kbeg = bound(0), kend = bound(16);
-        int32_t r = r0, rnext = bound(1);
-        for (int32_t k = kbeg; k < kend; k += 64) {
-            const int32_t kk = min(k + c, kend - 1);
-            const float wl = w[kk];
-            const int32_t j = col[kk];
-            const float2 xv = *reinterpret_cast<const float2*>(x0 + 2 * static_cast<int64_t>(j));
-            const int32_t cnt = min(64, kend - k);
-            for (int32_t q = 0; q < cnt; ++q) {
-                while (k + q >= rnext) {
-                    done(r);
-                    ++r;
-                    rnext = bound(r + 1 - r0);
-                }
-                const float wq = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wl), q));
-                const float xq = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, xv.x), q));
-                const float yq = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, xv.y), q));
-                h0 += wq * xq;
-                h1 += wq * yq;
-            }
-        }
-        for (; r < r0 + 16; ++r) done(r);
-    } else {
-        visit_rows<HD, float2>(
-            ptr, col, w, r0, r0 + 16, [&](int32_t j) { return make_float2(x0[2 * j], x0[2 * j + 1]); },
-            [&](float wp, float2 v) {
-                h0 += wp * v.x;
-                h1 += wp * v.y;
-            },
-            done);
     }
     s1 = wave4_sum(s1, sh);
     s2 = wave4_sum(s2, sh);
@@ -430,10 +424,13 @@ __device__ __forceinline__ void stage_bf16_split_t(const float* __restrict__ M, 
     }
 }
 
-template <int HD, bool MFMA, bool X3>
+// Y0: the layer below is layer 0, whose output is formed from H0 (y0_of) instead of read from Yp.
+template <int HD, bool MFMA, bool X3, bool Y0>
 __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                                    const float* __restrict__ w, const int32_t* __restrict__ tile_graph,
                                                    const int32_t* __restrict__ gend, const float* __restrict__ Yp,
+                                                   const float* __restrict__ H0, const float* __restrict__ W0,
+                                                   const float* __restrict__ b0,
                                                    const float* __restrict__ mup, const float* __restrict__ rsp,
                                                    const float* __restrict__ gam, const float* __restrict__ bet,
                                                    const float* __restrict__ W, const float* __restrict__ b,
@@ -460,8 +457,20 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
         stage_bf16<HD>(W, true, Bt);
     float h = 0.0f;
     const int32_t r0 = tile * TILE + wv * 16;
+    float w0 = 0.0f, w1 = 0.0f, bb0 = 0.0f;
+    if constexpr (Y0) {
+        w0 = W0[c];
+        w1 = W0[HD + c];
+        bb0 = b0[c];
+    }
     visit_rows<HD, float>(
-        ptr, col, w, r0, r0 + 16, [&](int32_t j) { return Yp[static_cast<int64_t>(j) * HD + c]; },
+        ptr, col, w, r0, r0 + 16,
+        [&](int32_t j) {
+            if constexpr (Y0)
+                return y0_of(reinterpret_cast<const float2*>(H0)[j], w0, w1, bb0);
+            else
+                return Yp[static_cast<int64_t>(j) * HD + c];
+        },
         [&](float wp, float v) { h += wp * normrelu(v, mu, rs, ga, be); },
         [&](int32_t row) {
             const float hv = row < end ? h : 0.0f;
@@ -563,10 +572,32 @@ __global__ __launch_bounds__(4 * HD) void stats_final_kernel(const double* __res
     rstd[g * HD + c] = static_cast<float>(1.0 / sqrt(var + static_cast<double>(kEps)));
 }
 
+// y of rows r0 .. r0 + 15 in channel c (0 past the graph's end): read from Y, or formed from H0
+// for layer 0; the 16 loads are issued together.
+template <int HD, bool Y0>
+__device__ __forceinline__ void load_rows(float (&yv)[16], int32_t r0, int32_t end, int c, const float* __restrict__ Y,
+                                          const float* __restrict__ H0, const float* __restrict__ W0,
+                                          const float* __restrict__ b0) {
+    if constexpr (Y0) {
+        const float w0 = W0[c], w1 = W0[HD + c], bb = b0[c];
+        float2 hv[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            hv[r] = r0 + r < end ? reinterpret_cast<const float2*>(H0)[r0 + r] : make_float2(0.0f, 0.0f);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) yv[r] = r0 + r < end ? y0_of(hv[r], w0, w1, bb) : 0.0f;
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) yv[r] = r0 + r < end ? Y[static_cast<int64_t>(r0 + r) * HD + c] : 0.0f;
+    }
+}
+
 // Per tile: sum, max and first arg-max of x = ReLU(IN(y)) per channel.
-template <int HD>
+template <int HD, bool Y0>
 __global__ __launch_bounds__(4 * HD) void pool_tile_kernel(const int32_t* __restrict__ tile_graph,
                                                        const int32_t* __restrict__ gend, const float* __restrict__ Y,
+                                                       const float* __restrict__ H0, const float* __restrict__ W0,
+                                                       const float* __restrict__ b0,
                                                        const float* __restrict__ mu, const float* __restrict__ rstd,
                                                        const float* __restrict__ gam, const float* __restrict__ bet,
                                                        double* __restrict__ tsum, float* __restrict__ tmax,
@@ -582,11 +613,7 @@ __global__ __launch_bounds__(4 * HD) void pool_tile_kernel(const int32_t* __rest
     float mx = -INFINITY;
     int32_t am = INT32_MAX;
     float yv[16];  // the 16 rows' loads are issued together
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int32_t row = tile * TILE + wv * 16 + r;
-        yv[r] = row < end ? Y[static_cast<int64_t>(row) * HD + c] : 0.0f;
-    }
+    load_rows<HD, Y0>(yv, tile * TILE + wv * 16, end, c, Y, H0, W0, b0);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int32_t row = tile * TILE + wv * 16 + r;
@@ -839,11 +866,13 @@ __global__ __launch_bounds__(128) void head_bwd_kernel(const float* __restrict__
 // Layer backward, first half, per tile: dX from pooling (mean and arg-max) and, below the last
 // layer, from the next layer's aggregation (A_hat^T dH = A_hat dH, A symmetric); ReLU and the
 // affine part of InstanceNorm; per-tile sums for the normalisation backward and gamma/beta.
-template <int HD>
+template <int HD, bool Y0>
 __global__ __launch_bounds__(4 * HD) void bwd_a_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                                    const float* __restrict__ w, const int32_t* __restrict__ tile_graph,
                                                    const int32_t* __restrict__ gend, const float* __restrict__ gcnt,
-                                                   const float* __restrict__ Y, const float* __restrict__ mu,
+                                                   const float* __restrict__ Y, const float* __restrict__ H0,
+                                                   const float* __restrict__ W0, const float* __restrict__ b0,
+                                                   const float* __restrict__ mu,
                                                    const float* __restrict__ rstd, const float* __restrict__ gam,
                                                    const float* __restrict__ bet, const float* __restrict__ dpooled,
                                                    const int32_t* __restrict__ argmax, int layer,
@@ -861,8 +890,7 @@ __global__ __launch_bounds__(4 * HD) void bwd_a_kernel(const int32_t* __restrict
     double sa = 0.0, sb = 0.0, sg = 0.0, sbe = 0.0;
     const int32_t r0 = tile * TILE + wv * 16;
     float yv[16];  // this wavefront's rows of Y, loaded together while the aggregation runs
-#pragma unroll
-    for (int r = 0; r < 16; ++r) yv[r] = r0 + r < end ? Y[static_cast<int64_t>(r0 + r) * HD + c] : 0.0f;
+    load_rows<HD, Y0>(yv, r0, end, c, Y, H0, W0, b0);
     float acc = 0.0f;
     if (dHn) {
         visit_rows<HD, float>(
@@ -933,9 +961,11 @@ __global__ __launch_bounds__(4 * HD) void bwd_final_kernel(const double* __restr
 // Layer backward, second half. dY = rstd (dxhat - mean(dxhat) - xhat mean(dxhat xhat));
 // dH = dY W^T (stored for the layer below unless first); partial dW = H^T dY and db = sum dY
 // accumulated over the tiles a workgroup visits (fixed grid of kWBlocks, fixed order).
-template <int HD, bool MFMA>
+template <int HD, bool MFMA, bool Y0>
 __global__ __launch_bounds__(4 * HD) void bwd_b_kernel(int ntiles, const int32_t* __restrict__ tile_graph,
                                                    const int32_t* __restrict__ gend, const float* __restrict__ Y,
+                                                   const float* __restrict__ H0, const float* __restrict__ W0,
+                                                   const float* __restrict__ b0,
                                                    const float* __restrict__ mu, const float* __restrict__ rstd,
                                                    const float* __restrict__ gmean, const float* __restrict__ dxh,
                                                    const float* __restrict__ H, int in_dim,
@@ -969,7 +999,10 @@ __global__ __launch_bounds__(4 * HD) void bwd_b_kernel(int ntiles, const int32_t
                 const int32_t row = tile * TILE + wv * 16 + r8 + r;
                 const int64_t k = static_cast<int64_t>(row) * HD + c;
                 const bool ok = row < end;
-                yv[r] = ok ? Y[k] : 0.0f;
+                if constexpr (Y0)
+                    yv[r] = ok ? y0_of(reinterpret_cast<const float2*>(H0)[row], W0[c], W0[HD + c], b0[c]) : 0.0f;
+                else
+                    yv[r] = ok ? Y[k] : 0.0f;
                 dv[r] = ok ? dxh[k] : 0.0f;
                 hv[r] = ok && c < in_dim ? H[static_cast<int64_t>(row) * in_dim + c] : 0.0f;
             }
@@ -1246,8 +1279,10 @@ size_t layout_batch(gcin_batch* b, uintptr_t base) {
     b->H0 = cv.take<float>(2 * N);
     for (int l = 0; l < NL; ++l) {
         // forward only: a layer reads the layer below and its pooling reads the layer itself, so
-        // two activation buffers in turn suffice and the aggregates are not kept
-        b->Y[l] = b->infer && l >= 2 ? b->Y[l - 2] : cv.take<float>(N * HD);
+        // two activation buffers in turn suffice (layers 1, 2, then 3 in layer 1's) and the
+        // aggregates are not kept
+        // layer 0's output is formed from H0 where needed and never stored
+        b->Y[l] = l == 0 ? nullptr : b->infer && l >= 3 ? b->Y[l - 2] : cv.take<float>(N * HD);
         b->H[l] = l == 0 || b->infer ? nullptr : cv.take<float>(N * HD);
         b->mu[l] = cv.take<float>(G * HD);
         b->rstd[l] = cv.take<float>(G * HD);
@@ -1453,8 +1488,9 @@ void forward_impl(gcin_batch* b, int degree, int precision, const float* P, floa
     constexpr int NT = 4 * HD;
     const Offs o = offsets(degree, HD);
     const int T = b->ntiles, G = b->G;
-    layer0_kernel<HD><<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->x0, b->d_tile_graph, b->d_gend, P + o.convW[0],
-                                        P + o.convb[0], b->H0, b->Y[0], b->tstat);
+    const float *W0 = P + o.convW[0], *b0 = P + o.convb[0];
+    layer0_kernel<HD><<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->x0, b->d_tile_graph, b->d_gend, W0, b0, b->H0,
+                                        b->tstat);
     const int C = b->nchunks;
     // statistics of layer l, then its readout (which feeds no later layer, so pooling each layer
     // as soon as its statistics exist leaves every result as it is and lets an inference-only
@@ -1462,21 +1498,26 @@ void forward_impl(gcin_batch* b, int degree, int precision, const float* P, floa
     auto stats_and_pool = [&](int l) {
         chunk_sum_kernel<HD, 2><<<C, NT, 0, st>>>(b->tstat, b->d_cbound, b->cbuf);
         stats_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->mu[l], b->rstd[l]);
-        pool_tile_kernel<HD><<<T, NT, 0, st>>>(b->d_tile_graph, b->d_gend, b->Y[l], b->mu[l], b->rstd[l], P + o.gam[l],
-                                               P + o.bet[l], b->tpsum, b->tpmax, b->tparg);
+        (l == 0 ? pool_tile_kernel<HD, true> : pool_tile_kernel<HD, false>)<<<T, NT, 0, st>>>(
+            b->d_tile_graph, b->d_gend, b->Y[l], b->H0, W0, b0, b->mu[l], b->rstd[l], P + o.gam[l], P + o.bet[l],
+            b->tpsum, b->tpmax, b->tparg);
         pool_chunk_kernel<HD><<<C, NT, 0, st>>>(b->tpsum, b->tpmax, b->tparg, b->d_cbound, b->cbuf, b->cmax, b->carg);
         pool_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->cmax, b->carg, b->d_gchunk, b->d_gcnt, l, b->pooled,
                                                 b->argmax);
     };
     stats_and_pool(0);
     for (int l = 1; l < NL; ++l) {
-        auto kern = layer_kernel<HD, false, false>;
-        if constexpr (HD == 64)
-            kern = precision == GCIN_BF16X3 ? layer_kernel<HD, true, true>
-                   : precision == GCIN_BF16 ? layer_kernel<HD, true, false> : layer_kernel<HD, false, false>;
-        kern<<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->d_tile_graph, b->d_gend, b->Y[l - 1], b->mu[l - 1],
-                               b->rstd[l - 1], P + o.gam[l - 1], P + o.bet[l - 1], P + o.convW[l], P + o.convb[l],
-                               b->H[l], b->Y[l], b->tstat);
+        const bool y0 = l == 1;
+        auto kern = y0 ? layer_kernel<HD, false, false, true> : layer_kernel<HD, false, false, false>;
+        if constexpr (HD == 64) {
+            if (precision == GCIN_BF16X3)
+                kern = y0 ? layer_kernel<HD, true, true, true> : layer_kernel<HD, true, true, false>;
+            else if (precision == GCIN_BF16)
+                kern = y0 ? layer_kernel<HD, true, false, true> : layer_kernel<HD, true, false, false>;
+        }
+        kern<<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->d_tile_graph, b->d_gend, b->Y[l - 1], b->H0, W0, b0,
+                               b->mu[l - 1], b->rstd[l - 1], P + o.gam[l - 1], P + o.bet[l - 1], P + o.convW[l],
+                               P + o.convb[l], b->H[l], b->Y[l], b->tstat);
         stats_and_pool(l);
     }
     head_fwd_kernel<HD><<<G, 128, 0, st>>>(P, o, b->pooled, b->hs, coeffs_out);
@@ -1495,9 +1536,10 @@ void backward_impl(gcin_batch* b, int degree, int precision, const float* P, con
     float* dHn = nullptr;  // dH of the layer above (for the aggregation backward)
     float* bufs[2] = {b->dHa, b->dHb};
     for (int l = NL - 1; l >= 0; --l) {
-        bwd_a_kernel<HD><<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->d_tile_graph, b->d_gend, b->d_gcnt, b->Y[l],
-                                           b->mu[l], b->rstd[l], P + o.gam[l], P + o.bet[l], b->dpooled, b->argmax, l,
-                                           dHn, b->dxh, b->tb);
+        const float *W0 = P + o.convW[0], *b0 = P + o.convb[0];
+        (l == 0 ? bwd_a_kernel<HD, true> : bwd_a_kernel<HD, false>)<<<T, NT, 0, st>>>(
+            b->ptr, b->col, b->w, b->d_tile_graph, b->d_gend, b->d_gcnt, b->Y[l], b->H0, W0, b0, b->mu[l], b->rstd[l],
+            P + o.gam[l], P + o.bet[l], b->dpooled, b->argmax, l, dHn, b->dxh, b->tb);
         chunk_sum_kernel<HD, 4><<<b->nchunks, NT, 0, st>>>(b->tb, b->d_cbound, b->cbuf);
         bwd_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->gmean, b->ggb);
         // gamma / beta of this layer
@@ -1507,11 +1549,11 @@ void backward_impl(gcin_batch* b, int degree, int precision, const float* P, con
         const int in_dim = l == 0 ? 2 : HD;
         const float* Hin = l == 0 ? b->H0 : b->H[l];
         const int grid = T < kWBlocks ? T : kWBlocks;
-        auto kern = bwd_b_kernel<HD, false>;
+        auto kern = l == 0 ? bwd_b_kernel<HD, false, true> : bwd_b_kernel<HD, false, false>;
         if constexpr (HD == 64)
-            if (precision != GCIN_FP32) kern = bwd_b_kernel<HD, true>;
-        kern<<<grid, NT, 0, st>>>(T, b->d_tile_graph, b->d_gend, b->Y[l], b->mu[l], b->rstd[l], b->gmean, b->dxh, Hin,
-                                  in_dim, P + o.convW[l], dHout, b->wpart, b->bpart);
+            if (precision != GCIN_FP32) kern = l == 0 ? bwd_b_kernel<HD, true, true> : bwd_b_kernel<HD, true, false>;
+        kern<<<grid, NT, 0, st>>>(T, b->d_tile_graph, b->d_gend, b->Y[l], b->H0, W0, b0, b->mu[l], b->rstd[l],
+                                  b->gmean, b->dxh, Hin, in_dim, P + o.convW[l], dHout, b->wpart, b->bpart);
         reduce_parts<float>(b->wpart, grid, HD * HD, in_dim * HD, grads + o.convW[l], st);
         reduce_parts<double>(b->bpart, grid, HD, HD, grads + o.convb[l], st);
         dHn = dHout;
