@@ -467,7 +467,7 @@ class Case:
         torch = self.torch
         n0, z0 = self.hh.levels[0].n, self.hh.levels[0].nnz
         k_ms, k_interval_ms = self.time_residual()
-        rows = 256 if z0 / n0 * 256 * 1.25 <= 4096 else 128
+        rows = _stream_rows(n0, z0)
         v0 = self.ds.level_view(0)
         # the method's bytes (FP32 value and 4-byte column per entry, row pointers, f, u gathered
         # once, r): the A-pass figure of the byte model; the packed layout moves fewer
@@ -574,6 +574,18 @@ def structured_case(torch, nu=1):
 
 
 CONFIGURED_OUTER = {"tet8m": "ir", "delaunay1m": "fcg", "cmesh4m": "fcg", "grid1m": "fcg"}
+
+
+def _stream_rows(n, nnz):
+    """Rows per workgroup of the CSR-stream kernels for a matrix (the library's rule), for labels."""
+    avg = nnz / n if n > 0 else 0.0
+    for r in (256, 128, 64):
+        if r * avg <= 0.9 * 2048:
+            return r
+    for r in (256, 128, 64, 32):
+        if r * avg * 1.25 <= 4096:
+            return r
+    return 0
 
 
 def _finite(v, nd=3):

@@ -2,9 +2,9 @@
 
 - a hub row with 4,500 entries (longer than a CSR-stream block's LDS buffer: the block falls back
   to per-row loops, and the level's halo is too large for the fused kernels);
-- a dense 256-node cluster aligned with one row block and coupled only within itself (65,536
-  entries in a block of 256 rows and no halo: the fused smoothing kernel's own-row products
-  exceed its LDS buffer and take its loop path);
+- a dense 128-node cluster inside one row block of 256 rows and coupled only within itself
+  (16,384 entries in that block: the fused smoothing kernel's own-row products exceed its LDS
+  buffer and take its loop path);
 - isolated unknowns (rows holding only their diagonal: no strong coupling, F points with an
   empty interpolation row).
 Each case: FP64 level operators bitwise equal to the oracle's sparse products on every level the
@@ -71,10 +71,12 @@ def make(kind):
     if kind == "cluster":
         N = 140
         i, j = _grid_edges(N)
-        c0 = 10 * 256  # one full row block of the 256-row kernels, coupled only within itself
-        out = (i >= c0) & (i < c0 + 256) | (j >= c0) & (j < c0 + 256)
+        # a 128-node clique coupled only within itself, inside one row block of the 256-row kernels
+        # (its 16k entries exceed the block's product buffer: the fused kernel's loop path)
+        c0 = 10 * 256
+        out = (i >= c0) & (i < c0 + 128) | (j >= c0) & (j < c0 + 128)
         i, j = i[~out], j[~out]
-        a, b = np.triu_indices(256, 1)
+        a, b = np.triu_indices(128, 1)
         i = np.concatenate([i, c0 + a])
         j = np.concatenate([j, c0 + b])
         w = np.concatenate([np.ones(i.size - a.size), rng.uniform(0.5, 1.5, a.size)])

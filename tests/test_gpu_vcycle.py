@@ -410,6 +410,9 @@ def test_ready_first_step_solves_equal_separate_passes(kind, smoother):
 
 def _stream_rows(n, nnz):
     avg = nnz / n if n > 0 else 0.0
+    for r in (256, 128, 64):
+        if r * avg <= 0.9 * 2048:
+            return r
     for r in (256, 128, 64, 32):
         if r * avg * 1.25 <= 4096:
             return r
