@@ -99,13 +99,52 @@ int amgg_rs_begin(const int32_t* rowptr, const int32_t* col, const double* val, 
 int amgg_rs_coarsen(amgg_rs* h, int* more);
 int amgg_rs_galerkin(amgg_rs* h);
 int amgg_rs_push_level(amgg_rs* h, int32_t n, const int32_t* rowptr, const int32_t* col, const double* val);
+/* The same coarsening step with the strength of connection and the interpolation formed elsewhere
+ * (amgg_strength_device, amgg_interp_device); the C/F split, a sequential greedy, stays here.
+ * amgg_rs_split with strong = NULL applies the level-count and size stopping rules to the last
+ * level: *more = 1 means the level is to be coarsened and its strength flags are wanted. Called
+ * again with strong (host, one byte per stored entry of the level's matrix in stored order, 1 =
+ * strong, as amgg_strength_device writes them) it computes the split: *more = 0 if coarsening
+ * stops there (no C point, or 10 n_c > 9 n), else *more = 1 and cf_out (host, n bytes) receives
+ * 1 for C points and 0 for F points. amgg_rs_push_interp then supplies the level's P (host CSR,
+ * n rows, nc = the number of C points, ascending columns; e.g. from amgg_interp_device), after
+ * which the next level's matrix is supplied as after amgg_rs_coarsen. With flags and P equal to
+ * the host setup's the result equals amgg_rs_setup's. Errors: AMGG_EINVAL, AMGG_ESTATE. */
+int amgg_rs_split(amgg_rs* h, const uint8_t* strong, int8_t* cf_out, int* more);
+int amgg_rs_push_interp(amgg_rs* h, int32_t nc, const int32_t* rowptr, const int32_t* col, const double* val);
 
 /* ------------------------------------------------------------------------------------
- * Device Galerkin product of one level (paper Sec. 2.2: the coarse operator is R A P with
- * R = P^T; Alg. 1, step 2).
+ * Device setup of one level: strength of connection, direct interpolation and the Galerkin
+ * product (paper Sec. 2.2: the coarse operator is R A P with R = P^T; Sec. 4: classical
+ * Ruge-Stueben; Alg. 1, step 2).
  * ------------------------------------------------------------------------------------ */
 typedef void* (*amgg_alloc_fn)(size_t bytes, void* user); /* device memory, or NULL */
 typedef void (*amgg_release_fn)(void* ptr, void* user);
+
+/* Strength of connection of one level on device `device` (Sec. 4: classical Ruge-Stueben with
+ * threshold theta), bitwise the host setup's: strong[p] = 1 when stored entry p of row i (column
+ * j != i) satisfies -a_ij >= theta max_{k != i}(-a_ik) with that max positive, else 0 (positive
+ * couplings are weak). A: device CSR (n rows, nnz entries, ascending columns, checked on the
+ * device), read only; strong: device, nnz bytes, written. alloc / release as for
+ * amgg_galerkin_device (one temporary). Synchronises the stream once. Errors: AMGG_EINVAL
+ * (NULL, bad size or pattern, theta outside (0, 1)), AMGG_EWORKSPACE, AMGG_EHIP. */
+int amgg_strength_device(int device, int32_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                         int32_t nnz, double theta, uint8_t* strong, amgg_alloc_fn alloc, amgg_release_fn release,
+                         void* user, void* stream);
+/* Direct interpolation of one level on device `device` (Sec. 2.2: the prolongation of classical
+ * Ruge-Stueben AMG), bitwise the host setup's: C points (cf[i] != 0) are numbered in ascending
+ * order and their rows of P are the identity; an F row with strong C neighbours C_i (strong,
+ * as amgg_strength_device writes it) gets w_ik = -(alpha_i a_ik) / (a_ii + sum of the row's
+ * positive off-diagonals), alpha_i = (sum of its negative off-diagonals) / (sum of a_ik over
+ * C_i), every sum in ascending column order; other F rows are empty. A, strong and cf (n bytes)
+ * are device arrays, read only. On success *nc is the number of C points and *p_rowptr (n + 1
+ * entries), *p_col, *p_val (*p_nnz entries) were obtained from alloc and belong to the caller;
+ * temporaries are released before the call returns, also on error. Synchronises the stream.
+ * Errors: AMGG_EINVAL (NULL, bad size or pattern, no C point), AMGG_EWORKSPACE, AMGG_EHIP. */
+int amgg_interp_device(int device, int32_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                       int32_t nnz, const uint8_t* strong, const int8_t* cf, amgg_alloc_fn alloc,
+                       amgg_release_fn release, void* user, int32_t* nc, int32_t** p_rowptr, int32_t** p_col,
+                       double** p_val, int32_t* p_nnz, void* stream);
 
 /* A_c = P^T (A P) on device `device`, bitwise equal to the host product of amgg_rs_setup:
  * R = P^T is the exact transpose, and each entry of A P and of R (A P) is accumulated over

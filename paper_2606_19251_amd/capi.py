@@ -85,6 +85,11 @@ SIGNATURES = {
     "amgg_rs_coarsen": (_I, [_VP, C.POINTER(_I)]),
     "amgg_rs_galerkin": (_I, [_VP]),
     "amgg_rs_push_level": (_I, [_VP, _I32, _VP, _VP, _VP]),
+    "amgg_rs_split": (_I, [_VP, _VP, _VP, C.POINTER(_I)]),
+    "amgg_rs_push_interp": (_I, [_VP, _I32, _VP, _VP, _VP]),
+    "amgg_strength_device": (_I, [_I, _I32, _VP, _VP, _VP, _I32, C.c_double, _VP, _VP, _VP, _VP, _VP]),
+    "amgg_interp_device": (_I, [_I, _I32, _VP, _VP, _VP, _I32, _VP, _VP, _VP, _VP, _VP, C.POINTER(_I32),
+                                C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_I32), _VP]),
     "amgg_galerkin_device": (_I, [_I, _I32, _I32, _VP, _VP, _VP, _I32, _VP, _VP, _VP, _I32, _VP, _VP, _VP,
                                   C.c_int64, C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_I32), _VP]),
     "amgg_create": (_I, [C.POINTER(_VP), _I, _I]),
@@ -233,7 +238,23 @@ def amgg_rs_push_level(h: int, n: int, rowptr: np.ndarray, col: np.ndarray, val:
     _check(lib().amgg_rs_push_level(h, n, _np_ptr(rowptr), _np_ptr(col), _np_ptr(val)), "amgg_rs_push_level")
 
 
-# ---------------------------------------------------------------------------- device Galerkin product
+def amgg_rs_split(h: int, strong: np.ndarray | None, cf_out: np.ndarray | None) -> int:
+    """Split query (strong None) or C/F split from host strength flags (uint8, one per entry)."""
+    more = _I()
+    sp = None if strong is None else np.ascontiguousarray(strong, np.uint8)
+    _check(lib().amgg_rs_split(h, _np_ptr(sp) if sp is not None else None,
+                               _np_ptr(cf_out) if cf_out is not None else None, C.byref(more)), "amgg_rs_split")
+    return more.value
+
+
+def amgg_rs_push_interp(h: int, nc: int, rowptr: np.ndarray, col: np.ndarray, val: np.ndarray):
+    rowptr = np.ascontiguousarray(rowptr, np.int32)
+    col = np.ascontiguousarray(col, np.int32)
+    val = np.ascontiguousarray(val, np.float64)
+    _check(lib().amgg_rs_push_interp(h, nc, _np_ptr(rowptr), _np_ptr(col), _np_ptr(val)), "amgg_rs_push_interp")
+
+
+# ---------------------------------------------------------------------------- device setup of a level
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
@@ -264,6 +285,38 @@ class TorchDeviceAllocator:
         """The allocation at ptr as a tensor of `count` elements of `dtype`, owned by the caller."""
         t = self.live.pop(ptr)
         return t[: count * self.torch.empty(0, dtype=dtype).element_size()].view(dtype)
+
+
+def amgg_strength_device(device: int, n: int, rowptr, col, val, theta: float, strong,
+                         allocator: TorchDeviceAllocator | None = None):
+    """Strength flags of a device CSR matrix into `strong` (uint8 tensor, one per entry)."""
+    import torch
+
+    dev = torch.device("cuda", device)
+    al = allocator if allocator is not None else TorchDeviceAllocator(torch, dev)
+    _check(lib().amgg_strength_device(device, n, rowptr.data_ptr(), col.data_ptr(), val.data_ptr(), int(col.numel()),
+                                      float(theta), strong.data_ptr(), al.alloc, al.release, None,
+                                      torch.cuda.current_stream(dev).cuda_stream), "amgg_strength_device")
+    assert not al.live, "temporaries left allocated"
+    return strong
+
+
+def amgg_interp_device(device: int, n: int, rowptr, col, val, strong, cf, allocator: TorchDeviceAllocator | None = None):
+    """Direct interpolation P of a device CSR matrix from device strength flags and C/F split
+    (int8 tensor); returns (nc, (rowptr, col, val) tensors)."""
+    import torch
+
+    dev = torch.device("cuda", device)
+    al = allocator if allocator is not None else TorchDeviceAllocator(torch, dev)
+    nc, rp, cl, vl, nnz = _I32(), _VP(), _VP(), _VP(), _I32()
+    _check(lib().amgg_interp_device(device, n, rowptr.data_ptr(), col.data_ptr(), val.data_ptr(), int(col.numel()),
+                                    strong.data_ptr(), cf.data_ptr(), al.alloc, al.release, None, C.byref(nc),
+                                    C.byref(rp), C.byref(cl), C.byref(vl), C.byref(nnz),
+                                    torch.cuda.current_stream(dev).cuda_stream), "amgg_interp_device")
+    out = (al.take(rp.value, torch.int32, n + 1), al.take(cl.value, torch.int32, nnz.value),
+           al.take(vl.value, torch.float64, nnz.value))
+    assert not al.live, "temporaries left allocated"
+    return nc.value, out
 
 
 def amgg_galerkin_device(device: int, n: int, nc: int, a_rowptr, a_col, a_val, p_rowptr, p_col, p_val,

@@ -1,5 +1,7 @@
-// Device Galerkin product of one level: A_c = R (A P) with R = P^T (paper Sec. 2.2; Alg. 1,
-// step 2), bitwise equal to the host product of the RS setup.
+// Device setup of one level (paper Sec. 2.2; Sec. 4: classical Ruge-Stueben, strength threshold
+// theta; Alg. 1, step 2), bitwise equal to the host RS setup: strength of connection, direct
+// interpolation from a given C/F split (the split itself, a sequential greedy, stays on the
+// host) and the Galerkin product A_c = R (A P) with R = P^T.
 //
 // Each sparse product C = L * M is formed in two phases:
 //   symbolic  every product L_ij M_jk is expanded to a key (row i, column k); one radix sort
@@ -454,7 +456,189 @@ DevCsr drop_zeros(Pool& pool, const DevCsr& C, hipStream_t st) {
     return D;
 }
 
+// ---------------------------------------------------------------------------------------
+// Strength and direct interpolation: one thread per row, the host setup's formulas in the
+// host setup's order (entries in stored, ascending column order; every operation rounded).
+// ---------------------------------------------------------------------------------------
+// strong[p] = 1 when entry p (column j != i) of row i has -a_ij >= theta max_{k != i}(-a_ik)
+// and that max is positive.
+__global__ void strength_kernel(int32_t n, const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                const double* __restrict__ val, double theta, uint8_t* __restrict__ strong) {
+    const int32_t i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const int32_t pb = ptr[i], pe = ptr[i + 1];
+    double big = -INFINITY;
+    bool any_off = false;
+    for (int32_t p = pb; p < pe; ++p) {
+        if (col[p] == i) continue;
+        any_off = true;
+        const double v = -val[p];
+        big = big < v ? v : big;
+    }
+    const bool some = any_off && big > 0.0;
+    const double cut = theta * big;
+    for (int32_t p = pb; p < pe; ++p) strong[p] = some && col[p] != i && -val[p] >= cut ? 1 : 0;
+}
+
+// cf as int32 with a trailing 0 (its exclusive scan numbers the C points)
+__global__ void cf_to_int_kernel(int32_t n, const int8_t* __restrict__ cf, int32_t* __restrict__ out) {
+    const int32_t i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) out[i] = cf[i] != 0 ? 1 : 0;
+    if (i == n) out[i] = 0;
+}
+
+// entries of P's row i: 1 for a C point, else the strong C neighbours (0: no interpolation)
+__global__ void interp_count_kernel(int32_t n, const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                    const uint8_t* __restrict__ strong, const int8_t* __restrict__ cf,
+                                    int32_t* __restrict__ cnt) {
+    const int32_t i = blockIdx.x * kThreads + threadIdx.x;
+    if (i == n) cnt[i] = 0;
+    if (i >= n) return;
+    if (cf[i] != 0) {
+        cnt[i] = 1;
+        return;
+    }
+    int32_t c = 0;
+    for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p) c += strong[p] && cf[col[p]] != 0 ? 1 : 0;
+    cnt[i] = c;
+}
+
+// Direct interpolation with positive couplings lumped on the diagonal: an F row with strong C
+// neighbours C_i gets w_ik = -(alpha_i a_ik) / (a_ii + sum of its positive off-diagonals), with
+// alpha_i = (sum of its negative off-diagonals) / (sum of a_ik over C_i); a C row is the identity.
+__global__ void interp_fill_kernel(int32_t n, const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                   const double* __restrict__ val, const uint8_t* __restrict__ strong,
+                                   const int8_t* __restrict__ cf, const int32_t* __restrict__ cidx,
+                                   const int32_t* __restrict__ prow, int32_t* __restrict__ pcol,
+                                   double* __restrict__ pval) {
+    const int32_t i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    int32_t q = prow[i];
+    if (cf[i] != 0) {
+        pcol[q] = cidx[i];
+        pval[q] = 1.0;
+        return;
+    }
+    if (prow[i + 1] == q) return;
+    const int32_t pb = ptr[i], pe = ptr[i + 1];
+    double a_ii = 0.0;
+    for (int32_t p = pb; p < pe; ++p)
+        if (col[p] == i) a_ii = val[p];
+    double lumped = a_ii, neg_sum = 0.0, strong_c_sum = 0.0;
+    for (int32_t p = pb; p < pe; ++p) {
+        const int32_t k = col[p];
+        if (k == i) continue;
+        const double a = val[p];
+        if (a > 0.0) lumped = lumped + a;
+        if (a < 0.0) neg_sum = neg_sum + a;
+        if (strong[p] && cf[k] != 0) strong_c_sum = strong_c_sum + a;
+    }
+    const double ratio = neg_sum / strong_c_sum;
+    for (int32_t p = pb; p < pe; ++p) {
+        const int32_t k = col[p];
+        if (!(strong[p] && cf[k] != 0)) continue;
+        pcol[q] = cidx[k];
+        pval[q] = -(ratio * val[p]) / lumped;
+        ++q;
+    }
+}
+
+// bad[0] = 1 unless (ptr, col) is a CSR pattern of n rows, nnz entries, ascending columns < n
+void validate_square(Pool& pool, int32_t n, int32_t nnz, const int32_t* ptr, const int32_t* col, const char* who,
+                     hipStream_t st) {
+    int32_t* bad = pool.get<int32_t>(1);
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, st, bad, 0);
+    launch(validate_csr_kernel, n, st, n, n, nnz, ptr, col, bad);
+    check(hipGetLastError(), "validate");
+    if (read_back(bad, st))
+        throw Failure{AMGG_EINVAL, std::string(who) + ": not a CSR pattern of the stated size with ascending columns"};
+    pool.put(bad);
+}
+
+template <typename T>
+void exclusive_scan_i32(Pool& pool, const T* in, int32_t* out, int64_t count, hipStream_t st) {
+    size_t tb = 0;
+    check(rocprim::exclusive_scan(nullptr, tb, in, out, int32_t{0}, static_cast<size_t>(count),
+                                  rocprim::plus<int32_t>(), st),
+          "scan size");
+    void* tmp = pool.get<unsigned char>(static_cast<int64_t>(tb));
+    check(rocprim::exclusive_scan(tmp, tb, in, out, int32_t{0}, static_cast<size_t>(count), rocprim::plus<int32_t>(),
+                                  st),
+          "scan");
+    pool.put(tmp);
+}
+
 }  // namespace
+
+extern "C" int amgg_strength_device(int device, int32_t n, const int32_t* rowptr, const int32_t* col,
+                                    const double* val, int32_t nnz, double theta, uint8_t* strong,
+                                    amgg_alloc_fn alloc, amgg_release_fn release, void* user, void* stream) {
+    return guarded([&]() -> int {
+        if (n <= 0 || nnz < 0 || !rowptr || !alloc || !release || (nnz > 0 && (!col || !val || !strong)))
+            return fail(AMGG_EINVAL, "amgg_strength_device: NULL argument or bad size");
+        if (!(theta > 0.0 && theta < 1.0)) return fail(AMGG_EINVAL, "amgg_strength_device: theta outside (0, 1)");
+        hipError_t e = hipSetDevice(device);
+        if (e != hipSuccess) return hip_fail(e, "amgg_strength_device: hipSetDevice");
+        const hipStream_t st = static_cast<hipStream_t>(stream);
+        try {
+            Pool pool(alloc, release, user, st);
+            validate_square(pool, n, nnz, rowptr, col, "amgg_strength_device", st);
+            launch(strength_kernel, n, st, n, rowptr, col, val, theta, strong);
+            check(hipGetLastError(), "strength");
+            return AMGG_OK;
+        } catch (const Failure& f) {
+            (void)hipStreamSynchronize(st);
+            return fail(f.code, f.msg);
+        }
+    });
+}
+
+extern "C" int amgg_interp_device(int device, int32_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                                  int32_t nnz, const uint8_t* strong, const int8_t* cf, amgg_alloc_fn alloc,
+                                  amgg_release_fn release, void* user, int32_t* nc, int32_t** p_rowptr,
+                                  int32_t** p_col, double** p_val, int32_t* p_nnz, void* stream) {
+    return guarded([&]() -> int {
+        if (n <= 0 || nnz < 0 || !rowptr || !cf || !alloc || !release || !nc || !p_rowptr || !p_col || !p_val ||
+            !p_nnz || (nnz > 0 && (!col || !val || !strong)))
+            return fail(AMGG_EINVAL, "amgg_interp_device: NULL argument or bad size");
+        hipError_t e = hipSetDevice(device);
+        if (e != hipSuccess) return hip_fail(e, "amgg_interp_device: hipSetDevice");
+        const hipStream_t st = static_cast<hipStream_t>(stream);
+        try {
+            Pool pool(alloc, release, user, st);
+            validate_square(pool, n, nnz, rowptr, col, "amgg_interp_device", st);
+            int32_t* tmp = pool.get<int32_t>(static_cast<int64_t>(n) + 1);
+            int32_t* cidx = pool.get<int32_t>(static_cast<int64_t>(n) + 1);
+            launch(cf_to_int_kernel, static_cast<int64_t>(n) + 1, st, n, cf, tmp);
+            exclusive_scan_i32(pool, tmp, cidx, static_cast<int64_t>(n) + 1, st);
+            const int32_t ncoarse = read_back(cidx + n, st);
+            if (ncoarse <= 0) throw Failure{AMGG_EINVAL, "amgg_interp_device: no C point"};
+            int32_t* prow = pool.get<int32_t>(static_cast<int64_t>(n) + 1);
+            launch(interp_count_kernel, static_cast<int64_t>(n) + 1, st, n, rowptr, col, strong, cf, tmp);
+            exclusive_scan_i32(pool, tmp, prow, static_cast<int64_t>(n) + 1, st);
+            const int32_t total = read_back(prow + n, st);
+            pool.put(tmp);
+            int32_t* pcol = pool.get<int32_t>(total);
+            double* pval = pool.get<double>(total);
+            launch(interp_fill_kernel, n, st, n, rowptr, col, val, strong, cf, cidx, prow, pcol, pval);
+            check(hipGetLastError(), "interpolation");
+            check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            pool.put(cidx);
+            pool.keep(prow);
+            pool.keep(pcol);
+            pool.keep(pval);
+            *nc = ncoarse;
+            *p_rowptr = prow;
+            *p_col = pcol;
+            *p_val = pval;
+            *p_nnz = total;
+            return AMGG_OK;
+        } catch (const Failure& f) {
+            (void)hipStreamSynchronize(st);
+            return fail(f.code, f.msg);
+        }
+    });
+}
 
 extern "C" int amgg_galerkin_device(int device, int32_t n, int32_t nc, const int32_t* a_rowptr, const int32_t* a_col,
                                     const double* a_val, int32_t a_nnz, const int32_t* p_rowptr, const int32_t* p_col,

@@ -295,8 +295,9 @@ struct amgg_rs {
     double theta = 0.25;
     int max_levels = 1;
     int32_t max_coarse = 1;
-    bool open = false;  // the last level has P and awaits its Galerkin product
-    bool done = false;  // coarsening stopped: the last level is the coarsest
+    bool open = false;   // the last level has P and awaits its Galerkin product
+    bool done = false;   // coarsening stopped: the last level is the coarsest
+    bool split = false;  // the last level has its C/F split (amgg_rs_split) and awaits P
 };
 
 namespace {
@@ -334,19 +335,45 @@ int begin_impl(const char* who, const int32_t* rowptr, const int32_t* col, const
     return AMGG_OK;
 }
 
+// The stopping rules that do not need the split: level count and size.
+bool may_coarsen(const amgg_rs* h) {
+    return static_cast<int>(h->levels.size()) < h->max_levels && h->levels.back().A.nrows > h->max_coarse;
+}
+
+// ... and the ones that do: no C point, or too few rows dropped.
+bool split_pays(const std::vector<int8_t>& cf) {
+    int64_t nc = 0;
+    for (int8_t c : cf) nc += c;
+    return nc > 0 && 10 * nc <= 9 * static_cast<int64_t>(cf.size());
+}
+
 // Strength, C/F split and interpolation of the last level, or the decision to stop there.
 bool coarsen_last(amgg_rs* h) {
     RsLevel& cur = h->levels.back();
-    const int32_t nl = cur.A.nrows;
-    if (static_cast<int>(h->levels.size()) >= h->max_levels || nl <= h->max_coarse) return false;
+    if (!may_coarsen(h)) return false;
     Csr S = strong_couplings(cur.A, h->theta);
     std::vector<int8_t> cf = first_pass_split(S);
-    int64_t nc = 0;
-    for (int8_t c : cf) nc += c;
-    if (nc == 0 || 10 * nc > 9 * static_cast<int64_t>(nl)) return false;
+    if (!split_pays(cf)) return false;
     cur.P = direct_interp(cur.A, S, cf);
     cur.cf = std::move(cf);
     return true;
+}
+
+// S of a matrix from one strength flag per stored entry (in stored order).
+Csr couplings_from_flags(const Csr& A, const uint8_t* strong) {
+    Csr S;
+    S.nrows = S.ncols = A.nrows;
+    S.ptr.assign(static_cast<size_t>(A.nrows) + 1, 0);
+    int32_t cnt = 0;
+    for (int32_t i = 0; i < A.nrows; ++i) {
+        for (int32_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) cnt += strong[p] ? 1 : 0;
+        S.ptr[i + 1] = cnt;
+    }
+    S.idx.resize(static_cast<size_t>(cnt));
+    int32_t q = 0;
+    for (int32_t p = 0; p < A.nnz(); ++p)
+        if (strong[p]) S.idx[q++] = A.idx[p];
+    return S;
 }
 
 }  // namespace
@@ -383,6 +410,7 @@ extern "C" int amgg_rs_coarsen(amgg_rs* h, int* more) {
     return amgg::guarded([&]() -> int {
         if (!h || !more) return amgg::fail(AMGG_EINVAL, "amgg_rs_coarsen: null argument");
         if (h->open) return amgg::fail(AMGG_ESTATE, "amgg_rs_coarsen: the last level still needs its coarse matrix");
+        if (h->split) return amgg::fail(AMGG_ESTATE, "amgg_rs_coarsen: the last level awaits its interpolation");
         if (h->done) {
             *more = 0;
             return AMGG_OK;
@@ -390,6 +418,66 @@ extern "C" int amgg_rs_coarsen(amgg_rs* h, int* more) {
         h->open = coarsen_last(h);
         h->done = !h->open;
         *more = h->open ? 1 : 0;
+        return AMGG_OK;
+    });
+}
+
+extern "C" int amgg_rs_split(amgg_rs* h, const uint8_t* strong, int8_t* cf_out, int* more) {
+    return amgg::guarded([&]() -> int {
+        if (!h || !more) return amgg::fail(AMGG_EINVAL, "amgg_rs_split: null argument");
+        if (h->open) return amgg::fail(AMGG_ESTATE, "amgg_rs_split: the last level still needs its coarse matrix");
+        if (h->split) return amgg::fail(AMGG_ESTATE, "amgg_rs_split: the last level awaits its interpolation");
+        *more = 0;
+        if (h->done) return AMGG_OK;
+        if (!may_coarsen(h)) {
+            h->done = true;
+            return AMGG_OK;
+        }
+        if (!strong) {  // query: the level is to be coarsened, its strength flags are wanted
+            *more = 1;
+            return AMGG_OK;
+        }
+        if (!cf_out) return amgg::fail(AMGG_EINVAL, "amgg_rs_split: null cf");
+        RsLevel& cur = h->levels.back();
+        std::vector<int8_t> cf = first_pass_split(couplings_from_flags(cur.A, strong));
+        if (!split_pays(cf)) {
+            h->done = true;
+            return AMGG_OK;
+        }
+        std::memcpy(cf_out, cf.data(), cf.size());
+        cur.cf = std::move(cf);
+        h->split = true;
+        *more = 1;
+        return AMGG_OK;
+    });
+}
+
+extern "C" int amgg_rs_push_interp(amgg_rs* h, int32_t nc, const int32_t* rowptr, const int32_t* col,
+                                   const double* val) {
+    return amgg::guarded([&]() -> int {
+        if (!h || !rowptr) return amgg::fail(AMGG_EINVAL, "amgg_rs_push_interp: null argument");
+        if (!h->split) return amgg::fail(AMGG_ESTATE, "amgg_rs_push_interp: no level awaits its interpolation");
+        RsLevel& cur = h->levels.back();
+        const int32_t n = cur.A.nrows;
+        int32_t want = 0;
+        for (int8_t c : cur.cf) want += c;
+        if (nc != want) return amgg::fail(AMGG_EINVAL, "amgg_rs_push_interp: column count differs from the C points");
+        const int32_t nnz = rowptr[n];
+        if (rowptr[0] != 0 || nnz < 0 || ((!col || !val) && nnz > 0))
+            return amgg::fail(AMGG_EINVAL, "amgg_rs_push_interp: bad row pointers or null col / val");
+        for (int32_t i = 0; i < n; ++i) {
+            if (rowptr[i + 1] < rowptr[i]) return amgg::fail(AMGG_EINVAL, "amgg_rs_push_interp: decreasing row pointers");
+            for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p)
+                if (col[p] < 0 || col[p] >= nc || (p > rowptr[i] && col[p] <= col[p - 1]))
+                    return amgg::fail(AMGG_EINVAL, "amgg_rs_push_interp: columns out of range or not ascending");
+        }
+        cur.P.nrows = n;
+        cur.P.ncols = nc;
+        cur.P.ptr.assign(rowptr, rowptr + n + 1);
+        cur.P.idx.assign(col, col + nnz);
+        cur.P.val.assign(val, val + nnz);
+        h->split = false;
+        h->open = true;
         return AMGG_OK;
     });
 }

@@ -38,19 +38,24 @@ class HostHierarchy:
 
     @classmethod
     def build(cls, rowptr, col, val, theta=0.25, max_levels=10, max_coarse=500, galerkin="host", device=0,
-              chunk_products=0, timings=None):
+              chunk_products=0, timings=None, coarsen="host"):
         """RS hierarchy of a host CSR matrix. galerkin="host" forms every coarse matrix in the
-        host setup; galerkin="device" forms them with amgg_galerkin_device on GPU `device`
-        (strength, C/F split and interpolation stay on the host; the results are bitwise
-        the same). With galerkin="device", `timings` (a dict) receives the seconds spent in
-        the host coarsening, the device products and the transfers between them."""
+        host setup; galerkin="device" forms them with amgg_galerkin_device on GPU `device`.
+        With galerkin="device", coarsen="device" also forms the strength of connection and the
+        interpolation on the GPU (amgg_strength_device, amgg_interp_device); the C/F split, a
+        sequential greedy, stays on the host. The results are bitwise the same in every case.
+        With galerkin="device", `timings` (a dict) receives the seconds spent in the host
+        coarsening (all of it, or the split alone), the device strength and interpolation, the
+        device products and the transfers between them."""
         rowptr = np.ascontiguousarray(rowptr, np.int32)
         n = rowptr.size - 1
+        if coarsen not in ("host", "device") or (coarsen == "device" and galerkin != "device"):
+            raise ValueError(f"coarsen must be 'host' or 'device' (the latter with galerkin='device'), not {coarsen!r}")
         if galerkin == "host":
             h = capi.amgg_rs_setup(rowptr, col, val, n, theta, max_levels, max_coarse)
         elif galerkin == "device":
             h = _rs_with_device_galerkin(rowptr, col, val, n, theta, max_levels, max_coarse, device, chunk_products,
-                                         timings if timings is not None else {})
+                                         timings if timings is not None else {}, coarsen == "device")
         else:
             raise ValueError(f"galerkin must be 'host' or 'device', not {galerkin!r}")
         try:
@@ -81,15 +86,17 @@ class HostHierarchy:
         return len(self.levels)
 
 
-def _rs_with_device_galerkin(rowptr, col, val, n, theta, max_levels, max_coarse, device, chunk_products, timings):
-    """Stepwise RS setup whose Galerkin products run on the GPU; returns the host handle."""
+def _rs_with_device_galerkin(rowptr, col, val, n, theta, max_levels, max_coarse, device, chunk_products, timings,
+                             device_coarsen=False):
+    """Stepwise RS setup whose Galerkin products (and, with device_coarsen, strength and
+    interpolation) run on the GPU; returns the host handle."""
     import time
 
     import torch
 
     dev = torch.device("cuda", device)
     clock = time.perf_counter
-    for k in ("coarsen_s", "galerkin_s", "transfer_s"):
+    for k in ("coarsen_s", "galerkin_s", "transfer_s") + (("strength_s", "interp_s") if device_coarsen else ()):
         timings.setdefault(k, 0.0)
     h = capi.amgg_rs_begin(rowptr, col, val, n, theta, max_levels, max_coarse)
     try:
@@ -99,23 +106,52 @@ def _rs_with_device_galerkin(rowptr, col, val, n, theta, max_levels, max_coarse,
         timings["transfer_s"] += clock() - t0
         lvl = 0
         while True:
-            t0 = clock()
-            more = capi.amgg_rs_coarsen(h)
-            timings["coarsen_s"] += clock() - t0
-            if not more:
-                break
-            t0 = clock()
-            n_l, _, nc, pnnz = capi.amgg_rs_level_size(h, lvl)
-            prp, pcl, pvl = np.empty(n_l + 1, np.int32), np.empty(pnnz, np.int32), np.empty(pnnz, np.float64)
-            capi.amgg_rs_copy_level(h, lvl, None, None, None, prp, pcl, pvl, None)
-            P = tuple(torch.from_numpy(a).to(dev) for a in (prp, pcl, pvl))
-            torch.cuda.synchronize(dev)
+            n_l = int(A[0].numel()) - 1
+            if device_coarsen:
+                if not capi.amgg_rs_split(h, None, None):
+                    break
+                t0 = clock()
+                strong = torch.empty(max(int(A[1].numel()), 1), dtype=torch.uint8, device=dev)
+                capi.amgg_strength_device(device, n_l, *A, theta, strong)
+                torch.cuda.synchronize(dev)
+                t1 = clock()
+                flags = strong.cpu().numpy()
+                cf = np.empty(n_l, np.int8)
+                t2 = clock()
+                more = capi.amgg_rs_split(h, flags, cf)
+                t3 = clock()
+                timings["strength_s"] += t1 - t0
+                timings["transfer_s"] += t2 - t1
+                timings["coarsen_s"] += t3 - t2
+                if not more:
+                    break
+                cf_d = torch.from_numpy(cf).to(dev)
+                t4 = clock()
+                nc, P = capi.amgg_interp_device(device, n_l, *A, strong, cf_d)
+                t5 = clock()
+                capi.amgg_rs_push_interp(h, nc, *(a.cpu().numpy() for a in P))
+                del strong, cf_d
+                timings["interp_s"] += t5 - t4
+                timings["transfer_s"] += (t4 - t3) + (clock() - t5)
+            else:
+                t0 = clock()
+                more = capi.amgg_rs_coarsen(h)
+                timings["coarsen_s"] += clock() - t0
+                if not more:
+                    break
+                t0 = clock()
+                _, _, nc, pnnz = capi.amgg_rs_level_size(h, lvl)
+                prp, pcl, pvl = np.empty(n_l + 1, np.int32), np.empty(pnnz, np.int32), np.empty(pnnz, np.float64)
+                capi.amgg_rs_copy_level(h, lvl, None, None, None, prp, pcl, pvl, None)
+                P = tuple(torch.from_numpy(a).to(dev) for a in (prp, pcl, pvl))
+                torch.cuda.synchronize(dev)
+                timings["transfer_s"] += clock() - t0
             t1 = clock()
             A = capi.amgg_galerkin_device(device, n_l, nc, *A, *P, chunk_products=chunk_products)
             t2 = clock()
             capi.amgg_rs_push_level(h, nc, *(a.cpu().numpy() for a in A))
             timings["galerkin_s"] += t2 - t1
-            timings["transfer_s"] += (t1 - t0) + (clock() - t2)
+            timings["transfer_s"] += clock() - t2
             lvl += 1
         return h
     except BaseException:

@@ -166,6 +166,86 @@ def test_stepwise_setup_equals_one_call_setup(source):
     _levels_equal(ref, got)
 
 
+def _oracle_strength_flags(A, theta=0.25):
+    """One byte per stored entry of A (stored order): 1 where the oracle's S holds the entry."""
+    S = amg.strength(A, theta)
+    flags = np.zeros(A.nnz, np.uint8)
+    for i in range(A.shape[0]):
+        cols = A.indices[A.indptr[i]:A.indptr[i + 1]]
+        flags[A.indptr[i]:A.indptr[i + 1]] = np.isin(cols, S.indices[S.indptr[i]:S.indptr[i + 1]])
+    return flags
+
+
+@pytest.mark.parametrize("kind", ["delaunay", "cmesh"])
+def test_split_from_strength_flags_equals_one_call_setup(kind):
+    """amgg_rs_split from strength flags, amgg_rs_push_interp and amgg_rs_push_level, all fed
+    from the oracle's strength, interpolation and Galerkin products, give the hierarchy of
+    amgg_rs_setup bit for bit (the path of the device-built strength and interpolation)."""
+    from paper_2606_19251_amd.solver import HostHierarchy
+
+    capi = _capi()
+    A = W.delaunay_p1(W.gmm_points(5000, 4)) if kind == "delaunay" else W.cmesh_fv(96, 48, "2412", 1e3)
+    ref = HostHierarchy.build(A.rowptr, A.col, A.val, max_coarse=60)
+    An, _, sing = amg.normalize(A, np.zeros(A.nrows))
+    ho = amg.setup(An, singular=sing, max_coarse=60)
+    h = capi.amgg_rs_begin(A.rowptr, A.col, A.val, A.nrows, 0.25, 10, 60)
+    try:
+        lvl = 0
+        while capi.amgg_rs_split(h, None, None):
+            L = ho.levels[lvl]
+            cf = np.empty(L.A.shape[0], np.int8)
+            if not capi.amgg_rs_split(h, _oracle_strength_flags(L.A), cf):
+                break
+            assert np.array_equal(cf, amg.cf_split(amg.strength(L.A, 0.25)) == amg.CPT)
+            P = L.P
+            capi.amgg_rs_push_interp(h, P.shape[1], P.indptr, P.indices, P.data)
+            Ac = ho.levels[lvl + 1].A
+            capi.amgg_rs_push_level(h, Ac.shape[0], Ac.indptr, Ac.indices, Ac.data)
+            lvl += 1
+        assert not capi.amgg_rs_split(h, None, None)  # stays stopped
+        got = HostHierarchy.from_handle(h)
+    finally:
+        capi.amgg_rs_free(h)
+    assert lvl == ref.nlevels - 1
+    _levels_equal(ref, got)
+
+
+def test_split_api_rejects_calls_out_of_sequence():
+    capi = _capi()
+    A = W.grid5(30)
+    An = amg.to_scipy(A)
+    h = capi.amgg_rs_begin(A.rowptr, A.col, A.val, A.nrows, 0.25, 10, 20)
+    try:
+        with pytest.raises(capi.AmggError) as e:  # no split yet
+            capi.amgg_rs_push_interp(h, 1, np.zeros(A.nrows + 1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+        assert e.value.code == capi.AMGG_ESTATE
+        assert capi.amgg_rs_split(h, None, None)
+        cf = np.empty(A.nrows, np.int8)
+        assert capi.amgg_rs_split(h, _oracle_strength_flags(An), cf)
+        with pytest.raises(capi.AmggError) as e:  # the split level awaits its P
+            capi.amgg_rs_coarsen(h)
+        assert e.value.code == capi.AMGG_ESTATE
+        S = amg.strength(An, 0.25)
+        P = amg.direct_interpolation(An, S, amg.cf_split(S))
+        assert np.array_equal(cf, amg.cf_split(S) == amg.CPT)
+        with pytest.raises(capi.AmggError) as e:  # wrong column count
+            capi.amgg_rs_push_interp(h, P.shape[1] + 1, P.indptr, P.indices, P.data)
+        assert e.value.code == capi.AMGG_EINVAL
+        bad = P.indices.copy()
+        bad[0] = P.shape[1]
+        with pytest.raises(capi.AmggError) as e:  # column out of range
+            capi.amgg_rs_push_interp(h, P.shape[1], P.indptr, bad, P.data)
+        assert e.value.code == capi.AMGG_EINVAL
+        capi.amgg_rs_push_interp(h, P.shape[1], P.indptr, P.indices, P.data)
+        with pytest.raises(capi.AmggError) as e:  # the coarse matrix is due
+            capi.amgg_rs_split(h, None, None)
+        assert e.value.code == capi.AMGG_ESTATE
+        capi.amgg_rs_galerkin(h)
+        assert capi.amgg_rs_info(h)[0] == 2
+    finally:
+        capi.amgg_rs_free(h)
+
+
 def test_stepwise_setup_rejects_calls_out_of_sequence():
     capi = _capi()
     A = W.grid5(30)
