@@ -159,15 +159,21 @@ __global__ __launch_bounds__(kBlock) void fcg_update_xr_kernel(int32_t n, double
                                                               const double* __restrict__ q,
                                                               double* __restrict__ rnew,
                                                               const double* __restrict__ s,
-                                                              double* __restrict__ partial) {
+                                                              double* __restrict__ partial, Cast32 cs) {
     if (s[kHalt] != 0.0 || s[kFlag] != 0.0) return;  // uniform over the grid
     const double a = s[kAlpha];
+    const double sc = cs.f ? s[kScaleNext] : 0.0;
     double v = 0.0;
     for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += kReduceBlocks * kBlock) {
         x[i] += a * p[i];
         const double ri = r[i] - a * q[i];
         rnew[i] = ri;
         v += ri * ri;
+        if (cs.f) {  // the next cycle's FP32 right-hand side (uniform branch)
+            const float fy = static_cast<float>(ri * sc);
+            cs.f[i] = fy;
+            if (cs.qd) cs.u[i] = cs.qd[i] * fy;
+        }
     }
     block_partial(v, partial);
 }
@@ -189,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void fcg_castback_dots_kernel(int32_t n, co
                                                                   const double* __restrict__ rold,
                                                                   double* __restrict__ z,
                                                                   double* __restrict__ partial2) {
-    const double nrm = s[kNorm];
+    const double nrm = s[kUnscale];
     double a = 0.0, b = 0.0;
     for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += kReduceBlocks * kBlock) {
         const double zi = static_cast<double>(u32[i]) * nrm;
@@ -398,8 +404,9 @@ hipError_t fcg_finish_pq(const double* partial, int count, double* s, hipStream_
 }
 
 hipError_t fcg_update_xr(int32_t n, double* x, const double* p, const double* r, const double* q, double* rnew,
-                         const double* s, double* partial, hipStream_t stream) {
-    fcg_update_xr_kernel<<<kReduceBlocks, kBlock, 0, stream>>>(n, x, p, r, q, rnew, s, partial);
+                         const double* s, double* partial, hipStream_t stream, const Cast32& cast) {
+    if ((cast.qd == nullptr) != (cast.u == nullptr)) return hipErrorInvalidValue;
+    fcg_update_xr_kernel<<<kReduceBlocks, kBlock, 0, stream>>>(n, x, p, r, q, rnew, s, partial, cast);
     return hipGetLastError();
 }
 

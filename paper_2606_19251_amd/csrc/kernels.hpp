@@ -237,9 +237,9 @@ enum FcgSlot : int {
     kTolRR = 12,  // tol^2 ||b||^2: the guarded steps halt below it
     kDivRR = 13,  // div^2 ||b||^2: ... and above it (or on a non-finite norm)
     kHalt = 14,   // 1.0 once a guarded step has halted the iteration
-    // Iterative refinement with FP32 cycles scales each residual by a power of two (exact in
-    // both directions) fixed before the residual is formed, so that the residual kernel can
-    // write the cycle's FP32 right-hand side itself: r_k is scaled by 2^-e, e the exponent of
+    // The outer loops with FP32 cycles scale each residual by a power of two (exact in both
+    // directions) fixed before the residual is formed, so that the kernel forming it can write
+    // the cycle's FP32 right-hand side itself: r_k is scaled by 2^-e, e the exponent of
     // ||r_{k-1}|| (r_k is at most about ||r_{k-1}||, so the FP32 values stay near 1).
     kScaleNext = 15,  // scale for the residual about to be formed
     kScaleCast = 16,  // scale of the residual held in FP32 (or to be cast next)
@@ -258,11 +258,12 @@ hipError_t fcg_clear_halt(double* s, hipStream_t stream);  // s[kHalt] = s[kFlag
 // moves kScaleNext to kScaleCast (and its inverse to kUnscale) and sets kScaleNext from the new norm
 hipError_t fcg_finish_rr_guarded(const double* partial, int count, double* s, hipStream_t stream);
 hipError_t fcg_finish_pq(const double* partial, int count, double* s, hipStream_t stream);  // pq, alpha = gamma/pq
-// x += a p ; rnew = r - a q (skipped, partials included, when halted)
+// x += a p ; rnew = r - a q (skipped, partials included, when halted); with cast.f also the next
+// cycle's FP32 right-hand side from rnew scaled by s[kScaleNext] (Cast32; cast.scale unused)
 hipError_t fcg_update_xr(int32_t n, double* x, const double* p, const double* r, const double* q, double* rnew,
-                         const double* s, double* partial, hipStream_t stream);
+                         const double* s, double* partial, hipStream_t stream, const Cast32& cast = Cast32{});
 hipError_t fcg_finish_rr(const double* partial, int count, double* s, hipStream_t stream);  // rr, norm, invnorm
-// z = (double)u32 * norm and partials of z.rnew, z.rold (2 * kReduceBlocks)
+// z = (double)u32 * s[kUnscale] and partials of z.rnew, z.rold (2 * kReduceBlocks)
 hipError_t fcg_castback_dots(int32_t n, const float* u32, const double* s, const double* rnew, const double* rold,
                              double* z, double* partial2, hipStream_t stream);
 hipError_t fcg_dots64(int32_t n, const double* z, const double* rnew, const double* rold, double* partial2,

@@ -36,11 +36,12 @@ struct Runner {
     amgg_ctx* c;
     int nu1, nu2, prec;
     hipError_t e = hipSuccess;
-    // Iterative refinement with FP32 cycles: the residual kernel writes the next cycle's FP32
-    // right-hand side itself (csr_resid_cast) instead of the FP64 residual and a cast pass; off
-    // with the fused kernels (amgg_set_fusion) and for matrices the CSR-stream kernels do not
-    // serve. Both forms give bitwise the same iterates.
-    bool ir_cast = false;
+    // FP32 cycles: the kernel that forms each residual also writes the next cycle's FP32
+    // right-hand side (iterative refinement: csr_resid_cast, which does not store the FP64
+    // residual; flexible CG: fcg_update_xr) instead of a separate cast pass; off with the fused
+    // kernels (amgg_set_fusion) and, for iterative refinement, on matrices the CSR-stream
+    // kernels do not serve. Both forms give bitwise the same iterates.
+    bool cast_fused = false;
 
     void ok(hipError_t r) {
         if (r != hipSuccess && e == hipSuccess) e = r;
@@ -83,7 +84,7 @@ struct Runner {
         Level& L0 = c->lv[0];
         const int32_t n = L0.n;
         double* s = c->scal;
-        const double* z = precondition(cur, st);
+        const double* z = precondition(cast_fused ? nullptr : cur, st, kScaleCast);
         if (prec == 32) {
             ok(fcg_castback_dots(n, last32, s, cur, first ? nullptr : prev, c->z, c->partial2, st));
             z = c->z;
@@ -95,7 +96,14 @@ struct Runner {
         int cnt = 0;
         ok(csr_spmv_dot(L0.A(), L0.val, c->p, c->q, c->partial, &cnt, st));
         ok(fcg_finish_pq(c->partial, cnt, s, st));
-        ok(fcg_update_xr(n, x, c->p, cur, c->q, prev, s, c->partial, st));
+        Cast32 cs;
+        if (cast_fused) {
+            const bool ready = takes_ready_u(c, 0, nu1);
+            cs.f = L0.f32;
+            cs.qd = ready ? L0.qd32 : nullptr;
+            cs.u = ready ? L0.u32 : nullptr;
+        }
+        ok(fcg_update_xr(n, x, c->p, cur, c->q, prev, s, c->partial, st, cs));
         ok(fcg_finish_rr_guarded(c->partial, kReduceBlocks, s, st));
     }
 
@@ -104,13 +112,13 @@ struct Runner {
     void ir_iteration(double* x, const double* bb, double* r, hipStream_t st) {
         Level& L0 = c->lv[0];
         const int32_t n = L0.n;
-        const double* e64 = precondition(ir_cast ? nullptr : r, st, kScaleCast);
+        const double* e64 = precondition(cast_fused ? nullptr : r, st, kScaleCast);
         if (prec == 64)
             ok(ir_update_f64(n, x, e64, c->scal, st));
         else
             ok(ir_update_f32(n, x, last32, c->scal, st));
         int cnt = 0;
-        if (ir_cast) {
+        if (cast_fused) {
             const bool ready = takes_ready_u(c, 0, nu1);
             Cast32 cs;
             cs.f = L0.f32;
@@ -202,7 +210,8 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
         Level& L0 = c->lv[0];
         const int32_t n = L0.n;
         const CsrView A = L0.A();
-        R.ir_cast = o->outer == AMGG_OUTER_IR && o->inner_precision == 32 && L0.fuse && stream_rows_for(n, L0.nnz) > 0;
+        R.cast_fused = o->inner_precision == 32 && L0.fuse &&
+                       (o->outer == AMGG_OUTER_FCG || (o->outer == AMGG_OUTER_IR && stream_rows_for(n, L0.nnz) > 0));
         double* s = c->scal;
         double* hs = c->host_scal;
         int vcycles = 0;
@@ -285,7 +294,7 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
         // asynchronous copy of the scalar block into one of two pinned slots; the host keeps
         // one iteration in flight while it inspects the previous one.
         R.ok(fcg_set_limits(s, o->tol, div_factor, st));
-        if (R.ir_cast) R.cast_rhs(c->ra, kScaleCast, st);  // the first cycle's right-hand side: b
+        if (R.cast_fused) R.cast_rhs(c->ra, kScaleCast, st);  // the first cycle's right-hand side: b
         struct InFlight {
             double* cu;
             double* pv;
@@ -370,6 +379,8 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
                     if (rel <= o->tol) return finish(0, rel, k);
                     if (k >= o->maxit) return finish(AMGG_MAXIT, rel, k);
                     R.ok(fcg_clear_halt(s, st));
+                    R.ok(ir_set_scales(s, st));
+                    if (R.cast_fused) R.cast_rhs(cur, kScaleCast, st);
                     first = true;
                     more = true;
                     continue;
@@ -406,7 +417,7 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
             R.ok(csr_resid_norm(A, L0.val, x, bb, c->ra, c->partial, &cnt, st));
             R.ok(fcg_finish_rr(c->partial, cnt, s, st));
             R.ok(ir_set_scales(s, st));
-            if (R.ir_cast) R.cast_rhs(c->ra, kScaleCast, st);
+            if (R.cast_fused) R.cast_rhs(c->ra, kScaleCast, st);
             cur = c->ra;
             prev = c->rb;
             first = true;
