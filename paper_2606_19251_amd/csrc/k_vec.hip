@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void fcg_castback_dots_kernel(int32_t n, co
     double a = 0.0, b = 0.0;
     for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += kReduceBlocks * kBlock) {
         const double zi = static_cast<double>(u32[i]) * nrm;
-        z[i] = zi;
+        if (z) z[i] = zi;
         a += zi * rnew[i];
         if (rold) b += zi * rold[i];
     }
@@ -240,6 +240,16 @@ __global__ void fcg_update_p_kernel(int32_t n, const double* __restrict__ z, dou
                                     const double* __restrict__ s, int first) {
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n) p[i] = first ? z[i] : z[i] + s[kBeta] * p[i];
+}
+
+// The same with z formed from the FP32 cycle output as fcg_castback_dots forms it (not stored).
+__global__ void fcg_update_p32_kernel(int32_t n, const float* __restrict__ u32, double* __restrict__ p,
+                                      const double* __restrict__ s, int first) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        const double zi = static_cast<double>(u32[i]) * s[kUnscale];
+        p[i] = first ? zi : zi + s[kBeta] * p[i];
+    }
 }
 
 __global__ void ir_update_f32_kernel(int32_t n, double* __restrict__ x, const float* __restrict__ u32,
@@ -435,6 +445,12 @@ hipError_t fcg_finish_beta(const double* partial2, double* s, int first, hipStre
 hipError_t fcg_update_p(int32_t n, const double* z, double* p, const double* s, int first, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     fcg_update_p_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, z, p, s, first);
+    return hipGetLastError();
+}
+
+hipError_t fcg_update_p32(int32_t n, const float* u32, double* p, const double* s, int first, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    fcg_update_p32_kernel<<<grid_for(n), kBlock, 0, stream>>>(n, u32, p, s, first);
     return hipGetLastError();
 }
 

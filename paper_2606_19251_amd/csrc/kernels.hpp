@@ -263,13 +263,15 @@ hipError_t fcg_finish_pq(const double* partial, int count, double* s, hipStream_
 hipError_t fcg_update_xr(int32_t n, double* x, const double* p, const double* r, const double* q, double* rnew,
                          const double* s, double* partial, hipStream_t stream, const Cast32& cast = Cast32{});
 hipError_t fcg_finish_rr(const double* partial, int count, double* s, hipStream_t stream);  // rr, norm, invnorm
-// z = (double)u32 * s[kUnscale] and partials of z.rnew, z.rold (2 * kReduceBlocks)
+// z = (double)u32 * s[kUnscale] (stored unless z is null) and partials of z.rnew, z.rold (2 * kReduceBlocks)
 hipError_t fcg_castback_dots(int32_t n, const float* u32, const double* s, const double* rnew, const double* rold,
                              double* z, double* partial2, hipStream_t stream);
 hipError_t fcg_dots64(int32_t n, const double* z, const double* rnew, const double* rold, double* partial2,
                       hipStream_t stream);
 hipError_t fcg_finish_beta(const double* partial2, double* s, int first, hipStream_t stream);
 hipError_t fcg_update_p(int32_t n, const double* z, double* p, const double* s, int first, hipStream_t stream);
+// p = z (+ beta p) with z = (double)u32 * s[kUnscale] formed in place, as fcg_castback_dots forms it
+hipError_t fcg_update_p32(int32_t n, const float* u32, double* p, const double* s, int first, hipStream_t stream);
 // IR: x += (double)u32 * norm  (or x += e64); skipped when halted
 hipError_t ir_update_f32(int32_t n, double* x, const float* u32, const double* s, hipStream_t stream);
 hipError_t ir_update_f64(int32_t n, double* x, const double* e, const double* s, hipStream_t stream);

@@ -86,13 +86,16 @@ struct Runner {
         double* s = c->scal;
         const double* z = precondition(cast_fused ? nullptr : cur, st, kScaleCast);
         if (prec == 32) {
-            ok(fcg_castback_dots(n, last32, s, cur, first ? nullptr : prev, c->z, c->partial2, st));
-            z = c->z;
+            // z = (double)u32 / scale is formed where it is used (the dots, then p), not stored
+            ok(fcg_castback_dots(n, last32, s, cur, first ? nullptr : prev, nullptr, c->partial2, st));
         } else {
             ok(fcg_dots64(n, z, cur, first ? nullptr : prev, c->partial2, st));
         }
         ok(fcg_finish_beta(c->partial2, s, first ? 1 : 0, st));
-        ok(fcg_update_p(n, z, c->p, s, first ? 1 : 0, st));
+        if (prec == 32)
+            ok(fcg_update_p32(n, last32, c->p, s, first ? 1 : 0, st));
+        else
+            ok(fcg_update_p(n, z, c->p, s, first ? 1 : 0, st));
         int cnt = 0;
         ok(csr_spmv_dot(L0.A(), L0.val, c->p, c->q, c->partial, &cnt, st));
         ok(fcg_finish_pq(c->partial, cnt, s, st));
