@@ -84,6 +84,31 @@ int amgg_rs_copy_level(const amgg_rs* h, int lvl, int32_t* rowptr, int32_t* col,
                        int32_t* p_rowptr, int32_t* p_col, double* p_val, int8_t* cf);
 void amgg_rs_free(amgg_rs* h);
 
+/* The same setup into caller-allocated host buffers, in two calls: amgg_rs_setup_query reports
+ * the hierarchy's sizes; amgg_rs_setup_fill, with the same inputs, writes every level into the
+ * caller's arrays, sized as the query reported (each call runs the whole setup, so a caller that
+ * wants it once keeps an amgg_rs handle instead). Errors as amgg_rs_setup, plus AMGG_EINVAL
+ * when a fill pointer is NULL where the level needs it. */
+typedef struct {
+    int nlevels;
+    int singular;
+    int32_t n[AMGG_MAX_LEVELS], nnz[AMGG_MAX_LEVELS];      /* A_l: rows, stored entries */
+    int32_t p_ncols[AMGG_MAX_LEVELS], p_nnz[AMGG_MAX_LEVELS]; /* P_l (0 on the coarsest level) */
+} amgg_hier_sizes;
+typedef struct {
+    int32_t* rowptr[AMGG_MAX_LEVELS]; /* n + 1 */
+    int32_t* col[AMGG_MAX_LEVELS];    /* nnz */
+    double* val[AMGG_MAX_LEVELS];     /* nnz */
+    int32_t* p_rowptr[AMGG_MAX_LEVELS]; /* n + 1 (levels above the coarsest) */
+    int32_t* p_col[AMGG_MAX_LEVELS];    /* p_nnz */
+    double* p_val[AMGG_MAX_LEVELS];     /* p_nnz */
+    int8_t* cf[AMGG_MAX_LEVELS];        /* n, may be NULL: 1 for C points */
+} amgg_hier_host;
+int amgg_rs_setup_query(const int32_t* rowptr, const int32_t* col, const double* val, int32_t n, double theta,
+                        int max_levels, int32_t max_coarse, amgg_hier_sizes* sizes_out);
+int amgg_rs_setup_fill(const int32_t* rowptr, const int32_t* col, const double* val, int32_t n, double theta,
+                       int max_levels, int32_t max_coarse, const amgg_hier_host* out);
+
 /* Stepwise form of amgg_rs_setup for callers that form the Galerkin products elsewhere
  * (amgg_galerkin_device). amgg_rs_begin validates the matrix as amgg_rs_setup does and
  * holds it as level 0. amgg_rs_coarsen works on the last level: it applies the stopping
@@ -222,6 +247,10 @@ typedef struct {
     int32_t stream_cap[3];
 } amgg_level_view;
 int amgg_level_view_get(const amgg_ctx* ctx, int lvl, amgg_level_view* out);
+/* Copy level lvl's FP64 smoother values Q^-1 (nnz entries on A_l's pattern, as assembled from
+ * Eq. 5; Sec. 3.1) into the caller's device buffer q_out (nnz doubles), ordered on `stream`.
+ * Errors: AMGG_EINVAL (bad level or NULL), AMGG_ESTATE (not finalized or no smoother set). */
+int amgg_get_smoother_values(const amgg_ctx* ctx, int lvl, double* q_out, void* stream);
 
 /* ------------------------------------------------------------------------------------
  * Smoother: sparse pseudo-inverse Q^{-1} on A_l's pattern (Sec. 3.1, Eq. 5; Alg. 1 step 8)

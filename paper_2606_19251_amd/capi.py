@@ -56,6 +56,17 @@ class amgg_solve_info(C.Structure):
                 ("fell_back", C.c_int)]
 
 
+class amgg_hier_sizes(C.Structure):
+    _fields_ = [("nlevels", C.c_int), ("singular", C.c_int), ("n", C.c_int32 * AMGG_MAX_LEVELS),
+                ("nnz", C.c_int32 * AMGG_MAX_LEVELS), ("p_ncols", C.c_int32 * AMGG_MAX_LEVELS),
+                ("p_nnz", C.c_int32 * AMGG_MAX_LEVELS)]
+
+
+class amgg_hier_host(C.Structure):
+    _fields_ = [(k, C.c_void_p * AMGG_MAX_LEVELS) for k in ("rowptr", "col", "val", "p_rowptr", "p_col", "p_val",
+                                                              "cf")]
+
+
 class amgg_judge_info(C.Structure):
     _fields_ = [("learned_wins", C.c_int), ("iterations", C.c_int * 2), ("status", C.c_int * 2),
                 ("log10_relres", C.c_double * 2), ("log10_rate", C.c_double * 2), ("ms_per_iter", C.c_double * 2),
@@ -86,6 +97,9 @@ SIGNATURES = {
     "amgg_rs_galerkin": (_I, [_VP]),
     "amgg_rs_push_level": (_I, [_VP, _I32, _VP, _VP, _VP]),
     "amgg_rs_split": (_I, [_VP, _VP, _VP, C.POINTER(_I)]),
+    "amgg_rs_setup_query": (_I, [_VP, _VP, _VP, _I32, C.c_double, _I, _I32, C.POINTER(amgg_hier_sizes)]),
+    "amgg_rs_setup_fill": (_I, [_VP, _VP, _VP, _I32, C.c_double, _I, _I32, C.POINTER(amgg_hier_host)]),
+    "amgg_get_smoother_values": (_I, [_VP, _I, _VP, _VP]),
     "amgg_rs_push_interp": (_I, [_VP, _I32, _VP, _VP, _VP]),
     "amgg_strength_device": (_I, [_I, _I32, _VP, _VP, _VP, _I32, C.c_double, _VP, _VP, _VP, _VP, _VP]),
     "amgg_interp_device": (_I, [_I, _I32, _VP, _VP, _VP, _I32, _VP, _VP, _VP, _VP, _VP, C.POINTER(_I32),
@@ -236,6 +250,30 @@ def amgg_rs_push_level(h: int, n: int, rowptr: np.ndarray, col: np.ndarray, val:
     col = np.ascontiguousarray(col, np.int32)
     val = np.ascontiguousarray(val, np.float64)
     _check(lib().amgg_rs_push_level(h, n, _np_ptr(rowptr), _np_ptr(col), _np_ptr(val)), "amgg_rs_push_level")
+
+
+def amgg_rs_setup_query(rowptr, col, val, n, theta=0.25, max_levels=10, max_coarse=500) -> amgg_hier_sizes:
+    rowptr, col, val = (np.ascontiguousarray(a, t) for a, t in ((rowptr, np.int32), (col, np.int32), (val, np.float64)))
+    z = amgg_hier_sizes()
+    _check(lib().amgg_rs_setup_query(_np_ptr(rowptr), _np_ptr(col), _np_ptr(val), n, theta, max_levels, max_coarse,
+                                     C.byref(z)), "amgg_rs_setup_query")
+    return z
+
+
+def amgg_rs_setup_fill(rowptr, col, val, n, theta, max_levels, max_coarse, levels):
+    """levels: per level a dict of caller-allocated numpy arrays (rowptr, col, val, and p_rowptr,
+    p_col, p_val above the coarsest level; cf optional), sized as amgg_rs_setup_query reported."""
+    rowptr, col, val = (np.ascontiguousarray(a, t) for a, t in ((rowptr, np.int32), (col, np.int32), (val, np.float64)))
+    out = amgg_hier_host()
+    for l, arrs in enumerate(levels):
+        for k, a in arrs.items():
+            getattr(out, k)[l] = a.ctypes.data if a is not None else None
+    _check(lib().amgg_rs_setup_fill(_np_ptr(rowptr), _np_ptr(col), _np_ptr(val), n, theta, max_levels, max_coarse,
+                                    C.byref(out)), "amgg_rs_setup_fill")
+
+
+def amgg_get_smoother_values(ctx, lvl, q_out, stream):
+    return _check(lib().amgg_get_smoother_values(ctx, lvl, q_out, stream), "amgg_get_smoother_values")
 
 
 def amgg_rs_split(h: int, strong: np.ndarray | None, cf_out: np.ndarray | None) -> int:

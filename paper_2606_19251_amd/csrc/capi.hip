@@ -662,6 +662,22 @@ static int set_coeffs_impl(amgg_ctx* c, int lvl, int degree, const double* coeff
     return AMGG_OK;
 }
 
+extern "C" int amgg_get_smoother_values(const amgg_ctx* c, int lvl, double* q_out, void* stream) {
+    return guarded([&]() -> int {
+        if (!c || !q_out || lvl < 0 || lvl >= c->nlevels)
+            return fail(AMGG_EINVAL, "amgg_get_smoother_values: null argument or bad level");
+        if (!c->finalized) return fail(AMGG_ESTATE, "amgg_get_smoother_values: hierarchy not finalized");
+        const Level& L = c->lv[lvl];
+        if (L.smoother == kSmootherNone) return fail(AMGG_ESTATE, "amgg_get_smoother_values: no smoother set");
+        hipError_t e = hipSetDevice(c->device);
+        if (e == hipSuccess && L.nnz > 0)
+            e = hipMemcpyAsync(q_out, L.q64, sizeof(double) * L.nnz, hipMemcpyDeviceToDevice,
+                               static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return hip_fail(e, "amgg_get_smoother_values");
+        return AMGG_OK;
+    });
+}
+
 extern "C" int amgg_set_smoother_coeffs(amgg_ctx* c, int lvl, int degree, const double* coeffs, void* stream) {
     return guarded([&] { return set_coeffs_impl(c, lvl, degree, coeffs, nullptr, stream); });
 }

@@ -559,3 +559,49 @@ extern "C" int amgg_rs_copy_level(const amgg_rs* h, int lvl, int32_t* rowptr, in
 }
 
 extern "C" void amgg_rs_free(amgg_rs* h) { delete h; }
+
+extern "C" int amgg_rs_setup_query(const int32_t* rowptr, const int32_t* col, const double* val, int32_t n,
+                                   double theta, int max_levels, int32_t max_coarse, amgg_hier_sizes* sizes_out) {
+    return amgg::guarded([&]() -> int {
+        if (!sizes_out) return amgg::fail(AMGG_EINVAL, "amgg_rs_setup_query: null sizes");
+        amgg_rs* h = nullptr;
+        const int rc = amgg_rs_setup(rowptr, col, val, n, theta, max_levels, max_coarse, &h);
+        if (rc != AMGG_OK) return rc;
+        amgg_hier_sizes z{};
+        z.nlevels = static_cast<int>(h->levels.size());
+        z.singular = h->singular;
+        for (int l = 0; l < z.nlevels; ++l) {
+            const RsLevel& L = h->levels[l];
+            z.n[l] = L.A.nrows;
+            z.nnz[l] = L.A.nnz();
+            z.p_ncols[l] = L.P.ncols;
+            z.p_nnz[l] = L.P.nnz();
+        }
+        *sizes_out = z;
+        amgg_rs_free(h);
+        return AMGG_OK;
+    });
+}
+
+extern "C" int amgg_rs_setup_fill(const int32_t* rowptr, const int32_t* col, const double* val, int32_t n,
+                                  double theta, int max_levels, int32_t max_coarse, const amgg_hier_host* out) {
+    return amgg::guarded([&]() -> int {
+        if (!out) return amgg::fail(AMGG_EINVAL, "amgg_rs_setup_fill: null output");
+        amgg_rs* h = nullptr;
+        const int rc = amgg_rs_setup(rowptr, col, val, n, theta, max_levels, max_coarse, &h);
+        if (rc != AMGG_OK) return rc;
+        const int nl = static_cast<int>(h->levels.size());
+        for (int l = 0; l < nl; ++l) {
+            const bool coarsest = l + 1 == nl;
+            if (!out->rowptr[l] || !out->col[l] || !out->val[l] ||
+                (!coarsest && (!out->p_rowptr[l] || !out->p_col[l] || !out->p_val[l]))) {
+                amgg_rs_free(h);
+                return amgg::fail(AMGG_EINVAL, "amgg_rs_setup_fill: null array for level " + std::to_string(l));
+            }
+            amgg_rs_copy_level(h, l, out->rowptr[l], out->col[l], out->val[l], coarsest ? nullptr : out->p_rowptr[l],
+                               coarsest ? nullptr : out->p_col[l], coarsest ? nullptr : out->p_val[l], out->cf[l]);
+        }
+        amgg_rs_free(h);
+        return AMGG_OK;
+    });
+}

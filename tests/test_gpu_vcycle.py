@@ -113,11 +113,17 @@ def test_smoother_values_bitexact(kind, cname):
     c, deg = COEFFS[cname]
     ds.set_coeffs(c, deg)
     torch.cuda.synchronize()
+    from paper_2606_19251_amd import capi
+
     for l in range(ho.nlevels - 1):
         q = amg.assemble_smoother(ho.levels[l].A, c, deg).data
         v = ds.level_view(l)
         assert np.array_equal(_bits(v["q_val"].cpu().numpy()), _bits(q)), f"level {l}"
         assert np.array_equal(_bits(v["q_val32"].cpu().numpy()), _bits(q.astype(np.float32)))
+        out = torch.empty(q.size, dtype=torch.float64, device="cuda")
+        capi.amgg_get_smoother_values(ds.ctx, l, out.data_ptr(), ds.stream)  # the copy into a caller buffer
+        torch.cuda.synchronize()
+        assert np.array_equal(_bits(out.cpu().numpy()), _bits(q)), f"level {l}"
 
 
 @pytest.mark.parametrize("kind", ["grid64", "grid64_deep", "delaunay20k", "gmm5k", "tiny", "cmesh32k", "tet30k"])

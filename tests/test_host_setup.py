@@ -303,3 +303,38 @@ def test_block_diagonal_hierarchy_layout():
                 else:
                     parts.append(sp.identity(h.levels[h.nlevels - 1].n, format="csr"))
             assert (P != sp.block_diag(parts).tocsr()).nnz == 0
+
+
+def test_query_fill_setup_equals_handle_setup():
+    """amgg_rs_setup_query / amgg_rs_setup_fill (the setup into caller-allocated host buffers)
+    give the sizes and the arrays of the handle-based setup, bit for bit."""
+    from paper_2606_19251_amd.solver import HostHierarchy
+
+    capi = _capi()
+    A = W.delaunay_p1(W.gmm_points(4000, 9))
+    ref = HostHierarchy.build(A.rowptr, A.col, A.val, max_coarse=60)
+    z = capi.amgg_rs_setup_query(A.rowptr, A.col, A.val, A.nrows, 0.25, 10, 60)
+    assert z.nlevels == ref.nlevels and bool(z.singular) == ref.singular
+    levels = []
+    for l in range(z.nlevels):
+        L = ref.levels[l]
+        assert (z.n[l], z.nnz[l]) == (L.n, L.nnz)
+        arrs = {"rowptr": np.empty(z.n[l] + 1, np.int32), "col": np.empty(z.nnz[l], np.int32),
+                "val": np.empty(z.nnz[l], np.float64), "cf": np.empty(z.n[l], np.int8)}
+        if l + 1 < z.nlevels:
+            assert (z.p_ncols[l], z.p_nnz[l]) == (L.p_ncols, int(L.p_col.size))
+            arrs.update(p_rowptr=np.empty(z.n[l] + 1, np.int32), p_col=np.empty(z.p_nnz[l], np.int32),
+                        p_val=np.empty(z.p_nnz[l], np.float64))
+        levels.append(arrs)
+    capi.amgg_rs_setup_fill(A.rowptr, A.col, A.val, A.nrows, 0.25, 10, 60, levels)
+    for l, arrs in enumerate(levels):
+        L = ref.levels[l]
+        assert np.array_equal(arrs["rowptr"], L.rowptr) and np.array_equal(arrs["col"], L.col)
+        assert np.array_equal(_bits(arrs["val"]), _bits(L.val)) and np.array_equal(arrs["cf"], L.cf)
+        if l + 1 < z.nlevels:
+            assert np.array_equal(arrs["p_rowptr"], L.p_rowptr) and np.array_equal(arrs["p_col"], L.p_col)
+            assert np.array_equal(_bits(arrs["p_val"]), _bits(L.p_val))
+    levels[0]["col"] = None
+    with pytest.raises(capi.AmggError) as e:
+        capi.amgg_rs_setup_fill(A.rowptr, A.col, A.val, A.nrows, 0.25, 10, 60, levels)
+    assert e.value.code == capi.AMGG_EINVAL
