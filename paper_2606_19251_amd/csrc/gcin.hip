@@ -347,10 +347,16 @@ __device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned
 // a_lo b_lo term is below FP32 resolution): an FP32-accurate product on the BF16 MFMA
 // units, used where the result feeds non-smooth operations (ReLU masks, arg-max pooling)
 // whose gradients must match an FP32/FP64 evaluation.
-template <int HD, bool MFMA, bool SPLIT = false, bool SPLITB = false>
+// GB: the bf16 copies of B (and of its low parts) are read from global memory, row-major [col][k]
+// with row stride HD (Bg, Bglo; formed once per forward by weights_bf16_kernel), not from LDS:
+// the weights are shared by every tile and stay in cache, and the LDS left to a workgroup is its
+// tile (more workgroups per CU).
+template <int HD, bool MFMA, bool SPLIT = false, bool SPLITB = false, bool GB = false>
 __device__ __forceinline__ void tile_gemm(const float (*A)[HD + 1], const float* __restrict__ Bf,
                                           const unsigned short (*Bt)[HD + 8], float (*D)[HD + 1],
-                                          const unsigned short (*Btlo)[HD + 8] = nullptr) {
+                                          const unsigned short (*Btlo)[HD + 8] = nullptr,
+                                          const unsigned short* __restrict__ Bg = nullptr,
+                                          const unsigned short* __restrict__ Bglo = nullptr) {
     static_assert(!MFMA || HD == 64, "the MFMA tiling is written for 64 channels");
     const int wv = threadIdx.x / HD, lane = threadIdx.x % HD;
     if constexpr (!MFMA) {
@@ -381,13 +387,19 @@ __device__ __forceinline__ void tile_gemm(const float (*A)[HD + 1], const float*
             const bf16x8 al = __builtin_bit_cast(bf16x8, alv);
             for (int nb = 0; nb < 4; ++nb) {
                 u16x8 bv;
-                for (int e = 0; e < 8; ++e) bv[e] = Bt[nb * 16 + i][ks + kq + e];
+                if constexpr (GB)
+                    bv = *reinterpret_cast<const u16x8*>(Bg + (nb * 16 + i) * HD + ks + kq);
+                else
+                    for (int e = 0; e < 8; ++e) bv[e] = Bt[nb * 16 + i][ks + kq + e];
                 const bf16x8 b = __builtin_bit_cast(bf16x8, bv);
                 acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nb], 0, 0, 0);
                 if constexpr (SPLIT) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b, acc[nb], 0, 0, 0);
                 if constexpr (SPLITB) {
                     u16x8 blv;
-                    for (int e = 0; e < 8; ++e) blv[e] = Btlo[nb * 16 + i][ks + kq + e];
+                    if constexpr (GB)
+                        blv = *reinterpret_cast<const u16x8*>(Bglo + (nb * 16 + i) * HD + ks + kq);
+                    else
+                        for (int e = 0; e < 8; ++e) blv[e] = Btlo[nb * 16 + i][ks + kq + e];
                     const bf16x8 bl = __builtin_bit_cast(bf16x8, blv);
                     acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc[nb], 0, 0, 0);
                 }
@@ -425,6 +437,24 @@ __device__ __forceinline__ void stage_bf16_split_t(const float* __restrict__ M, 
 }
 
 // Y0: the layer below is layer 0, whose output is formed from H0 (y0_of) instead of read from Yp.
+// bf16 hi / lo parts of the 64 x 64 weights of layers 1 .. NL-1, transposed ([col][k]) for
+// tile_gemm's global-memory operand: block l - 1 forms layer l into wbf + (l - 1) 2 HD^2 (hi) and
+// the HD^2 entries after it (lo).
+template <int HD>
+__global__ __launch_bounds__(256) void weights_bf16_kernel(const float* __restrict__ P, Offs o,
+                                                         unsigned short* __restrict__ wbf) {
+    const int l = blockIdx.x + 1;
+    const float* W = P + o.convW[l];
+    unsigned short* hi = wbf + static_cast<int64_t>(blockIdx.x) * 2 * HD * HD;
+    for (int e = threadIdx.x; e < HD * HD; e += blockDim.x) {
+        const int k = e / HD, c = e % HD;
+        unsigned short h, lo;
+        split_bf16(W[e], h, lo);
+        hi[c * HD + k] = h;
+        hi[HD * HD + c * HD + k] = lo;
+    }
+}
+
 template <int HD, bool MFMA, bool X3, bool Y0>
 __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                                    const float* __restrict__ w, const int32_t* __restrict__ tile_graph,
@@ -434,27 +464,21 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
                                                    const float* __restrict__ mup, const float* __restrict__ rsp,
                                                    const float* __restrict__ gam, const float* __restrict__ bet,
                                                    const float* __restrict__ W, const float* __restrict__ b,
+                                                   const unsigned short* __restrict__ wbf,
                                                    float* __restrict__ Hout, float* __restrict__ Y,
                                                    double* __restrict__ tstat) {
     // The product overwrites the aggregates in place: every wavefront reads only its own 16
     // rows of Hs and writes the same rows, each output after all of its row's reads (the
-    // stores depend on them), so one tile buffer serves both and twice as many workgroups fit
-    // a CU's LDS.
+    // stores depend on them), so one tile buffer serves both; with the weights' bf16 parts
+    // read from global memory (wbf: hi, then lo) the tile and the statistics are all the LDS a
+    // workgroup holds (8 workgroups per CU).
     __shared__ float Hs[TILE][HD + 1];
     float (*Ds)[HD + 1] = Hs;
-    // the statistics buffer reuses the weight tile, which is no longer read after the product
-    __shared__ __align__(16) unsigned short Bt[HD][HD + 8];
-    static_assert(sizeof(Bt) >= 4 * HD * sizeof(double), "statistics buffer fits the weight tile");
-    double (*sh)[HD] = reinterpret_cast<double (*)[HD]>(&Bt[0][0]);
-    __shared__ unsigned short Btlo[X3 ? HD : 1][HD + 8];
+    __shared__ double sh[4][HD];
     const int tile = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
     const int g = tile_graph[tile];
     const int32_t end = gend[g];
     const float mu = mup[g * HD + c], rs = rsp[g * HD + c], ga = gam[c], be = bet[c];
-    if constexpr (X3 && MFMA)
-        stage_bf16_split_t<HD>(W, Bt, Btlo);
-    else if constexpr (MFMA)
-        stage_bf16<HD>(W, true, Bt);
     float h = 0.0f;
     const int32_t r0 = tile * TILE + wv * 16;
     float w0 = 0.0f, w1 = 0.0f, bb0 = 0.0f;
@@ -479,7 +503,7 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
             h = 0.0f;
         });
     __syncthreads();
-    tile_gemm<HD, MFMA, true, X3>(Hs, W, Bt, Ds, Btlo);
+    tile_gemm<HD, MFMA, true, X3, true>(Hs, W, nullptr, Ds, nullptr, wbf, wbf + HD * HD);
     __syncthreads();
     const float bc = b[c];
     double s1 = 0.0, s2 = 0.0;
@@ -1223,6 +1247,7 @@ struct gcin_batch {
     float* d_gcnt = nullptr;
     int32_t *ptr = nullptr, *col = nullptr;
     float *w = nullptr, *x0 = nullptr, *H0 = nullptr;
+    unsigned short* wbf = nullptr;  // bf16 hi / lo parts of the weights of layers 1 .. NL-1
     float* Y[NL] = {};
     float* H[NL] = {};
     double* tstat = nullptr;
@@ -1298,6 +1323,7 @@ size_t layout_batch(gcin_batch* b, uintptr_t base) {
     b->hs.s = cv.take<float>(G * JK);
     b->hs.a1 = cv.take<float>(G * M1);
     b->hs.a2 = cv.take<float>(G * M2);
+    b->wbf = cv.take<unsigned short>(static_cast<size_t>(NL - 1) * 2 * HD * HD);
     if (b->infer) return (cv.off + 255) & ~static_cast<size_t>(255);  // no backward buffers
     b->dpooled = cv.take<float>(G * NL * 2 * HD);
     const Offs o4 = offsets(AMGG_MAX_DEGREE, b->hd);
@@ -1506,6 +1532,8 @@ void forward_impl(gcin_batch* b, int degree, int precision, const float* P, floa
                                                 b->argmax);
     };
     stats_and_pool(0);
+    const bool mfma = HD == 64 && precision != GCIN_FP32;
+    if (mfma) weights_bf16_kernel<HD><<<NL - 1, 256, 0, st>>>(P, o, b->wbf);
     for (int l = 1; l < NL; ++l) {
         const bool y0 = l == 1;
         auto kern = y0 ? layer_kernel<HD, false, false, true> : layer_kernel<HD, false, false, false>;
@@ -1517,7 +1545,8 @@ void forward_impl(gcin_batch* b, int degree, int precision, const float* P, floa
         }
         kern<<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->d_tile_graph, b->d_gend, b->Y[l - 1], b->H0, W0, b0,
                                b->mu[l - 1], b->rstd[l - 1], P + o.gam[l - 1], P + o.bet[l - 1], P + o.convW[l],
-                               P + o.convb[l], b->H[l], b->Y[l], b->tstat);
+                               P + o.convb[l], b->wbf + static_cast<int64_t>(l - 1) * 2 * HD * HD, b->H[l], b->Y[l],
+                               b->tstat);
         stats_and_pool(l);
     }
     head_fwd_kernel<HD><<<G, 128, 0, st>>>(P, o, b->pooled, b->hs, coeffs_out);
