@@ -14,6 +14,10 @@ Further workloads reported in the same line (skipped with --only-headline):
               aspect ratio 1e4, Dirichlet far field), flexible CG;
   training    one training step (Alg. 1) on the 32-mesh clustered batch;
   structured  a 1024 x 1024 5-point grid with the 32-channel GCIN.
+Optional headline (--workload tetdel1m, not in the default line): finite-volume Poisson on the
+Delaunay tetrahedralisation of a jittered 55^3 lattice (about 1.06M cells; qhull's output differs
+slightly between hosts), all-Neumann, with the networks trained on small Delaunay
+tetrahedralisations; its mesh takes 10-25 s to generate.
 Ruge-Stueben hierarchy (theta 0.25, <= 10 levels, coarsest <= 500 rows); each mesh family uses
 the GCIN weights trained on small meshes of that family. One step = one complete solve from
 x = 0 with the hierarchy, the smoother and the right-hand side resident in HBM (setup is
@@ -302,10 +306,12 @@ WORKLOADS = {
     "cmesh4m": ("gcin_cmesh_deg2.npz", "FV Poisson on a 4096 x 1024 C-mesh around NACA 2412, wall aspect 1e4"),
     "grid1m": ("gcin_grid_h32_deg2.npz", "5-point Laplacian on a 1024 x 1024 structured grid, Dirichlet "
                                          "(32-channel GCIN)"),
+    "tetdel1m": ("gcin_tetdel_deg2_d4.npz", "FV Poisson on the Delaunay tetrahedra of a jittered 55^3 lattice "
+                                         "(about 1.06M cells), all-Neumann"),
 }
 
 
-SPARSE_ALL_LEVELS = {"delaunay1m": "gcin_deg2.npz", "tet8m": "gcin_tet_deg2.npz"}
+SPARSE_ALL_LEVELS = {"delaunay1m": "gcin_deg2.npz", "tet8m": "gcin_tet_deg2.npz", "tetdel1m": "gcin_tetdel_deg2.npz"}
 
 
 def make_workload(name):
@@ -315,6 +321,8 @@ def make_workload(name):
         return W.delaunay_p1_problem(1_000_000, 0)
     if name == "tet8m":
         return W.tet_kuhn_problem(111, 0)
+    if name == "tetdel1m":
+        return W.tet_fv_problem(55, 0)
     if name == "grid1m":
         A = W.grid5(1024)
         return A, W.rhs_uniform(A.nrows, 0)
@@ -574,7 +582,7 @@ def structured_case(torch, nu=1):
     return res
 
 
-CONFIGURED_OUTER = {"tet8m": "ir", "delaunay1m": "fcg", "cmesh4m": "fcg", "grid1m": "fcg"}
+CONFIGURED_OUTER = {"tet8m": "ir", "tetdel1m": "ir", "delaunay1m": "fcg", "cmesh4m": "fcg", "grid1m": "fcg"}
 
 
 def _stream_rows(n, nnz):

@@ -5,6 +5,7 @@ Training problems (all levels of all meshes of a mini-batch in one GCIN launch),
   cmesh     finite-volume C-meshes around random NACA 4-digit sections, ~24k-41k cells, wall
             aspect ratios 1e3-1e4 (for the 4M-cell airfoil mesh, 128 times larger);
   tet       finite-volume Poisson on jittered Kuhn tetrahedral meshes, ~8k-55k cells;
+  tetdel    the same on Delaunay tetrahedralisations of jittered lattices, ~9k-50k cells;
   grid      5-point Laplacians on square structured grids, 2k-16k nodes, Dirichlet (the
             structured case, for which the paper proposes the smaller 32-channel GCIN, App. B.3:
             --hidden 32);
@@ -49,6 +50,8 @@ def make_matrix(family, rng, seed):
     if family == "tet":
         P, T = W.kuhn_tets(int(rng.integers(12, 23)), seed, float(rng.uniform(0.05, 0.15)))
         return W.tet_fv_mesh(P, T)
+    if family == "tetdel":
+        return W.tet_fv(W.jittered_lattice(int(rng.integers(12, 21)), seed))
     if family == "grid":
         return W.grid5(int(rng.integers(45, 127)))
     raise ValueError(family)
@@ -211,7 +214,7 @@ def main(argv=None):
     ap.add_argument("--min-lr", type=float, default=1e-5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--seeds", type=int, default=1, help="independent initialisations; the best is kept")
-    ap.add_argument("--family", choices=[*FAMILIES, "grid", "mixed"], default="delaunay")
+    ap.add_argument("--family", choices=[*FAMILIES, "tetdel", "grid", "mixed"], default="delaunay")
     ap.add_argument("--hidden", type=int, choices=[64, 32], default=64, help="GCIN channels")
     ap.add_argument("--diag-levels", type=int, default=0,
                     help="finest levels whose smoother takes the diagonal form of Eq. 5 (f_o = 0)")

@@ -31,6 +31,8 @@ def _meshes(family):
         return [W.delaunay_p1(W.gmm_points(n, 70_000 + k)) for k, n in enumerate((9000, 12000, 15000))]
     if family == "tet":
         return [W.tet_fv_mesh(*W.kuhn_tets(m, 71_000 + m, 0.12)) for m in (16, 19, 22)]
+    if family == "tetdel":  # Delaunay tetrahedralisations of jittered lattices
+        return [W.tet_fv(W.jittered_lattice(m, 73_000 + m)) for m in (14, 17, 20)]
     return [W.cmesh_fv(256, 128, code, 1e4) for code in ("2412", "0012", "4415")]
 
 
@@ -41,6 +43,10 @@ def _meshes(family):
                                             ("delaunay", "gcin_deg2_d3.npz"), ("tet", "gcin_tet_deg2_d2.npz"),
                                             ("tet", "gcin_tet_deg2_d4.npz"), ("delaunay", "gcin_deg2_d8.npz"),
                                             ("cmesh", "gcin_cmesh_deg2.npz"),
+                                            # Delaunay tetrahedra: the network trained on them (diagonal
+                                            # form on the 4 finest levels) and the Kuhn-trained one
+                                            # with the sparse form on every level
+                                            ("tetdel", "gcin_tetdel_deg2_d4.npz"), ("tetdel", "gcin_tet_deg2.npz"),
                                             # one model trained on the union of the three families (on
                                             # the C-meshes it gains nothing: Eq. 13 metric +0.008)
                                             ("delaunay", "gcin_mixed_deg2.npz"), ("tet", "gcin_mixed_deg2.npz"),
