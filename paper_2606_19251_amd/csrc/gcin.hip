@@ -178,6 +178,61 @@ __device__ __forceinline__ void visit_rows(const int32_t* __restrict__ ptr, cons
     for (; r < r1; ++r) done(r);
 }
 
+// The same walk for 64 channels with 16-byte gathers: the 16 lanes of group q = lane / 16 own the
+// rows [r0 + 4 q, r0 + 4 q + 4) and lane p = lane % 16 holds channels 4 p .. 4 p + 3, so that one
+// load instruction brings four neighbour rows (the load units process a wavefront's addresses a few
+// lanes per cycle, which bounds a gather of one 4-byte channel per lane). Each row's entries are
+// still visited in stored order, so every channel's sum is the one visit_rows forms. A group takes
+// its entries kBatchX4 at a time, their indices and weights held by its first lanes; use(w, v)
+// gets the four channels as a float4, done(row) is called once per row of the group.
+constexpr int kBatchX4 = 8;
+
+template <class Load, class Use, class Done>
+__device__ __forceinline__ void visit_rows_x4(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                              const float* __restrict__ w, int32_t r0, Load load, Use use,
+                                              Done done) {
+    constexpr int B = kBatchX4;
+    const int p = static_cast<int>(threadIdx.x % 16);
+    const int32_t g0 = r0 + 4 * static_cast<int32_t>((threadIdx.x % 64) / 16);  // the group's first row
+    const int32_t rp = ptr[g0 + min(p, 4)];
+    auto bound = [&](int32_t i) { return __shfl(rp, i, 16); };  // ptr[g0 + i], i <= 4
+    const int32_t kbeg = bound(0), kend = bound(4);
+    int32_t r = g0;
+    int32_t rnext = bound(1);
+    const int32_t l = p % B;
+    int32_t cl = 0;
+    float wl = 0.0f;
+    if (kbeg < kend) {
+        const int32_t kk = min(kbeg + l, kend - 1);
+        cl = col[kk];
+        wl = w[kk];
+    }
+    for (int32_t k = kbeg; k < kend; k += B) {
+        float4 vj[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) vj[q] = load(__shfl(cl, q, 16));
+        const float wcur = wl;
+        if (k + B < kend) {
+            const int32_t kk = min(k + B + l, kend - 1);
+            cl = col[kk];
+            wl = w[kk];
+        }
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const float wq = __shfl(wcur, q, 16);
+            if (k + q < kend) {
+                while (k + q >= rnext) {
+                    done(r);
+                    ++r;
+                    rnext = bound(r + 1 - g0);
+                }
+                use(wq, vj[q]);
+            }
+        }
+    }
+    for (; r < g0 + 4; ++r) done(r);
+}
+
 // Sum over the 4 wavefronts of a workgroup, per channel (lane), into out[c] (thread wave 0).
 template <int HD>
 __device__ __forceinline__ double wave4_sum(double v, double (*sh)[HD]) {
@@ -471,7 +526,7 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
     // rows of Hs and writes the same rows, each output after all of its row's reads (the
     // stores depend on them), so one tile buffer serves both; with the weights' bf16 parts
     // read from global memory (wbf: hi, then lo) the tile and the statistics are all the LDS a
-    // workgroup holds (8 workgroups per CU).
+    // workgroup holds (LDS would admit 8 workgroups per CU; registers admit 4 wavefronts per SIMD).
     __shared__ float Hs[TILE][HD + 1];
     float (*Ds)[HD + 1] = Hs;
     __shared__ double sh[4][HD];
@@ -487,21 +542,64 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
         w1 = W0[HD + c];
         bb0 = b0[c];
     }
-    visit_rows<HD, float>(
-        ptr, col, w, r0, r0 + 16,
-        [&](int32_t j) {
-            if constexpr (Y0)
-                return y0_of(reinterpret_cast<const float2*>(H0)[j], w0, w1, bb0);
-            else
-                return Yp[static_cast<int64_t>(j) * HD + c];
-        },
-        [&](float wp, float v) { h += wp * normrelu(v, mu, rs, ga, be); },
-        [&](int32_t row) {
-            const float hv = row < end ? h : 0.0f;
-            Hs[row - tile * TILE][c] = hv;
-            if (Hout) Hout[static_cast<int64_t>(row) * HD + c] = hv;  // kept for a backward only
-            h = 0.0f;
-        });
+    if constexpr (HD == 64) {
+        // channels 4 p .. 4 p + 3 of the lane's group (see visit_rows_x4)
+        const int c4 = 4 * static_cast<int>(threadIdx.x % 16);
+        const float4 mu4 = *reinterpret_cast<const float4*>(mup + g * HD + c4);
+        const float4 rs4 = *reinterpret_cast<const float4*>(rsp + g * HD + c4);
+        const float4 ga4 = *reinterpret_cast<const float4*>(gam + c4);
+        const float4 be4 = *reinterpret_cast<const float4*>(bet + c4);
+        float4 w04 = make_float4(0.f, 0.f, 0.f, 0.f), w14 = w04, bb4 = w04;
+        if constexpr (Y0) {
+            w04 = *reinterpret_cast<const float4*>(W0 + c4);
+            w14 = *reinterpret_cast<const float4*>(W0 + HD + c4);
+            bb4 = *reinterpret_cast<const float4*>(b0 + c4);
+        }
+        float4 h4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        visit_rows_x4(
+            ptr, col, w, r0,
+            [&](int32_t j) {
+                if constexpr (Y0) {
+                    const float2 hv = reinterpret_cast<const float2*>(H0)[j];
+                    return make_float4(y0_of(hv, w04.x, w14.x, bb4.x), y0_of(hv, w04.y, w14.y, bb4.y),
+                                       y0_of(hv, w04.z, w14.z, bb4.z), y0_of(hv, w04.w, w14.w, bb4.w));
+                } else {
+                    return *reinterpret_cast<const float4*>(Yp + static_cast<int64_t>(j) * HD + c4);
+                }
+            },
+            [&](float wp, const float4& v) {
+                h4.x += wp * normrelu(v.x, mu4.x, rs4.x, ga4.x, be4.x);
+                h4.y += wp * normrelu(v.y, mu4.y, rs4.y, ga4.y, be4.y);
+                h4.z += wp * normrelu(v.z, mu4.z, rs4.z, ga4.z, be4.z);
+                h4.w += wp * normrelu(v.w, mu4.w, rs4.w, ga4.w, be4.w);
+            },
+            [&](int32_t row) {
+                const float4 hv = row < end ? h4 : make_float4(0.f, 0.f, 0.f, 0.f);
+                float* hs = &Hs[row - tile * TILE][c4];
+                hs[0] = hv.x;
+                hs[1] = hv.y;
+                hs[2] = hv.z;
+                hs[3] = hv.w;
+                if (Hout) *reinterpret_cast<float4*>(Hout + static_cast<int64_t>(row) * HD + c4) = hv;
+                h4 = make_float4(0.f, 0.f, 0.f, 0.f);
+            });
+    } else {
+        visit_rows<HD, float>(
+            ptr, col, w, r0, r0 + 16,
+            [&](int32_t j) {
+                if constexpr (Y0)
+                    return y0_of(reinterpret_cast<const float2*>(H0)[j], w0, w1, bb0);
+                else
+                    return Yp[static_cast<int64_t>(j) * HD + c];
+            },
+            [&](float wp, float v) { h += wp * normrelu(v, mu, rs, ga, be); },
+            [&](int32_t row) {
+                const float hv = row < end ? h : 0.0f;
+                Hs[row - tile * TILE][c] = hv;
+                if (Hout) Hout[static_cast<int64_t>(row) * HD + c] = hv;  // kept for a backward only
+                h = 0.0f;
+            });
+    }
     __syncthreads();
     tile_gemm<HD, MFMA, true, X3, true>(Hs, W, nullptr, Ds, nullptr, wbf, wbf + HD * HD);
     __syncthreads();
