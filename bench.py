@@ -444,7 +444,7 @@ class Case:
         xh = self.x.cpu().numpy()
         fb = self.f - self.f.mean() if self.hh.singular else self.f
         true_rel = float(np.linalg.norm(fb - self.A.to_scipy() @ xh) / np.linalg.norm(fb))
-        tag = "FCG" if outer == capi.AMGG_OUTER_FCG else "IR"
+        tag = ("FCG" if outer == capi.AMGG_OUTER_FCG else "IR") + (f" V({nu},{nu})" if nu != 1 else "")
         log(f"{self.name} {smoother} {tag}: {ms:.3f} ms/solve, {info.vcycles} V-cycles, rc={rc}, "
             f"fell_back={info.fell_back}, rel={true_rel:.2e}")
         return {"ms": round(ms, 4), "ms_median": round(median, 4), "vcycles": info.vcycles,
@@ -792,6 +792,12 @@ def run(args, cpu_job):
                 continue
             c2 = Case(torch, name, with_host_setup=(name == "delaunay1m"))
             out[name] = workload_report(torch, c2, 5, 1, args.nu, outers)
+            if name == "delaunay1m" and args.nu == 1:
+                # the paper's default cycle V(2,2), a secondary figure (the networks were trained on
+                # V(1,1) cycles)
+                v22 = {sm: c2.solves(sm, capi.AMGG_OUTER_FCG, 5, 1, 2) for sm in ("jacobi", "gnn")}
+                v22["gnn_over_jacobi_time"] = round(v22["gnn"]["ms"] / v22["jacobi"]["ms"], 4)
+                out[name]["fcg_v22"] = v22
             c2.ds.close()
             del c2
         out["training"] = training_step(torch)

@@ -310,11 +310,12 @@ extern "C" int amgg_create(amgg_ctx** out, int device, int nlevels) {
         auto* c = new amgg_ctx();
         c->device = device;
         c->nlevels = nlevels;
-        if ((e = hipSetDevice(device)) != hipSuccess ||
-            (e = hipHostMalloc(&c->host_scal, sizeof(double) * kSlots * 3)) != hipSuccess ||
-            (e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming)) != hipSuccess) {
+        if ((e = hipSetDevice(device)) == hipSuccess &&
+            (e = hipHostMalloc(&c->host_scal, sizeof(double) * kSlots * (1 + kPipeline))) == hipSuccess &&
+            (e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) == hipSuccess)
+            for (hipEvent_t& ev : c->ev)
+                if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) break;
+        if (e != hipSuccess) {
             for (hipEvent_t ev : c->ev)
                 if (ev) (void)hipEventDestroy(ev);
             if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);

@@ -17,6 +17,9 @@ namespace amgg {
 enum : int { kSmootherNone = 0, kSmootherDiagonal = 1, kSmootherSparse = 2 };
 constexpr int kChunkRows = 256;  // rows per workgroup of the segmented (per-block) sums
 constexpr int kMaxCoef = 2 * AMGG_MAX_DEGREE + 1;
+// Outer iterations of a solve enqueued at once (the one the host inspects and those behind it), so
+// that a host thread late by up to kPipeline - 1 iterations leaves no gap on the stream.
+constexpr int kPipeline = 3;
 
 struct Level {
     bool loaded = false, p_loaded = false;
@@ -151,9 +154,9 @@ struct amgg_ctx {
     int singular = 0;
     void* ws = nullptr;
     size_t ws_bytes = 0;
-    double* host_scal = nullptr;  // pinned host copies of the device scalars: 3 slots of kSlots
+    double* host_scal = nullptr;  // pinned host copies of the device scalars: 1 + kPipeline slots of kSlots
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
-    hipEvent_t ev[2] = {nullptr, nullptr};  // completion of the two pipelined scalar copies
+    hipEvent_t ev[amgg::kPipeline] = {};  // completion of the pipelined scalar copies
     struct Graph {
         std::string key;
         hipGraphExec_t exec;

@@ -294,15 +294,15 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
         }
 
         // IR and flexible CG: each iteration is enqueued (a graph launch) together with an
-        // asynchronous copy of the scalar block into one of two pinned slots; the host keeps
-        // one iteration in flight while it inspects the previous one.
+        // asynchronous copy of the scalar block into one of kPipeline pinned slots; the host keeps
+        // up to kPipeline - 1 iterations in flight behind the one it inspects.
         R.ok(fcg_set_limits(s, o->tol, div_factor, st));
         if (R.cast_fused) R.cast_rhs(c->ra, kScaleCast, st);  // the first cycle's right-hand side: b
         struct InFlight {
             double* cu;
             double* pv;
         };
-        std::vector<InFlight> q;  // enqueued, not yet inspected (at most two)
+        std::vector<InFlight> q;  // enqueued, not yet inspected (at most kPipeline)
         int launched = 0;
         bool more = true;  // false once a stop is decided and only the in-flight one remains
         auto launch = [&]() -> hipError_t {
@@ -320,7 +320,7 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
             }
             first = false;
             if (e != hipSuccess) return e;
-            const int slot = launched % 2;
+            const int slot = launched % kPipeline;
             if ((e = hipMemcpyAsync(hs + (1 + slot) * kSlots, s, sizeof(double) * kSlots, hipMemcpyDeviceToHost,
                                     st)) != hipSuccess ||
                 (e = hipEventRecord(c->ev[slot], st)) != hipSuccess)
@@ -336,20 +336,25 @@ extern "C" int amgg_solve(amgg_ctx* c, const amgg_solve_opts* o, const double* b
             R.ok(hipStreamSynchronize(st));
             return R.e == hipSuccess;
         };
-        // Enqueue ahead only while the in-flight iteration is not expected to converge (its
-        // residual predicted from the last ratio stays above twice the tolerance): an iteration
-        // enqueued after the converging one would run its whole cycle for nothing.
+        // Enqueue ahead only while the in-flight iterations are not expected to converge (the
+        // residual after the last of them, predicted from the last ratio, stays above twice the
+        // tolerance): an iteration enqueued after the converging one would run its whole cycle for
+        // nothing.
         auto ahead = [&]() {
             if (hist.size() < 3) return true;
             const double last = hist[hist.size() - 1], ratio = std::min(1.0, last / hist[hist.size() - 2]);
-            return last * ratio > 2.0 * o->tol;
+            double pred = last;
+            for (size_t m = 0; m < q.size(); ++m) pred *= ratio;
+            return pred > 2.0 * o->tol;
         };
         for (;;) {
             hipError_t e = hipSuccess;
             if (q.empty()) e = launch();
-            if (e == hipSuccess && more && q.size() == 1 && launched < o->maxit && ahead()) e = launch();
+            while (e == hipSuccess && more && q.size() < static_cast<size_t>(kPipeline) && launched < o->maxit &&
+                   ahead())
+                e = launch();
             if (e != hipSuccess) return hip_fail(e, "amgg_solve");
-            const int slot = k % 2;
+            const int slot = k % kPipeline;
             if ((e = hipEventSynchronize(c->ev[slot])) != hipSuccess) return hip_fail(e, "amgg_solve");
             const double* hk = hs + (1 + slot) * kSlots;
             const InFlight it = q.front();
