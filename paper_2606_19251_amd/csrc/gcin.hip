@@ -533,15 +533,7 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
     const int tile = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
     const int g = tile_graph[tile];
     const int32_t end = gend[g];
-    const float mu = mup[g * HD + c], rs = rsp[g * HD + c], ga = gam[c], be = bet[c];
-    float h = 0.0f;
     const int32_t r0 = tile * TILE + wv * 16;
-    float w0 = 0.0f, w1 = 0.0f, bb0 = 0.0f;
-    if constexpr (Y0) {
-        w0 = W0[c];
-        w1 = W0[HD + c];
-        bb0 = b0[c];
-    }
     if constexpr (HD == 64) {
         // channels 4 p .. 4 p + 3 of the lane's group (see visit_rows_x4)
         const int c4 = 4 * static_cast<int>(threadIdx.x % 16);
@@ -584,6 +576,14 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
                 h4 = make_float4(0.f, 0.f, 0.f, 0.f);
             });
     } else {
+        const float mu = mup[g * HD + c], rs = rsp[g * HD + c], ga = gam[c], be = bet[c];
+        float w0 = 0.0f, w1 = 0.0f, bb0 = 0.0f;
+        if constexpr (Y0) {
+            w0 = W0[c];
+            w1 = W0[HD + c];
+            bb0 = b0[c];
+        }
+        float h = 0.0f;
         visit_rows<HD, float>(
             ptr, col, w, r0, r0 + 16,
             [&](int32_t j) {
