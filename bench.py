@@ -223,6 +223,9 @@ def _cpu_baseline_job(conn, workload, budget_s, throughput_procs):
 
         from oracle import amg
 
+        # below the GPU process in the scheduler: the outer loops' host thread inspects an
+        # iteration every ~0.2 ms on the smaller meshes, and waking it late idles the GPU
+        os.nice(10)
         t0 = time.time()
         A, f = make_workload(workload)
         mesh_s = time.time() - t0
