@@ -75,32 +75,39 @@ Csr pattern_transpose(const Csr& S) {
     return T;
 }
 
-// Max tournament tree over the undecided points. A node holds the packed maximum
-// (measure << 32 | ~index) of its range, so the root answers "largest lambda, smallest
-// index" without looking anything up, and an update stops climbing as soon as a node keeps
-// its value.
+// Max tournament tree over the undecided points, 8 children per node (a node's children are one
+// 64-byte line, and an 8M-point level is 8 levels deep instead of 23). A node holds the packed
+// maximum (measure << 32 | ~index) of its range, so the root answers "largest lambda, smallest
+// index" without looking anything up, and an update stops climbing as soon as a node keeps its
+// value. Every level is padded to a multiple of 8 entries with the empty value.
 class ArgmaxTree {
   public:
     explicit ArgmaxTree(const std::vector<int64_t>& key) {
-        n_ = static_cast<int32_t>(key.size());
-        size_ = 1;
-        while (size_ < n_) size_ <<= 1;
-        node_.assign(2 * static_cast<size_t>(size_), kEmpty);
-        for (int32_t i = 0; i < n_; ++i) node_[size_ + i] = pack(key[i], i);
-        for (int32_t v = size_ - 1; v >= 1; --v) node_[v] = std::max(node_[2 * v], node_[2 * v + 1]);
+        size_t count = key.size();
+        std::vector<int64_t> leaf(pad8(count), kEmpty);
+        for (size_t i = 0; i < count; ++i) leaf[i] = pack(key[i], static_cast<int32_t>(i));
+        level_.push_back(std::move(leaf));
+        while (count > 1) {
+            count = (count + 7) / 8;
+            const std::vector<int64_t>& below = level_.back();
+            std::vector<int64_t> up(pad8(count), kEmpty);
+            for (size_t v = 0; v < count; ++v) up[v] = max8(&below[8 * v]);
+            level_.push_back(std::move(up));
+        }
     }
     static constexpr int64_t kDecided = INT64_MIN;
     int32_t top() const {
-        const int64_t t = node_[1];
+        const int64_t t = level_.back()[0];
         return t == kEmpty ? -1 : static_cast<int32_t>(~static_cast<uint32_t>(t & 0xFFFFFFFFu));
     }
     void set(int32_t i, int64_t k) {
-        size_t v = static_cast<size_t>(size_) + i;
-        node_[v] = pack(k, i);
-        for (v >>= 1; v >= 1; v >>= 1) {
-            const int64_t m = std::max(node_[2 * v], node_[2 * v + 1]);
-            if (node_[v] == m) break;
-            node_[v] = m;
+        size_t v = static_cast<size_t>(i);
+        level_[0][v] = pack(k, i);
+        for (size_t l = 1; l < level_.size(); ++l) {
+            v >>= 3;
+            const int64_t m = max8(&level_[l - 1][8 * v]);
+            if (level_[l][v] == m) break;
+            level_[l][v] = m;
         }
     }
 
@@ -111,8 +118,13 @@ class ArgmaxTree {
         if (k == kDecided) return kEmpty;
         return static_cast<int64_t>(static_cast<uint64_t>(k) << 32) | static_cast<int64_t>(~static_cast<uint32_t>(i));
     }
-    int32_t n_ = 0, size_ = 1;
-    std::vector<int64_t> node_;
+    static size_t pad8(size_t n) { return n <= 8 ? 8 : (n + 7) / 8 * 8; }  // the root level is never empty
+    static int64_t max8(const int64_t* c) {
+        const int64_t a = std::max(std::max(c[0], c[1]), std::max(c[2], c[3]));
+        const int64_t b = std::max(std::max(c[4], c[5]), std::max(c[6], c[7]));
+        return std::max(a, b);
+    }
+    std::vector<std::vector<int64_t>> level_;
 };
 
 // Ruge-Stueben first pass. Returns cf[i] = 1 for C points, 0 for F points.
