@@ -243,6 +243,35 @@ def test_maxit_and_errors():
         ds.vcycle(_dev(f), _dev(f), 9, 1, 64)
 
 
+@pytest.mark.parametrize("outer", ["ir", "fcg"])
+def test_truncated_solves_are_prefixes_of_the_full_run(outer):
+    """The outer loop enqueues iterations ahead of the one it inspects; none of them may touch the
+    result once the iteration limit is reached. A solve stopped after k iterations reports the first
+    k + 1 entries of the longer solve's residual history bitwise, returns the same x on a repeat,
+    and (iterative refinement, whose history is the true residual) an x whose FP64 residual,
+    recomputed on the host, is that history's last entry."""
+    from paper_2606_19251_amd import capi
+
+    A, f, ho, hp, ds = _setup("delaunay20k")
+    ds.set_jacobi()
+    code = capi.AMGG_OUTER_IR if outer == "ir" else capi.AMGG_OUTER_FCG
+    kw = dict(outer=code, precision=32, tol=1e-30, fallback=False, history_cap=16)
+    _, rc, info, full = ds.solve(_dev(f), maxit=8, **kw)
+    assert rc == capi.AMGG_MAXIT and info.iterations == 8 and len(full) == 9
+    S = amg.to_scipy(A)
+    fb = f - f.mean() if hp.singular else f
+    for k in range(1, 8):
+        x1, rc, info, hist = ds.solve(_dev(f), maxit=k, **kw)
+        x1 = x1.cpu().numpy()
+        assert rc == capi.AMGG_MAXIT and info.iterations == k and info.vcycles == k, (outer, k)
+        assert np.array_equal(_bits(np.asarray(hist)), _bits(np.asarray(full[:k + 1]))), (outer, k)
+        x2, _, _, _ = ds.solve(_dev(f), maxit=k, **kw)
+        assert np.array_equal(_bits(x1), _bits(x2.cpu().numpy())), (outer, k)
+        if outer == "ir":
+            rel = np.linalg.norm(fb - S @ x1) / np.linalg.norm(fb)
+            assert abs(rel - hist[-1]) <= 1e-7 * hist[-1], (k, rel, hist[-1])
+
+
 def test_zero_rhs_returns_zero():
     from paper_2606_19251_amd import capi
 
