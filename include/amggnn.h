@@ -365,7 +365,9 @@ typedef struct {
  * b, x: device FP64 n_0-vectors (x is overwritten). For a singular hierarchy b is
  * projected to zero mean first. history (host, may be NULL) receives up to history_cap
  * relative residuals, entry 0 being 1. Returns 0 on convergence, a positive outcome code
- * otherwise, negative on error. Synchronises the stream once per iteration. */
+ * otherwise, negative on error. The host waits for each iteration's scalars (residual norm,
+ * flags) while up to two further iterations are already enqueued on the stream; iterations
+ * enqueued past the one that stops the solve leave x as it is. Returns with the stream idle. */
 int amgg_solve(amgg_ctx* ctx, const amgg_solve_opts* opts, const double* b, double* x,
                amgg_solve_info* info, double* history, int history_cap, void* stream);
 
