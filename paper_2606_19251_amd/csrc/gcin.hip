@@ -183,8 +183,9 @@ __device__ __forceinline__ void visit_rows(const int32_t* __restrict__ ptr, cons
 // load instruction brings four neighbour rows (the load units process a wavefront's addresses a few
 // lanes per cycle, which bounds a gather of one 4-byte channel per lane). Each row's entries are
 // still visited in stored order, so every channel's sum is the one visit_rows forms. A group takes
-// its entries kBatchX4 at a time, their indices and weights held by its first lanes; use(w, v)
-// gets the four channels as a float4, done(row) is called once per row of the group.
+// its entries kBatchX4 at a time, their indices and weights held by its first lanes; use(w, v, s)
+// gets the four channels as a float4 and s = the row when the entry is the row's own (column =
+// row), else -1; done(row) is called once per row of the group.
 constexpr int kBatchX4 = 8;
 
 template <class Load, class Use, class Done>
@@ -212,6 +213,7 @@ __device__ __forceinline__ void visit_rows_x4(const int32_t* __restrict__ ptr, c
 #pragma unroll
         for (int q = 0; q < B; ++q) vj[q] = load(__shfl(cl, q, 16));
         const float wcur = wl;
+        const int32_t ccur = cl;
         if (k + B < kend) {
             const int32_t kk = min(k + B + l, kend - 1);
             cl = col[kk];
@@ -220,13 +222,14 @@ __device__ __forceinline__ void visit_rows_x4(const int32_t* __restrict__ ptr, c
 #pragma unroll
         for (int q = 0; q < B; ++q) {
             const float wq = __shfl(wcur, q, 16);
+            const int32_t jq = __shfl(ccur, q, 16);
             if (k + q < kend) {
                 while (k + q >= rnext) {
                     done(r);
                     ++r;
                     rnext = bound(r + 1 - g0);
                 }
-                use(wq, vj[q]);
+                use(wq, vj[q], jq == r ? r : -1);
             }
         }
     }
@@ -521,7 +524,12 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
                                                    const float* __restrict__ W, const float* __restrict__ b,
                                                    const unsigned short* __restrict__ wbf,
                                                    float* __restrict__ Hout, float* __restrict__ Y,
-                                                   double* __restrict__ tstat) {
+                                                   double* __restrict__ tstat, double* __restrict__ psum,
+                                                   float* __restrict__ pmax, int32_t* __restrict__ parg) {
+    // With 64 channels the kernel also forms the per-tile readout partials of the layer below
+    // (psum / pmax / parg as pool_tile_kernel writes them): every row's own entry of A_hat brings
+    // that row's normalised, rectified input x, which is kept in Xs and pooled after the
+    // aggregation in pool_tile_kernel's order, so the layer below needs no pooling pass.
     // The product overwrites the aggregates in place: every wavefront reads only its own 16
     // rows of Hs and writes the same rows, each output after all of its row's reads (the
     // stores depend on them), so one tile buffer serves both; with the weights' bf16 parts
@@ -530,6 +538,9 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
     __shared__ float Hs[TILE][HD + 1];
     float (*Ds)[HD + 1] = Hs;
     __shared__ double sh[4][HD];
+    __shared__ float Xs[HD == 64 ? TILE : 1][HD + 1];
+    __shared__ float smax[4][HD];
+    __shared__ int32_t sarg[4][HD];
     const int tile = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
     const int g = tile_graph[tile];
     const int32_t end = gend[g];
@@ -559,11 +570,22 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
                     return *reinterpret_cast<const float4*>(Yp + static_cast<int64_t>(j) * HD + c4);
                 }
             },
-            [&](float wp, const float4& v) {
-                h4.x += wp * normrelu(v.x, mu4.x, rs4.x, ga4.x, be4.x);
-                h4.y += wp * normrelu(v.y, mu4.y, rs4.y, ga4.y, be4.y);
-                h4.z += wp * normrelu(v.z, mu4.z, rs4.z, ga4.z, be4.z);
-                h4.w += wp * normrelu(v.w, mu4.w, rs4.w, ga4.w, be4.w);
+            [&](float wp, const float4& v, int32_t self) {
+                const float4 x = make_float4(normrelu(v.x, mu4.x, rs4.x, ga4.x, be4.x),
+                                             normrelu(v.y, mu4.y, rs4.y, ga4.y, be4.y),
+                                             normrelu(v.z, mu4.z, rs4.z, ga4.z, be4.z),
+                                             normrelu(v.w, mu4.w, rs4.w, ga4.w, be4.w));
+                h4.x += wp * x.x;
+                h4.y += wp * x.y;
+                h4.z += wp * x.z;
+                h4.w += wp * x.w;
+                if (self >= 0) {
+                    float* xs = &Xs[self - tile * TILE][c4];
+                    xs[0] = x.x;
+                    xs[1] = x.y;
+                    xs[2] = x.z;
+                    xs[3] = x.w;
+                }
             },
             [&](int32_t row) {
                 const float4 hv = row < end ? h4 : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -601,6 +623,38 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
             });
     }
     __syncthreads();
+    if constexpr (HD == 64) {
+        // readout partials of the layer below: sum, max and first arg-max of x per channel over
+        // the tile's rows (each row's x came with its own entry; rows past the graph have none)
+        double s = 0.0;
+        float mx = -INFINITY;
+        int32_t am = INT32_MAX;
+        for (int r = 0; r < 16; ++r) {
+            const int lr = wv * 16 + r;
+            const int32_t row = tile * TILE + lr;
+            if (row < end) {
+                const float x = Xs[lr][c];
+                s += x;
+                if (x > mx) {
+                    mx = x;
+                    am = row;
+                }
+            }
+        }
+        smax[wv][c] = mx;
+        sarg[wv][c] = am;
+        s = wave4_sum(s, sh);
+        if (wv == 0) {
+            for (int k = 1; k < 4; ++k)
+                if (smax[k][c] > mx) {
+                    mx = smax[k][c];
+                    am = sarg[k][c];
+                }
+            psum[tile * HD + c] = s;
+            pmax[tile * HD + c] = mx;
+            parg[tile * HD + c] = am;
+        }
+    }
     tile_gemm<HD, MFMA, true, X3, true>(Hs, W, nullptr, Ds, nullptr, wbf, wbf + HD * HD);
     __syncthreads();
     const float bc = b[c];
@@ -1616,20 +1670,31 @@ void forward_impl(gcin_batch* b, int degree, int precision, const float* P, floa
     layer0_kernel<HD><<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->x0, b->d_tile_graph, b->d_gend, W0, b0, b->H0,
                                         b->tstat);
     const int C = b->nchunks;
-    // statistics of layer l, then its readout (which feeds no later layer, so pooling each layer
-    // as soon as its statistics exist leaves every result as it is and lets an inference-only
-    // batch reuse the buffer of layer l - 1 for layer l + 1)
-    auto stats_and_pool = [&](int l) {
+    // Statistics of layer l, then its readout, which feeds no later layer: pooling each layer as
+    // soon as its statistics exist leaves every result as it is and lets an inference-only batch
+    // reuse the buffer of layer l - 1 for layer l + 1. With 64 channels the readout partials of
+    // layer l are formed by the kernel of layer l + 1 (from the rows' own entries of A_hat), the
+    // last layer's by a pooling pass; the per-graph reductions follow either way.
+    auto stats = [&](int l) {
         chunk_sum_kernel<HD, 2><<<C, NT, 0, st>>>(b->tstat, b->d_cbound, b->cbuf);
         stats_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->mu[l], b->rstd[l]);
+    };
+    auto pool_tiles = [&](int l) {
         (l == 0 ? pool_tile_kernel<HD, true> : pool_tile_kernel<HD, false>)<<<T, NT, 0, st>>>(
             b->d_tile_graph, b->d_gend, b->Y[l], b->H0, W0, b0, b->mu[l], b->rstd[l], P + o.gam[l], P + o.bet[l],
             b->tpsum, b->tpmax, b->tparg);
+    };
+    auto pool_graphs = [&](int l) {
         pool_chunk_kernel<HD><<<C, NT, 0, st>>>(b->tpsum, b->tpmax, b->tparg, b->d_cbound, b->cbuf, b->cmax, b->carg);
         pool_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->cmax, b->carg, b->d_gchunk, b->d_gcnt, l, b->pooled,
                                                 b->argmax);
     };
-    stats_and_pool(0);
+    constexpr bool fused_pool = HD == 64;
+    stats(0);
+    if (!fused_pool) {
+        pool_tiles(0);
+        pool_graphs(0);
+    }
     const bool mfma = HD == 64 && precision != GCIN_FP32;
     if (mfma) weights_bf16_kernel<HD><<<NL - 1, 256, 0, st>>>(P, o, b->wbf);
     for (int l = 1; l < NL; ++l) {
@@ -1644,8 +1709,17 @@ void forward_impl(gcin_batch* b, int degree, int precision, const float* P, floa
         kern<<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->d_tile_graph, b->d_gend, b->Y[l - 1], b->H0, W0, b0,
                                b->mu[l - 1], b->rstd[l - 1], P + o.gam[l - 1], P + o.bet[l - 1], P + o.convW[l],
                                P + o.convb[l], b->wbf + static_cast<int64_t>(l - 1) * 2 * HD * HD, b->H[l], b->Y[l],
-                               b->tstat);
-        stats_and_pool(l);
+                               b->tstat, fused_pool ? b->tpsum : nullptr, b->tpmax, b->tparg);
+        if (fused_pool) pool_graphs(l - 1);
+        stats(l);
+        if (!fused_pool) {
+            pool_tiles(l);
+            pool_graphs(l);
+        }
+    }
+    if (fused_pool) {
+        pool_tiles(NL - 1);
+        pool_graphs(NL - 1);
     }
     head_fwd_kernel<HD><<<G, 128, 0, st>>>(P, o, b->pooled, b->hs, coeffs_out);
 }
