@@ -253,9 +253,10 @@ __device__ __forceinline__ double wave4_sum(double v, double (*sh)[HD]) {
 // A workgroup owns 256 consecutive rows of the level graph. Each thread writes its row's
 // pointer and degree feature and marks the row's entries in an LDS map; the entries are then
 // copied with unit stride (columns shifted to the graph's first batch row, weights a_ij, 1 for
-// the self-loop of A_hat, whose entry also writes the a_ii feature). A block whose entries do
-// not fit the map is copied row by row.
-constexpr int kFillCap = 4096;
+// the self-loop of A_hat, whose entry also writes the a_ii feature). The map holds 64 entries per
+// row on average (the coarse levels of the 3D hierarchies have 25-60); a block whose entries do
+// not fit it is copied row by row.
+constexpr int kFillCap = 16384;
 
 __global__ __launch_bounds__(256) void fill_graph_kernel(int32_t n, const int32_t* __restrict__ rp,
                                                         const int32_t* __restrict__ cl,
