@@ -536,12 +536,9 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
     // stores depend on them), so one tile buffer serves both; with the weights' bf16 parts
     // read from global memory (wbf: hi, then lo) the tile and the statistics are all the LDS a
     // workgroup holds (LDS would admit 8 workgroups per CU; registers admit 4 wavefronts per SIMD).
-    __shared__ float Hs[TILE][HD + 1];
+    __shared__ __align__(16) float Hs[TILE][HD + 1];  // aggregates, products, then the reductions
     float (*Ds)[HD + 1] = Hs;
-    __shared__ double sh[4][HD];
     __shared__ float Xs[HD == 64 ? TILE : 1][HD + 1];
-    __shared__ float smax[4][HD];
-    __shared__ int32_t sarg[4][HD];
     const int tile = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
     const int g = tile_graph[tile];
     const int32_t end = gend[g];
@@ -624,42 +621,15 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
             });
     }
     __syncthreads();
-    if constexpr (HD == 64) {
-        // readout partials of the layer below: sum, max and first arg-max of x per channel over
-        // the tile's rows (each row's x came with its own entry; rows past the graph have none)
-        double s = 0.0;
-        float mx = -INFINITY;
-        int32_t am = INT32_MAX;
-        for (int r = 0; r < 16; ++r) {
-            const int lr = wv * 16 + r;
-            const int32_t row = tile * TILE + lr;
-            if (row < end) {
-                const float x = Xs[lr][c];
-                s += x;
-                if (x > mx) {
-                    mx = x;
-                    am = row;
-                }
-            }
-        }
-        smax[wv][c] = mx;
-        sarg[wv][c] = am;
-        s = wave4_sum(s, sh);
-        if (wv == 0) {
-            for (int k = 1; k < 4; ++k)
-                if (smax[k][c] > mx) {
-                    mx = smax[k][c];
-                    am = sarg[k][c];
-                }
-            psum[tile * HD + c] = s;
-            pmax[tile * HD + c] = mx;
-            parg[tile * HD + c] = am;
-        }
-    }
     tile_gemm<HD, MFMA, true, X3, true>(Hs, W, nullptr, Ds, nullptr, wbf, wbf + HD * HD);
     __syncthreads();
+    // y of the wave's rows with the per-tile sums of y and y^2 and, with 64 channels, the readout
+    // partials of the layer below (sum, max and first arg-max of x per channel; each row's x came
+    // with its own entry, rows past the graph have none), each summed over the rows in order
     const float bc = b[c];
-    double s1 = 0.0, s2 = 0.0;
+    double s1 = 0.0, s2 = 0.0, ps = 0.0;
+    float mx = -INFINITY;
+    int32_t am = INT32_MAX;
     for (int r = 0; r < 16; ++r) {
         const int lr = wv * 16 + r;
         const int32_t row = tile * TILE + lr;
@@ -668,14 +638,46 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
             y = Ds[lr][c] + bc;
             s1 += y;
             s2 += static_cast<double>(y) * y;
+            if constexpr (HD == 64) {
+                const float x = Xs[lr][c];
+                ps += x;
+                if (x > mx) {
+                    mx = x;
+                    am = row;
+                }
+            }
         }
         Y[static_cast<int64_t>(row) * HD + c] = y;
     }
-    s1 = wave4_sum(s1, sh);
-    s2 = wave4_sum(s2, sh);
+    // every wave has read its rows of the tile, whose space now holds the four waves' partials;
+    // wave 0 combines them in wave order
+    __syncthreads();
+    double (*r1)[HD] = reinterpret_cast<double (*)[HD]>(&Hs[0][0]);
+    double (*r2)[HD] = r1 + 4;
+    double (*rp)[HD] = r1 + 8;
+    float (*rmax)[HD] = reinterpret_cast<float (*)[HD]>(r1 + 12);
+    int32_t (*rarg)[HD] = reinterpret_cast<int32_t (*)[HD]>(rmax + 4);
+    r1[wv][c] = s1;
+    r2[wv][c] = s2;
+    if constexpr (HD == 64) {
+        rp[wv][c] = ps;
+        rmax[wv][c] = mx;
+        rarg[wv][c] = am;
+    }
+    __syncthreads();
     if (wv == 0) {
-        tstat[tile * 2 * HD + c] = s1;
-        tstat[tile * 2 * HD + HD + c] = s2;
+        tstat[tile * 2 * HD + c] = r1[0][c] + r1[1][c] + r1[2][c] + r1[3][c];
+        tstat[tile * 2 * HD + HD + c] = r2[0][c] + r2[1][c] + r2[2][c] + r2[3][c];
+        if constexpr (HD == 64) {
+            for (int k = 1; k < 4; ++k)
+                if (rmax[k][c] > mx) {
+                    mx = rmax[k][c];
+                    am = rarg[k][c];
+                }
+            psum[tile * HD + c] = rp[0][c] + rp[1][c] + rp[2][c] + rp[3][c];
+            pmax[tile * HD + c] = mx;
+            parg[tile * HD + c] = am;
+        }
     }
 }
 
