@@ -118,8 +118,8 @@ def outer_bytes_fcg(n: int, nnz: int, idx: int) -> float:
 # as null once that source changes (summaries under profiles/).
 TRAFFIC_SOURCE = "paper_2606_19251_amd/csrc/k_csr.hip"
 TRAFFIC = {  # workload -> (sha256 prefix of TRAFFIC_SOURCE, bytes per launch)
-    "delaunay1m": ("14c7a244c7c89f7e", 72729658),
-    "tet8m": ("14c7a244c7c89f7e", 389087505),
+    "delaunay1m": ("14c7a244c7c89f7e", 72729649),
+    "tet8m": ("14c7a244c7c89f7e", 389149914),
 }
 
 
