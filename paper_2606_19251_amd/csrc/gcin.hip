@@ -178,25 +178,27 @@ __device__ __forceinline__ void visit_rows(const int32_t* __restrict__ ptr, cons
     for (; r < r1; ++r) done(r);
 }
 
-// The same walk for 64 channels with 16-byte gathers: the 16 lanes of group q = lane / 16 own the
-// rows [r0 + 4 q, r0 + 4 q + 4) and lane p = lane % 16 holds channels 4 p .. 4 p + 3, so that one
-// load instruction brings four neighbour rows (the load units process a wavefront's addresses a few
-// lanes per cycle, which bounds a gather of one 4-byte channel per lane). Each row's entries are
+// The same walk with 16-byte gathers: the HD / 4 = G lanes of group q (of the 4 HD lanes that own
+// rows [r0, r0 + 16)) own the rows [r0 + 4 q, r0 + 4 q + 4) and lane p of the group holds channels
+// 4 p .. 4 p + 3, so that one load instruction brings 64 / G neighbour rows (the load units
+// process a wavefront's addresses a few lanes per cycle, which bounds a gather of one 4-byte
+// channel per lane). Each row's entries are
 // still visited in stored order, so every channel's sum is the one visit_rows forms. A group takes
 // its entries kBatchX4 at a time, their indices and weights held by its first lanes; use(w, v, s)
 // gets the four channels as a float4 and s = the row when the entry is the row's own (column =
 // row), else -1; done(row) is called once per row of the group.
 constexpr int kBatchX4 = 8;
 
-template <class Load, class Use, class Done>
+template <int G, class Load, class Use, class Done>
 __device__ __forceinline__ void visit_rows_x4(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                               const float* __restrict__ w, int32_t r0, Load load, Use use,
                                               Done done) {
+    static_assert(G == 16 || G == 8, "groups of 16 (64 channels) or 8 (32 channels) lanes");
     constexpr int B = kBatchX4;
-    const int p = static_cast<int>(threadIdx.x % 16);
-    const int32_t g0 = r0 + 4 * static_cast<int32_t>((threadIdx.x % 64) / 16);  // the group's first row
+    const int p = static_cast<int>(threadIdx.x % G);
+    const int32_t g0 = r0 + 4 * static_cast<int32_t>((threadIdx.x % (4 * G)) / G);  // the group's first row
     const int32_t rp = ptr[g0 + min(p, 4)];
-    auto bound = [&](int32_t i) { return __shfl(rp, i, 16); };  // ptr[g0 + i], i <= 4
+    auto bound = [&](int32_t i) { return __shfl(rp, i, G); };  // ptr[g0 + i], i <= 4
     const int32_t kbeg = bound(0), kend = bound(4);
     int32_t r = g0;
     int32_t rnext = bound(1);
@@ -211,7 +213,7 @@ __device__ __forceinline__ void visit_rows_x4(const int32_t* __restrict__ ptr, c
     for (int32_t k = kbeg; k < kend; k += B) {
         float4 vj[B];
 #pragma unroll
-        for (int q = 0; q < B; ++q) vj[q] = load(__shfl(cl, q, 16));
+        for (int q = 0; q < B; ++q) vj[q] = load(__shfl(cl, q, G));
         const float wcur = wl;
         const int32_t ccur = cl;
         if (k + B < kend) {
@@ -221,8 +223,8 @@ __device__ __forceinline__ void visit_rows_x4(const int32_t* __restrict__ ptr, c
         }
 #pragma unroll
         for (int q = 0; q < B; ++q) {
-            const float wq = __shfl(wcur, q, 16);
-            const int32_t jq = __shfl(ccur, q, 16);
+            const float wq = __shfl(wcur, q, G);
+            const int32_t jq = __shfl(ccur, q, G);
             if (k + q < kend) {
                 while (k + q >= rnext) {
                     done(r);
@@ -527,10 +529,10 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
                                                    float* __restrict__ Hout, float* __restrict__ Y,
                                                    double* __restrict__ tstat, double* __restrict__ psum,
                                                    float* __restrict__ pmax, int32_t* __restrict__ parg) {
-    // With 64 channels the kernel also forms the per-tile readout partials of the layer below
-    // (psum / pmax / parg as pool_tile_kernel writes them): every row's own entry of A_hat brings
-    // that row's normalised, rectified input x, which is kept in Xs and pooled after the
-    // aggregation in pool_tile_kernel's order, so the layer below needs no pooling pass.
+    // The kernel also forms the per-tile readout partials of the layer below (psum / pmax / parg
+    // as pool_tile_kernel writes them): every row's own entry of A_hat brings that row's
+    // normalised, rectified input x, which is kept in Xs and pooled in the output loop in
+    // pool_tile_kernel's order, so the layer below needs no pooling pass.
     // The product overwrites the aggregates in place: every wavefront reads only its own 16
     // rows of Hs and writes the same rows, each output after all of its row's reads (the
     // stores depend on them), so one tile buffer serves both; with the weights' bf16 parts
@@ -538,14 +540,15 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
     // workgroup holds (LDS would admit 8 workgroups per CU; registers admit 4 wavefronts per SIMD).
     __shared__ __align__(16) float Hs[TILE][HD + 1];  // aggregates, products, then the reductions
     float (*Ds)[HD + 1] = Hs;
-    __shared__ float Xs[HD == 64 ? TILE : 1][HD + 1];
+    __shared__ float Xs[TILE][HD + 1];
     const int tile = blockIdx.x, wv = threadIdx.x / HD, c = threadIdx.x % HD;
     const int g = tile_graph[tile];
     const int32_t end = gend[g];
     const int32_t r0 = tile * TILE + wv * 16;
-    if constexpr (HD == 64) {
+    {
         // channels 4 p .. 4 p + 3 of the lane's group (see visit_rows_x4)
-        const int c4 = 4 * static_cast<int>(threadIdx.x % 16);
+        constexpr int G = HD / 4;
+        const int c4 = 4 * static_cast<int>(threadIdx.x % G);
         const float4 mu4 = *reinterpret_cast<const float4*>(mup + g * HD + c4);
         const float4 rs4 = *reinterpret_cast<const float4*>(rsp + g * HD + c4);
         const float4 ga4 = *reinterpret_cast<const float4*>(gam + c4);
@@ -557,7 +560,7 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
             bb4 = *reinterpret_cast<const float4*>(b0 + c4);
         }
         float4 h4 = make_float4(0.f, 0.f, 0.f, 0.f);
-        visit_rows_x4(
+        visit_rows_x4<G>(
             ptr, col, w, r0,
             [&](int32_t j) {
                 if constexpr (Y0) {
@@ -595,37 +598,13 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
                 if (Hout) *reinterpret_cast<float4*>(Hout + static_cast<int64_t>(row) * HD + c4) = hv;
                 h4 = make_float4(0.f, 0.f, 0.f, 0.f);
             });
-    } else {
-        const float mu = mup[g * HD + c], rs = rsp[g * HD + c], ga = gam[c], be = bet[c];
-        float w0 = 0.0f, w1 = 0.0f, bb0 = 0.0f;
-        if constexpr (Y0) {
-            w0 = W0[c];
-            w1 = W0[HD + c];
-            bb0 = b0[c];
-        }
-        float h = 0.0f;
-        visit_rows<HD, float>(
-            ptr, col, w, r0, r0 + 16,
-            [&](int32_t j) {
-                if constexpr (Y0)
-                    return y0_of(reinterpret_cast<const float2*>(H0)[j], w0, w1, bb0);
-                else
-                    return Yp[static_cast<int64_t>(j) * HD + c];
-            },
-            [&](float wp, float v) { h += wp * normrelu(v, mu, rs, ga, be); },
-            [&](int32_t row) {
-                const float hv = row < end ? h : 0.0f;
-                Hs[row - tile * TILE][c] = hv;
-                if (Hout) Hout[static_cast<int64_t>(row) * HD + c] = hv;  // kept for a backward only
-                h = 0.0f;
-            });
     }
     __syncthreads();
     tile_gemm<HD, MFMA, true, X3, true>(Hs, W, nullptr, Ds, nullptr, wbf, wbf + HD * HD);
     __syncthreads();
-    // y of the wave's rows with the per-tile sums of y and y^2 and, with 64 channels, the readout
-    // partials of the layer below (sum, max and first arg-max of x per channel; each row's x came
-    // with its own entry, rows past the graph have none), each summed over the rows in order
+    // y of the wave's rows with the per-tile sums of y and y^2 and the readout partials of the
+    // layer below (sum, max and first arg-max of x per channel; each row's x came with its own
+    // entry, rows past the graph have none), each summed over the rows in order
     const float bc = b[c];
     double s1 = 0.0, s2 = 0.0, ps = 0.0;
     float mx = -INFINITY;
@@ -638,13 +617,11 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
             y = Ds[lr][c] + bc;
             s1 += y;
             s2 += static_cast<double>(y) * y;
-            if constexpr (HD == 64) {
-                const float x = Xs[lr][c];
-                ps += x;
-                if (x > mx) {
-                    mx = x;
-                    am = row;
-                }
+            const float x = Xs[lr][c];
+            ps += x;
+            if (x > mx) {
+                mx = x;
+                am = row;
             }
         }
         Y[static_cast<int64_t>(row) * HD + c] = y;
@@ -659,25 +636,21 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
     int32_t (*rarg)[HD] = reinterpret_cast<int32_t (*)[HD]>(rmax + 4);
     r1[wv][c] = s1;
     r2[wv][c] = s2;
-    if constexpr (HD == 64) {
-        rp[wv][c] = ps;
-        rmax[wv][c] = mx;
-        rarg[wv][c] = am;
-    }
+    rp[wv][c] = ps;
+    rmax[wv][c] = mx;
+    rarg[wv][c] = am;
     __syncthreads();
     if (wv == 0) {
         tstat[tile * 2 * HD + c] = r1[0][c] + r1[1][c] + r1[2][c] + r1[3][c];
         tstat[tile * 2 * HD + HD + c] = r2[0][c] + r2[1][c] + r2[2][c] + r2[3][c];
-        if constexpr (HD == 64) {
-            for (int k = 1; k < 4; ++k)
-                if (rmax[k][c] > mx) {
-                    mx = rmax[k][c];
-                    am = rarg[k][c];
-                }
-            psum[tile * HD + c] = rp[0][c] + rp[1][c] + rp[2][c] + rp[3][c];
-            pmax[tile * HD + c] = mx;
-            parg[tile * HD + c] = am;
-        }
+        for (int k = 1; k < 4; ++k)
+            if (rmax[k][c] > mx) {
+                mx = rmax[k][c];
+                am = rarg[k][c];
+            }
+        psum[tile * HD + c] = rp[0][c] + rp[1][c] + rp[2][c] + rp[3][c];
+        pmax[tile * HD + c] = mx;
+        parg[tile * HD + c] = am;
     }
 }
 
@@ -1675,9 +1648,9 @@ void forward_impl(gcin_batch* b, int degree, int precision, const float* P, floa
     const int C = b->nchunks;
     // Statistics of layer l, then its readout, which feeds no later layer: pooling each layer as
     // soon as its statistics exist leaves every result as it is and lets an inference-only batch
-    // reuse the buffer of layer l - 1 for layer l + 1. With 64 channels the readout partials of
-    // layer l are formed by the kernel of layer l + 1 (from the rows' own entries of A_hat), the
-    // last layer's by a pooling pass; the per-graph reductions follow either way.
+    // reuse the buffer of layer l - 1 for layer l + 1. The readout partials of layer l are formed
+    // by the kernel of layer l + 1 (from the rows' own entries of A_hat), the last layer's by a
+    // pooling pass; the per-graph reductions follow.
     auto stats = [&](int l) {
         chunk_sum_kernel<HD, 2><<<C, NT, 0, st>>>(b->tstat, b->d_cbound, b->cbuf);
         stats_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->d_gchunk, b->d_gcnt, b->mu[l], b->rstd[l]);
@@ -1692,12 +1665,7 @@ void forward_impl(gcin_batch* b, int degree, int precision, const float* P, floa
         pool_final_kernel<HD><<<G, NT, 0, st>>>(b->cbuf, b->cmax, b->carg, b->d_gchunk, b->d_gcnt, l, b->pooled,
                                                 b->argmax);
     };
-    constexpr bool fused_pool = HD == 64;
     stats(0);
-    if (!fused_pool) {
-        pool_tiles(0);
-        pool_graphs(0);
-    }
     const bool mfma = HD == 64 && precision != GCIN_FP32;
     if (mfma) weights_bf16_kernel<HD><<<NL - 1, 256, 0, st>>>(P, o, b->wbf);
     for (int l = 1; l < NL; ++l) {
@@ -1712,18 +1680,12 @@ void forward_impl(gcin_batch* b, int degree, int precision, const float* P, floa
         kern<<<T, NT, 0, st>>>(b->ptr, b->col, b->w, b->d_tile_graph, b->d_gend, b->Y[l - 1], b->H0, W0, b0,
                                b->mu[l - 1], b->rstd[l - 1], P + o.gam[l - 1], P + o.bet[l - 1], P + o.convW[l],
                                P + o.convb[l], b->wbf + static_cast<int64_t>(l - 1) * 2 * HD * HD, b->H[l], b->Y[l],
-                               b->tstat, fused_pool ? b->tpsum : nullptr, b->tpmax, b->tparg);
-        if (fused_pool) pool_graphs(l - 1);
+                               b->tstat, b->tpsum, b->tpmax, b->tparg);
+        pool_graphs(l - 1);
         stats(l);
-        if (!fused_pool) {
-            pool_tiles(l);
-            pool_graphs(l);
-        }
     }
-    if (fused_pool) {
-        pool_tiles(NL - 1);
-        pool_graphs(NL - 1);
-    }
+    pool_tiles(NL - 1);
+    pool_graphs(NL - 1);
     head_fwd_kernel<HD><<<G, 128, 0, st>>>(P, o, b->pooled, b->hs, coeffs_out);
 }
 
