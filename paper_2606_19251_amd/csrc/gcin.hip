@@ -182,11 +182,11 @@ __device__ __forceinline__ void visit_rows(const int32_t* __restrict__ ptr, cons
 // rows [r0, r0 + 16)) own the rows [r0 + 4 q, r0 + 4 q + 4) and lane p of the group holds channels
 // 4 p .. 4 p + 3, so that one load instruction brings 64 / G neighbour rows (the load units
 // process a wavefront's addresses a few lanes per cycle, which bounds a gather of one 4-byte
-// channel per lane). Each row's entries are
-// still visited in stored order, so every channel's sum is the one visit_rows forms. A group takes
-// its entries kBatchX4 at a time, their indices and weights held by its first lanes; use(w, v, s)
-// gets the four channels as a float4 and s = the row when the entry is the row's own (column =
-// row), else -1; done(row) is called once per row of the group.
+// channel per lane). Each row's entries are still visited in stored order, so every channel's sum
+// is the one visit_rows forms. A group takes its entries kBatchX4 at a time, their indices and
+// weights held by its first lanes; use(w, v, s) gets the four channels as a float4 and s = the
+// row when the entry is the row's own (column = row), else -1; done(row) is called once per row
+// of the group.
 constexpr int kBatchX4 = 8;
 
 template <int G, class Load, class Use, class Done>
@@ -535,9 +535,10 @@ __global__ __launch_bounds__(4 * HD) void layer_kernel(const int32_t* __restrict
     // pool_tile_kernel's order, so the layer below needs no pooling pass.
     // The product overwrites the aggregates in place: every wavefront reads only its own 16
     // rows of Hs and writes the same rows, each output after all of its row's reads (the
-    // stores depend on them), so one tile buffer serves both; with the weights' bf16 parts
-    // read from global memory (wbf: hi, then lo) the tile and the statistics are all the LDS a
-    // workgroup holds (LDS would admit 8 workgroups per CU; registers admit 4 wavefronts per SIMD).
+    // stores depend on them), so one tile buffer serves both, and after the output loop it holds
+    // the per-tile reductions; with the weights' bf16 parts read from global memory (wbf: hi,
+    // then lo) the tile and the rows' own inputs Xs are all the LDS a workgroup holds (33 KB with
+    // 64 channels: 4 workgroups per CU, as many as the registers admit).
     __shared__ __align__(16) float Hs[TILE][HD + 1];  // aggregates, products, then the reductions
     float (*Ds)[HD + 1] = Hs;
     __shared__ float Xs[TILE][HD + 1];
