@@ -104,6 +104,40 @@ def test_forward_bf16_matches_oracle():
     print(f"[gpu] forward rel err fp32 {_rel(out32, ref):.2e} bf16 {_rel(out, ref):.2e}", flush=True)
 
 
+def _banded(n, half):
+    """A symmetric M-matrix with 2 half + 1 entries per interior row: 256-row blocks of it hold more
+    entries than the graph batch's entry-to-row map, so they are copied row by row."""
+    import scipy.sparse as sp
+
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    band = (np.abs(i - j) <= half) & (i != j)
+    off = np.where(band, -(1.0 + 0.5 * ((i + j) % 7) / 7.0), 0.0)
+    A = sp.csr_matrix(off + np.diag(-off.sum(axis=1) + 0.1))
+    A.sort_indices()
+    return A
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-4), (1, 2e-2)])
+def test_forward_with_row_by_row_copied_blocks_matches_oracle(precision, tol):
+    """Graphs whose 256-row blocks exceed the batch copy's entry map (71 entries per row) next to
+    ordinary mesh levels: the same coefficients as the oracle's forward."""
+    from paper_2606_19251_amd.gcin import GraphBatch
+
+    flat, p64 = _params(9)
+    B = _banded(600, 35)
+    assert min(B.indptr[256] - B.indptr[0], B.indptr[512] - B.indptr[256]) > 16384  # copied row by row
+    ho, ds = _solvers()[2]
+    graphs = [tuple(torch.from_numpy(a).cuda() for a in (B.indptr.astype(np.int32), B.indices.astype(np.int32),
+                                                         B.data.astype(np.float64)))]
+    graphs += [ds.A[l] for l in range(ds.nlevels)]
+    mats = [B] + [ho.levels[l].A for l in range(ho.nlevels)]
+    out = GraphBatch(graphs, torch.device("cuda", 0)).forward(torch.from_numpy(flat).cuda(), 2, precision)
+    ref = OG.forward_np(p64, mats)
+    err = _rel(out.cpu().numpy(), ref)
+    print(f"[gpu] banded + mesh forward precision {precision}: {err:.2e}", flush=True)
+    assert err <= tol, err
+
+
 def test_forward_batch_independent_bitwise():
     from paper_2606_19251_amd import capi
     from paper_2606_19251_amd.gcin import GraphBatch
