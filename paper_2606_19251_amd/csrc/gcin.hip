@@ -410,8 +410,8 @@ __device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned
 // whose gradients must match an FP32/FP64 evaluation.
 // GB: the bf16 copies of B (and of its low parts) are read from global memory, row-major [col][k]
 // with row stride HD (Bg, Bglo; formed once per forward by weights_bf16_kernel), not from LDS:
-// the weights are shared by every tile and stay in cache, and the LDS left to a workgroup is its
-// tile (more workgroups per CU).
+// the weights are shared by every tile and stay in cache, and a workgroup's LDS holds no copy of
+// them.
 template <int HD, bool MFMA, bool SPLIT = false, bool SPLITB = false, bool GB = false>
 __device__ __forceinline__ void tile_gemm(const float (*A)[HD + 1], const float* __restrict__ Bf,
                                           const unsigned short (*Bt)[HD + 8], float (*D)[HD + 1],
