@@ -620,17 +620,18 @@ def workload_report(torch, case, steps, warmup, nu, outers, with_roofline=True):
     obytes = {"ir": outer_bytes_ir(n0, z0, idx0), "fcg": outer_bytes_fcg(n0, z0, idx0)}
     olbytes = {"ir": outer_bytes_ir(n0, z0, lidx0), "fcg": outer_bytes_fcg(n0, z0, lidx0)}
     code = {"ir": capi.AMGG_OUTER_IR, "fcg": capi.AMGG_OUTER_FCG}
-    out = {"workload": f"{WORKLOADS[case.name][1]} (n={n0}, nnz={z0})", "levels": [L.n for L in hh.levels],
-           "level_nnz": [L.nnz for L in hh.levels], "configured_outer": CONFIGURED_OUTER[case.name],
-           "vcycle_bytes": {k: int(v) for k, v in vbytes.items()},
-           "vcycle_layout_bytes": {k: int(v) for k, v in lbytes.items()},
-           "packed_columns": [{"rows": v["pack_rows"], "far": v["pack_far"]} for v in views]}
     vbytes["gnn_sparse_all_levels"] = vbytes["gnn"]
     lbytes["gnn_sparse_all_levels"] = lbytes["gnn"]
     if case.pred.diag_levels > 0:  # the cost-aware network: one-pass diagonal steps on its finest levels
         vbytes["gnn"] = level_bytes_vcycle(hh, views, smoother_sparse=True, diag_levels=case.pred.diag_levels)
         lbytes["gnn"] = level_bytes_vcycle(hh, views, smoother_sparse=True, diag_levels=case.pred.diag_levels,
                                            layout=True)
+    out = {"workload": f"{WORKLOADS[case.name][1]} (n={n0}, nnz={z0})", "levels": [L.n for L in hh.levels],
+           "level_nnz": [L.nnz for L in hh.levels], "configured_outer": CONFIGURED_OUTER[case.name],
+           "vcycle_bytes": {k: int(v) for k, v in vbytes.items()},
+           "vcycle_layout_bytes": {k: int(v) for k, v in lbytes.items()},
+           "outer_iteration_bytes": {k: int(v) for k, v in obytes.items()},
+           "packed_columns": [{"rows": v["pack_rows"], "far": v["pack_far"]} for v in views]}
     out["gnn_diag_levels"] = case.pred.diag_levels
     for outer in outers:
         res = {}
